@@ -1,0 +1,90 @@
+"""Seeded synthetic SPD inputs shared by the oracle and the HIP path.
+
+This module holds input recipes only: no step of the factorization is here.
+The paper factors randomly generated SPD matrices (Results, first paragraph)
+and motivates the method with Gaussian-process kernels (Introduction); the
+recipes below are those workloads at fixed seeds:
+
+  gg_plus_identity(n, seed)   A = G G^T / n + I, G iid N(0,1); spectrum in
+                              about [1, 5] (kappa ~ 5).
+  se_kernel(n, seed, ...)     squared-exponential kernel on n points uniform
+                              in [0,1]^2, A_ij = exp(-|x_i-x_j|^2/(2 l^2)) +
+                              nugget * delta_ij (lengthscale 0.1, nugget 1e-2).
+  integer_factor(n, seed)     an integer lower-triangular L0 with positive
+                              diagonal and A = L0 L0^T computed exactly; every
+                              correct FP64 Cholesky returns L0 bit for bit.
+
+Both sides of a parity test receive the identical FP64 bytes produced here.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def gg_plus_identity(n: int, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    A = G @ G.T / n + np.eye(n)
+    return np.ascontiguousarray((A + A.T) * 0.5)
+
+
+def se_points(n: int, seed: int = 1) -> np.ndarray:
+    return np.random.default_rng(seed).random((n, 2))
+
+
+def se_kernel(n: int, seed: int = 1, lengthscale: float = 0.1, nugget: float = 1e-2,
+              rows: slice | None = None) -> np.ndarray:
+    """SE kernel matrix (or the row block `rows` of it).  Squared distances are
+    formed coordinate-wise, never through the |x|^2+|y|^2-2xy expansion, so
+    they are never negative."""
+    x = se_points(n, seed)
+    r = rows if rows is not None else slice(0, n)
+    xr = x[r]
+    d0 = xr[:, 0:1] - x[None, :, 0]
+    d1 = xr[:, 1:2] - x[None, :, 1]
+    K = np.exp(-(d0 * d0 + d1 * d1) / (2.0 * lengthscale * lengthscale))
+    idx = np.arange(r.start, r.start + xr.shape[0])
+    K[np.arange(xr.shape[0]), idx] += nugget
+    return np.ascontiguousarray(K)
+
+
+def se_kernel_device(n: int, seed: int = 1, lengthscale: float = 0.1, nugget: float = 1e-2,
+                     device="cuda", lda: int | None = None, block: int = 4096):
+    """Same recipe as se_kernel, built row block by row block on the device
+    with torch (for n where a host copy would be slow).  Returns an (n, lda)
+    float64 tensor whose first n columns hold A; the points come from the
+    same numpy seed."""
+    import torch
+    lda = lda or n
+    x = torch.from_numpy(se_points(n, seed)).to(device)
+    A = torch.empty((n, lda), dtype=torch.float64, device=device)
+    inv = 1.0 / (2.0 * lengthscale * lengthscale)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        d0 = x[r0:r1, 0:1] - x[None, :, 0]
+        d1 = x[r0:r1, 1:2] - x[None, :, 1]
+        blk = torch.exp(-(d0 * d0 + d1 * d1) * inv)
+        ii = torch.arange(r1 - r0, device=device)
+        blk[ii, ii + r0] += nugget
+        A[r0:r1, :n] = blk
+    return A
+
+
+def integer_factor(n: int, seed: int = 0, diag_max: int = 3, off_max: int = 2,
+                   band: int | None = None):
+    """Return (A, L0): L0 integer lower triangular, diagonal in [1, diag_max],
+    off-diagonals in [-off_max, off_max] (within `band` of the diagonal if
+    given), and A = L0 L0^T formed exactly in int64.  Every partial sum of the
+    factorization is then an integer far below 2^53, each square root is of a
+    perfect square and each division is exact, so any correct FP64 Cholesky
+    in any summation order reproduces L0 exactly."""
+    rng = np.random.default_rng(seed)
+    L0 = rng.integers(-off_max, off_max + 1, size=(n, n), dtype=np.int64)
+    L0 = np.tril(L0, -1)
+    if band is not None:
+        i, j = np.indices((n, n))
+        L0[(i - j) > band] = 0
+    L0 += np.diag(rng.integers(1, diag_max + 1, size=n, dtype=np.int64))
+    A = L0 @ L0.T
+    assert np.abs(A).max() < 2 ** 40
+    return np.ascontiguousarray(A.astype(np.float64)), np.ascontiguousarray(L0.astype(np.float64))
