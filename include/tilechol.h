@@ -1,0 +1,184 @@
+/*
+ * tilechol.h -- C ABI of the MI355X (gfx950) tiled Cholesky library.
+ *
+ * Operation (Methods, "Tiled Cholesky Decomposition"): the symmetric
+ * positive-definite matrix A is partitioned into square tiles A_{I,J} of
+ * side T; only the diagonal and strictly lower tiles are used, and the
+ * right-looking algorithm (Fig. 1) overwrites them in place with the lower
+ * Cholesky factor L, A = L L^T, through four tile operations:
+ *   POTRF  A_JJ <- chol(A_JJ)
+ *   TRSM   A_IJ <- A_IJ A_JJ^{-T}             (I > J)
+ *   SYRK   A_II <- A_II - A_IJ A_IJ^T         (I > J)
+ *   GEMM   A_IK <- A_IK - A_IJ A_KJ^T         (J < K < I)
+ * The tile operations are ordered by their data dependencies (Methods,
+ * "Implementations": the task graph of Fig. 3).  Two schedules are offered,
+ * the GPU analogues of the paper's collapsed fork-join variant and of its
+ * asynchronous task variant with explicit dependencies.
+ *
+ * Conventions shared by every entry point
+ *   Storage   row-major: element (i, j) of A lives at A[i * lda + j],
+ *             lda >= max(1, n).  Only the lower triangle including the
+ *             diagonal is read or written; the strict upper triangle is
+ *             never touched.  (A column-major caller holding a symmetric A
+ *             finds L^T in its upper triangle.)
+ *   Tiles     M = ceil(n / T) tiles per dimension; the last tile row and
+ *             column are ragged with side n - (M - 1) T.  T > n is allowed
+ *             (one tile).  All sizes and offsets are 64-bit.
+ *   Memory    A, B and the workspace are device pointers owned by the
+ *             caller; the library never allocates, frees or retains device
+ *             memory.  `stream` is a hipStream_t passed as void* (NULL is
+ *             the default stream); all work is enqueued on it.
+ *   Errors    argument checks happen before anything is enqueued, so a
+ *             call that returns CHOL_EINVAL or CHOL_EWORKSPACE has written
+ *             nothing.  chol_last_bad_arg() names the offending argument.
+ *             No C++ exception crosses this interface.
+ *   Threads   calls are thread-safe; calls that share a workspace or a
+ *             matrix must be ordered by the caller (same stream, or events).
+ */
+#ifndef TILECHOL_H
+#define TILECHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  > 0: numerical outcome; < 0: caller or runtime error. */
+enum {
+  CHOL_OK = 0,
+  CHOL_NOT_SPD = 1,     /* a leading minor is not positive definite; see *info */
+  CHOL_EINVAL = -1,     /* invalid argument (chol_last_bad_arg gives which)     */
+  CHOL_EDEVICE = -2,    /* a HIP runtime call failed                             */
+  CHOL_EWORKSPACE = -3, /* work_bytes smaller than the *_workspace_size result   */
+  CHOL_ETIMEOUT = -4    /* a dependency wait of the asynchronous schedule
+                           exceeded chol_set_wait_limit; factor unspecified     */
+};
+
+/* Schedules (Methods, "Implementations", the fork-join collapsed and task
+ * asynchronous variants). */
+enum {
+  /* One launch per phase of each step J: POTRF(J), the TRSM panel of column
+   * J, and the collapsed SYRK+GEMM trailing update of step J; stream order is
+   * the barrier between phases. */
+  CHOL_SCHED_FORK_JOIN = 0,
+  /* One persistent launch.  Workgroups take work units in a fixed
+   * topological order from an atomic ticket, wait on per-block dependency
+   * counters in the workspace, run the unit, and publish its completion. */
+  CHOL_SCHED_ASYNC_DAG = 1
+};
+
+/* Bytes of device workspace chol_factor needs for (n, T, sched); < 0 on
+ * invalid arguments.  The workspace holds the dependency counters, the work
+ * ticket, an error flag and the device copy of info; its contents need not
+ * be initialised by the caller. */
+int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched);
+
+/* Largest tile count per dimension the asynchronous schedule accepts
+ * (ceil(n / T) above it returns CHOL_EINVAL naming T). */
+#define CHOL_ASYNC_MAX_TILES 2048
+
+/* Factor A = L L^T in place (Methods, Fig. 1, right-looking tiled order).
+ *   A          device pointer, n x n row-major with leading dimension lda.
+ *   T          tile side, T >= 1.
+ *   sched      CHOL_SCHED_FORK_JOIN or CHOL_SCHED_ASYNC_DAG; both run the
+ *              same tile-operation bodies in the same per-tile update order
+ *              (ascending J), so they return bit-identical factors.
+ *   work       device workspace of at least chol_factor_workspace_size bytes
+ *              (may be NULL only when n == 0).
+ *   stream     hipStream_t as void*.
+ *   info       host pointer or NULL.  If non-NULL the call synchronises the
+ *              stream and stores 0 on success or k > 0 when the leading
+ *              minor of order k is not positive definite (a pivot <= 0 or
+ *              NaN at global column k - 1, LAPACK potrf convention); columns
+ *              before k - 1 then hold L and the rest is unspecified.  If
+ *              NULL the call is fully asynchronous and its outcome is only
+ *              visible through chol_factor_info().
+ * Returns CHOL_OK, CHOL_NOT_SPD (only when info != NULL), CHOL_ETIMEOUT
+ * (only when info != NULL) or a negative error code. */
+int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched,
+                void* work, int64_t work_bytes, void* stream, int64_t* info);
+
+/* Read the outcome of the last chol_factor enqueued with this workspace:
+ * synchronises `stream`, stores info as above, and returns CHOL_OK,
+ * CHOL_NOT_SPD or CHOL_ETIMEOUT. */
+int chol_factor_info(const void* work, void* stream, int64_t* info);
+
+/* Bytes of device workspace chol_solve needs; < 0 on invalid arguments. */
+int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
+
+/* Solve A X = B with the factor from chol_factor (the paper's motivating
+ * use, SPD linear systems via the Cholesky decomposition): forward
+ * substitution L Y = B over tile rows, then backward substitution
+ * L^T X = Y.
+ *   L      device pointer to the factor (lower triangle read only).
+ *   B      device pointer, n x nrhs row-major, leading dimension
+ *          ldb >= max(1, nrhs); overwritten by X.
+ *   T      tile side used for the sweep (need not equal the factor's T).
+ * Returns CHOL_OK or a negative error code.  Stream-ordered; no host sync. */
+int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T,
+               double* B, int64_t nrhs, int64_t ldb,
+               void* work, int64_t work_bytes, void* stream);
+
+/* Batched factorization of `batch` independent SPD matrices of uneven sizes.
+ *   A      host array of `batch` device pointers.
+ *   n, lda host arrays of `batch` sizes / leading dimensions.
+ *   T      host array of `batch` tile sides, or NULL to let the library pick
+ *          T from n alone (deterministic).
+ *   info   host array of `batch` results or NULL (as for chol_factor).
+ * Returns CHOL_OK, CHOL_NOT_SPD if any matrix failed (info says which), or a
+ * negative error code. */
+int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T);
+int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, int64_t batch,
+                        const int64_t* T, void* work, int64_t work_bytes, void* stream,
+                        int64_t* info);
+
+/* Tile side the library picks for order n when the caller passes none. */
+int64_t chol_default_tile(int64_t n);
+
+/* ---- introspection of the tile DAG (host only; no device is touched) ----
+ * Work units are the pieces the schedules launch: POTRF(J) is one unit;
+ * TRSM(I, J) is split into row blocks of CHOL_BLOCK rows; the SYRK/GEMM
+ * update of tile (I, K) at step J is split into CHOL_BLOCK x CHOL_BLOCK
+ * output blocks (only blocks on or below the diagonal for SYRK). */
+#define CHOL_BLOCK 128
+
+/* Work-unit kinds as encoded by chol_dag_enumerate. */
+enum { CHOL_UNIT_POTRF = 0, CHOL_UNIT_TRSM = 1, CHOL_UNIT_UPDATE = 2 };
+
+/* Tile-task counts for (n, T) (Results, "Problem Size Scaling": M POTRF,
+ * M(M-1)/2 TRSM and SYRK each, M(M-1)(M-2)/6 GEMM): counts[0..3] =
+ * POTRF, TRSM, SYRK, GEMM tasks; counts[4] = work units of the asynchronous
+ * schedule.  Returns CHOL_OK or CHOL_EINVAL. */
+int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]);
+
+/* Write the asynchronous schedule's work units in dispatch (ticket) order.
+ * Each unit is 6 int32 values {kind, J, I, a, K, b}: the tile indices and
+ * the CHOL_BLOCK sub-block indices inside them (unused fields are -1).
+ * `grid` is the number of persistent workgroups the order is tuned for
+ * (it sets how far the panel of step J+1 runs ahead of step J's bulk
+ * update).  Writes min(cap, total) units; returns the total, or a negative
+ * error code. */
+int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int64_t cap);
+
+/* Number of persistent workgroups the asynchronous schedule launches on the
+ * current device (co-resident capacity); < 0 on error.  Touches the device. */
+int64_t chol_async_grid(void);
+
+/* Upper bound in seconds on any single dependency wait of the asynchronous
+ * schedule (default 10).  A wait that exceeds it ends the factorization
+ * with CHOL_ETIMEOUT instead of a hang.  Process-wide; values < 0 are
+ * rejected.  Returns the previous value. */
+double chol_set_wait_limit(double seconds);
+
+/* 1-based index of the argument that made the last call on this thread
+ * return CHOL_EINVAL or CHOL_EWORKSPACE; 0 if none. */
+int chol_last_bad_arg(void);
+
+/* Static description of a status code. */
+const char* chol_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TILECHOL_H */

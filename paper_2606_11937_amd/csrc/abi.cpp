@@ -1,0 +1,246 @@
+// abi.cpp -- the extern "C" entry points declared in include/tilechol.h:
+// argument validation, workspace sizing and dispatch to the launchers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <new>
+
+#include "../../include/tilechol.h"
+#include "dag.h"
+#include "launch.h"
+
+static_assert(CHOL_BLOCK == TC_BLK, "sub-block size of the ABI and the kernels differ");
+
+namespace {
+thread_local int g_bad_arg = 0;
+std::atomic<double> g_wait_limit_s{10.0};
+
+int bad(int idx, int code = CHOL_EINVAL) {
+  g_bad_arg = idx;
+  return code;
+}
+inline int64_t max1(int64_t x) { return x > 1 ? x : 1; }
+const int64_t kMaxN = (int64_t)1 << 31;
+
+int64_t wait_ticks() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+  const double t = g_wait_limit_s.load() * 1e3 * (double)khz;
+  return t > 9e18 ? (int64_t)9e18 : (int64_t)t;
+}
+
+int status_from(int32_t err, int64_t dinfo, int64_t* info) {
+  if (info) *info = err == 1 ? dinfo : 0;
+  if (err == 1) return CHOL_NOT_SPD;
+  if (err == 2) return CHOL_ETIMEOUT;
+  return CHOL_OK;
+}
+
+int check_factor_args(double* A, int64_t n, int64_t lda, int64_t T, int sched) {
+  if (n < 0 || n >= kMaxN) return bad(2);
+  if (lda < max1(n)) return bad(3);
+  if (T < 1) return bad(4);
+  if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(5);
+  if (sched == CHOL_SCHED_ASYNC_DAG && n > 0 && tc_cdiv(n, T) > CHOL_ASYNC_MAX_TILES) return bad(4);
+  if (n > 0 && A == nullptr) return bad(1);
+  return CHOL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int chol_last_bad_arg(void) { return g_bad_arg; }
+
+const char* chol_status_str(int status) {
+  switch (status) {
+    case CHOL_OK: return "success";
+    case CHOL_NOT_SPD: return "matrix is not positive definite (see info)";
+    case CHOL_EINVAL: return "invalid argument (see chol_last_bad_arg)";
+    case CHOL_EDEVICE: return "HIP runtime error";
+    case CHOL_EWORKSPACE: return "workspace too small";
+    case CHOL_ETIMEOUT: return "dependency wait exceeded the wait limit";
+    default: return "unknown status";
+  }
+}
+
+double chol_set_wait_limit(double seconds) {
+  if (!(seconds >= 0.0)) return -1.0;
+  return g_wait_limit_s.exchange(seconds);
+}
+
+int64_t chol_default_tile(int64_t n) {
+  if (n <= 4096) return 128;
+  if (n <= 16384) return 256;
+  return 512;
+}
+
+int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched) {
+  g_bad_arg = 0;
+  if (n < 0 || n >= kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(3);
+  return tc_ws_bytes(n > 0 ? n : 1, T);
+}
+
+int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, int64_t work_bytes,
+                void* stream, int64_t* info) {
+  g_bad_arg = 0;
+  if (int e = check_factor_args(A, n, lda, T, sched)) return e;
+  if (n == 0) {
+    if (info) *info = 0;
+    return CHOL_OK;
+  }
+  if (work == nullptr) return bad(6);
+  if (work_bytes < tc_ws_bytes(n, T)) return bad(7, CHOL_EWORKSPACE);
+  hipStream_t st = (hipStream_t)stream;
+  int64_t grid = 0;
+  if (sched == CHOL_SCHED_ASYNC_DAG) {
+    grid = tc_async_grid_size();
+    if (grid <= 0) return CHOL_EDEVICE;
+  }
+  if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks()) != 0) return CHOL_EDEVICE;
+  if (info == nullptr) return CHOL_OK;
+  int32_t err = 0;
+  int64_t dinfo = 0;
+  if (tc_read_status(work, st, &err, &dinfo) != 0) return CHOL_EDEVICE;
+  return status_from(err, dinfo, info);
+}
+
+int chol_factor_info(const void* work, void* stream, int64_t* info) {
+  g_bad_arg = 0;
+  if (work == nullptr) return bad(1);
+  if (info == nullptr) return bad(3);
+  int32_t err = 0;
+  int64_t dinfo = 0;
+  if (tc_read_status(work, (hipStream_t)stream, &err, &dinfo) != 0) return CHOL_EDEVICE;
+  return status_from(err, dinfo, info);
+}
+
+int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
+  g_bad_arg = 0;
+  if (n < 0 || n >= kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (nrhs < 0) return bad(3);
+  return 0;
+}
+
+int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb, void* work,
+               int64_t work_bytes, void* stream) {
+  g_bad_arg = 0;
+  (void)work;
+  if (n < 0 || n >= kMaxN) return bad(2);
+  if (lda < max1(n)) return bad(3);
+  if (T < 1) return bad(4);
+  if (nrhs < 0) return bad(6);
+  if (ldb < max1(nrhs)) return bad(7);
+  if (work_bytes < 0) return bad(9);
+  if (n == 0 || nrhs == 0) return CHOL_OK;
+  if (L == nullptr) return bad(1);
+  if (B == nullptr) return bad(5);
+  return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, (hipStream_t)stream) == 0 ? CHOL_OK : CHOL_EDEVICE;
+}
+
+int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(1);
+  if (batch > 0 && n == nullptr) return bad(2);
+  int64_t total = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 0 || n[i] >= kMaxN) return bad(2);
+    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
+    if (t < 1) return bad(3);
+    total += (tc_ws_bytes(n[i] > 0 ? n[i] : 1, t) + 255) & ~(int64_t)255;
+  }
+  return total;
+}
+
+int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, int64_t batch, const int64_t* T,
+                        void* work, int64_t work_bytes, void* stream, int64_t* info) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(4);
+  if (batch == 0) return CHOL_OK;
+  if (A == nullptr) return bad(1);
+  if (n == nullptr) return bad(2);
+  if (lda == nullptr) return bad(3);
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 0 || n[i] >= kMaxN) return bad(2);
+    if (lda[i] < max1(n[i])) return bad(3);
+    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
+    if (t < 1) return bad(5);
+    if (n[i] > 0 && A[i] == nullptr) return bad(1);
+  }
+  const int64_t need = chol_factor_batched_workspace_size(batch, n, T);
+  if (need < 0) return CHOL_EINVAL;
+  if (work == nullptr) return bad(6);
+  if (work_bytes < need) return bad(7, CHOL_EWORKSPACE);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)work;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
+    const int64_t nb = n[i] > 0 ? n[i] : 1;
+    if (n[i] > 0 && tc_launch_factor(A[i], n[i], lda[i], t, CHOL_SCHED_FORK_JOIN, w, st, 0, 0) != 0)
+      return CHOL_EDEVICE;
+    w += (tc_ws_bytes(nb, t) + 255) & ~(int64_t)255;
+  }
+  if (info == nullptr) return CHOL_OK;
+  int worst = CHOL_OK;
+  w = (char*)work;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
+    const int64_t nb = n[i] > 0 ? n[i] : 1;
+    info[i] = 0;
+    if (n[i] > 0) {
+      int32_t err = 0;
+      int64_t dinfo = 0;
+      if (tc_read_status(w, st, &err, &dinfo) != 0) return CHOL_EDEVICE;
+      const int s = status_from(err, dinfo, &info[i]);
+      if (s != CHOL_OK && worst == CHOL_OK) worst = s;
+    }
+    w += (tc_ws_bytes(nb, t) + 255) & ~(int64_t)255;
+  }
+  return worst;
+}
+
+int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]) {
+  g_bad_arg = 0;
+  if (n < 1 || n >= kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (counts == nullptr) return bad(3);
+  TcGeom g = tc_geom(n, T, 0);
+  tc_task_counts(g, counts);
+  int64_t total = 0;
+  for (int32_t P = 0; P < g.M; ++P) total += tc_phase_size(g, P);
+  counts[4] = total;
+  return CHOL_OK;
+}
+
+int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int64_t cap) {
+  g_bad_arg = 0;
+  if (n < 1 || n >= kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (grid < 1) return bad(3);
+  if (cap < 0) return bad(5);
+  if (cap > 0 && out == nullptr) return bad(4);
+  TcGeom g = tc_geom(n, T, 2 * grid);
+  int64_t k = 0;
+  for (int32_t P = 0; P < g.M; ++P) {
+    const int64_t sz = tc_phase_size(g, P);
+    for (int64_t r = 0; r < sz; ++r, ++k) {
+      if (k < cap) {
+        TcUnit u = tc_decode_in_phase(g, P, r);
+        int32_t* o = out + 6 * k;
+        o[0] = u.kind; o[1] = u.J; o[2] = u.I; o[3] = u.a; o[4] = u.K; o[5] = u.b;
+      }
+    }
+  }
+  return k;
+}
+
+int64_t chol_async_grid(void) {
+  const int64_t g = tc_async_grid_size();
+  return g > 0 ? g : CHOL_EDEVICE;
+}
+
+}  // extern "C"

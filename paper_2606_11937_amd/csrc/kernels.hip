@@ -1,0 +1,441 @@
+// kernels.hip -- gfx950 kernels and host launchers of the two factorization
+// schedules and of the triangular solves.
+//
+//   fork-join  (Methods, "fork-join collapsed"): per step J one launch for
+//              POTRF(J), one for the TRSM panel of column J, one for the
+//              collapsed SYRK+GEMM trailing update; kernel boundaries on the
+//              stream are the barriers.
+//   async DAG  (Methods, "task asynchronous" with explicit dependencies):
+//              one persistent launch; workgroups take units in ticket order
+//              (a topological order, see dag.h), wait until the per-block
+//              counters say the unit's inputs are final, run it, and publish
+//              its completion.  No global barrier.
+//
+// Both schedules call the same tile bodies from tile_ops.h with the same
+// work-unit decomposition, so their factors are bit-identical.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dag.h"
+#include "launch.h"
+#include "tile_ops.h"
+
+// ---------------------------------------------------------------- workspace
+// [0, 256)              TcWsHeader
+// [256, +8*(M+1))       phase offsets (async only), rounded to 256 bytes
+// then int32 pdone[NRB] (panel columns finalised per row block)
+// then int32 ver[NRB*NRB] (updates applied per output block)
+struct TcWsHeader {
+  int32_t ticket;
+  int32_t error;  // 0 ok, 1 not SPD, 2 dependency-wait timeout
+  int64_t info;   // failing global column + 1
+};
+
+struct TcWs {
+  TcWsHeader* hdr;
+  int64_t* offs;
+  int32_t* pdone;
+  int32_t* ver;
+};
+
+static inline int64_t tc_round256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+int64_t tc_ws_bytes(int64_t n, int64_t T) {
+  TcGeom g = tc_geom(n, T, 0);
+  int64_t b = 256;
+  b += tc_round256(8 * ((int64_t)g.M + 1));
+  b += tc_round256(4 * (int64_t)g.NRB);
+  b += tc_round256(4 * (int64_t)g.NRB * g.NRB);
+  return b;
+}
+
+static TcWs tc_ws_map(void* base, const TcGeom& g) {
+  TcWs w;
+  char* p = (char*)base;
+  w.hdr = (TcWsHeader*)p;
+  p += 256;
+  w.offs = (int64_t*)p;
+  p += tc_round256(8 * ((int64_t)g.M + 1));
+  w.pdone = (int32_t*)p;
+  p += tc_round256(4 * (int64_t)g.NRB);
+  w.ver = (int32_t*)p;
+  return w;
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void tc_fill_zero(int32_t* p, int64_t count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = 0;
+}
+
+// Phase offsets of the ticket space: offs[P] = first ticket of phase P.
+__global__ void tc_phase_offsets(TcGeom g, int64_t* offs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t acc = 0;
+  for (int32_t P = 0; P < g.M; ++P) {
+    offs[P] = acc;
+    acc += tc_phase_size(g, P);
+  }
+  offs[g.M] = acc;
+}
+
+__device__ __forceinline__ bool tc_err_set(const TcWsHeader* h) {
+  return __hip_atomic_load(&h->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ void tc_report_fail(TcWsHeader* h, int32_t code, int64_t info) {
+  int32_t expected = 0;
+  if (__hip_atomic_compare_exchange_strong(&h->error, &expected, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)) {
+    __hip_atomic_store(&h->info, info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ------------------------------------------------------------ unit runners
+union TcSmem {
+  TcTrsmSmem trsm;
+  TcPotrfSmem potrf;
+};
+
+__device__ __forceinline__ void tc_run_potrf(double* A, int64_t lda, const TcGeom& g, int32_t J, TcWsHeader* h,
+                                             TcSmem& sm) {
+  const int64_t d0 = (int64_t)J * g.T;
+  const int td = (int)tc_tdim(g, J);
+  const int bad = tc_potrf_tile(A + d0 * lda + d0, lda, td, sm.potrf);
+  if (bad >= 0 && threadIdx.x == 0) tc_report_fail(h, 1, d0 + bad + 1);
+}
+
+__device__ __forceinline__ void tc_run_trsm(double* A, int64_t lda, const TcGeom& g, int32_t I, int32_t a, int32_t J,
+                                            TcSmem& sm) {
+  const int64_t r0 = tc_row0(g, I, a);
+  const int64_t c0 = (int64_t)J * g.T;
+  tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm.trsm);
+}
+
+__device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u) {
+  const int64_t ri = tc_row0(g, u.I, u.a);
+  const int64_t rk = tc_row0(g, u.K, u.b);
+  const int64_t cj = (int64_t)u.J * g.T;
+  tc_update_block(A + ri * lda + rk, A + ri * lda + cj, A + rk * lda + cj, lda, tc_rows(g, u.I, u.a),
+                  tc_rows(g, u.K, u.b), (int)g.T, ri == rk);
+}
+
+// ---------------------------------------------------------- fork-join kernels
+__global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+  __shared__ TcSmem sm;
+  if (tc_err_set(ws.hdr)) return;
+  tc_run_potrf(A, lda, g, J, ws.hdr, sm);
+}
+
+__global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+  __shared__ TcSmem sm;
+  if (tc_err_set(ws.hdr)) return;
+  const int64_t r = blockIdx.x;
+  const int32_t I = J + 1 + (int32_t)(r / g.SB);
+  const int32_t a = (int32_t)(r % g.SB);
+  tc_run_trsm(A, lda, g, I, a, J, sm);
+}
+
+__global__ __launch_bounds__(TC_THREADS) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+  if (tc_err_set(ws.hdr)) return;
+  const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
+  tc_run_update(A, lda, g, u);
+}
+
+// ------------------------------------------------------- persistent kernel
+#define TC_MAX_PHASES 2048
+
+// Dependency test of unit u (see dag.h): all reads are relaxed agent-scope
+// atomics; the caller issues the acquire fence once the unit is ready.
+__device__ __forceinline__ bool tc_unit_ready(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
+  auto ld = [](const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+  const int64_t NRB = g.NRB;
+  if (u.kind == TC_UNIT_UPDATE) {
+    const int32_t gi = tc_gid(g, u.I, u.a), gk = tc_gid(g, u.K, u.b);
+    return ld(ws.pdone + gi) > u.J && ld(ws.pdone + gk) > u.J && ld(ws.ver + gi * NRB + gk) >= u.J;
+  }
+  if (u.kind == TC_UNIT_TRSM) {
+    if (ld(ws.pdone + tc_gid(g, u.J, 0)) <= u.J) return false;
+    const int32_t gi = tc_gid(g, u.I, u.a);
+    const int32_t sj = tc_sb(g, u.J);
+    for (int32_t b = 0; b < sj; ++b)
+      if (ld(ws.ver + gi * NRB + tc_gid(g, u.J, b)) < u.J) return false;
+    return true;
+  }
+  const int32_t sj = tc_sb(g, u.J);
+  for (int32_t a = 0; a < sj; ++a)
+    for (int32_t b = 0; b <= a; ++b)
+      if (ld(ws.ver + (int64_t)tc_gid(g, u.J, a) * NRB + tc_gid(g, u.J, b)) < u.J) return false;
+  return true;
+}
+
+__device__ __forceinline__ void tc_unit_publish(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
+  auto add = [](int32_t* p) { __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+  if (u.kind == TC_UNIT_UPDATE) {
+    add(ws.ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.K, u.b));
+  } else if (u.kind == TC_UNIT_TRSM) {
+    add(ws.pdone + tc_gid(g, u.I, u.a));
+  } else {
+    const int32_t sj = tc_sb(g, u.J);
+    for (int32_t a = 0; a < sj; ++a) add(ws.pdone + tc_gid(g, u.J, a));
+  }
+}
+
+__global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
+  __shared__ TcSmem sm;
+  __shared__ int64_t offs[TC_MAX_PHASES + 1];
+  __shared__ int64_t s_ticket;
+  __shared__ int32_t s_go;
+  for (int i = threadIdx.x; i <= g.M; i += TC_THREADS) offs[i] = ws.offs[i];
+  __syncthreads();
+  const int64_t total = offs[g.M];
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = __hip_atomic_fetch_add(&ws.hdr->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t t = s_ticket;
+    if (t >= total) break;
+    // phase of ticket t: last P with offs[P] <= t
+    int32_t lo = 0, hi = g.M - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const TcUnit u = tc_decode_in_phase(g, lo, t - offs[lo]);
+    if (threadIdx.x == 0) {
+      int32_t go = 1;
+      const uint64_t t0 = wall_clock64();
+      while (!tc_unit_ready(g, ws, u)) {
+        if (tc_err_set(ws.hdr)) { go = 0; break; }
+        if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(ws.hdr, 2, 0); go = 0; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    if (u.kind == TC_UNIT_UPDATE) {
+      tc_run_update(A, lda, g, u);
+    } else if (u.kind == TC_UNIT_TRSM) {
+      tc_run_trsm(A, lda, g, u.I, u.a, u.J, sm);
+    } else {
+      tc_run_potrf(A, lda, g, u.J, ws.hdr, sm);
+    }
+    // every wave makes its stores visible device-wide before the unit is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0 && !tc_err_set(ws.hdr)) tc_unit_publish(g, ws, u);
+  }
+}
+
+// ------------------------------------------------------------- solve kernels
+// Forward substitution L_JJ Y = B_J on one diagonal tile (td rows), in place
+// in B (nrhs columns).  Blocked by 16 rows: first B[c0+i] -= sum_{t<c0}
+// L[c0+i][t] Y[t], then a sequential 16-step substitution per right-hand side.
+__global__ __launch_bounds__(TC_THREADS) void tc_solve_diag_fwd(const double* L, int64_t lda, int td, double* B,
+                                                                int64_t nrhs, int64_t ldb) {
+  __shared__ double Lc[16 * 17];
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < td; c0 += 16) {
+    const int nb = td - c0 < 16 ? td - c0 : 16;
+    {
+      const int i = tid >> 4, j = tid & 15;
+      Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
+    }
+    // rows c0..c0+nb, right-hand sides in chunks of 16
+    for (int64_t cb = 0; cb < nrhs; cb += 16) {
+      const int i = tid >> 4, c = (int)cb + (tid & 15);
+      if (i < nb && c < nrhs) {
+        const double* lr = L + (int64_t)(c0 + i) * lda;
+        double s = B[(int64_t)(c0 + i) * ldb + c];
+        for (int t = 0; t < c0; ++t) s = s - lr[t] * B[(int64_t)t * ldb + c];
+        B[(int64_t)(c0 + i) * ldb + c] = s;
+      }
+    }
+    __syncthreads();
+    for (int64_t c = tid; c < nrhs; c += TC_THREADS) {
+      double* bc = B + (int64_t)c0 * ldb + c;
+      for (int i = 0; i < nb; ++i) {
+        double s = bc[(int64_t)i * ldb];
+        for (int q = 0; q < i; ++q) s = s - Lc[i * 17 + q] * bc[(int64_t)q * ldb];
+        bc[(int64_t)i * ldb] = s / Lc[i * 17 + i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward substitution L_JJ^T X = Y on one diagonal tile, blocked by 16 rows
+// from the bottom: Y[r] -= sum_{t > block} L[t][r] X[t], then a sequential
+// substitution with the transposed 16 x 16 block.
+__global__ __launch_bounds__(TC_THREADS) void tc_solve_diag_bwd(const double* L, int64_t lda, int td, double* B,
+                                                                int64_t nrhs, int64_t ldb) {
+  __shared__ double Lc[16 * 17];
+  const int tid = threadIdx.x;
+  const int nblk = (td + 15) / 16;
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    const int c0 = kb * 16;
+    const int nb = td - c0 < 16 ? td - c0 : 16;
+    const int e = c0 + nb;
+    {
+      const int i = tid >> 4, j = tid & 15;
+      Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
+    }
+    for (int64_t cb = 0; cb < nrhs; cb += 16) {
+      const int i = tid >> 4, c = (int)cb + (tid & 15);
+      if (i < nb && c < nrhs) {
+        double s = B[(int64_t)(c0 + i) * ldb + c];
+        for (int t = e; t < td; ++t) s = s - L[(int64_t)t * lda + c0 + i] * B[(int64_t)t * ldb + c];
+        B[(int64_t)(c0 + i) * ldb + c] = s;
+      }
+    }
+    __syncthreads();
+    for (int64_t c = tid; c < nrhs; c += TC_THREADS) {
+      double* bc = B + (int64_t)c0 * ldb + c;
+      for (int i = nb - 1; i >= 0; --i) {
+        double s = bc[(int64_t)i * ldb];
+        for (int q = i + 1; q < nb; ++q) s = s - Lc[q * 17 + i] * bc[(int64_t)q * ldb];
+        bc[(int64_t)i * ldb] = s / Lc[i * 17 + i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Forward sweep update below tile J: B[r] -= L[r, J*T : J*T+td] Y_J for the
+// rows r of [r0, n).  One workgroup per 16 rows; 16 lanes per row split the
+// contraction (coalesced 128-byte row segments), reduced through LDS.
+__global__ __launch_bounds__(TC_THREADS) void tc_solve_upd_fwd(const double* L, int64_t lda, int64_t r0, int64_t n,
+                                                               int64_t c0, int td, double* B, int64_t nrhs,
+                                                               int64_t ldb) {
+  __shared__ double red[16][17];
+  const int tid = threadIdx.x;
+  const int rl = tid >> 4, kl = tid & 15;
+  const int64_t r = r0 + (int64_t)blockIdx.x * 16 + rl;
+  const bool live = r < n;
+  const double* lr = L + (live ? r : r0) * lda + c0;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    double s = 0.0;
+    if (live)
+      for (int t = kl; t < td; t += 16) s += lr[t] * B[(c0 + t) * ldb + c];
+    red[rl][kl] = s;
+    __syncthreads();
+    if (kl == 0 && live) {
+      double acc = 0.0;
+      for (int q = 0; q < 16; ++q) acc += red[rl][q];
+      B[r * ldb + c] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Backward sweep update above tile J: Y[r] -= sum_t L[J*T + t][r] X_J[t] for
+// rows r < J*T.  One thread per row r (coalesced along the rows of L's block
+// row J); X_J is staged in LDS in chunks of 16 right-hand sides.
+__global__ __launch_bounds__(TC_THREADS) void tc_solve_upd_bwd(const double* L, int64_t lda, int64_t rows,
+                                                               int64_t c0, int td, double* B, int64_t nrhs,
+                                                               int64_t ldb) {
+  __shared__ double xs[64][16];
+  const int64_t r = (int64_t)blockIdx.x * TC_THREADS + threadIdx.x;
+  for (int64_t cb = 0; cb < nrhs; cb += 16) {
+    const int nc = nrhs - cb < 16 ? (int)(nrhs - cb) : 16;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int t0 = 0; t0 < td; t0 += 64) {
+      const int tn = td - t0 < 64 ? td - t0 : 64;
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * 16; e += TC_THREADS) {
+        const int tt = e >> 4, q = e & 15;
+        xs[tt][q] = (tt < tn && q < nc) ? B[(c0 + t0 + tt) * ldb + cb + q] : 0.0;
+      }
+      __syncthreads();
+      if (r < rows) {
+        for (int tt = 0; tt < tn; ++tt) {
+          const double l = L[(c0 + t0 + tt) * lda + r];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc[q] += l * xs[tt][q];
+        }
+      }
+    }
+    if (r < rows)
+      for (int q = 0; q < nc; ++q) B[r * ldb + cb + q] -= acc[q];
+  }
+}
+
+// ------------------------------------------------------------ host launchers
+static int tc_chk(hipError_t e) { return e == hipSuccess ? 0 : TC_LAUNCH_EDEVICE; }
+
+int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
+                     int64_t grid, int64_t wait_ticks) {
+  const int64_t Q = 2 * (grid > 0 ? grid : 256);
+  TcGeom g = tc_geom(n, T, Q);
+  TcWs ws = tc_ws_map(work, g);
+  // clear header and counters with a fill kernel (graph-capture friendly)
+  const int64_t words = (tc_ws_bytes(n, T)) / 4;
+  hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, words);
+  if (int e = tc_chk(hipGetLastError())) return e;
+  if (sched == 0) {
+    for (int32_t J = 0; J < g.M; ++J) {
+      hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      const int64_t nt = tc_rows_below(g, J);
+      if (nt > 0) hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      const int64_t nu = tc_trailing_units(g, J);
+      if (nu > 0) hipLaunchKernelGGL(tc_fj_update, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+    }
+    return tc_chk(hipGetLastError());
+  }
+  if (g.M > TC_MAX_PHASES) return TC_LAUNCH_EINVAL;
+  hipLaunchKernelGGL(tc_phase_offsets, dim3(1), dim3(64), 0, st, g, ws.offs);
+  hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
+  return tc_chk(hipGetLastError());
+}
+
+int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info) {
+  TcWsHeader h;
+  if (hipMemcpyAsync(&h, work, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  *error = h.error;
+  *info = h.info;
+  return 0;
+}
+
+int64_t tc_async_grid_size() {
+  static int64_t cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (dev >= 0 && dev < 64 && cached[dev] > 0) return cached[dev];
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tc_async, TC_THREADS, 0) != hipSuccess) return -1;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return -1;
+  int64_t gsz = (int64_t)(per_cu > 0 ? per_cu : 1) * p.multiProcessorCount;
+  if (dev >= 0 && dev < 64) cached[dev] = gsz;
+  return gsz;
+}
+
+int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
+                    hipStream_t st) {
+  const int64_t M = tc_cdiv(n, T);
+  for (int64_t J = 0; J < M; ++J) {
+    const int64_t c0 = J * T;
+    const int td = (int)(n - c0 < T ? n - c0 : T);
+    hipLaunchKernelGGL(tc_solve_diag_fwd, dim3(1), dim3(TC_THREADS), 0, st, L + c0 * lda + c0, lda, td,
+                       B + c0 * ldb, nrhs, ldb);
+    const int64_t r0 = c0 + td;
+    if (r0 < n)
+      hipLaunchKernelGGL(tc_solve_upd_fwd, dim3((unsigned)tc_cdiv(n - r0, 16)), dim3(TC_THREADS), 0, st, L, lda, r0,
+                         n, c0, td, B, nrhs, ldb);
+  }
+  for (int64_t J = M - 1; J >= 0; --J) {
+    const int64_t c0 = J * T;
+    const int td = (int)(n - c0 < T ? n - c0 : T);
+    hipLaunchKernelGGL(tc_solve_diag_bwd, dim3(1), dim3(TC_THREADS), 0, st, L + c0 * lda + c0, lda, td,
+                       B + c0 * ldb, nrhs, ldb);
+    if (c0 > 0)
+      hipLaunchKernelGGL(tc_solve_upd_bwd, dim3((unsigned)tc_cdiv(c0, TC_THREADS)), dim3(TC_THREADS), 0, st, L, lda,
+                         c0, c0, td, B, nrhs, ldb);
+  }
+  return tc_chk(hipGetLastError());
+}

@@ -1,0 +1,21 @@
+// launch.h -- internal interface between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TC_LAUNCH_EDEVICE (-2)
+#define TC_LAUNCH_EINVAL (-1)
+
+// Workspace bytes chol_factor needs (both schedules use one layout).
+int64_t tc_ws_bytes(int64_t n, int64_t T);
+// Enqueue one factorization.  grid: persistent workgroups (async only);
+// wait_ticks: dependency-wait limit in wall-clock ticks (async only).
+int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
+                     int64_t grid, int64_t wait_ticks);
+// Synchronise the stream and read the error flag / info of a workspace.
+int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info);
+// Co-resident workgroups of the persistent kernel on the current device.
+int64_t tc_async_grid_size();
+// Enqueue forward + backward substitution with tile side T.
+int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
+                    hipStream_t st);

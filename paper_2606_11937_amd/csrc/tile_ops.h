@@ -1,0 +1,372 @@
+// tile_ops.h -- gfx950 device bodies of the four tile operations (Methods,
+// "Tiled Cholesky Decomposition": POTRF, TRSM, SYRK, GEMM).  Both schedules
+// call exactly these bodies, so they produce bit-identical factors.
+//
+// Every body runs on one workgroup of TC_THREADS = 256 threads (4 wave64s).
+// Matrices are row-major with leading dimension lda; only lower-triangle
+// entries are read or written.
+//
+// The contraction core is v_mfma_f64_16x16x4_f64 (FP64 matrix cores).  Its
+// operand/result lane layout, measured on gfx950 with one-hot inputs:
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l, item q holds D[4 q + l / 16][l % 16]
+// All three tile products here are of the "NT" form X Y^T with X and Y both
+// row-major with the contraction index contiguous, so A and B fragments are
+// loaded the same way: lane (r = l % 16, s = l / 16) reads four consecutive
+// doubles k0 + 4s .. k0 + 4s + 3 of row r, and MFMA number m of a 16-wide k
+// chunk consumes element m.  The contraction order inside one output entry is
+// therefore fixed (chunk by chunk; within a chunk, MFMA m sums k0+m, k0+4+m,
+// k0+8+m, k0+12+m) and identical for every entry and both schedules.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TC_THREADS 256
+
+typedef double tc_v4d __attribute__((ext_vector_type(4)));
+typedef double tc_d2 __attribute__((ext_vector_type(2), aligned(8)));
+
+__device__ __forceinline__ tc_v4d tc_mfma(double a, double b, tc_v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Four consecutive doubles of one row, as two 16-byte loads.
+struct tc_q4 {
+  tc_d2 lo, hi;
+};
+__device__ __forceinline__ tc_q4 tc_ld4(const double* p) {
+  tc_q4 q;
+  q.lo = *(const tc_d2*)p;
+  q.hi = *(const tc_d2*)(p + 2);
+  return q;
+}
+// Same, but elements at or beyond `lim` (relative to p) read as zero.
+__device__ __forceinline__ tc_q4 tc_ld4_tail(const double* p, int lim) {
+  tc_q4 q;
+  q.lo.x = lim > 0 ? p[0] : 0.0;
+  q.lo.y = lim > 1 ? p[1] : 0.0;
+  q.hi.x = lim > 2 ? p[2] : 0.0;
+  q.hi.y = lim > 3 ? p[3] : 0.0;
+  return q;
+}
+__device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
+  return m == 0 ? q.lo.x : m == 1 ? q.lo.y : m == 2 ? q.hi.x : q.hi.y;
+}
+
+// ---------------------------------------------------------------------------
+// SYRK / GEMM update of one output block (the trailing-update tile ops):
+//   C[r][c] -= sum_{t < kd} PA[r][t] * PB[c][t]     0 <= r < mr, 0 <= c < mc
+// restricted to r >= c when `diag` (a block on the matrix diagonal, SYRK).
+// mr, mc <= 128.  Wave w computes the 64 x 64 quadrant (w & 1, w >> 1) with
+// 4 x 4 MFMA accumulators; operands go straight from global memory (L2) into
+// registers, one 16-wide k chunk ahead of the MFMAs.  Rows/columns beyond
+// mr/mc are clamped to valid addresses and never stored.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tc_update_block(double* __restrict__ C, const double* __restrict__ PA,
+                                                const double* __restrict__ PB, int64_t lda, int mr, int mc,
+                                                int kd, bool diag) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  if (diag && wn > wm) return;  // quadrant strictly above the diagonal
+  if (wm * 64 >= mr || wn * 64 >= mc) return;
+  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
+
+  const double* pa[4];
+  const double* pb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int ra = wm * 64 + i * 16 + r16;
+    ra = ra < mr ? ra : mr - 1;
+    pa[i] = PA + (int64_t)ra * lda + s4;
+    int rb = wn * 64 + i * 16 + r16;
+    rb = rb < mc ? rb : mc - 1;
+    pb[i] = PB + (int64_t)rb * lda + s4;
+  }
+
+  tc_v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = tc_v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int kfull = kd & ~15;
+  tc_q4 ca[4], cb[4];
+  if (kfull > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ca[i] = tc_ld4(pa[i]);
+      cb[i] = tc_ld4(pb[i]);
+    }
+  }
+  for (int k0 = 0; k0 < kfull; k0 += 16) {
+    tc_q4 na[4], nb[4];
+    const bool more = k0 + 16 < kfull;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        na[i] = tc_ld4(pa[i] + k0 + 16);
+        nb[i] = tc_ld4(pb[i] + k0 + 16);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ca[i], m), tc_el(cb[j], m), acc[i][j]);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ca[i] = na[i];
+        cb[i] = nb[i];
+      }
+    }
+  }
+  if (kfull < kd) {  // ragged k tail, zero filled
+    const int lim = kd - kfull - s4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ca[i] = tc_ld4_tail(pa[i] + kfull, lim);
+      cb[i] = tc_ld4_tail(pb[i] + kfull, lim);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ca[i], m), tc_el(cb[j], m), acc[i][j]);
+  }
+
+  // epilogue: C -= acc on the stored part
+  const int orow = lane >> 4, ocol = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 16 + 4 * q + orow;
+        const int c = wn * 64 + j * 16 + ocol;
+        if (r < mr && c < mc && (!diag || r >= c)) {
+          double* p = C + (int64_t)r * lda + c;
+          *p = *p - acc[i][j][q];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Left-looking MFMA accumulation for one 16 x 16 output group:
+//   acc[r][j] = sum_{t < kd} X[r][t] * Y[j][t],  r < 16 (rows of X), j < 16
+// X rows clamped to xr valid rows, Y rows to yr valid rows; kd % 16 == 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ tc_v4d tc_nt16(const double* __restrict__ X, int xr, const double* __restrict__ Y,
+                                          int yr, int64_t lda, int kd) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
+  const double* px = X + (int64_t)(r16 < xr ? r16 : xr - 1) * lda + s4;
+  const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
+  tc_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int k0 = 0;
+  // two independent accumulators over alternating chunks keep two MFMA chains
+  // in flight; they are summed at the end (fixed order).
+  for (; k0 + 32 <= kd; k0 += 32) {
+    tc_q4 x0 = tc_ld4(px + k0), y0 = tc_ld4(py + k0);
+    tc_q4 x1 = tc_ld4(px + k0 + 16), y1 = tc_ld4(py + k0 + 16);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      acc0 = tc_mfma(tc_el(x0, m), tc_el(y0, m), acc0);
+      acc1 = tc_mfma(tc_el(x1, m), tc_el(y1, m), acc1);
+    }
+  }
+  if (k0 < kd) {
+    tc_q4 x0 = tc_ld4(px + k0), y0 = tc_ld4(py + k0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc0 = tc_mfma(tc_el(x0, m), tc_el(y0, m), acc0);
+  }
+  return acc0 + acc1;
+}
+
+// Scatter a 16 x 16 MFMA result into a row-major LDS buffer (ld 17).
+__device__ __forceinline__ void tc_acc_to_lds(double* buf, tc_v4d acc) {
+  const int lane = threadIdx.x & 63;
+  const int orow = lane >> 4, ocol = lane & 15;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) buf[(4 * q + orow) * 17 + ocol] = acc[q];
+}
+
+// Forward substitution of one row against a factored nb x nb diagonal block
+// held in LDS (Lc, ld 17):  x_j = (v_j - sum_{q<j} x_q Lc[j][q]) / Lc[j][j].
+// v holds the row on entry, x on exit.  Sequential in q (ascending).
+__device__ __forceinline__ void tc_subst_row(double v[16], const double* Lc, int nb) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j < nb) {
+      double s = v[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) s = s - v[q] * Lc[j * 17 + q];
+      v[j] = s / Lc[j * 17 + j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// TRSM work unit: X <- X L^{-T} for mr <= 128 rows of a tile (I, J), I > J,
+// with L = L_JJ (td x td, factored).  Left-looking over 16-column blocks:
+// for each block c0, v = X[:, c0:c0+16] - X[:, :c0] L[c0:c0+16, :c0]^T (MFMA),
+// then forward substitution against the 16 x 16 diagonal block of L.
+// Wave w owns rows 32w .. 32w+31 (two 16-row MFMA groups).
+// LDS: 4 waves x 32 x 17 doubles + 16 x 17 doubles.
+// ---------------------------------------------------------------------------
+struct TcTrsmSmem {
+  double buf[4][32 * 17];
+  double Lc[16 * 17];
+};
+
+__device__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
+                              TcTrsmSmem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int row0 = w * 32;
+  for (int c0 = 0; c0 < td; c0 += 16) {
+    const int nb = td - c0 < 16 ? td - c0 : 16;
+    // stage the diagonal block L[c0.., c0..] (lower part; rest zero)
+    {
+      const int i = tid >> 4, j = tid & 15;
+      sm.Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
+    }
+    // left-looking products for this wave's two row groups
+    if (row0 < mr) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int rr = row0 + 16 * g;
+        tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
+        if (rr < mr && c0 > 0) acc = tc_nt16(X + (int64_t)rr * lda, mr - rr, L + (int64_t)c0 * lda, nb, lda, c0);
+        tc_acc_to_lds(&sm.buf[w][g * 16 * 17], acc);
+      }
+    }
+    __syncthreads();
+    if (lane < 32 && row0 + lane < mr) {
+      const int r = row0 + lane;
+      double* xr = X + (int64_t)r * lda + c0;
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = j < nb ? xr[j] - sm.buf[w][lane * 17 + j] : 0.0;
+      tc_subst_row(v, sm.Lc, nb);
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < nb) xr[j] = v[j];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// POTRF work unit: in-place lower Cholesky of the td x td diagonal tile D.
+// Left-looking over 16-column blocks c0:
+//   1. wave 0: diagonal group v = D[c0:, c0:] - D[c0:, :c0] D[c0:, :c0]^T
+//      (16 x 16, MFMA), factored unblocked in LDS (right-looking, sequential
+//      over the column, the POTRF definition on a 16 x 16 block);
+//   2. all waves: the 16-row groups below, MFMA products then forward
+//      substitution against the new diagonal block (the in-tile TRSM).
+// A pivot d <= 0 or NaN stops the factorization: returns the 0-based
+// in-tile column, else -1.
+// ---------------------------------------------------------------------------
+struct TcPotrfSmem {
+  double buf[4][16 * 17];
+  double Lc[16 * 17];
+  int fail;
+};
+
+__device__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) sm.fail = -1;
+  __syncthreads();
+  for (int c0 = 0; c0 < td; c0 += 16) {
+    const int nb = td - c0 < 16 ? td - c0 : 16;
+    double* Dc = D + (int64_t)c0 * lda;  // row c0
+    if (w == 0) {
+      tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
+      if (c0 > 0) acc = tc_nt16(Dc, nb, Dc, nb, lda, c0);
+      tc_acc_to_lds(sm.buf[0], acc);
+    }
+    __syncthreads();
+    if (tid < 256) {
+      const int i = tid >> 4, j = tid & 15;
+      sm.Lc[i * 17 + j] = (i < nb && j <= i) ? Dc[(int64_t)i * lda + c0 + j] - sm.buf[0][i * 17 + j] : 0.0;
+    }
+    __syncthreads();
+    // unblocked factorization of the 16 x 16 block by wave 0, column by column
+    if (w == 0) {
+      const int i = lane >> 2;        // row handled (16 rows x 4 lanes)
+      const int kq = lane & 3;        // this lane updates columns k = kq, kq+4, ...
+      for (int j = 0; j < nb; ++j) {
+        const double d = sm.Lc[j * 17 + j];
+        const bool ok = d > 0.0;
+        if (!ok) {
+          if (lane == 0 && sm.fail < 0) sm.fail = c0 + j;
+          break;
+        }
+        const double ljj = sqrt(d);
+        __builtin_amdgcn_wave_barrier();
+        // column j below the diagonal; lane (i, kq==0) owns l_ij
+        double lij = 0.0;
+        if (i > j && i < nb) lij = sm.Lc[i * 17 + j] / ljj;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);
+        if (kq == 0) {
+          if (i == j) sm.Lc[j * 17 + j] = ljj;
+          else if (i > j && i < nb) sm.Lc[i * 17 + j] = lij;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // trailing update a_ik -= l_ij l_kj for j < k <= i
+        if (i > j && i < nb) {
+          for (int k = j + 1 + ((kq - (j + 1)) & 3); k <= i; k += 4)
+            sm.Lc[i * 17 + k] = sm.Lc[i * 17 + k] - lij * sm.Lc[k * 17 + j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    if (sm.fail >= 0) return sm.fail;
+    // write the factored diagonal block back
+    {
+      const int i = tid >> 4, j = tid & 15;
+      if (i < nb && j <= i) Dc[(int64_t)i * lda + c0 + j] = sm.Lc[i * 17 + j];
+    }
+    // rows below the diagonal block, one 16-row group per wave at a time
+    const int ngroups = (td - c0 - nb + 15) / 16;
+    for (int gbase = 0; gbase < ngroups; gbase += 4) {
+      const int g = gbase + w;
+      const int r0 = c0 + nb + 16 * g;
+      if (g < ngroups) {
+        const int rows = td - r0 < 16 ? td - r0 : 16;
+        tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
+        if (c0 > 0) acc = tc_nt16(D + (int64_t)r0 * lda, rows, Dc, nb, lda, c0);
+        tc_acc_to_lds(sm.buf[w], acc);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < rows) {
+          double* xr = D + (int64_t)(r0 + lane) * lda + c0;
+          double v[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) v[j] = j < nb ? xr[j] - sm.buf[w][lane * 17 + j] : 0.0;
+          tc_subst_row(v, sm.Lc, nb);
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j < nb) xr[j] = v[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+  }
+  return -1;
+}

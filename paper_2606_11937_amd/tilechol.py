@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libtilechol.so (the C ABI in include/tilechol.h).
+
+Every function here only marshals arguments: tensors become device pointers
+and sizes, the current torch stream becomes the HIP stream, and workspaces
+are allocated with torch (the library itself never allocates).  All
+computation happens in the HIP kernels of the library.  If the library is
+missing this module raises on import instead of falling back to anything.
+
+Names follow the C ABI: chol_factor, chol_solve, chol_factor_batched, ...
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtilechol.so")
+
+CHOL_OK = 0
+CHOL_NOT_SPD = 1
+CHOL_EINVAL = -1
+CHOL_EDEVICE = -2
+CHOL_EWORKSPACE = -3
+CHOL_ETIMEOUT = -4
+CHOL_SCHED_FORK_JOIN = 0
+CHOL_SCHED_ASYNC_DAG = 1
+CHOL_BLOCK = 128
+CHOL_ASYNC_MAX_TILES = 2048
+SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG}
+
+# (name, restype, argtypes) for every symbol of include/tilechol.h
+_i64, _int, _dbl, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+_pi64, _pi32 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = [
+    ("chol_factor_workspace_size", _i64, [_i64, _i64, _int]),
+    ("chol_factor", _int, [_vp, _i64, _i64, _i64, _int, _vp, _i64, _vp, _pi64]),
+    ("chol_factor_info", _int, [_vp, _vp, _pi64]),
+    ("chol_solve_workspace_size", _i64, [_i64, _i64, _i64]),
+    ("chol_solve", _int, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp]),
+    ("chol_factor_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
+    ("chol_factor_batched", _int, [ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp, _i64, _vp, _pi64]),
+    ("chol_default_tile", _i64, [_i64]),
+    ("chol_dag_counts", _int, [_i64, _i64, _pi64]),
+    ("chol_dag_enumerate", _i64, [_i64, _i64, _i64, _pi32, _i64]),
+    ("chol_async_grid", _i64, []),
+    ("chol_set_wait_limit", _dbl, [_dbl]),
+    ("chol_last_bad_arg", _int, []),
+    ("chol_status_str", ctypes.c_char_p, [_int]),
+]
+
+
+class TileCholError(RuntimeError):
+    def __init__(self, status: int, where: str, bad_arg: int = 0):
+        msg = f"{where}: {status_str(status)} (status {status}"
+        if bad_arg:
+            msg += f", argument {bad_arg}"
+        super().__init__(msg + ")")
+        self.status = status
+        self.bad_arg = bad_arg
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2606_11937_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(status: int) -> str:
+    return lib.chol_status_str(int(status)).decode()
+
+
+def last_bad_arg() -> int:
+    return int(lib.chol_last_bad_arg())
+
+
+def _sched(s) -> int:
+    return SCHEDULES[s] if isinstance(s, str) else int(s)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_matrix(A, name="A"):
+    import torch
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.float64 or A.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float64 torch tensor")
+    if not A.is_cuda:
+        raise TypeError(f"{name} must live on the GPU")
+    if A.shape[1] > 0 and A.stride(1) != 1:
+        raise TypeError(f"{name} must be row-major (stride(1) == 1)")
+
+
+# ----------------------------------------------------------------- factor
+def chol_factor_workspace_size(n: int, T: int, sched="fork_join") -> int:
+    return int(lib.chol_factor_workspace_size(n, T, _sched(sched)))
+
+
+def factor_workspace(n: int, T: int, sched="fork_join", device="cuda"):
+    import torch
+    nb = chol_factor_workspace_size(n, T, sched)
+    if nb < 0:
+        raise TileCholError(int(nb), "chol_factor_workspace_size", last_bad_arg())
+    return torch.empty(max(nb, 8), dtype=torch.uint8, device=device)
+
+
+def chol_factor(A, T: int, sched="fork_join", n: int | None = None, work=None, stream=None,
+                sync: bool = True) -> int:
+    """Factor A (n x n view of a row-major float64 GPU tensor) in place.
+    Returns info (0, or k > 0 for a non-positive-definite leading minor of
+    order k) when sync, else None.  Raises TileCholError on errors."""
+    _check_matrix(A)
+    n = A.shape[0] if n is None else n
+    lda = A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1])
+    if work is None:
+        work = factor_workspace(n, T, sched, A.device)
+    info = ctypes.c_int64(0)
+    st = lib.chol_factor(ctypes.c_void_p(A.data_ptr()), n, lda, T, _sched(sched),
+                         ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream),
+                         ctypes.byref(info) if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor", last_bad_arg())
+    return int(info.value) if sync else None
+
+
+def chol_factor_info(work, stream=None) -> int:
+    info = ctypes.c_int64(0)
+    st = lib.chol_factor_info(ctypes.c_void_p(work.data_ptr()), _stream(stream), ctypes.byref(info))
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor_info", last_bad_arg())
+    return int(info.value)
+
+
+# ------------------------------------------------------------------ solve
+def chol_solve_workspace_size(n: int, T: int, nrhs: int) -> int:
+    return int(lib.chol_solve_workspace_size(n, T, nrhs))
+
+
+def chol_solve(L, B, T: int, n: int | None = None, work=None, stream=None) -> None:
+    """Overwrite B (n x nrhs row-major float64 GPU tensor) with (L L^T)^{-1} B."""
+    _check_matrix(L, "L")
+    _check_matrix(B, "B")
+    n = L.shape[0] if n is None else n
+    lda = L.stride(0) if L.shape[0] > 1 else max(1, L.shape[1])
+    nrhs = B.shape[1]
+    ldb = B.stride(0) if B.shape[0] > 1 else max(1, nrhs)
+    wptr, wbytes = (work.data_ptr(), work.numel()) if work is not None else (0, 0)
+    st = lib.chol_solve(ctypes.c_void_p(L.data_ptr()), n, lda, T, ctypes.c_void_p(B.data_ptr()), nrhs, ldb,
+                        ctypes.c_void_p(wptr), wbytes, _stream(stream))
+    if st != CHOL_OK:
+        raise TileCholError(st, "chol_solve", last_bad_arg())
+
+
+# ---------------------------------------------------------------- batched
+def chol_factor_batched_workspace_size(ns, Ts=None) -> int:
+    b = len(ns)
+    n_arr = (ctypes.c_int64 * b)(*ns)
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    return int(lib.chol_factor_batched_workspace_size(b, n_arr, t_arr))
+
+
+def chol_factor_batched(As, Ts=None, work=None, stream=None, sync: bool = True):
+    """Factor a list of square row-major float64 GPU tensors in place.
+    Returns the list of infos when sync."""
+    import torch
+    b = len(As)
+    for A in As:
+        _check_matrix(A)
+    ns = [A.shape[0] for A in As]
+    ldas = [A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1]) for A in As]
+    if work is None:
+        nb = chol_factor_batched_workspace_size(ns, Ts)
+        if nb < 0:
+            raise TileCholError(nb, "chol_factor_batched_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=As[0].device if b else "cuda")
+    ptrs = (ctypes.c_void_p * b)(*[A.data_ptr() for A in As])
+    n_arr = (ctypes.c_int64 * b)(*ns)
+    l_arr = (ctypes.c_int64 * b)(*ldas)
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    infos = (ctypes.c_int64 * max(b, 1))()
+    st = lib.chol_factor_batched(ptrs, n_arr, l_arr, b, t_arr, ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                 _stream(stream), infos if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor_batched", last_bad_arg())
+    return [int(infos[i]) for i in range(b)] if sync else None
+
+
+# ----------------------------------------------------------- introspection
+def chol_default_tile(n: int) -> int:
+    return int(lib.chol_default_tile(n))
+
+
+def chol_dag_counts(n: int, T: int):
+    c = (ctypes.c_int64 * 5)()
+    st = lib.chol_dag_counts(n, T, c)
+    if st != CHOL_OK:
+        raise TileCholError(st, "chol_dag_counts", last_bad_arg())
+    return {"potrf": c[0], "trsm": c[1], "syrk": c[2], "gemm": c[3], "units": c[4]}
+
+
+def chol_dag_enumerate(n: int, T: int, grid: int = 256):
+    """Work units of the asynchronous schedule in ticket order as an
+    (N, 6) int32 numpy array of {kind, J, I, a, K, b}."""
+    import numpy as np
+    total = int(lib.chol_dag_enumerate(n, T, grid, None, 0))
+    if total < 0:
+        raise TileCholError(total, "chol_dag_enumerate", last_bad_arg())
+    out = np.zeros((total, 6), dtype=np.int32)
+    got = lib.chol_dag_enumerate(n, T, grid, out.ctypes.data_as(_pi32), total)
+    assert got == total
+    return out
+
+
+def chol_async_grid() -> int:
+    g = int(lib.chol_async_grid())
+    if g < 0:
+        raise TileCholError(g, "chol_async_grid")
+    return g
+
+
+def chol_set_wait_limit(seconds: float) -> float:
+    return float(lib.chol_set_wait_limit(seconds))

@@ -1,0 +1,247 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every symbol its header declares, validates arguments before touching the
+device, and its tile DAG (counts, roles, dispatch order) matches the
+independent model in dag_model.py."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dag_model as dm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tilechol.h")
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2606_11937_amd import tilechol
+    return tilechol
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(chol_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("chol_factor", "chol_solve", "chol_factor_batched", "chol_factor_workspace_size",
+                     "chol_solve_workspace_size", "chol_factor_batched_workspace_size"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(tc):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(tc.lib, name), name
+    bound = {s[0] for s in tc.SIGNATURES}
+    assert bound == set(names), (bound ^ set(names))
+
+
+def test_status_strings(tc):
+    for s in (0, 1, -1, -2, -3, -4):
+        assert tc.status_str(s) and tc.status_str(s) != "unknown status"
+    assert tc.status_str(99) == "unknown status"
+
+
+def _factor_raw(tc, A, n, lda, T, sched, work, wbytes, info=True):
+    inf = ctypes.c_int64(-7)
+    st = tc.lib.chol_factor(A, n, lda, T, sched, work, wbytes, None, ctypes.byref(inf) if info else None)
+    return st, inf.value
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("args,bad_arg,code", [
+    ((FAKE, -1, 4, 2, 0), 2, -1),     # n < 0
+    ((FAKE, 8, 7, 2, 0), 3, -1),      # lda < n
+    ((FAKE, 8, 8, 0, 0), 4, -1),      # T < 1
+    ((FAKE, 8, 8, 4, 2), 5, -1),      # unknown schedule
+    ((None, 8, 8, 4, 0), 1, -1),      # NULL matrix
+    ((FAKE, 1 << 20, 1 << 20, 1, 1), 4, -1),  # too many tiles for the async schedule
+])
+def test_factor_argument_checks(tc, args, bad_arg, code):
+    A, n, lda, T, sched = args
+    st, _ = _factor_raw(tc, A, n, lda, T, sched, FAKE, 1 << 40)
+    assert st == code
+    assert tc.last_bad_arg() == bad_arg
+
+
+def test_factor_workspace_checks(tc):
+    need = tc.chol_factor_workspace_size(64, 16, 0)
+    assert need > 0
+    st, _ = _factor_raw(tc, FAKE, 64, 64, 16, 0, None, need)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 6
+    st, _ = _factor_raw(tc, FAKE, 64, 64, 16, 0, FAKE, need - 1)
+    assert st == tc.CHOL_EWORKSPACE and tc.last_bad_arg() == 7
+
+
+def test_factor_empty_matrix_is_ok(tc):
+    st, info = _factor_raw(tc, None, 0, 1, 4, 1, None, 0)
+    assert st == tc.CHOL_OK and info == 0
+
+
+def test_workspace_sizes(tc):
+    assert tc.chol_factor_workspace_size(-1, 4, 0) == tc.CHOL_EINVAL
+    assert tc.chol_factor_workspace_size(4, 0, 0) == tc.CHOL_EINVAL
+    assert tc.chol_factor_workspace_size(4, 4, 7) == tc.CHOL_EINVAL
+    a = tc.chol_factor_workspace_size(1024, 128, 0)
+    b = tc.chol_factor_workspace_size(1024, 128, 1)
+    assert a == b > 0
+    # counters grow with the number of row blocks
+    assert tc.chol_factor_workspace_size(32768, 128, 1) > tc.chol_factor_workspace_size(8192, 128, 1)
+    assert tc.chol_solve_workspace_size(100, 16, 3) == 0
+    assert tc.chol_solve_workspace_size(100, 0, 3) == tc.CHOL_EINVAL
+
+
+@pytest.mark.parametrize("args,bad_arg", [
+    ((FAKE, -1, 4, 4, FAKE, 1, 1), 2),
+    ((FAKE, 8, 4, 4, FAKE, 1, 1), 3),
+    ((FAKE, 8, 8, 0, FAKE, 1, 1), 4),
+    ((FAKE, 8, 8, 4, FAKE, -1, 1), 6),
+    ((FAKE, 8, 8, 4, FAKE, 3, 2), 7),
+    ((None, 8, 8, 4, FAKE, 1, 1), 1),
+    ((FAKE, 8, 8, 4, None, 1, 1), 5),
+])
+def test_solve_argument_checks(tc, args, bad_arg):
+    L, n, lda, T, B, nrhs, ldb = args
+    st = tc.lib.chol_solve(L, n, lda, T, B, nrhs, ldb, None, 0, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == bad_arg
+
+
+def test_batched_argument_checks(tc):
+    n = (ctypes.c_int64 * 2)(4, 8)
+    lda = (ctypes.c_int64 * 2)(4, 7)
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, 2, None, FAKE, 1 << 30, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 3
+    assert tc.lib.chol_factor_batched(ptrs, n, lda, -1, None, FAKE, 1, None, None) == tc.CHOL_EINVAL
+    assert tc.lib.chol_factor_batched(None, n, lda, 0, None, None, 0, None, None) == tc.CHOL_OK
+    assert tc.chol_factor_batched_workspace_size([4, 8], None) > 0
+
+
+def test_wait_limit_setter(tc):
+    prev = tc.chol_set_wait_limit(3.0)
+    assert tc.chol_set_wait_limit(prev) == 3.0
+    assert tc.chol_set_wait_limit(-1.0) == -1.0
+
+
+def test_default_tile_is_deterministic(tc):
+    for n in (1, 100, 1024, 8192, 32768):
+        T = tc.chol_default_tile(n)
+        assert T >= 1 and T == tc.chol_default_tile(n)
+
+
+# ------------------------------------------------------------------- DAG
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 8, 16, 64, 256])
+def test_task_counts_match_paper(tc, M):
+    # Results, problem-size scaling: M POTRF, M(M-1)/2 TRSM and SYRK, M(M-1)(M-2)/6 GEMM
+    c = tc.chol_dag_counts(M * 128, 128)
+    assert c["potrf"] == M
+    assert c["trsm"] == c["syrk"] == M * (M - 1) // 2
+    assert c["gemm"] == M * (M - 1) * (M - 2) // 6
+    assert c["potrf"] + c["trsm"] + c["syrk"] + c["gemm"] == M * (M + 1) * (M + 2) // 6
+    # the model's program-order task list agrees
+    kinds = [t[0] for t in dm.tile_tasks(M)]
+    assert kinds.count("GEMM") == c["gemm"] and kinds.count("TRSM") == c["trsm"]
+
+
+@pytest.mark.parametrize("M", [1, 2, 4, 8, 12])
+def test_critical_path_is_3M_minus_2(M):
+    tasks = dm.tile_tasks(M)
+    assert dm.critical_path(tasks, dm.dependency_edges(tasks)) == 3 * M - 2
+
+
+def test_first_step_roles_match_fig2(tc):
+    # 4 x 4 tiles, J = 0: P at (0,0); T at (1..3,0); S at (1,1),(2,2),(3,3);
+    # G at (2,1),(3,1),(3,2)
+    units = tc.chol_dag_enumerate(4 * 128, 128, grid=8)
+    roles = {}
+    for kind, J, I, a, K, b in units:
+        if J != 0:
+            continue
+        if kind == dm.POTRF:
+            roles[(I, I)] = "P"
+        elif kind == dm.TRSM:
+            roles[(I, 0)] = "T"
+        else:
+            roles[(I, K)] = "S" if I == K else "G"
+    assert roles == {(0, 0): "P", (1, 0): "T", (2, 0): "T", (3, 0): "T", (1, 1): "S", (2, 2): "S",
+                     (3, 3): "S", (2, 1): "G", (3, 1): "G", (3, 2): "G"}
+
+
+CASES = [(1, 1), (5, 3), (128, 128), (300, 128), (1024, 128), (1000, 96), (777, 256), (2048, 512),
+         (1536, 200), (640, 1024), (4096, 256)]
+
+
+@pytest.mark.parametrize("n,T", CASES)
+@pytest.mark.parametrize("grid", [1, 7, 256])
+def test_ticket_order_is_topological(tc, n, T, grid):
+    g = dm.Geom(n, T)
+    units = tc.chol_dag_enumerate(n, T, grid=grid)
+    assert len(units) == tc.chol_dag_counts(n, T)["units"]
+    assert dm.check_ticket_order(g, units) == []
+
+
+@pytest.mark.parametrize("n,T", CASES)
+def test_units_cover_every_block_update_once(tc, n, T):
+    """Each lower output block receives exactly one update per earlier step,
+    each panel row block exactly one TRSM per earlier column, each diagonal
+    tile one POTRF: the decomposition covers Fig. 1 exactly."""
+    g = dm.Geom(n, T)
+    units = tc.chol_dag_enumerate(n, T, grid=16)
+    seen = set()
+    for u in units:
+        key = tuple(int(x) for x in u)
+        assert key not in seen
+        seen.add(key)
+    expect = set()
+    for J in range(g.M):
+        expect.add((dm.POTRF, J, J, -1, -1, -1))
+        for I in range(J + 1, g.M):
+            for a in range(g.sb(I)):
+                expect.add((dm.TRSM, J, I, a, -1, -1))
+            for K in range(J + 1, I + 1):
+                for a in range(g.sb(I)):
+                    for b in range(g.sb(K)):
+                        if I == K and b > a:
+                            continue
+                        expect.add((dm.UPDATE, J, I, a, K, b))
+    assert seen == expect
+
+
+def test_dropped_dependency_is_detected():
+    """The order checker itself: moving a GEMM unit ahead of the TRSM it
+    reads must be reported."""
+    g = dm.Geom(512, 128)
+    units = [list(u) for u in _program_order_units(g)]
+    i_trsm = next(i for i, u in enumerate(units) if u[0] == dm.TRSM and u[2] == 2)
+    i_gemm = next(i for i, u in enumerate(units) if u[0] == dm.UPDATE and u[2] == 2 and u[4] == 1)
+    assert dm.check_ticket_order(g, units) == []
+    units.insert(i_trsm, units.pop(i_gemm))
+    assert dm.check_ticket_order(g, units) != []
+
+
+def _program_order_units(g):
+    out = []
+    for J in range(g.M):
+        out.append((dm.POTRF, J, J, -1, -1, -1))
+        for I in range(J + 1, g.M):
+            for a in range(g.sb(I)):
+                out.append((dm.TRSM, J, I, a, -1, -1))
+        for I in range(J + 1, g.M):
+            for K in range(J + 1, I + 1):
+                for a in range(g.sb(I)):
+                    for b in range(g.sb(K)):
+                        if I == K and b > a:
+                            continue
+                        out.append((dm.UPDATE, J, I, a, K, b))
+    return np.array(out, dtype=np.int32)

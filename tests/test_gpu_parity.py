@@ -1,0 +1,265 @@
+"""Parity of the HIP factorization and solve against the CPU oracle.
+
+All calls go through the C ABI (ctypes binding).  Tolerances:
+  e_row  = max_{i>=j} |L~_ij - L_ij| / sqrt(A_ii) <= 1e-10  (sqrt(A_ii) is the
+           2-norm of row i of L, so it bounds |L_ij|; this is the
+           elementwise relative bar, read row-scaled so that tiny entries
+           produced by cancellation are not held to a relative bound they
+           cannot meet in floating point)
+  rho    = ||A - L L^T||_F / (n u ||A||_F) <= 10,  u = 2^-53
+  eta    = solve backward error <= 1e-12
+Integer-exact inputs (A = L0 L0^T with integer L0) must come back bit for
+bit, and the two schedules must agree bit for bit on every input.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_11937_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E_ROW_TOL = 1e-10
+RHO_TOL = 10.0
+ETA_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_11937_amd import tilechol
+    return tilechol
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def gpu_factor(tc, A: np.ndarray, T: int, sched, lda: int | None = None):
+    import torch
+    n = A.shape[0]
+    lda = lda or n
+    buf = torch.full((max(n, 1), lda), float("nan"), dtype=torch.float64, device="cuda")
+    buf[:n, :n] = torch.from_numpy(A)
+    view = buf[:n]
+    info = tc.chol_factor(view, T, sched, n=n)
+    torch.cuda.synchronize()
+    return buf[:n, :n].cpu().numpy(), info
+
+
+def both(tc, A, T, lda=None):
+    Lf, i1 = gpu_factor(tc, A, T, "fork_join", lda)
+    La, i2 = gpu_factor(tc, A, T, "async_dag", lda)
+    return Lf, i1, La, i2
+
+
+def lower_equal(X, Y):
+    return np.array_equal(np.tril(X), np.tril(Y), equal_nan=False)
+
+
+# ------------------------------------------------------------- parity config
+def test_parity_config_n1024_T128(tc):
+    """n = 1024, T = 128, A = G G^T / n + I (seed 0): the small parity case."""
+    A = inputs.gg_plus_identity(1024, seed=0)
+    Lref, info = oracle.potrf(A)
+    assert info == 0
+    Lf, i1, La, i2 = both(tc, A, 128)
+    assert i1 == i2 == 0
+    assert lower_equal(Lf, La), "schedules differ"
+    e_row = oracle.row_scaled_error(Lf, Lref, A)
+    rel = np.abs(np.tril(Lf) - np.tril(Lref)) / np.maximum(np.abs(np.tril(Lref)), 1e-300)
+    rel = rel[np.tril_indices(1024)]
+    rho = oracle.scaled_residual(A, Lf)
+    say(f"n=1024 T=128 e_row={e_row:.3e} strict_rel_max={rel.max():.3e} rho={rho:.3f}")
+    assert e_row <= E_ROW_TOL
+    assert (rel > 1e-10).sum() == 0
+    assert rho <= RHO_TOL
+
+
+@pytest.mark.parametrize("n,T", [(1, 1), (1, 128), (7, 3), (16, 16), (100, 128), (129, 128), (200, 64),
+                                 (300, 100), (513, 128), (777, 256), (1000, 96), (1100, 512), (640, 1024)])
+def test_parity_shapes(tc, n, T):
+    """Ragged tiles, T > n, tiles smaller than a 128-row block, several tiles."""
+    say(f"case n={n} T={T}")
+    A = inputs.gg_plus_identity(n, seed=n + T)
+    Lref, _ = oracle.potrf(A)
+    Lf, i1, La, i2 = both(tc, A, T)
+    assert i1 == i2 == 0
+    assert lower_equal(Lf, La)
+    assert oracle.row_scaled_error(Lf, Lref, A) <= E_ROW_TOL
+    assert oracle.scaled_residual(A, Lf) <= RHO_TOL
+
+
+@pytest.mark.parametrize("n,T", [(384, 128), (600, 256), (1000, 128)])
+def test_parity_se_kernel(tc, n, T):
+    """Squared-exponential kernel inputs (lengthscale 0.1, nugget 1e-2)."""
+    A = inputs.se_kernel(n, seed=1)
+    Lref, _ = oracle.potrf(A)
+    Lf, i1, La, i2 = both(tc, A, T)
+    assert i1 == i2 == 0
+    assert lower_equal(Lf, La)
+    assert oracle.row_scaled_error(Lf, Lref, A) <= E_ROW_TOL
+    assert oracle.scaled_residual(A, Lf) <= RHO_TOL
+
+
+# ---------------------------------------------------------------- exactness
+@pytest.mark.parametrize("n,T", [(5, 2), (64, 16), (200, 128), (256, 128), (333, 64), (700, 256)])
+def test_integer_factor_bitwise(tc, n, T):
+    A, L0 = inputs.integer_factor(n, seed=3 + n)
+    Lf, i1, La, i2 = both(tc, A, T)
+    assert i1 == i2 == 0
+    assert lower_equal(Lf, L0)
+    assert lower_equal(La, L0)
+
+
+def test_identity_and_diagonal(tc):
+    d = np.linspace(0.5, 9.0, 300)
+    for A, L in ((np.eye(300), np.eye(300)), (np.diag(d), np.diag(np.sqrt(d)))):
+        Lf, i1, La, i2 = both(tc, A, 128)
+        assert i1 == i2 == 0
+        assert lower_equal(Lf, L) and lower_equal(La, L)
+
+
+# --------------------------------------------------------------- invariances
+def test_tile_size_invariance(tc):
+    A = inputs.gg_plus_identity(768, seed=21)
+    Ls = [gpu_factor(tc, A, T, "async_dag")[0] for T in (64, 128, 256, 384, 768)]
+    for L in Ls[1:]:
+        assert oracle.row_scaled_error(L, Ls[0], A) <= E_ROW_TOL
+    A2, L0 = inputs.integer_factor(512, seed=22)
+    for T in (32, 128, 256, 512):
+        assert lower_equal(gpu_factor(tc, A2, T, "fork_join")[0], L0)
+
+
+def test_leading_block_invariance(tc):
+    A = inputs.gg_plus_identity(1024, seed=23)
+    L, _ = gpu_factor(tc, A, 128, "async_dag")
+    for m in (128, 384, 512):
+        Lm, _ = gpu_factor(tc, A[:m, :m], 128, "async_dag")
+        assert lower_equal(Lm, L[:m, :m]), m
+
+
+def test_upper_triangle_untouched_and_padding(tc):
+    import torch
+    n, lda, T = 300, 333, 128
+    A = inputs.gg_plus_identity(n, seed=24)
+    for sched in ("fork_join", "async_dag"):
+        buf = torch.full((n, lda), 7.25, dtype=torch.float64, device="cuda")
+        low = torch.from_numpy(np.tril(A)).cuda()
+        buf[:, :n] = torch.where(torch.tril(torch.ones(n, n, dtype=torch.bool, device="cuda")), low,
+                                 torch.full_like(low, float("nan")))
+        info = tc.chol_factor(buf, T, sched, n=n)
+        assert info == 0
+        out = buf.cpu().numpy()
+        assert np.all(np.isnan(out[:, :n][np.triu_indices(n, 1)]))
+        assert np.all(out[:, n:] == 7.25)
+        Lref, _ = oracle.potrf(A)
+        assert oracle.row_scaled_error(out[:, :n], Lref, A) <= E_ROW_TOL
+
+
+# ---------------------------------------------------------------- failures
+@pytest.mark.parametrize("col", [0, 5, 127, 128, 300, 511])
+def test_not_spd_reports_first_failing_column(tc, col):
+    n = 512
+    A, L0 = inputs.integer_factor(n, seed=31)
+    B = A.copy()
+    B[col, col] = float(np.sum(L0[col, :col] ** 2)) - 1.0  # pivot at col becomes -1
+    _, iref = oracle.potrf(B)
+    assert iref == col + 1
+    for sched in ("fork_join", "async_dag"):
+        _, info = gpu_factor(tc, B, 128, sched)
+        assert info == col + 1, (sched, info)
+
+
+def test_nan_pivot(tc):
+    A = inputs.gg_plus_identity(256, seed=32)
+    A[200, 200] = np.nan
+    _, iref = oracle.potrf(A)
+    for sched in ("fork_join", "async_dag"):
+        _, info = gpu_factor(tc, A, 64, sched)
+        assert info == iref == 201
+
+
+def test_wait_limit_ends_the_factorization(tc):
+    """A zero dependency-wait limit must end the persistent kernel with
+    ETIMEOUT (or finish correctly if no unit ever had to wait); it must
+    never hang."""
+    import torch
+    A = inputs.gg_plus_identity(1024, seed=33)
+    prev = tc.chol_set_wait_limit(0.0)
+    try:
+        buf = torch.from_numpy(A).cuda()
+        try:
+            info = tc.chol_factor(buf, 128, "async_dag")
+            outcome = "ok"
+        except tc.TileCholError as e:
+            assert e.status == tc.CHOL_ETIMEOUT
+            outcome = "timeout"
+    finally:
+        tc.chol_set_wait_limit(prev)
+    say("zero wait limit outcome:", outcome)
+    if outcome == "ok":
+        assert info == 0
+        Lref, _ = oracle.potrf(A)
+        assert oracle.row_scaled_error(buf.cpu().numpy(), Lref, A) <= E_ROW_TOL
+    # the library is usable afterwards
+    L, info = gpu_factor(tc, A, 128, "async_dag")
+    assert info == 0
+
+
+# -------------------------------------------------------------------- solve
+def test_solve_integer_exact(tc):
+    import torch
+    n = 400
+    A, L0 = inputs.integer_factor(n, seed=41, diag_max=1, band=3)
+    X = np.random.default_rng(42).integers(-5, 6, size=(n, 3)).astype(np.float64)
+    B = A @ X
+    for T in (64, 128, 400):
+        Lg = torch.from_numpy(L0).cuda()
+        Bg = torch.from_numpy(B).cuda()
+        tc.chol_solve(Lg, Bg, T)
+        assert np.array_equal(Bg.cpu().numpy(), X), T
+
+
+@pytest.mark.parametrize("n,nrhs,T", [(1, 1, 8), (130, 1, 128), (1024, 16, 128), (999, 5, 256), (512, 20, 64)])
+def test_solve_backward_error(tc, n, nrhs, T):
+    import torch
+    A = inputs.gg_plus_identity(n, seed=43 + n)
+    B = np.random.default_rng(44).standard_normal((n, nrhs))
+    Ag = torch.from_numpy(A).cuda()
+    assert tc.chol_factor(Ag, T, "async_dag") == 0
+    Bg = torch.from_numpy(B).cuda()
+    tc.chol_solve(Ag, Bg, T)
+    X = Bg.cpu().numpy()
+    eta = oracle.backward_error(A, X, B)
+    Lref, _ = oracle.potrf(A)
+    Xref = oracle.solve(Lref, B)
+    say(f"solve n={n} nrhs={nrhs} eta={eta:.2e}")
+    assert eta <= ETA_TOL
+    assert np.abs(X - Xref).max() <= 1e-10 * max(1.0, np.abs(Xref).max())
+
+
+# ------------------------------------------------------------------ batched
+def test_batched_uneven_sizes(tc):
+    import torch
+    rng = np.random.default_rng(51)
+    ns = [1, 17, 100, 128, 129, 300, 513, 64, 1000]
+    As = [inputs.gg_plus_identity(n, seed=int(rng.integers(1 << 30))) for n in ns]
+    bufs = [torch.from_numpy(A).cuda() for A in As]
+    infos = tc.chol_factor_batched(bufs)
+    assert infos == [0] * len(ns)
+    for A, b in zip(As, bufs):
+        Lref, _ = oracle.potrf(A)
+        assert oracle.row_scaled_error(b.cpu().numpy(), Lref, A) <= E_ROW_TOL
+    # one failing member is reported in its slot only
+    Bad = As[3].copy()
+    Bad[10, 10] = -1.0
+    bufs = [torch.from_numpy(A).cuda() for A in (As[2], Bad, As[4])]
+    infos = tc.chol_factor_batched(bufs, Ts=[64, 64, 64])
+    assert infos[0] == 0 and infos[2] == 0 and infos[1] == oracle.potrf(Bad)[1]
