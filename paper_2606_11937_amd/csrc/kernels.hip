@@ -189,19 +189,31 @@ __global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, T
   __shared__ int32_t s_go;
   for (int i = threadIdx.x; i <= g.M; i += TC_THREADS) offs[i] = ws.offs[i];
   __syncthreads();
-  const int64_t total = offs[g.M];
+  // Everything that steers this loop is made wave-uniform (tc_uniform), so
+  // all waves run the same sequence of barriers.
+  const int64_t total = tc_uniform(offs[g.M]);
+  // The previous unit is published by thread 0 right before it fetches the
+  // next ticket, in one branch between two barriers.  Keeping the publish and
+  // the fetch in a single thread-0 region (rather than one at the end of the
+  // loop and one at its start) leaves the compiler no pair of identical
+  // thread-0 conditions to thread into a second, divergent inner loop that
+  // would run barriers without thread 0.
+  TcUnit prev = {-1, -1, -1, -1, -1, -1};
   for (;;) {
-    if (threadIdx.x == 0) s_ticket = __hip_atomic_fetch_add(&ws.hdr->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      if (prev.kind >= 0 && !tc_err_set(ws.hdr)) tc_unit_publish(g, ws, prev);
+      s_ticket = __hip_atomic_fetch_add(&ws.hdr->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
-    const int64_t t = s_ticket;
+    const int64_t t = tc_uniform(s_ticket);
     if (t >= total) break;
     // phase of ticket t: last P with offs[P] <= t
     int32_t lo = 0, hi = g.M - 1;
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) >> 1;
-      if (offs[mid] <= t) lo = mid; else hi = mid - 1;
+      if (tc_uniform(offs[mid]) <= t) lo = mid; else hi = mid - 1;
     }
-    const TcUnit u = tc_decode_in_phase(g, lo, t - offs[lo]);
+    const TcUnit u = tc_decode_in_phase(g, lo, t - tc_uniform(offs[lo]));
     if (threadIdx.x == 0) {
       int32_t go = 1;
       const uint64_t t0 = wall_clock64();
@@ -214,7 +226,7 @@ __global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, T
       s_go = go;
     }
     __syncthreads();
-    if (!s_go) break;
+    if (!tc_uniform(s_go)) break;
     if (u.kind == TC_UNIT_UPDATE) {
       tc_run_update(A, lda, g, u);
     } else if (u.kind == TC_UNIT_TRSM) {
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, T
     // every wave makes its stores visible device-wide before the unit is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0 && !tc_err_set(ws.hdr)) tc_unit_publish(g, ws, u);
+    prev = u;
   }
 }
 

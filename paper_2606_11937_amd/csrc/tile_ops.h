@@ -27,6 +27,21 @@
 typedef double tc_v4d __attribute__((ext_vector_type(4)));
 typedef double tc_d2 __attribute__((ext_vector_type(2), aligned(8)));
 
+// Broadcast lane 0's value to the whole wave as a uniform (scalar) value.
+// Values read from LDS that steer loops or branches containing barriers go
+// through these, so the compiler sees the control flow as uniform and keeps
+// every wave's barrier sequence identical to the source.
+__device__ __forceinline__ int32_t tc_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t tc_uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(uint64_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double tc_uniform(double v) {
+  const int64_t b = tc_uniform((int64_t)__builtin_bit_cast(int64_t, v));
+  return __builtin_bit_cast(double, b);
+}
+
 __device__ __forceinline__ tc_v4d tc_mfma(double a, double b, tc_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -301,7 +316,7 @@ __device__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotr
       const int i = lane >> 2;        // row handled (16 rows x 4 lanes)
       const int kq = lane & 3;        // this lane updates columns k = kq, kq+4, ...
       for (int j = 0; j < nb; ++j) {
-        const double d = sm.Lc[j * 17 + j];
+        const double d = tc_uniform(sm.Lc[j * 17 + j]);
         const bool ok = d > 0.0;
         if (!ok) {
           if (lane == 0 && sm.fail < 0) sm.fail = c0 + j;
@@ -332,7 +347,8 @@ __device__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotr
       }
     }
     __syncthreads();
-    if (sm.fail >= 0) return sm.fail;
+    const int fail = tc_uniform((int32_t)sm.fail);
+    if (fail >= 0) return fail;
     // write the factored diagonal block back
     {
       const int i = tid >> 4, j = tid & 15;
