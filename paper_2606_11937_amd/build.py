@@ -22,6 +22,9 @@ HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-fast-math", "-ffp-contract=fast",
+    # MFMA accumulators in ordinary VGPRs: avoids per-iteration copies between
+    # the VGPR and AGPR files in the contraction loops
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

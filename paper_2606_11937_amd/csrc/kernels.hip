@@ -96,6 +96,7 @@ __device__ __forceinline__ void tc_report_fail(TcWsHeader* h, int32_t code, int6
 union TcSmem {
   TcTrsmSmem trsm;
   TcPotrfSmem potrf;
+  TcUpdSmem upd;
 };
 
 __device__ __forceinline__ void tc_run_potrf(double* A, int64_t lda, const TcGeom& g, int32_t J, TcWsHeader* h,
@@ -113,34 +114,41 @@ __device__ __forceinline__ void tc_run_trsm(double* A, int64_t lda, const TcGeom
   tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm.trsm);
 }
 
-__device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u) {
+__device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u, TcSmem& sm) {
   const int64_t ri = tc_row0(g, u.I, u.a);
   const int64_t rk = tc_row0(g, u.K, u.b);
   const int64_t cj = (int64_t)u.J * g.T;
   tc_update_block(A + ri * lda + rk, A + ri * lda + cj, A + rk * lda + cj, lda, tc_rows(g, u.I, u.a),
-                  tc_rows(g, u.K, u.b), (int)g.T, ri == rk);
+                  tc_rows(g, u.K, u.b), (int)g.T, ri == rk, sm.upd);
 }
 
 // ---------------------------------------------------------- fork-join kernels
+// The fork-join kernels declare only the shared memory their body uses (the
+// persistent kernel needs the union of all of them).
 __global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
-  __shared__ TcSmem sm;
+  __shared__ TcPotrfSmem sm;
   if (tc_err_set(ws.hdr)) return;
-  tc_run_potrf(A, lda, g, J, ws.hdr, sm);
+  const int64_t d0 = (int64_t)J * g.T;
+  const int bad = tc_potrf_tile(A + d0 * lda + d0, lda, (int)tc_tdim(g, J), sm);
+  if (bad >= 0 && threadIdx.x == 0) tc_report_fail(ws.hdr, 1, d0 + bad + 1);
 }
 
 __global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
-  __shared__ TcSmem sm;
+  __shared__ TcTrsmSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const int64_t r = blockIdx.x;
   const int32_t I = J + 1 + (int32_t)(r / g.SB);
   const int32_t a = (int32_t)(r % g.SB);
-  tc_run_trsm(A, lda, g, I, a, J, sm);
+  const int64_t r0 = tc_row0(g, I, a);
+  const int64_t c0 = (int64_t)J * g.T;
+  tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm);
 }
 
 __global__ __launch_bounds__(TC_THREADS) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+  __shared__ TcUpdSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
-  tc_run_update(A, lda, g, u);
+  tc_run_update(A, lda, g, u, *reinterpret_cast<TcSmem*>(&sm));
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, T
     __syncthreads();
     if (!tc_uniform(s_go)) break;
     if (u.kind == TC_UNIT_UPDATE) {
-      tc_run_update(A, lda, g, u);
+      tc_run_update(A, lda, g, u, sm);
     } else if (u.kind == TC_UNIT_TRSM) {
       tc_run_trsm(A, lda, g, u.I, u.a, u.J, sm);
     } else {

@@ -74,31 +74,62 @@ __device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
 //   C[r][c] -= sum_{t < kd} PA[r][t] * PB[c][t]     0 <= r < mr, 0 <= c < mc
 // restricted to r >= c when `diag` (a block on the matrix diagonal, SYRK).
 // mr, mc <= 128.  Wave w computes the 64 x 64 quadrant (w & 1, w >> 1) with
-// 4 x 4 MFMA accumulators; operands go straight from global memory (L2) into
-// registers, one 16-wide k chunk ahead of the MFMAs.  Rows/columns beyond
-// mr/mc are clamped to valid addresses and never stored.
+// 4 x 4 MFMA accumulators.
+//
+// Operands are staged through LDS in 16-wide k chunks, three chunks deep:
+// every thread issues direct-to-LDS 16-byte loads (global_load_lds_dwordx4,
+// no registers involved) for chunk c+2 while the MFMAs of chunk c run, and
+// one barrier per chunk publishes the landed chunk to all four waves.
+// LDS layout of one operand tile: 128 rows x 8 slots of 16 bytes (two k
+// values); slot j of row r is stored at position j ^ ((r >> 1) & 7) of the
+// row, which makes the 16-row fragment reads of the MFMAs bank-conflict
+// free.  A direct-to-LDS load writes lane i's 16 bytes to slot i of a
+// 64-slot (1 KB) window, so each lane simply fetches the global element that
+// belongs in its slot.  Rows beyond mr / mc are clamped to valid addresses
+// and never stored; a ragged k tail is handled from registers.
 // ---------------------------------------------------------------------------
+#define TC_UPD_STAGES 3
+struct TcUpdSmem {
+  double tile[TC_UPD_STAGES][2][128 * 16];  // [stage][A|B][row * 16 + slot * 2 + e]
+};
+
+typedef __attribute__((address_space(3))) void tc_lds_void;
+
+__device__ __forceinline__ int tc_swz(int r) { return (r >> 1) & 7; }
+
 __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const double* __restrict__ PA,
                                                 const double* __restrict__ PB, int64_t lda, int mr, int mc,
-                                                int kd, bool diag) {
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+                                                int kd, bool diag, TcUpdSmem& sm) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
-  if (diag && wn > wm) return;  // quadrant strictly above the diagonal
-  if (wm * 64 >= mr || wn * 64 >= mc) return;
+  // waves with nothing to store still stage operands and take part in barriers
+  const bool active = !(diag && wn > wm) && wm * 64 < mr && wn * 64 < mc;
   const int r16 = lane & 15, s4 = (lane >> 4) * 4;
 
-  const double* pa[4];
-  const double* pb[4];
+  // --- staging addresses: wave w, load q covers LDS slots [(w*8+q)*64, +64)
+  //     of the combined 256-row (A rows then B rows) stage
+  const int kfull = kd & ~15;
+  const double* gsrc[8];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int ra = wm * 64 + i * 16 + r16;
-    ra = ra < mr ? ra : mr - 1;
-    pa[i] = PA + (int64_t)ra * lda + s4;
-    int rb = wn * 64 + i * 16 + r16;
-    rb = rb < mc ? rb : mc - 1;
-    pb[i] = PB + (int64_t)rb * lda + s4;
+  for (int q = 0; q < 8; ++q) {
+    const int R = (w * 8 + q) * 8 + (lane >> 3);  // 0..255
+    const int r = R & 127;
+    const int j = (lane & 7) ^ tc_swz(r);         // logical slot held by this lane's position
+    const double* base = R < 128 ? PA + (int64_t)(r < mr ? r : mr - 1) * lda
+                                 : PB + (int64_t)(r < mc ? r : mc - 1) * lda;
+    gsrc[q] = base + 2 * j;
   }
+  auto stage_load = [&](int st, int k0) {
+    tc_lds_void* dst = (tc_lds_void*)&sm.tile[st][0][0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(gsrc[q] + k0),
+                                       (tc_lds_void*)((char __attribute__((address_space(3)))*)dst +
+                                                      (w * 8 + q) * 1024),
+                                       16, 0, 0);
+  };
 
   tc_v4d acc[4][4];
 #pragma unroll
@@ -106,52 +137,66 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = tc_v4d{0.0, 0.0, 0.0, 0.0};
 
-  const int kfull = kd & ~15;
-  tc_q4 ca[4], cb[4];
-  if (kfull > 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ca[i] = tc_ld4(pa[i]);
-      cb[i] = tc_ld4(pb[i]);
-    }
-  }
-  for (int k0 = 0; k0 < kfull; k0 += 16) {
-    tc_q4 na[4], nb[4];
-    const bool more = k0 + 16 < kfull;
-    if (more) {
+  // fragment read: row-block i of operand t (0 = A rows wm*64.., 1 = B rows wn*64..)
+  auto frag = [&](int st, int t, int i) {
+    const int r = (t == 0 ? wm : wn) * 64 + i * 16 + r16;
+    const double* row = &sm.tile[st][t][r * 16];
+    const int sw = tc_swz(r);
+    const int j0 = (s4 >> 1), j1 = j0 + 1;  // slots of k = 4s..4s+1 and 4s+2..4s+3
+    tc_q4 q;
+    q.lo = *(const tc_d2*)(row + 2 * (j0 ^ sw));
+    q.hi = *(const tc_d2*)(row + 2 * (j1 ^ sw));
+    return q;
+  };
+
+  const int nchunk = kfull >> 4;
+  if (nchunk > 0) stage_load(0, 0);
+  if (nchunk > 1) stage_load(1, 16);
+  for (int c = 0; c < nchunk; ++c) {
+    // wait for this thread's loads of chunk c (chunk c+1 may stay in flight)
+    // (s_waitcnt encodings: 0x0F78 = vmcnt(8), 0x0F70 = vmcnt(0); expcnt and
+    // lgkmcnt left at their maxima)
+    if (c + 1 < nchunk) __builtin_amdgcn_s_waitcnt(0x0F78); else __builtin_amdgcn_s_waitcnt(0x0F70);
+    // A plain barrier: every thread has already waited for its own loads of
+    // chunk c, so after it all of chunk c is in LDS.  (A fenced barrier would
+    // also wait for the loads of chunks c+1 and c+2 still in flight.)
+    __builtin_amdgcn_s_barrier();
+    if (c + 2 < nchunk) stage_load((c + 2) % TC_UPD_STAGES, (c + 2) * 16);
+    if (active) {
+      const int st = c % TC_UPD_STAGES;
+      tc_q4 fa[4], fb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        na[i] = tc_ld4(pa[i] + k0 + 16);
-        nb[i] = tc_ld4(pb[i] + k0 + 16);
+        fa[i] = frag(st, 0, i);
+        fb[i] = frag(st, 1, i);
       }
-    }
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ca[i], m), tc_el(cb[j], m), acc[i][j]);
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ca[i] = na[i];
-        cb[i] = nb[i];
-      }
+          for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(fa[i], m), tc_el(fb[j], m), acc[i][j]);
     }
   }
-  if (kfull < kd) {  // ragged k tail, zero filled
+  if (!active) return;
+  if (kfull < kd) {  // ragged k tail, from registers, zero filled
     const int lim = kd - kfull - s4;
+    tc_q4 ta[4], tb[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      ca[i] = tc_ld4_tail(pa[i] + kfull, lim);
-      cb[i] = tc_ld4_tail(pb[i] + kfull, lim);
+      int ra = wm * 64 + i * 16 + r16;
+      ra = ra < mr ? ra : mr - 1;
+      int rb = wn * 64 + i * 16 + r16;
+      rb = rb < mc ? rb : mc - 1;
+      ta[i] = tc_ld4_tail(PA + (int64_t)ra * lda + kfull + s4, lim);
+      tb[i] = tc_ld4_tail(PB + (int64_t)rb * lda + kfull + s4, lim);
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ca[i], m), tc_el(cb[j], m), acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ta[i], m), tc_el(tb[j], m), acc[i][j]);
   }
 
   // epilogue: C -= acc on the stored part
