@@ -76,7 +76,7 @@ int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched);
 
 /* Largest tile count per dimension the asynchronous schedule accepts
  * (ceil(n / T) above it returns CHOL_EINVAL naming T). */
-#define CHOL_ASYNC_MAX_TILES 2048
+#define CHOL_ASYNC_MAX_TILES 1024
 
 /* Factor A = L L^T in place (Methods, Fig. 1, right-looking tiled order).
  *   A          device pointer, n x n row-major with leading dimension lda.
@@ -104,18 +104,24 @@ int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched,
  * CHOL_NOT_SPD or CHOL_ETIMEOUT. */
 int chol_factor_info(const void* work, void* stream, int64_t* info);
 
-/* Bytes of device workspace chol_solve needs; < 0 on invalid arguments. */
+/* Bytes of device workspace chol_solve needs (a few counters); < 0 on
+ * invalid arguments. */
 int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
 
 /* Solve A X = B with the factor from chol_factor (the paper's motivating
  * use, SPD linear systems via the Cholesky decomposition): forward
- * substitution L Y = B over tile rows, then backward substitution
- * L^T X = Y.
+ * substitution L Y = B, then backward substitution L^T X = Y, each one
+ * launch over 64-row blocks that wait on per-sweep completion counters.
  *   L      device pointer to the factor (lower triangle read only).
  *   B      device pointer, n x nrhs row-major, leading dimension
  *          ldb >= max(1, nrhs); overwritten by X.
- *   T      tile side used for the sweep (need not equal the factor's T).
- * Returns CHOL_OK or a negative error code.  Stream-ordered; no host sync. */
+ *   T      tile side of the factor (validated, T >= 1; the sweeps use their
+ *          own 64-row blocks, so any T gives the same X).
+ *   work   device workspace of chol_solve_workspace_size bytes (contents
+ *          need not be initialised; calls sharing it must be ordered).
+ * Returns CHOL_OK or a negative error code.  Stream-ordered; no host sync.
+ * A sweep whose dependency wait exceeds chol_set_wait_limit stops early and
+ * leaves B unspecified instead of hanging. */
 int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T,
                double* B, int64_t nrhs, int64_t ldb,
                void* work, int64_t work_bytes, void* stream);

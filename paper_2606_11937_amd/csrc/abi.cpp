@@ -123,23 +123,24 @@ int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
   if (n < 0 || n >= kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (nrhs < 0) return bad(3);
-  return 0;
+  return tc_solve_ws_bytes();
 }
 
 int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb, void* work,
                int64_t work_bytes, void* stream) {
   g_bad_arg = 0;
-  (void)work;
   if (n < 0 || n >= kMaxN) return bad(2);
   if (lda < max1(n)) return bad(3);
   if (T < 1) return bad(4);
   if (nrhs < 0) return bad(6);
   if (ldb < max1(nrhs)) return bad(7);
-  if (work_bytes < 0) return bad(9);
   if (n == 0 || nrhs == 0) return CHOL_OK;
   if (L == nullptr) return bad(1);
   if (B == nullptr) return bad(5);
-  return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, (hipStream_t)stream) == 0 ? CHOL_OK : CHOL_EDEVICE;
+  if (work == nullptr) return bad(8);
+  if (work_bytes < tc_solve_ws_bytes()) return bad(9, CHOL_EWORKSPACE);
+  return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, work, (hipStream_t)stream, wait_ticks()) == 0 ? CHOL_OK
+                                                                                                  : CHOL_EDEVICE;
 }
 
 int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {

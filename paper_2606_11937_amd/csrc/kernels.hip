@@ -144,7 +144,7 @@ __global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda,
   tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm);
 }
 
-__global__ __launch_bounds__(TC_THREADS) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
   __shared__ TcUpdSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(TC_THREADS) void tc_fj_update(double* A, int64_t ld
 }
 
 // ------------------------------------------------------- persistent kernel
-#define TC_MAX_PHASES 2048
+#define TC_MAX_PHASES 1024
 
 // Dependency test of unit u (see dag.h): all reads are relaxed agent-scope
 // atomics; the caller issues the acquire fence once the unit is ready.
@@ -190,7 +190,7 @@ __device__ __forceinline__ void tc_unit_publish(const TcGeom& g, const TcWs& ws,
   }
 }
 
-__global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
+__global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_async(double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
   __shared__ TcSmem sm;
   __shared__ int64_t offs[TC_MAX_PHASES + 1];
   __shared__ int64_t s_ticket;
@@ -249,141 +249,6 @@ __global__ __launch_bounds__(TC_THREADS) void tc_async(double* A, int64_t lda, T
   }
 }
 
-// ------------------------------------------------------------- solve kernels
-// Forward substitution L_JJ Y = B_J on one diagonal tile (td rows), in place
-// in B (nrhs columns).  Blocked by 16 rows: first B[c0+i] -= sum_{t<c0}
-// L[c0+i][t] Y[t], then a sequential 16-step substitution per right-hand side.
-__global__ __launch_bounds__(TC_THREADS) void tc_solve_diag_fwd(const double* L, int64_t lda, int td, double* B,
-                                                                int64_t nrhs, int64_t ldb) {
-  __shared__ double Lc[16 * 17];
-  const int tid = threadIdx.x;
-  for (int c0 = 0; c0 < td; c0 += 16) {
-    const int nb = td - c0 < 16 ? td - c0 : 16;
-    {
-      const int i = tid >> 4, j = tid & 15;
-      Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
-    }
-    // rows c0..c0+nb, right-hand sides in chunks of 16
-    for (int64_t cb = 0; cb < nrhs; cb += 16) {
-      const int i = tid >> 4, c = (int)cb + (tid & 15);
-      if (i < nb && c < nrhs) {
-        const double* lr = L + (int64_t)(c0 + i) * lda;
-        double s = B[(int64_t)(c0 + i) * ldb + c];
-        for (int t = 0; t < c0; ++t) s = s - lr[t] * B[(int64_t)t * ldb + c];
-        B[(int64_t)(c0 + i) * ldb + c] = s;
-      }
-    }
-    __syncthreads();
-    for (int64_t c = tid; c < nrhs; c += TC_THREADS) {
-      double* bc = B + (int64_t)c0 * ldb + c;
-      for (int i = 0; i < nb; ++i) {
-        double s = bc[(int64_t)i * ldb];
-        for (int q = 0; q < i; ++q) s = s - Lc[i * 17 + q] * bc[(int64_t)q * ldb];
-        bc[(int64_t)i * ldb] = s / Lc[i * 17 + i];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Backward substitution L_JJ^T X = Y on one diagonal tile, blocked by 16 rows
-// from the bottom: Y[r] -= sum_{t > block} L[t][r] X[t], then a sequential
-// substitution with the transposed 16 x 16 block.
-__global__ __launch_bounds__(TC_THREADS) void tc_solve_diag_bwd(const double* L, int64_t lda, int td, double* B,
-                                                                int64_t nrhs, int64_t ldb) {
-  __shared__ double Lc[16 * 17];
-  const int tid = threadIdx.x;
-  const int nblk = (td + 15) / 16;
-  for (int kb = nblk - 1; kb >= 0; --kb) {
-    const int c0 = kb * 16;
-    const int nb = td - c0 < 16 ? td - c0 : 16;
-    const int e = c0 + nb;
-    {
-      const int i = tid >> 4, j = tid & 15;
-      Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
-    }
-    for (int64_t cb = 0; cb < nrhs; cb += 16) {
-      const int i = tid >> 4, c = (int)cb + (tid & 15);
-      if (i < nb && c < nrhs) {
-        double s = B[(int64_t)(c0 + i) * ldb + c];
-        for (int t = e; t < td; ++t) s = s - L[(int64_t)t * lda + c0 + i] * B[(int64_t)t * ldb + c];
-        B[(int64_t)(c0 + i) * ldb + c] = s;
-      }
-    }
-    __syncthreads();
-    for (int64_t c = tid; c < nrhs; c += TC_THREADS) {
-      double* bc = B + (int64_t)c0 * ldb + c;
-      for (int i = nb - 1; i >= 0; --i) {
-        double s = bc[(int64_t)i * ldb];
-        for (int q = i + 1; q < nb; ++q) s = s - Lc[q * 17 + i] * bc[(int64_t)q * ldb];
-        bc[(int64_t)i * ldb] = s / Lc[i * 17 + i];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Forward sweep update below tile J: B[r] -= L[r, J*T : J*T+td] Y_J for the
-// rows r of [r0, n).  One workgroup per 16 rows; 16 lanes per row split the
-// contraction (coalesced 128-byte row segments), reduced through LDS.
-__global__ __launch_bounds__(TC_THREADS) void tc_solve_upd_fwd(const double* L, int64_t lda, int64_t r0, int64_t n,
-                                                               int64_t c0, int td, double* B, int64_t nrhs,
-                                                               int64_t ldb) {
-  __shared__ double red[16][17];
-  const int tid = threadIdx.x;
-  const int rl = tid >> 4, kl = tid & 15;
-  const int64_t r = r0 + (int64_t)blockIdx.x * 16 + rl;
-  const bool live = r < n;
-  const double* lr = L + (live ? r : r0) * lda + c0;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    double s = 0.0;
-    if (live)
-      for (int t = kl; t < td; t += 16) s += lr[t] * B[(c0 + t) * ldb + c];
-    red[rl][kl] = s;
-    __syncthreads();
-    if (kl == 0 && live) {
-      double acc = 0.0;
-      for (int q = 0; q < 16; ++q) acc += red[rl][q];
-      B[r * ldb + c] -= acc;
-    }
-    __syncthreads();
-  }
-}
-
-// Backward sweep update above tile J: Y[r] -= sum_t L[J*T + t][r] X_J[t] for
-// rows r < J*T.  One thread per row r (coalesced along the rows of L's block
-// row J); X_J is staged in LDS in chunks of 16 right-hand sides.
-__global__ __launch_bounds__(TC_THREADS) void tc_solve_upd_bwd(const double* L, int64_t lda, int64_t rows,
-                                                               int64_t c0, int td, double* B, int64_t nrhs,
-                                                               int64_t ldb) {
-  __shared__ double xs[64][16];
-  const int64_t r = (int64_t)blockIdx.x * TC_THREADS + threadIdx.x;
-  for (int64_t cb = 0; cb < nrhs; cb += 16) {
-    const int nc = nrhs - cb < 16 ? (int)(nrhs - cb) : 16;
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int t0 = 0; t0 < td; t0 += 64) {
-      const int tn = td - t0 < 64 ? td - t0 : 64;
-      __syncthreads();
-      for (int e = threadIdx.x; e < 64 * 16; e += TC_THREADS) {
-        const int tt = e >> 4, q = e & 15;
-        xs[tt][q] = (tt < tn && q < nc) ? B[(c0 + t0 + tt) * ldb + cb + q] : 0.0;
-      }
-      __syncthreads();
-      if (r < rows) {
-        for (int tt = 0; tt < tn; ++tt) {
-          const double l = L[(c0 + t0 + tt) * lda + r];
-#pragma unroll
-          for (int q = 0; q < 16; ++q) acc[q] += l * xs[tt][q];
-        }
-      }
-    }
-    if (r < rows)
-      for (int q = 0; q < nc; ++q) B[r * ldb + cb + q] -= acc[q];
-  }
-}
-
 // ------------------------------------------------------------ host launchers
 static int tc_chk(hipError_t e) { return e == hipSuccess ? 0 : TC_LAUNCH_EDEVICE; }
 
@@ -433,29 +298,4 @@ int64_t tc_async_grid_size() {
   int64_t gsz = (int64_t)(per_cu > 0 ? per_cu : 1) * p.multiProcessorCount;
   if (dev >= 0 && dev < 64) cached[dev] = gsz;
   return gsz;
-}
-
-int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
-                    hipStream_t st) {
-  const int64_t M = tc_cdiv(n, T);
-  for (int64_t J = 0; J < M; ++J) {
-    const int64_t c0 = J * T;
-    const int td = (int)(n - c0 < T ? n - c0 : T);
-    hipLaunchKernelGGL(tc_solve_diag_fwd, dim3(1), dim3(TC_THREADS), 0, st, L + c0 * lda + c0, lda, td,
-                       B + c0 * ldb, nrhs, ldb);
-    const int64_t r0 = c0 + td;
-    if (r0 < n)
-      hipLaunchKernelGGL(tc_solve_upd_fwd, dim3((unsigned)tc_cdiv(n - r0, 16)), dim3(TC_THREADS), 0, st, L, lda, r0,
-                         n, c0, td, B, nrhs, ldb);
-  }
-  for (int64_t J = M - 1; J >= 0; --J) {
-    const int64_t c0 = J * T;
-    const int td = (int)(n - c0 < T ? n - c0 : T);
-    hipLaunchKernelGGL(tc_solve_diag_bwd, dim3(1), dim3(TC_THREADS), 0, st, L + c0 * lda + c0, lda, td,
-                       B + c0 * ldb, nrhs, ldb);
-    if (c0 > 0)
-      hipLaunchKernelGGL(tc_solve_upd_bwd, dim3((unsigned)tc_cdiv(c0, TC_THREADS)), dim3(TC_THREADS), 0, st, L, lda,
-                         c0, c0, td, B, nrhs, ldb);
-  }
-  return tc_chk(hipGetLastError());
 }

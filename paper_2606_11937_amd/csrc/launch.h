@@ -16,6 +16,8 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, vo
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info);
 // Co-resident workgroups of the persistent kernel on the current device.
 int64_t tc_async_grid_size();
-// Enqueue forward + backward substitution with tile side T.
+// Workspace bytes of the solve (block tickets and done counters).
+int64_t tc_solve_ws_bytes();
+// Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
-                    hipStream_t st);
+                    void* work, hipStream_t st, int64_t wait_ticks);

@@ -1,0 +1,234 @@
+// solve.hip -- A X = B with the Cholesky factor (the paper's motivating use:
+// SPD linear systems through the decomposition): forward substitution
+// L Y = B, then backward substitution L^T X = Y, in place in B.
+//
+// Both sweeps are single launches over 64-row blocks.  Each workgroup takes
+// a block from an atomic ticket (ascending for the forward sweep, descending
+// for the backward one), so a workgroup only ever waits for blocks whose
+// tickets are smaller, all held by running workgroups.  A "done" counter in
+// the workspace records how many blocks, in sweep order, are finished; a
+// workgroup folds in every finished block it sees (no waiting), re-reads the
+// counter, and waits only for the last few blocks before its own.  Blocks
+// finish and publish in sweep order.  The sweep streams L once from HBM
+// while the chain of 64 x 64 triangular solves runs.
+//
+// Rounding order, for bitwise reproducibility: for row i of block b and
+// right-hand side c, each of the four thread quarters p accumulates its 16
+// columns of every earlier block in ascending order, the quarters are
+// combined in order p = 0..3 and subtracted from B, and the in-block
+// substitution is sequential in the column index.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.h"
+
+#define SV_NB 64        // rows per block
+#define SV_RC 16        // right-hand sides per pass
+#define SV_THREADS 256
+
+struct SvWs {
+  int32_t ticket_f, done_f, ticket_b, done_b;
+  int32_t error, pad[59];
+};
+
+__device__ __forceinline__ int32_t sv_ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *cnt > need (or the error flag / time limit trips).  Returns the
+// value seen, or -1 on abort.  Called by every thread; the acquire fence
+// orders this thread's later loads of the published blocks.
+__device__ __forceinline__ int32_t sv_wait_above(const int32_t* cnt, int32_t need, SvWs* ws, int64_t wait_ticks) {
+  int32_t v = sv_ld(cnt);
+  if (v <= need) {
+    const uint64_t t0 = wall_clock64();
+    while ((v = sv_ld(cnt)) <= need) {
+      if (sv_ld(&ws->error)) return -1;
+      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
+        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return -1;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return v;
+}
+
+__device__ __forceinline__ int32_t sv_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Publish block completion in sweep order: wait until `done` == pos, then
+// set it to pos + 1.  All threads have fenced their stores before.
+__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, SvWs* ws, int64_t wait_ticks) {
+  if (threadIdx.x == 0) {
+    if (sv_wait_above(done, pos - 1, ws, wait_ticks) >= 0)
+      __hip_atomic_store(done, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.
+__global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                         double* __restrict__ B, int64_t nrhs, int64_t ldb,
+                                                         SvWs* ws, int64_t wait_ticks) {
+  __shared__ double part[4][SV_NB][SV_RC + 1];
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ int32_t s_b;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t b = sv_uniform(s_b);
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  // stage the diagonal block (lower part)
+  for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : 0.0;
+  }
+  // thread (r, p): row r, columns 16p .. 16p+15 of every earlier block
+  const int r = tid >> 2, p = tid & 3;
+  const bool live = r < nr;
+  const double* lrow = L + (r0 + (live ? r : 0)) * lda + 16 * p;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
+    const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
+    double acc[SV_RC];
+#pragma unroll
+    for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
+    int32_t j = 0;
+    while (j < b) {
+      const int32_t ready = sv_wait_above(&ws->done_f, j, ws, wait_ticks);
+      if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
+      const int32_t jend = ready < b ? ready : b;
+      for (; j < jend; ++j) {
+        if (!live) continue;
+        const double* lj = lrow + (int64_t)j * SV_NB;
+        const double* yj = B + ((int64_t)j * SV_NB + 16 * p) * ldb + c0;
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+          const double l = lj[k];
+#pragma unroll
+          for (int c = 0; c < SV_RC; ++c)
+            if (c < nc) acc[c] += l * yj[(int64_t)k * ldb + c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < SV_RC; ++c) part[p][r][c] = acc[c];
+    __syncthreads();
+    // one wave per right-hand side: lane k holds row k of the block
+    const int w = tid >> 6, lane = tid & 63;
+    for (int c = w; c < nc; c += 4) {
+      double v = 0.0;
+      if (lane < nr) {
+        const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
+        v = B[(r0 + lane) * ldb + c0 + c] - s;
+      }
+      for (int i = 0; i < nr; ++i) {
+        double xi = 0.0;
+        if (lane == i) xi = v / Lbb[i][i];
+        xi = __shfl(xi, i, 64);
+        if (lane == i) v = xi;
+        if (lane > i) v = v - Lbb[lane][i] * xi;
+      }
+      if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
+    }
+    __syncthreads();
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_f, b, ws, wait_ticks);
+}
+
+// --------------------------------------------------------------- backward
+// x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j), block b = nb - 1 - ticket.
+__global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
+                                                          SvWs* ws, int64_t wait_ticks) {
+  __shared__ double part[4][SV_NB][SV_RC + 1];
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ int32_t s_t;
+  const int tid = threadIdx.x;
+  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
+  if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t t = sv_uniform(s_t);
+  const int32_t b = nb - 1 - t;
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : 0.0;
+  }
+  // thread (r, p): output row r of the block (column r of each L_jb), rows
+  // 16p .. 16p+15 of every later block; consecutive r are consecutive
+  // addresses, so each wave reads 64 contiguous doubles per k
+  const int r = tid & 63, p = tid >> 6;
+  const bool live = r < nr;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
+    const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
+    double acc[SV_RC];
+#pragma unroll
+    for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
+    int32_t d = 0;  // blocks done from the end; block j is done iff j >= nb - d
+    int32_t j = nb - 1;
+    while (j > b) {
+      const int32_t ready = sv_wait_above(&ws->done_b, nb - 1 - j, ws, wait_ticks);
+      if (ready < 0) break;
+      d = ready;
+      const int32_t jlow = nb - d > b + 1 ? nb - d : b + 1;
+      for (; j >= jlow; --j) {
+        const int64_t j0 = (int64_t)j * SV_NB;
+        const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+        if (!live) continue;
+        for (int k = 16 * p; k < 16 * p + 16 && k < njr; ++k) {
+          const double l = L[(j0 + k) * lda + r0 + r];
+          const double* xk = B + (j0 + k) * ldb + c0;
+#pragma unroll
+          for (int c = 0; c < SV_RC; ++c)
+            if (c < nc) acc[c] += l * xk[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < SV_RC; ++c) part[p][r][c] = acc[c];
+    __syncthreads();
+    const int w = tid >> 6, lane = tid & 63;
+    for (int c = w; c < nc; c += 4) {
+      double v = 0.0;
+      if (lane < nr) {
+        const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
+        v = B[(r0 + lane) * ldb + c0 + c] - s;
+      }
+      for (int i = nr - 1; i >= 0; --i) {
+        double xi = 0.0;
+        if (lane == i) xi = v / Lbb[i][i];
+        xi = __shfl(xi, i, 64);
+        if (lane == i) v = xi;
+        if (lane < i) v = v - Lbb[i][lane] * xi;
+      }
+      if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
+    }
+    __syncthreads();
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_b, t, ws, wait_ticks);
+}
+
+__global__ void sv_clear(SvWs* ws) {
+  if (threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)ws)[threadIdx.x] = 0;
+}
+
+int64_t tc_solve_ws_bytes() { return (int64_t)sizeof(SvWs); }
+
+int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
+                    void* work, hipStream_t st, int64_t wait_ticks) {
+  (void)T;
+  const int64_t nb = (n + SV_NB - 1) / SV_NB;
+  SvWs* ws = (SvWs*)work;
+  hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+  hipLaunchKernelGGL(sv_forward, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb, ws, wait_ticks);
+  hipLaunchKernelGGL(sv_backward, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb, ws,
+                     wait_ticks);
+  return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}

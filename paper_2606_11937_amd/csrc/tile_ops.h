@@ -88,7 +88,7 @@ __device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
 // belongs in its slot.  Rows beyond mr / mc are clamped to valid addresses
 // and never stored; a ragged k tail is handled from registers.
 // ---------------------------------------------------------------------------
-#define TC_UPD_STAGES 3
+#define TC_UPD_STAGES 2
 struct TcUpdSmem {
   double tile[TC_UPD_STAGES][2][128 * 16];  // [stage][A|B][row * 16 + slot * 2 + e]
 };
@@ -130,6 +130,21 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
                                                       (w * 8 + q) * 1024),
                                        16, 0, 0);
   };
+  // the ragged last chunk (kd % 16 != 0): ordinary guarded loads, zero past
+  // kd, stored to the same LDS positions the direct loads would fill
+  auto stage_tail = [&](int st, int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int R = (w * 8 + q) * 8 + (lane >> 3);
+      const int r = R & 127;
+      const int j = (lane & 7) ^ tc_swz(r);
+      const int k = k0 + 2 * j;
+      tc_d2 v;
+      v.x = k < kd ? gsrc[q][k0] : 0.0;
+      v.y = k + 1 < kd ? gsrc[q][k0 + 1] : 0.0;
+      *(tc_d2*)(&sm.tile[st][0][0] + ((w * 8 + q) * 64 + lane) * 2) = v;
+    }
+  };
 
   tc_v4d acc[4][4];
 #pragma unroll
@@ -137,38 +152,43 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = tc_v4d{0.0, 0.0, 0.0, 0.0};
 
-  // fragment read: row-block i of operand t (0 = A rows wm*64.., 1 = B rows wn*64..)
-  auto frag = [&](int st, int t, int i) {
+  // fragment half h of row-block i of operand t (0 = A rows wm*64..,
+  // 1 = B rows wn*64..): the slot holding k = 4s + 2h, 4s + 2h + 1
+  auto frag = [&](int st, int t, int i, int h) {
     const int r = (t == 0 ? wm : wn) * 64 + i * 16 + r16;
     const double* row = &sm.tile[st][t][r * 16];
-    const int sw = tc_swz(r);
-    const int j0 = (s4 >> 1), j1 = j0 + 1;  // slots of k = 4s..4s+1 and 4s+2..4s+3
-    tc_q4 q;
-    q.lo = *(const tc_d2*)(row + 2 * (j0 ^ sw));
-    q.hi = *(const tc_d2*)(row + 2 * (j1 ^ sw));
-    return q;
+    const int j = (s4 >> 1) + h;
+    return *(const tc_d2*)(row + 2 * (j ^ tc_swz(r)));
   };
 
-  const int nchunk = kfull >> 4;
-  if (nchunk > 0) stage_load(0, 0);
-  if (nchunk > 1) stage_load(1, 16);
+  const int nfull = kfull >> 4;
+  const int nchunk = (kd + 15) >> 4;
+  if (nfull > 0) stage_load(0, 0);
+  else if (nchunk > 0) stage_tail(0, 0);
   for (int c = 0; c < nchunk; ++c) {
-    // wait for this thread's loads of chunk c (chunk c+1 may stay in flight)
-    // (s_waitcnt encodings: 0x0F78 = vmcnt(8), 0x0F70 = vmcnt(0); expcnt and
-    // lgkmcnt left at their maxima)
-    if (c + 1 < nchunk) __builtin_amdgcn_s_waitcnt(0x0F78); else __builtin_amdgcn_s_waitcnt(0x0F70);
-    // A plain barrier: every thread has already waited for its own loads of
-    // chunk c, so after it all of chunk c is in LDS.  (A fenced barrier would
-    // also wait for the loads of chunks c+1 and c+2 still in flight.)
+    // this thread's loads of chunk c are the only ones in flight; the guarded
+    // path of a ragged chunk also needs its LDS stores done
+    // (s_waitcnt encodings: 0x0F70 = vmcnt(0), 0x0070 = vmcnt(0) lgkmcnt(0))
+    if (c < nfull) __builtin_amdgcn_s_waitcnt(0x0F70); else __builtin_amdgcn_s_waitcnt(0x0070);
+    // A plain barrier: after it every thread's part of chunk c is in LDS and
+    // every wave has finished reading chunk c-1, whose stage is refilled next.
     __builtin_amdgcn_s_barrier();
-    if (c + 2 < nchunk) stage_load((c + 2) % TC_UPD_STAGES, (c + 2) * 16);
+    if (c + 1 < nfull) stage_load((c + 1) % TC_UPD_STAGES, (c + 1) * 16);
+    else if (c + 1 < nchunk) stage_tail((c + 1) % TC_UPD_STAGES, (c + 1) * 16);
     if (active) {
       const int st = c % TC_UPD_STAGES;
       tc_q4 fa[4], fb[4];
+      // low halves first: the MFMAs of k steps 0 and 1 can start while the
+      // high halves are still being read
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        fa[i] = frag(st, 0, i);
-        fb[i] = frag(st, 1, i);
+        fa[i].lo = frag(st, 0, i, 0);
+        fb[i].lo = frag(st, 1, i, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fa[i].hi = frag(st, 0, i, 1);
+        fb[i].hi = frag(st, 1, i, 1);
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m)
@@ -179,30 +199,13 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
     }
   }
   if (!active) return;
-  if (kfull < kd) {  // ragged k tail, from registers, zero filled
-    const int lim = kd - kfull - s4;
-    tc_q4 ta[4], tb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int ra = wm * 64 + i * 16 + r16;
-      ra = ra < mr ? ra : mr - 1;
-      int rb = wn * 64 + i * 16 + r16;
-      rb = rb < mc ? rb : mc - 1;
-      ta[i] = tc_ld4_tail(PA + (int64_t)ra * lda + kfull + s4, lim);
-      tb[i] = tc_ld4_tail(PB + (int64_t)rb * lda + kfull + s4, lim);
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(ta[i], m), tc_el(tb[j], m), acc[i][j]);
-  }
 
-  // epilogue: C -= acc on the stored part
+  // epilogue: C -= acc on the stored part, one 16-row group at a time (the
+  // scheduling barriers keep the compiler from hoisting all 64 loads of C
+  // ahead of the first subtraction, which would need 128 more registers)
   const int orow = lane >> 4, ocol = lane & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -214,6 +217,8 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
           *p = *p - acc[i][j][q];
         }
       }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -284,7 +289,7 @@ struct TcTrsmSmem {
   double Lc[16 * 17];
 };
 
-__device__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
+__device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
                               TcTrsmSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int row0 = w * 32;
@@ -338,7 +343,7 @@ struct TcPotrfSmem {
   int fail;
 };
 
-__device__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
+__device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) sm.fail = -1;
   __syncthreads();

@@ -25,7 +25,7 @@ CHOL_ETIMEOUT = -4
 CHOL_SCHED_FORK_JOIN = 0
 CHOL_SCHED_ASYNC_DAG = 1
 CHOL_BLOCK = 128
-CHOL_ASYNC_MAX_TILES = 2048
+CHOL_ASYNC_MAX_TILES = 1024
 SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG}
 
 # (name, restype, argtypes) for every symbol of include/tilechol.h
@@ -154,7 +154,13 @@ def chol_solve(L, B, T: int, n: int | None = None, work=None, stream=None) -> No
     lda = L.stride(0) if L.shape[0] > 1 else max(1, L.shape[1])
     nrhs = B.shape[1]
     ldb = B.stride(0) if B.shape[0] > 1 else max(1, nrhs)
-    wptr, wbytes = (work.data_ptr(), work.numel()) if work is not None else (0, 0)
+    if work is None:
+        import torch
+        nb = chol_solve_workspace_size(n, T, nrhs)
+        if nb < 0:
+            raise TileCholError(nb, "chol_solve_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=B.device)
+    wptr, wbytes = work.data_ptr(), work.numel()
     st = lib.chol_solve(ctypes.c_void_p(L.data_ptr()), n, lda, T, ctypes.c_void_p(B.data_ptr()), nrhs, ldb,
                         ctypes.c_void_p(wptr), wbytes, _stream(stream))
     if st != CHOL_OK:

@@ -98,7 +98,7 @@ def test_workspace_sizes(tc):
     assert a == b > 0
     # counters grow with the number of row blocks
     assert tc.chol_factor_workspace_size(32768, 128, 1) > tc.chol_factor_workspace_size(8192, 128, 1)
-    assert tc.chol_solve_workspace_size(100, 16, 3) == 0
+    assert 0 < tc.chol_solve_workspace_size(100, 16, 3) <= 4096
     assert tc.chol_solve_workspace_size(100, 0, 3) == tc.CHOL_EINVAL
 
 
@@ -113,8 +113,18 @@ def test_workspace_sizes(tc):
 ])
 def test_solve_argument_checks(tc, args, bad_arg):
     L, n, lda, T, B, nrhs, ldb = args
-    st = tc.lib.chol_solve(L, n, lda, T, B, nrhs, ldb, None, 0, None)
+    st = tc.lib.chol_solve(L, n, lda, T, B, nrhs, ldb, FAKE, 1 << 20, None)
     assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == bad_arg
+
+
+def test_solve_workspace_checks(tc):
+    need = tc.chol_solve_workspace_size(8, 4, 1)
+    st = tc.lib.chol_solve(FAKE, 8, 8, 4, FAKE, 1, 1, None, need, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 8
+    st = tc.lib.chol_solve(FAKE, 8, 8, 4, FAKE, 1, 1, FAKE, need - 1, None)
+    assert st == tc.CHOL_EWORKSPACE and tc.last_bad_arg() == 9
+    # nothing to solve: OK without touching anything
+    assert tc.lib.chol_solve(None, 0, 1, 4, None, 3, 3, None, 0, None) == tc.CHOL_OK
 
 
 def test_batched_argument_checks(tc):
