@@ -23,7 +23,10 @@
  *             finds L^T in its upper triangle.)
  *   Tiles     M = ceil(n / T) tiles per dimension; the last tile row and
  *             column are ragged with side n - (M - 1) T.  T > n is allowed
- *             (one tile).  All sizes and offsets are 64-bit.
+ *             (one tile).  All sizes and offsets are 64-bit; n and lda are
+ *             at most CHOL_MAX_N (a 2^20-order FP64 matrix is 8 TB, far
+ *             beyond one device, and the limit lets 128-row staging loads
+ *             use 32-bit offsets).
  *   Memory    A, B and the workspace are device pointers owned by the
  *             caller; the library never allocates, frees or retains device
  *             memory.  `stream` is a hipStream_t passed as void* (NULL is
@@ -43,6 +46,8 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+#define CHOL_MAX_N 1048576
 
 /* Status codes.  > 0: numerical outcome; < 0: caller or runtime error. */
 enum {

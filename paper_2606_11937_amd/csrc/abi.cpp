@@ -21,7 +21,9 @@ int bad(int idx, int code = CHOL_EINVAL) {
   return code;
 }
 inline int64_t max1(int64_t x) { return x > 1 ? x : 1; }
-const int64_t kMaxN = (int64_t)1 << 31;
+// Largest order / leading dimension: the staging loads address one
+// 128-row block with 32-bit byte offsets.
+const int64_t kMaxN = (int64_t)1 << 20;
 
 int64_t wait_ticks() {
   int dev = 0, khz = 0;
@@ -39,8 +41,8 @@ int status_from(int32_t err, int64_t dinfo, int64_t* info) {
 }
 
 int check_factor_args(double* A, int64_t n, int64_t lda, int64_t T, int sched) {
-  if (n < 0 || n >= kMaxN) return bad(2);
-  if (lda < max1(n)) return bad(3);
+  if (n < 0 || n > kMaxN) return bad(2);
+  if (lda < max1(n) || lda > kMaxN) return bad(3);
   if (T < 1) return bad(4);
   if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(5);
   if (sched == CHOL_SCHED_ASYNC_DAG && n > 0 && tc_cdiv(n, T) > CHOL_ASYNC_MAX_TILES) return bad(4);
@@ -78,7 +80,7 @@ int64_t chol_default_tile(int64_t n) {
 
 int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched) {
   g_bad_arg = 0;
-  if (n < 0 || n >= kMaxN) return bad(1);
+  if (n < 0 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(3);
   return tc_ws_bytes(n > 0 ? n : 1, T);
@@ -120,7 +122,7 @@ int chol_factor_info(const void* work, void* stream, int64_t* info) {
 
 int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
   g_bad_arg = 0;
-  if (n < 0 || n >= kMaxN) return bad(1);
+  if (n < 0 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (nrhs < 0) return bad(3);
   return tc_solve_ws_bytes();
@@ -129,8 +131,8 @@ int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
 int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb, void* work,
                int64_t work_bytes, void* stream) {
   g_bad_arg = 0;
-  if (n < 0 || n >= kMaxN) return bad(2);
-  if (lda < max1(n)) return bad(3);
+  if (n < 0 || n > kMaxN) return bad(2);
+  if (lda < max1(n) || lda > kMaxN) return bad(3);
   if (T < 1) return bad(4);
   if (nrhs < 0) return bad(6);
   if (ldb < max1(nrhs)) return bad(7);
@@ -149,7 +151,7 @@ int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, cons
   if (batch > 0 && n == nullptr) return bad(2);
   int64_t total = 0;
   for (int64_t i = 0; i < batch; ++i) {
-    if (n[i] < 0 || n[i] >= kMaxN) return bad(2);
+    if (n[i] < 0 || n[i] > kMaxN) return bad(2);
     const int64_t t = T ? T[i] : chol_default_tile(n[i]);
     if (t < 1) return bad(3);
     total += (tc_ws_bytes(n[i] > 0 ? n[i] : 1, t) + 255) & ~(int64_t)255;
@@ -166,8 +168,8 @@ int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, 
   if (n == nullptr) return bad(2);
   if (lda == nullptr) return bad(3);
   for (int64_t i = 0; i < batch; ++i) {
-    if (n[i] < 0 || n[i] >= kMaxN) return bad(2);
-    if (lda[i] < max1(n[i])) return bad(3);
+    if (n[i] < 0 || n[i] > kMaxN) return bad(2);
+    if (lda[i] < max1(n[i]) || lda[i] > kMaxN) return bad(3);
     const int64_t t = T ? T[i] : chol_default_tile(n[i]);
     if (t < 1) return bad(5);
     if (n[i] > 0 && A[i] == nullptr) return bad(1);
@@ -206,7 +208,7 @@ int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, 
 
 int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]) {
   g_bad_arg = 0;
-  if (n < 1 || n >= kMaxN) return bad(1);
+  if (n < 1 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (counts == nullptr) return bad(3);
   TcGeom g = tc_geom(n, T, 0);
@@ -219,7 +221,7 @@ int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]) {
 
 int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int64_t cap) {
   g_bad_arg = 0;
-  if (n < 1 || n >= kMaxN) return bad(1);
+  if (n < 1 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (grid < 1) return bad(3);
   if (cap < 0) return bad(5);

@@ -76,17 +76,21 @@ __device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
 // mr, mc <= 128.  Wave w computes the 64 x 64 quadrant (w & 1, w >> 1) with
 // 4 x 4 MFMA accumulators.
 //
-// Operands are staged through LDS in 16-wide k chunks, three chunks deep:
-// every thread issues direct-to-LDS 16-byte loads (global_load_lds_dwordx4,
-// no registers involved) for chunk c+2 while the MFMAs of chunk c run, and
-// one barrier per chunk publishes the landed chunk to all four waves.
+// Operands are staged through LDS in 16-wide k chunks, two stages deep, with
+// direct-to-LDS buffer loads (16 bytes per lane, no registers involved).
 // LDS layout of one operand tile: 128 rows x 8 slots of 16 bytes (two k
-// values); slot j of row r is stored at position j ^ ((r >> 1) & 7) of the
-// row, which makes the 16-row fragment reads of the MFMAs bank-conflict
-// free.  A direct-to-LDS load writes lane i's 16 bytes to slot i of a
-// 64-slot (1 KB) window, so each lane simply fetches the global element that
-// belongs in its slot.  Rows beyond mr / mc are clamped to valid addresses
-// and never stored; a ragged k tail is handled from registers.
+// values); slot j of row r sits at position j ^ (r & 7) of its row, which
+// keeps the 128-bit fragment reads of the MFMAs free of bank conflicts.  A
+// direct-to-LDS load writes lane i's 16 bytes to slot i of a 64-slot window,
+// so each lane fetches the global element that belongs in its slot.  The
+// buffer resource spans exactly the block's mr (mc) rows: rows beyond them
+// read as zero and are never stored.
+//
+// Fragment registers roll half a chunk ahead: the high halves (k steps 2, 3)
+// of chunk c are read while the MFMAs of its low halves run; the barrier that
+// publishes chunk c+1 sits in the middle of chunk c; the low halves of chunk
+// c+1 are read while the MFMAs of chunk c's high halves run.  One 64-register
+// fragment set and a 64 KB stage pair let two workgroups share a CU.
 // ---------------------------------------------------------------------------
 #define TC_UPD_STAGES 2
 struct TcUpdSmem {
@@ -94,8 +98,9 @@ struct TcUpdSmem {
 };
 
 typedef __attribute__((address_space(3))) void tc_lds_void;
+typedef double tc_d2a16 __attribute__((ext_vector_type(2), aligned(16)));
 
-__device__ __forceinline__ int tc_swz(int r) { return (r >> 1) & 7; }
+__device__ __forceinline__ int tc_swz(int r) { return r & 7; }
 
 __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const double* __restrict__ PA,
                                                 const double* __restrict__ PB, int64_t lda, int mr, int mc,
@@ -106,44 +111,53 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
   const int wm = w & 1, wn = w >> 1;
   // waves with nothing to store still stage operands and take part in barriers
   const bool active = !(diag && wn > wm) && wm * 64 < mr && wn * 64 < mc;
-  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
+  const int r16 = lane & 15, s2 = (lane >> 4) * 2;
 
-  // --- staging addresses: wave w, load q covers LDS slots [(w*8+q)*64, +64)
-  //     of the combined 256-row (A rows then B rows) stage
-  const int kfull = kd & ~15;
-  const double* gsrc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int R = (w * 8 + q) * 8 + (lane >> 3);  // 0..255
-    const int r = R & 127;
-    const int j = (lane & 7) ^ tc_swz(r);         // logical slot held by this lane's position
-    const double* base = R < 128 ? PA + (int64_t)(r < mr ? r : mr - 1) * lda
-                                 : PB + (int64_t)(r < mc ? r : mc - 1) * lda;
-    gsrc[q] = base + 2 * j;
-  }
+  // --- staging: waves 0,1 fetch A rows, waves 2,3 B rows; load q of wave w
+  //     fills LDS slots [(w*8+q)*64, +64) = rows (w&1)*64 + q*8 .. +8
+  const int nrow = w < 2 ? mr : mc;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(w < 2 ? PA : PB), (short)0, (int)((int64_t)nrow * lda * 8), 0x00020000);
+  const int rl0 = (w & 1) * 64 + (lane >> 3);
+  const unsigned vof0 = (unsigned)(rl0 * lda * 8 + 16 * ((lane & 7) ^ tc_swz(rl0)));
+  const unsigned rowstep = (unsigned)(8 * lda * 8);
   auto stage_load = [&](int st, int k0) {
-    tc_lds_void* dst = (tc_lds_void*)&sm.tile[st][0][0];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      __builtin_amdgcn_global_load_lds((const void*)(gsrc[q] + k0),
-                                       (tc_lds_void*)((char __attribute__((address_space(3)))*)dst +
-                                                      (w * 8 + q) * 1024),
-                                       16, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrc,
+          (tc_lds_void*)((char __attribute__((address_space(3)))*)(tc_lds_void*)&sm.tile[st][0][0] +
+                         (w * 8 + q) * 1024),
+          16, vof0 + q * rowstep, (unsigned)(k0 * 8), 0, 0);
   };
   // the ragged last chunk (kd % 16 != 0): ordinary guarded loads, zero past
-  // kd, stored to the same LDS positions the direct loads would fill
+  // kd or past the block's rows, stored where the direct loads would put them
   auto stage_tail = [&](int st, int k0) {
+    const double* gb = w < 2 ? PA : PB;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int R = (w * 8 + q) * 8 + (lane >> 3);
-      const int r = R & 127;
+      const int r = rl0 + q * 8;
       const int j = (lane & 7) ^ tc_swz(r);
       const int k = k0 + 2 * j;
+      const double* src = gb + (int64_t)(r < nrow ? r : 0) * lda + k;
       tc_d2 v;
-      v.x = k < kd ? gsrc[q][k0] : 0.0;
-      v.y = k + 1 < kd ? gsrc[q][k0 + 1] : 0.0;
+      v.x = (r < nrow && k < kd) ? src[0] : 0.0;
+      v.y = (r < nrow && k + 1 < kd) ? src[1] : 0.0;
       *(tc_d2*)(&sm.tile[st][0][0] + ((w * 8 + q) * 64 + lane) * 2) = v;
     }
+  };
+  auto stage = [&](int st, int c, int nfull) {
+    if (c < nfull) stage_load(st, c * 16); else stage_tail(st, c * 16);
+  };
+  // fragment half h (k = 4s + 2h, 4s + 2h + 1) of row-block i of operand t
+  // (0 = A rows wm*64.., 1 = B rows wn*64..)
+  auto rd = [&](int st, int t, int i, int h) -> tc_d2 {
+    const int r = (t == 0 ? wm : wn) * 64 + i * 16 + r16;
+    const tc_d2a16 v = *(const tc_d2a16*)(&sm.tile[st][t][r * 16] + 2 * ((s2 + h) ^ tc_swz(r)));
+    tc_d2 o;
+    o.x = v.x;
+    o.y = v.y;
+    return o;
   };
 
   tc_v4d acc[4][4];
@@ -152,50 +166,60 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = tc_v4d{0.0, 0.0, 0.0, 0.0};
 
-  // fragment half h of row-block i of operand t (0 = A rows wm*64..,
-  // 1 = B rows wn*64..): the slot holding k = 4s + 2h, 4s + 2h + 1
-  auto frag = [&](int st, int t, int i, int h) {
-    const int r = (t == 0 ? wm : wn) * 64 + i * 16 + r16;
-    const double* row = &sm.tile[st][t][r * 16];
-    const int j = (s4 >> 1) + h;
-    return *(const tc_d2*)(row + 2 * (j ^ tc_swz(r)));
-  };
-
-  const int nfull = kfull >> 4;
-  const int nchunk = (kd + 15) >> 4;
-  if (nfull > 0) stage_load(0, 0);
-  else if (nchunk > 0) stage_tail(0, 0);
-  for (int c = 0; c < nchunk; ++c) {
-    // this thread's loads of chunk c are the only ones in flight; the guarded
-    // path of a ragged chunk also needs its LDS stores done
-    // (s_waitcnt encodings: 0x0F70 = vmcnt(0), 0x0070 = vmcnt(0) lgkmcnt(0))
-    if (c < nfull) __builtin_amdgcn_s_waitcnt(0x0F70); else __builtin_amdgcn_s_waitcnt(0x0070);
-    // A plain barrier: after it every thread's part of chunk c is in LDS and
-    // every wave has finished reading chunk c-1, whose stage is refilled next.
-    __builtin_amdgcn_s_barrier();
-    if (c + 1 < nfull) stage_load((c + 1) % TC_UPD_STAGES, (c + 1) * 16);
-    else if (c + 1 < nchunk) stage_tail((c + 1) % TC_UPD_STAGES, (c + 1) * 16);
+  // (s_waitcnt encodings: 0x0F70 = vmcnt(0); 0x0070 = vmcnt(0) lgkmcnt(0);
+  //  expcnt and unnamed counters at their maxima)
+  const int nfull = kd >> 4;
+  const int nch = (kd + 15) >> 4;
+  tc_d2 La[4], Lb[4], Ha[4], Hb[4];
+  if (nch > 0) stage(0, 0, nfull);
+  if (nch > 1) stage(1, 1, nfull);
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __builtin_amdgcn_s_barrier();
+  if (active && nch > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      La[i] = rd(0, 0, i, 0);
+      Lb[i] = rd(0, 1, i, 0);
+    }
+  }
+  for (int c = 0; c < nch; ++c) {
+    const int st = c & 1;
     if (active) {
-      const int st = c % TC_UPD_STAGES;
-      tc_q4 fa[4], fb[4];
-      // low halves first: the MFMAs of k steps 0 and 1 can start while the
-      // high halves are still being read
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        fa[i].lo = frag(st, 0, i, 0);
-        fb[i].lo = frag(st, 1, i, 0);
+        Ha[i] = rd(st, 0, i, 1);
+        Hb[i] = rd(st, 1, i, 1);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        fa[i].hi = frag(st, 0, i, 1);
-        fb[i].hi = frag(st, 1, i, 1);
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = tc_mfma(tc_el(fa[i], m), tc_el(fb[j], m), acc[i][j]);
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = tc_mfma(m ? La[i].y : La[i].x, m ? Lb[j].y : Lb[j].x, acc[i][j]);
+    }
+    if (c + 1 < nch) {
+      // chunk c+1 has landed and this wave's reads of chunk c are complete;
+      // a plain barrier (a fenced one would also wait for unrelated traffic)
+      __builtin_amdgcn_s_waitcnt(0x0070);
+      __builtin_amdgcn_s_barrier();
+      if (c + 2 < nch) stage(st, c + 2, nfull);  // chunk c's stage is free now
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          La[i] = rd(st ^ 1, 0, i, 0);
+          Lb[i] = rd(st ^ 1, 1, i, 0);
+        }
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = tc_mfma(m ? Ha[i].y : Ha[i].x, m ? Hb[j].y : Hb[j].x, acc[i][j]);
     }
   }
   if (!active) return;

@@ -67,6 +67,8 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails val
     ((FAKE, 8, 8, 4, 2), 5, -1),      # unknown schedule
     ((None, 8, 8, 4, 0), 1, -1),      # NULL matrix
     ((FAKE, 1 << 20, 1 << 20, 1, 1), 4, -1),  # too many tiles for the async schedule
+    ((FAKE, 8, (1 << 20) + 1, 4, 0), 3, -1),  # lda beyond CHOL_MAX_N
+    ((FAKE, (1 << 20) + 1, (1 << 20) + 1, 4, 0), 2, -1),  # n beyond CHOL_MAX_N
 ])
 def test_factor_argument_checks(tc, args, bad_arg, code):
     A, n, lda, T, sched = args
