@@ -172,6 +172,12 @@ int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]);
  * error code. */
 int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int64_t cap);
 
+/* Write the units of the fork-join schedule's trailing-update launch of step
+ * J (the collapsed SYRK + GEMM launch, Methods, fork-join) in launch order,
+ * one workgroup per unit, 6 int32 each as above.  Writes min(cap, total)
+ * units; returns the total or a negative error code. */
+int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, int64_t cap);
+
 /* Number of persistent workgroups the asynchronous schedule launches on the
  * current device (co-resident capacity); < 0 on error.  Touches the device. */
 int64_t chol_async_grid(void);

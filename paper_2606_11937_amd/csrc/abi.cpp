@@ -241,6 +241,23 @@ int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int
   return k;
 }
 
+int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, int64_t cap) {
+  g_bad_arg = 0;
+  if (n < 1 || n > kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  const TcGeom g = tc_geom(n, T, 0);
+  if (J < 0 || J >= g.M) return bad(3);
+  if (cap < 0) return bad(5);
+  if (cap > 0 && out == nullptr) return bad(4);
+  const int64_t total = tc_trailing_units(g, (int32_t)J);
+  for (int64_t k = 0; k < total && k < cap; ++k) {
+    const TcUnit u = tc_decode_trailing(g, (int32_t)J, (int32_t)J, k);
+    int32_t* o = out + 6 * k;
+    o[0] = u.kind; o[1] = u.J; o[2] = u.I; o[3] = u.a; o[4] = u.K; o[5] = u.b;
+  }
+  return total;
+}
+
 int64_t chol_async_grid(void) {
   const int64_t g = tc_async_grid_size();
   return g > 0 ? g : CHOL_EDEVICE;

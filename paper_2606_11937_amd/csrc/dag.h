@@ -206,3 +206,4 @@ TC_HD void tc_task_counts(const TcGeom& g, int64_t c[4]) {
   c[2] = M * (M - 1) / 2;
   c[3] = M * (M - 1) * (M - 2) / 6;
 }
+

@@ -190,62 +190,100 @@ __device__ __forceinline__ void tc_unit_publish(const TcGeom& g, const TcWs& ws,
   }
 }
 
-__global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_async(double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
+// Loop-invariant launch state of the persistent kernel that is not a pointer.
+// It lives in LDS and is re-read on every pass (after a compiler-only memory
+// barrier) instead of being held in scalar registers across the unit bodies:
+// the update body alone needs nearly the whole register file, and state
+// carried around the loop would otherwise be spilled inside its inner loop.
+// The pointers stay kernel arguments so that the compiler still knows they
+// address global memory (a pointer read back from LDS would turn every access
+// into a flat instruction, which also counts against the LDS wait counter).
+struct TcCtx {
+  TcGeom g;
+  int64_t wait_ticks;
+  int64_t total;
+};
+
+__device__ __forceinline__ int64_t tc_ctx64(const int64_t& v) { return tc_uniform(v); }
+__device__ __forceinline__ int32_t tc_ctx32(const int32_t& v) { return tc_uniform(v); }
+
+__device__ __forceinline__ TcGeom tc_ctx_geom(const TcGeom& s) {
+  TcGeom g;
+  g.n = tc_ctx64(s.n);
+  g.T = tc_ctx64(s.T);
+  g.M = tc_ctx32(s.M);
+  g.SB = tc_ctx32(s.SB);
+  g.SBL = tc_ctx32(s.SBL);
+  g.NRB = tc_ctx32(s.NRB);
+  g.Q = tc_ctx64(s.Q);
+  return g;
+}
+
+__global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_async(
+    double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
   __shared__ TcSmem sm;
   __shared__ int64_t offs[TC_MAX_PHASES + 1];
-  __shared__ int64_t s_ticket;
+  __shared__ TcCtx s_ctx;
+  __shared__ TcUnit s_unit;
   __shared__ int32_t s_go;
   for (int i = threadIdx.x; i <= g.M; i += TC_THREADS) offs[i] = ws.offs[i];
+  if (threadIdx.x == 0) {
+    s_ctx.g = g;
+    s_ctx.wait_ticks = wait_ticks;
+    s_unit.kind = -1;
+  }
   __syncthreads();
-  // Everything that steers this loop is made wave-uniform (tc_uniform), so
-  // all waves run the same sequence of barriers.
-  const int64_t total = tc_uniform(offs[g.M]);
-  // The previous unit is published by thread 0 right before it fetches the
-  // next ticket, in one branch between two barriers.  Keeping the publish and
-  // the fetch in a single thread-0 region (rather than one at the end of the
-  // loop and one at its start) leaves the compiler no pair of identical
-  // thread-0 conditions to thread into a second, divergent inner loop that
-  // would run barriers without thread 0.
-  TcUnit prev = {-1, -1, -1, -1, -1, -1};
+  if (threadIdx.x == 0) s_ctx.total = offs[g.M];
+  __syncthreads();
   for (;;) {
+    // nothing read from LDS before this point is reused after it
+    asm volatile("" ::: "memory");
+    // Thread 0 alone publishes the previous unit, takes the next ticket,
+    // decodes it and waits for its inputs, all in one branch between two
+    // barriers.  One thread-0 region per pass leaves the compiler no pair of
+    // identical thread-0 conditions to thread into a second, divergent inner
+    // loop that would run barriers without thread 0.
     if (threadIdx.x == 0) {
-      if (prev.kind >= 0 && !tc_err_set(ws.hdr)) tc_unit_publish(g, ws, prev);
-      s_ticket = __hip_atomic_fetch_add(&ws.hdr->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const int64_t t = tc_uniform(s_ticket);
-    if (t >= total) break;
-    // phase of ticket t: last P with offs[P] <= t
-    int32_t lo = 0, hi = g.M - 1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (tc_uniform(offs[mid]) <= t) lo = mid; else hi = mid - 1;
-    }
-    const TcUnit u = tc_decode_in_phase(g, lo, t - tc_uniform(offs[lo]));
-    if (threadIdx.x == 0) {
-      int32_t go = 1;
-      const uint64_t t0 = wall_clock64();
-      while (!tc_unit_ready(g, ws, u)) {
-        if (tc_err_set(ws.hdr)) { go = 0; break; }
-        if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(ws.hdr, 2, 0); go = 0; break; }
-        __builtin_amdgcn_s_sleep(1);
+      const TcGeom cg = s_ctx.g;
+      const TcUnit prev = s_unit;
+      if (prev.kind >= 0 && !tc_err_set(ws.hdr)) tc_unit_publish(cg, ws, prev);
+      const int64_t t = __hip_atomic_fetch_add(&ws.hdr->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int32_t go = 0;
+      if (t < s_ctx.total) {
+        // phase of ticket t: last P with offs[P] <= t
+        int32_t lo = 0, hi = cg.M - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (offs[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const TcUnit u = tc_decode_in_phase(cg, lo, t - offs[lo]);
+        go = 1;
+        const uint64_t t0 = wall_clock64();
+        while (!tc_unit_ready(cg, ws, u)) {
+          if (tc_err_set(ws.hdr)) { go = 0; break; }
+          if (wall_clock64() - t0 > (uint64_t)s_ctx.wait_ticks) { tc_report_fail(ws.hdr, 2, 0); go = 0; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_unit = u;
       }
-      if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_go = go;
     }
     __syncthreads();
     if (!tc_uniform(s_go)) break;
+    const TcUnit u = {tc_ctx32(s_unit.kind), tc_ctx32(s_unit.J), tc_ctx32(s_unit.I),
+                      tc_ctx32(s_unit.a), tc_ctx32(s_unit.K), tc_ctx32(s_unit.b)};
+    const TcGeom cg = tc_ctx_geom(s_ctx.g);
     if (u.kind == TC_UNIT_UPDATE) {
-      tc_run_update(A, lda, g, u, sm);
+      tc_run_update(A, lda, cg, u, sm);
     } else if (u.kind == TC_UNIT_TRSM) {
-      tc_run_trsm(A, lda, g, u.I, u.a, u.J, sm);
+      tc_run_trsm(A, lda, cg, u.I, u.a, u.J, sm);
     } else {
-      tc_run_potrf(A, lda, g, u.J, ws.hdr, sm);
+      tc_run_potrf(A, lda, cg, u.J, ws.hdr, sm);
     }
     // every wave makes its stores visible device-wide before the unit is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    prev = u;
   }
 }
 

@@ -31,6 +31,16 @@ typedef double tc_d2 __attribute__((ext_vector_type(2), aligned(8)));
 // Values read from LDS that steer loops or branches containing barriers go
 // through these, so the compiler sees the control flow as uniform and keeps
 // every wave's barrier sequence identical to the source.
+// Thread index behind a compiler-only barrier.  Tile bodies derive their
+// lane offsets from it, so the persistent kernel recomputes them at the start
+// of each body instead of hoisting them out of its unit loop, where they would
+// stay live (and spill) across the other bodies.
+__device__ __forceinline__ int tc_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ int32_t tc_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int64_t tc_uniform(int64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(uint64_t)v);
@@ -105,7 +115,7 @@ __device__ __forceinline__ int tc_swz(int r) { return r & 7; }
 __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const double* __restrict__ PA,
                                                 const double* __restrict__ PB, int64_t lda, int mr, int mc,
                                                 int kd, bool diag, TcUpdSmem& sm) {
-  const int tid = threadIdx.x;
+  const int tid = tc_tid();
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -252,7 +262,7 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ tc_v4d tc_nt16(const double* __restrict__ X, int xr, const double* __restrict__ Y,
                                           int yr, int64_t lda, int kd) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tc_tid() & 63;
   const int r16 = lane & 15, s4 = (lane >> 4) * 4;
   const double* px = X + (int64_t)(r16 < xr ? r16 : xr - 1) * lda + s4;
   const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
@@ -279,7 +289,7 @@ __device__ __forceinline__ tc_v4d tc_nt16(const double* __restrict__ X, int xr, 
 
 // Scatter a 16 x 16 MFMA result into a row-major LDS buffer (ld 17).
 __device__ __forceinline__ void tc_acc_to_lds(double* buf, tc_v4d acc) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tc_tid() & 63;
   const int orow = lane >> 4, ocol = lane & 15;
 #pragma unroll
   for (int q = 0; q < 4; ++q) buf[(4 * q + orow) * 17 + ocol] = acc[q];
@@ -315,7 +325,7 @@ struct TcTrsmSmem {
 
 __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
                               TcTrsmSmem& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
   const int row0 = w * 32;
   for (int c0 = 0; c0 < td; c0 += 16) {
     const int nb = td - c0 < 16 ? td - c0 : 16;
@@ -368,7 +378,7 @@ struct TcPotrfSmem {
 };
 
 __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
   if (tid == 0) sm.fail = -1;
   __syncthreads();
   for (int c0 = 0; c0 < td; c0 += 16) {

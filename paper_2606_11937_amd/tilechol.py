@@ -42,6 +42,7 @@ SIGNATURES = [
     ("chol_default_tile", _i64, [_i64]),
     ("chol_dag_counts", _int, [_i64, _i64, _pi64]),
     ("chol_dag_enumerate", _i64, [_i64, _i64, _i64, _pi32, _i64]),
+    ("chol_dag_forkjoin_update", _i64, [_i64, _i64, _i64, _pi32, _i64]),
     ("chol_async_grid", _i64, []),
     ("chol_set_wait_limit", _dbl, [_dbl]),
     ("chol_last_bad_arg", _int, []),
@@ -224,6 +225,17 @@ def chol_dag_enumerate(n: int, T: int, grid: int = 256):
     out = np.zeros((total, 6), dtype=np.int32)
     got = lib.chol_dag_enumerate(n, T, grid, out.ctypes.data_as(_pi32), total)
     assert got == total
+    return out
+
+
+def chol_dag_forkjoin_update(n: int, T: int, J: int):
+    """Units of the fork-join trailing-update launch of step J, launch order."""
+    import numpy as np
+    total = int(lib.chol_dag_forkjoin_update(n, T, J, None, 0))
+    if total < 0:
+        raise TileCholError(total, "chol_dag_forkjoin_update", last_bad_arg())
+    out = np.zeros((total, 6), dtype=np.int32)
+    lib.chol_dag_forkjoin_update(n, T, J, out.ctypes.data_as(_pi32), total)
     return out
 
 

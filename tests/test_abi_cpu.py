@@ -257,3 +257,23 @@ def _program_order_units(g):
                             continue
                         out.append((dm.UPDATE, J, I, a, K, b))
     return np.array(out, dtype=np.int32)
+
+
+@pytest.mark.parametrize("n,T", CASES)
+def test_forkjoin_update_launch_covers_each_step(tc, n, T):
+    """The launch order of each fork-join trailing update visits
+    every lower output block of the step's trailing matrix exactly once."""
+    g = dm.Geom(n, T)
+    for J in range(g.M):
+        got = tc.chol_dag_forkjoin_update(n, T, J)
+        keys = [tuple(int(x) for x in u) for u in got]
+        assert len(keys) == len(set(keys))
+        expect = set()
+        for I in range(J + 1, g.M):
+            for K in range(J + 1, I + 1):
+                for a in range(g.sb(I)):
+                    for b in range(g.sb(K)):
+                        if I == K and b > a:
+                            continue
+                        expect.add((dm.UPDATE, J, I, a, K, b))
+        assert set(keys) == expect, J
