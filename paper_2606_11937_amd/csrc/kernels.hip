@@ -93,7 +93,7 @@ __device__ __forceinline__ void tc_report_fail(TcWsHeader* h, int32_t code, int6
 }
 
 // ------------------------------------------------------------ unit runners
-union TcSmem {
+union alignas(512) TcSmem {
   TcTrsmSmem trsm;
   TcPotrfSmem potrf;
   TcUpdSmem upd;

@@ -103,7 +103,11 @@ __device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
 // fragment set and a 64 KB stage pair let two workgroups share a CU.
 // ---------------------------------------------------------------------------
 #define TC_UPD_STAGES 2
-struct TcUpdSmem {
+// The swizzle below is conflict-free only relative to a bank-period-aligned
+// base, and the 128-bit reads need 16-byte alignment: the stages are placed
+// on a 512-byte boundary wherever the struct is declared (alone, or inside the
+// persistent kernel's union next to other shared variables).
+struct alignas(512) TcUpdSmem {
   double tile[TC_UPD_STAGES][2][128 * 16];  // [stage][A|B][row * 16 + slot * 2 + e]
 };
 
