@@ -299,19 +299,129 @@ __device__ __forceinline__ void tc_acc_to_lds(double* buf, tc_v4d acc) {
   for (int q = 0; q < 4; ++q) buf[(4 * q + orow) * 17 + ocol] = acc[q];
 }
 
-// Forward substitution of one row against a factored nb x nb diagonal block
-// held in LDS (Lc, ld 17):  x_j = (v_j - sum_{q<j} x_q Lc[j][q]) / Lc[j][j].
-// v holds the row on entry, x on exit.  Sequential in q (ascending).
-__device__ __forceinline__ void tc_subst_row(double v[16], const double* Lc, int nb) {
+// Left-looking MFMA products of up to 64 rows (four 16-row groups):
+//   P[r][j] = sum over the 16-wide k chunks c of `par` of X[r][k] Y[j][k],
+// r < 64 (X rows clamped to xr valid rows), j < 16 (Y rows clamped to yr),
+// k < kd with kd % 16 == 0.  par = 0 takes the even chunks, 1 the odd ones
+// and -1 all of them, accumulated as even + odd (the two sums kept apart and
+// added at the end, the same arithmetic whichever waves compute them).  The
+// result goes to LDS as 64 rows of ld 17.  The Y fragment is shared by the
+// four groups, whose independent MFMA chains hide each other's latency.
+__device__ __forceinline__ void tc_nt64(const double* __restrict__ X, int xr, const double* __restrict__ Y, int yr,
+                                        int64_t lda, int kd, int par, double* buf) {
+  const int lane = tc_tid() & 63;
+  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
+  const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
+  const double* px[4];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (j < nb) {
-      double s = v[j];
+  for (int g = 0; g < 4; ++g) {
+    const int r = 16 * g + r16;
+    px[g] = X + (int64_t)(r < xr ? r : xr - 1) * lda + s4;
+  }
+  tc_v4d e[4], o[4];
 #pragma unroll
-      for (int q = 0; q < j; ++q) s = s - v[q] * Lc[j * 17 + q];
-      v[j] = s / Lc[j * 17 + j];
+  for (int g = 0; g < 4; ++g) {
+    e[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
+    o[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  const int nch = kd >> 4;
+  const int step = par < 0 ? 1 : 2;
+  for (int c = par < 0 ? 0 : par; c < nch; c += step) {
+    const tc_q4 y0 = tc_ld4(py + 16 * c);
+    tc_q4 x0[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) x0[g] = tc_ld4(px[g] + 16 * c);
+    if (c & 1) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) o[g] = tc_mfma(tc_el(x0[g], m), tc_el(y0, m), o[g]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) e[g] = tc_mfma(tc_el(x0[g], m), tc_el(y0, m), e[g]);
     }
   }
+  if (par < 0) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) e[g] = e[g] + o[g];
+  } else if (par == 1) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) e[g] = o[g];
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) tc_acc_to_lds(buf + g * 16 * 17, e[g]);
+}
+
+// The factored 16 x 16 diagonal block is kept in LDS transposed, one column
+// of L per TC_LT-double row (16-byte aligned): Lt[j * TC_LT + i] = L[i][j]
+// for i >= j, zero above; Lt[j * TC_LT + 16] holds 1 / L[j][j].  Columns j
+// past the block's order nb hold a unit diagonal, so a substitution can run
+// all 16 steps unconditionally (their values stay zero).  The values one
+// step needs are contiguous and every lane reads the same address.
+#define TC_LT 18
+
+// x / d from the correctly rounded reciprocal r = 1 / d and one residual
+// correction (Markstein's method): q0 = x r, e = x - q0 d (exact with an
+// FMA), q = q0 + e r.  The result is exact whenever x / d is representable
+// and otherwise within one unit in the last place of the rounded quotient.
+// It takes three dependent operations instead of a full division.
+__device__ __forceinline__ double tc_div_rcp(double x, double d, double r) {
+  const double q0 = x * r;
+  const double e = __builtin_fma(-q0, d, x);
+  return __builtin_fma(e, r, q0);
+}
+
+// Forward substitution of one row against the factored diagonal block:
+//   x_j = (v_j - sum_{q<j} x_q L[j][q]) / L[j][j].
+// v holds the row on entry, x on exit (entries past nb are zero on entry and
+// stay zero).  Column-oriented: step j finishes x_j and then subtracts
+// x_j L[i][j] from every later v_i, so each v_i receives the subtractions of
+// the row-oriented form in the same ascending order of q; the column of L
+// for step j + 1 is read while step j computes.
+__device__ __forceinline__ void tc_subst_row(double v[16], const double* Lt) {
+  double cur[17];
+#pragma unroll
+  for (int i = 0; i < 17; ++i) cur[i] = Lt[i];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    // a compiler-only barrier per step that also pins the previous result:
+    // the LDS loads of column j + 1 may overlap step j, but neither loads are
+    // hoisted nor arithmetic sunk across steps (each column held in registers
+    // costs 34 of them)
+    if (j > 0) asm volatile("" : "+v"(v[j - 1]) : : "memory");
+    double nxt[17];
+    if (j + 1 < 16) {
+#pragma unroll
+      for (int i = j + 1; i < 17; ++i) nxt[i] = Lt[(j + 1) * TC_LT + i];
+    }
+    v[j] = tc_div_rcp(v[j], cur[j], cur[16]);
+#pragma unroll
+    for (int i = j + 1; i < 16; ++i) v[i] = v[i] - v[j] * cur[i];
+    if (j + 1 < 16) {
+#pragma unroll
+      for (int i = j + 1; i < 17; ++i) cur[i] = nxt[i];
+    }
+  }
+}
+
+// Stage the lower nb x nb part of the 16 x 16 block at B (row-major, ld lda)
+// into Lt (transposed, zero-filled, unit diagonal past nb, reciprocals of
+// the diagonal); all TC_THREADS threads take part.
+__device__ __forceinline__ void tc_stage_lt(double* Lt, const double* B, int64_t lda, int nb) {
+  const int tid = tc_tid();
+  const int i = tid >> 4, j = tid & 15;
+  const double val = (i < nb && j <= i) ? B[(int64_t)i * lda + j] : (i == j ? 1.0 : 0.0);
+  Lt[j * TC_LT + i] = val;
+  if (i == j) Lt[j * TC_LT + 16] = 1.0 / val;
+}
+
+__device__ __forceinline__ double tc_readlane(double v, int l) {
+  const int64_t b = __builtin_bit_cast(int64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(uint64_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)b >> 32), l);
+  return __builtin_bit_cast(double, (int64_t)(((uint64_t)hi << 32) | lo));
 }
 
 // ---------------------------------------------------------------------------
@@ -319,46 +429,41 @@ __device__ __forceinline__ void tc_subst_row(double v[16], const double* Lc, int
 // with L = L_JJ (td x td, factored).  Left-looking over 16-column blocks:
 // for each block c0, v = X[:, c0:c0+16] - X[:, :c0] L[c0:c0+16, :c0]^T (MFMA),
 // then forward substitution against the 16 x 16 diagonal block of L.
-// Wave w owns rows 32w .. 32w+31 (two 16-row MFMA groups).
-// LDS: 4 waves x 32 x 17 doubles + 16 x 17 doubles.
+// Waves 0 and 1 own rows 0..63 and 64..127: they form the even-chunk part of
+// the products of their rows and substitute them, one row per lane; waves 2
+// and 3 form the odd-chunk part of the same rows.  A row's 16 inputs are
+// fetched before the products so that their latency hides behind them.
 // ---------------------------------------------------------------------------
-struct TcTrsmSmem {
-  double buf[4][32 * 17];
-  double Lc[16 * 17];
+struct alignas(16) TcTrsmSmem {
+  double buf[4][64 * 17];  // [wave] products: even chunks (waves 0, 1), odd (2, 3)
+  double Lt[16 * TC_LT];
 };
 
 __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
                               TcTrsmSmem& sm) {
   const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
-  const int row0 = w * 32;
+  const int half = w & 1;
+  const int row0 = half * 64;
+  const int nrows = mr - row0 < 64 ? mr - row0 : 64;  // rows of this half (may be <= 0)
+  const bool mine = w < 2 && lane < nrows;
+  double* xr0 = X + (int64_t)(row0 + (mine ? lane : 0)) * lda;
   for (int c0 = 0; c0 < td; c0 += 16) {
     const int nb = td - c0 < 16 ? td - c0 : 16;
-    // stage the diagonal block L[c0.., c0..] (lower part; rest zero)
-    {
-      const int i = tid >> 4, j = tid & 15;
-      sm.Lc[i * 17 + j] = (i < nb && j <= i) ? L[(int64_t)(c0 + i) * lda + c0 + j] : 0.0;
-    }
-    // left-looking products for this wave's two row groups
-    if (row0 < mr) {
+    double v[16];
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        const int rr = row0 + 16 * g;
-        tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
-        if (rr < mr && c0 > 0) acc = tc_nt16(X + (int64_t)rr * lda, mr - rr, L + (int64_t)c0 * lda, nb, lda, c0);
-        tc_acc_to_lds(&sm.buf[w][g * 16 * 17], acc);
-      }
-    }
+    for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr0[c0 + j] : 0.0;
+    tc_stage_lt(sm.Lt, L + (int64_t)c0 * lda + c0, lda, nb);
+    if (nrows > 0 && c0 > 0)
+      tc_nt64(X + (int64_t)row0 * lda, nrows, L + (int64_t)c0 * lda, nb, lda, c0, w >> 1, sm.buf[w]);
     __syncthreads();
-    if (lane < 32 && row0 + lane < mr) {
-      const int r = row0 + lane;
-      double* xr = X + (int64_t)r * lda + c0;
-      double v[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = j < nb ? xr[j] - sm.buf[w][lane * 17 + j] : 0.0;
-      tc_subst_row(v, sm.Lc, nb);
+    if (mine) {
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        if (j < nb) xr[j] = v[j];
+        if (j < nb && c0 > 0) v[j] = v[j] - (sm.buf[half][lane * 17 + j] + sm.buf[half + 2][lane * 17 + j]);
+      tc_subst_row(v, sm.Lt);
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < nb) xr0[c0 + j] = v[j];
     }
     __syncthreads();
   }
@@ -368,16 +473,20 @@ __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const doub
 // POTRF work unit: in-place lower Cholesky of the td x td diagonal tile D.
 // Left-looking over 16-column blocks c0:
 //   1. wave 0: diagonal group v = D[c0:, c0:] - D[c0:, :c0] D[c0:, :c0]^T
-//      (16 x 16, MFMA), factored unblocked in LDS (right-looking, sequential
-//      over the column, the POTRF definition on a 16 x 16 block);
-//   2. all waves: the 16-row groups below, MFMA products then forward
-//      substitution against the new diagonal block (the in-tile TRSM).
+//      (16 x 16, MFMA), then the unblocked factorization of that block in
+//      registers (right-looking, sequential over the column, the POTRF
+//      definition on a 16 x 16 block): lane i holds row i, and the pivot
+//      and the column entries each step needs are read from their owner
+//      lanes;
+//   2. all waves: the rows below, 64 per wave at a time (one per lane):
+//      MFMA products, then forward substitution against the new diagonal
+//      block (the in-tile TRSM).
 // A pivot d <= 0 or NaN stops the factorization: returns the 0-based
 // in-tile column, else -1.
 // ---------------------------------------------------------------------------
-struct TcPotrfSmem {
-  double buf[4][16 * 17];
-  double Lc[16 * 17];
+struct alignas(16) TcPotrfSmem {
+  double buf[4][64 * 17];
+  double Lt[16 * TC_LT];
   int fail;
 };
 
@@ -389,78 +498,84 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
     const int nb = td - c0 < 16 ? td - c0 : 16;
     double* Dc = D + (int64_t)c0 * lda;  // row c0
     if (w == 0) {
+      const bool own = lane < nb;
+      const double* dr = Dc + (int64_t)(own ? lane : 0) * lda + c0;
+      double a[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a[k] = (own && k <= lane) ? dr[k] : 0.0;
       tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
       if (c0 > 0) acc = tc_nt16(Dc, nb, Dc, nb, lda, c0);
       tc_acc_to_lds(sm.buf[0], acc);
-    }
-    __syncthreads();
-    if (tid < 256) {
-      const int i = tid >> 4, j = tid & 15;
-      sm.Lc[i * 17 + j] = (i < nb && j <= i) ? Dc[(int64_t)i * lda + c0 + j] - sm.buf[0][i * 17 + j] : 0.0;
-    }
-    __syncthreads();
-    // unblocked factorization of the 16 x 16 block by wave 0, column by column
-    if (w == 0) {
-      const int i = lane >> 2;        // row handled (16 rows x 4 lanes)
-      const int kq = lane & 3;        // this lane updates columns k = kq, kq+4, ...
-      for (int j = 0; j < nb; ++j) {
-        const double d = tc_uniform(sm.Lc[j * 17 + j]);
-        const bool ok = d > 0.0;
-        if (!ok) {
-          if (lane == 0 && sm.fail < 0) sm.fail = c0 + j;
-          break;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (own && k <= lane) a[k] = a[k] - sm.buf[0][lane * 17 + k];
+      // unblocked factorization; every branch below is wave-uniform
+      int bad = -1;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double rj = 1.0;
+        if (j < nb && bad < 0) {
+          const double d = tc_readlane(a[j], j);
+          if (!(d > 0.0)) {
+            bad = j;
+          } else {
+            const double ljj = sqrt(d);
+            rj = 1.0 / ljj;
+            if (lane == j) a[j] = ljj;
+            else if (lane > j) a[j] = tc_div_rcp(a[j], ljj, rj);
+            // trailing update a_ik -= l_ij l_kj for j < k <= i
+#pragma unroll
+            for (int k = j + 1; k < 16; ++k) {
+              const double lkj = tc_readlane(a[j], k);
+              if (lane >= k) a[k] = a[k] - a[j] * lkj;
+            }
+          }
         }
-        const double ljj = sqrt(d);
-        __builtin_amdgcn_wave_barrier();
-        // column j below the diagonal; lane (i, kq==0) owns l_ij
-        double lij = 0.0;
-        if (i > j && i < nb) lij = sm.Lc[i * 17 + j] / ljj;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_s_waitcnt(0);
-        if (kq == 0) {
-          if (i == j) sm.Lc[j * 17 + j] = ljj;
-          else if (i > j && i < nb) sm.Lc[i * 17 + j] = lij;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // trailing update a_ik -= l_ij l_kj for j < k <= i
-        if (i > j && i < nb) {
-          for (int k = j + 1 + ((kq - (j + 1)) & 3); k <= i; k += 4)
-            sm.Lc[i * 17 + k] = sm.Lc[i * 17 + k] - lij * sm.Lc[k * 17 + j];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) sm.Lt[j * TC_LT + 16] = rj;
+      }
+      if (lane == 0 && bad >= 0) sm.fail = c0 + bad;
+      if (lane < 16) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          sm.Lt[k * TC_LT + lane] = (own && k <= lane) ? a[k] : (k == lane ? 1.0 : 0.0);
+      }
+      if (own && bad < 0) {
+        double* o = Dc + (int64_t)lane * lda + c0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k <= lane) o[k] = a[k];
       }
     }
     __syncthreads();
     const int fail = tc_uniform((int32_t)sm.fail);
     if (fail >= 0) return fail;
-    // write the factored diagonal block back
-    {
-      const int i = tid >> 4, j = tid & 15;
-      if (i < nb && j <= i) Dc[(int64_t)i * lda + c0 + j] = sm.Lc[i * 17 + j];
-    }
-    // rows below the diagonal block, one 16-row group per wave at a time
-    const int ngroups = (td - c0 - nb + 15) / 16;
-    for (int gbase = 0; gbase < ngroups; gbase += 4) {
-      const int g = gbase + w;
-      const int r0 = c0 + nb + 16 * g;
-      if (g < ngroups) {
-        const int rows = td - r0 < 16 ? td - r0 : 16;
-        tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
-        if (c0 > 0) acc = tc_nt16(D + (int64_t)r0 * lda, rows, Dc, nb, lda, c0);
-        tc_acc_to_lds(sm.buf[w], acc);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < rows) {
-          double* xr = D + (int64_t)(r0 + lane) * lda + c0;
-          double v[16];
+    // rows below the diagonal block, 64 per wave at a time
+    const int below = td - c0 - nb;
+    for (int rb = 0; rb < below; rb += 256) {
+      const int rw0 = c0 + nb + rb + 64 * w;
+      const int myrows = td - rw0 < 64 ? td - rw0 : 64;
+      if (myrows > 0) {
+        const bool mine = lane < myrows;
+        double* xr = D + (int64_t)(rw0 + (mine ? lane : 0)) * lda + c0;
+        double v[16];
 #pragma unroll
-          for (int j = 0; j < 16; ++j) v[j] = j < nb ? xr[j] - sm.buf[w][lane * 17 + j] : 0.0;
-          tc_subst_row(v, sm.Lc, nb);
+        for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr[j] : 0.0;
+        if (c0 > 0) {
+          tc_nt64(D + (int64_t)rw0 * lda, myrows, Dc, nb, lda, c0, -1, sm.buf[w]);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (mine) {
+          if (c0 > 0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (j < nb) v[j] = v[j] - sm.buf[w][lane * 17 + j];
+          }
+          tc_subst_row(v, sm.Lt);
 #pragma unroll
           for (int j = 0; j < 16; ++j)
             if (j < nb) xr[j] = v[j];
