@@ -260,35 +260,48 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 }
 
 // ---------------------------------------------------------------------------
-// Left-looking MFMA accumulation for one 16 x 16 output group:
-//   acc[r][j] = sum_{t < kd} X[r][t] * Y[j][t],  r < 16 (rows of X), j < 16
-// X rows clamped to xr valid rows, Y rows to yr valid rows; kd % 16 == 0.
+// Left-looking MFMA products of G 16-row groups against one 16-row group:
+//   acc[g][r][j] += sum over the 16-wide k chunks c = cs, cs + step, ... < kd/16
+//                   of X[16 g + r][k] Y[j][k],
+// X rows clamped to xr valid rows, Y rows to yr valid rows, kd % 16 == 0.
+// Each group has one accumulator, so a group's sum runs over its chunks in
+// ascending order; splitting the chunks of a product over several waves
+// (cs = wave, step = number of waves) gives partial sums that the caller adds
+// in a fixed order.  The Y fragment is shared by the G groups, whose
+// independent MFMA chains hide one another's latency, and the loads of the
+// next chunk are issued before the MFMAs of the current one.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ tc_v4d tc_nt16(const double* __restrict__ X, int xr, const double* __restrict__ Y,
-                                          int yr, int64_t lda, int kd) {
+template <int G>
+__device__ __forceinline__ void tc_ntg(const double* __restrict__ X, int xr, const double* __restrict__ Y, int yr,
+                                       int64_t lda, int kd, int cs, int step, tc_v4d acc[G]) {
   const int lane = tc_tid() & 63;
   const int r16 = lane & 15, s4 = (lane >> 4) * 4;
-  const double* px = X + (int64_t)(r16 < xr ? r16 : xr - 1) * lda + s4;
   const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
-  tc_v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int k0 = 0;
-  // two independent accumulators over alternating chunks keep two MFMA chains
-  // in flight; they are summed at the end (fixed order).
-  for (; k0 + 32 <= kd; k0 += 32) {
-    tc_q4 x0 = tc_ld4(px + k0), y0 = tc_ld4(py + k0);
-    tc_q4 x1 = tc_ld4(px + k0 + 16), y1 = tc_ld4(py + k0 + 16);
+  const double* px[G];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      acc0 = tc_mfma(tc_el(x0, m), tc_el(y0, m), acc0);
-      acc1 = tc_mfma(tc_el(x1, m), tc_el(y1, m), acc1);
-    }
+  for (int g = 0; g < G; ++g) {
+    const int r = 16 * g + r16;
+    px[g] = X + (int64_t)(r < xr ? r : xr - 1) * lda + s4;
   }
-  if (k0 < kd) {
-    tc_q4 x0 = tc_ld4(px + k0), y0 = tc_ld4(py + k0);
+  const int nch = kd >> 4;
+  if (cs >= nch) return;
+  tc_q4 y = tc_ld4(py + 16 * cs), x[G];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc0 = tc_mfma(tc_el(x0, m), tc_el(y0, m), acc0);
+  for (int g = 0; g < G; ++g) x[g] = tc_ld4(px[g] + 16 * cs);
+  for (int c = cs; c < nch; c += step) {
+    const int cn = c + step < nch ? c + step : c;  // the last pass re-reads its own chunk
+    const tc_q4 yn = tc_ld4(py + 16 * cn);
+    tc_q4 xn[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) xn[g] = tc_ld4(px[g] + 16 * cn);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[g] = tc_mfma(tc_el(x[g], m), tc_el(y, m), acc[g]);
+    y = yn;
+#pragma unroll
+    for (int g = 0; g < G; ++g) x[g] = xn[g];
   }
-  return acc0 + acc1;
 }
 
 // Scatter a 16 x 16 MFMA result into a row-major LDS buffer (ld 17).
@@ -299,59 +312,16 @@ __device__ __forceinline__ void tc_acc_to_lds(double* buf, tc_v4d acc) {
   for (int q = 0; q < 4; ++q) buf[(4 * q + orow) * 17 + ocol] = acc[q];
 }
 
-// Left-looking MFMA products of up to 64 rows (four 16-row groups):
-//   P[r][j] = sum over the 16-wide k chunks c of `par` of X[r][k] Y[j][k],
-// r < 64 (X rows clamped to xr valid rows), j < 16 (Y rows clamped to yr),
-// k < kd with kd % 16 == 0.  par = 0 takes the even chunks, 1 the odd ones
-// and -1 all of them, accumulated as even + odd (the two sums kept apart and
-// added at the end, the same arithmetic whichever waves compute them).  The
-// result goes to LDS as 64 rows of ld 17.  The Y fragment is shared by the
-// four groups, whose independent MFMA chains hide each other's latency.
-__device__ __forceinline__ void tc_nt64(const double* __restrict__ X, int xr, const double* __restrict__ Y, int yr,
-                                        int64_t lda, int kd, int par, double* buf) {
-  const int lane = tc_tid() & 63;
-  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
-  const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
-  const double* px[4];
+// The G-group products of tc_ntg written to LDS as 16 G rows of ld 17.
+template <int G>
+__device__ __forceinline__ void tc_ntg_lds(const double* __restrict__ X, int xr, const double* __restrict__ Y,
+                                           int yr, int64_t lda, int kd, int cs, int step, double* buf) {
+  tc_v4d acc[G];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int r = 16 * g + r16;
-    px[g] = X + (int64_t)(r < xr ? r : xr - 1) * lda + s4;
-  }
-  tc_v4d e[4], o[4];
+  for (int g = 0; g < G; ++g) acc[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
+  tc_ntg<G>(X, xr, Y, yr, lda, kd, cs, step, acc);
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    e[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
-    o[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
-  }
-  const int nch = kd >> 4;
-  const int step = par < 0 ? 1 : 2;
-  for (int c = par < 0 ? 0 : par; c < nch; c += step) {
-    const tc_q4 y0 = tc_ld4(py + 16 * c);
-    tc_q4 x0[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) x0[g] = tc_ld4(px[g] + 16 * c);
-    if (c & 1) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) o[g] = tc_mfma(tc_el(x0[g], m), tc_el(y0, m), o[g]);
-    } else {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) e[g] = tc_mfma(tc_el(x0[g], m), tc_el(y0, m), e[g]);
-    }
-  }
-  if (par < 0) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) e[g] = e[g] + o[g];
-  } else if (par == 1) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) e[g] = o[g];
-  }
-#pragma unroll
-  for (int g = 0; g < 4; ++g) tc_acc_to_lds(buf + g * 16 * 17, e[g]);
+  for (int g = 0; g < G; ++g) tc_acc_to_lds(buf + g * 16 * 17, acc[g]);
 }
 
 // The factored 16 x 16 diagonal block is kept in LDS transposed, one column
@@ -454,7 +424,7 @@ __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const doub
     for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr0[c0 + j] : 0.0;
     tc_stage_lt(sm.Lt, L + (int64_t)c0 * lda + c0, lda, nb);
     if (nrows > 0 && c0 > 0)
-      tc_nt64(X + (int64_t)row0 * lda, nrows, L + (int64_t)c0 * lda, nb, lda, c0, w >> 1, sm.buf[w]);
+      tc_ntg_lds<4>(X + (int64_t)row0 * lda, nrows, L + (int64_t)c0 * lda, nb, lda, c0, w >> 1, 2, sm.buf[w]);
     __syncthreads();
     if (mine) {
 #pragma unroll
@@ -472,8 +442,9 @@ __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const doub
 // ---------------------------------------------------------------------------
 // POTRF work unit: in-place lower Cholesky of the td x td diagonal tile D.
 // Left-looking over 16-column blocks c0:
-//   1. wave 0: diagonal group v = D[c0:, c0:] - D[c0:, :c0] D[c0:, :c0]^T
-//      (16 x 16, MFMA), then the unblocked factorization of that block in
+//   1. diagonal group v = D[c0:, c0:] - D[c0:, :c0] D[c0:, :c0]^T (16 x 16,
+//      MFMA, the k chunks dealt to the four waves and their partial sums
+//      added in wave order), then by wave 0 the unblocked factorization in
 //      registers (right-looking, sequential over the column, the POTRF
 //      definition on a 16 x 16 block): lane i holds row i, and the pivot
 //      and the column entries each step needs are read from their owner
@@ -497,21 +468,23 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
   for (int c0 = 0; c0 < td; c0 += 16) {
     const int nb = td - c0 < 16 ? td - c0 : 16;
     double* Dc = D + (int64_t)c0 * lda;  // row c0
+    const bool own = w == 0 && lane < nb;
+    const double* dr = Dc + (int64_t)(own ? lane : 0) * lda + c0;
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a[k] = (own && k <= lane) ? dr[k] : 0.0;
+    // diagonal group products, the chunks dealt to the four waves
+    if (c0 > 0) tc_ntg_lds<1>(Dc, nb, Dc, nb, lda, c0, w, 4, sm.buf[w]);
+    __syncthreads();
     if (w == 0) {
-      const bool own = lane < nb;
-      const double* dr = Dc + (int64_t)(own ? lane : 0) * lda + c0;
-      double a[16];
+      if (c0 > 0) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) a[k] = (own && k <= lane) ? dr[k] : 0.0;
-      tc_v4d acc = {0.0, 0.0, 0.0, 0.0};
-      if (c0 > 0) acc = tc_nt16(Dc, nb, Dc, nb, lda, c0);
-      tc_acc_to_lds(sm.buf[0], acc);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (own && k <= lane) a[k] = a[k] - sm.buf[0][lane * 17 + k];
+        for (int k = 0; k < 16; ++k)
+          if (own && k <= lane) {
+            const int q = lane * 17 + k;
+            a[k] = a[k] - (((sm.buf[0][q] + sm.buf[1][q]) + sm.buf[2][q]) + sm.buf[3][q]);
+          }
+      }
       // unblocked factorization; every branch below is wave-uniform
       int bad = -1;
 #pragma unroll
@@ -564,7 +537,7 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
 #pragma unroll
         for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr[j] : 0.0;
         if (c0 > 0) {
-          tc_nt64(D + (int64_t)rw0 * lda, myrows, Dc, nb, lda, c0, -1, sm.buf[w]);
+          tc_ntg_lds<4>(D + (int64_t)rw0 * lda, myrows, Dc, nb, lda, c0, 0, 1, sm.buf[w]);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
