@@ -1,25 +1,32 @@
 """Benchmark of the FP64 tiled Cholesky hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--n 32768] [--T 512]
-                    [--sched async_dag|fork_join] [--no-cpu-baseline]
+                    [--sched fork_join|async_dag] [--no-cpu-baseline]
     python bench.py --sweep [--ns 8192,16384,32768] [--Ts 128,256,512,1024]
 
 A step is one pass of the whole hot path over one resident synthetic input:
-chol_factor (tiled right-looking factorization, all tile ops and the DAG
-schedule) followed by chol_solve of one right-hand side with the factor.
-The input is the squared-exponential kernel matrix on n points uniform in
-[0,1]^2 (lengthscale 0.1, nugget 1e-2), generated on the device; every step
-gets its own pre-built copy, so nothing but the hot path runs in the timed
-region.  value = (n^3/3) / step time in TFLOP/s.
+chol_factor (tiled right-looking factorization: every POTRF, TRSM, SYRK and
+GEMM tile operation and the schedule that orders them) followed by
+chol_solve of one right-hand side with the factor.  The input is the
+squared-exponential kernel matrix on n points uniform in [0,1]^2
+(lengthscale 0.1, nugget 1e-2), generated on the device; every step gets its
+own pre-built copy, so the timed region holds nothing but the hot path.
+value = (n^3/3) / mean step time, in TFLOP/s.
 
-The default run prints one JSON line (the contract line) with a `roofline`
-object for the dominant kernel and a `cpu_baseline` object (the CPU oracle
-timed on this host on a bounded sample).  --sweep prints one JSON line per
-(n, T, schedule) with factor-only medians and is not the contract line.
+The default run prints one JSON line (the contract line) with
+  roofline      the dominant kernel's algorithmic FP64 rate against the
+                MI355X FP64 matrix peak; the kernel's launch times come from
+                HIP events the library records on its own stream around each
+                launch during the timed steps (chol_timing_enable);
+  cpu_baseline  the CPU oracle timed on this host on a bounded sample.
+--sweep prints one JSON line per (n, T, schedule) with factor-only times
+(3 warm-ups, then the median of --reps runs with min and max); those lines
+are not the contract line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -31,17 +38,36 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Cholesky TFLOP/s (n^3/3) & served solves/s + p99 at bwd err<=1e-12"
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
-HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of the trailing-update kernel per launch, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE) over the default configuration, each
+# scaled by what the same counter reads for a plain copy of known size
+# (fetch x2.0, write x1.0).  `sources` is the SHA-256 of the kernel sources
+# the counters were taken with: if the sources differ, the figure no longer
+# describes this kernel and the line reports traffic as null.
+TRAFFIC = {
+    # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources)
+}
+KERNEL_SOURCES = ["paper_2606_11937_amd/csrc/tile_ops.h", "paper_2606_11937_amd/csrc/kernels.hip",
+                  "paper_2606_11937_amd/csrc/dag.h"]
+
+
+def sources_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--T", type=int, default=512)
-    p.add_argument("--sched", default="async_dag", choices=["async_dag", "fork_join"])
+    p.add_argument("--sched", default="fork_join", choices=["async_dag", "fork_join"])
     p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4096, help="order of the oracle's leading-block sample")
@@ -49,17 +75,31 @@ def parse():
     p.add_argument("--ns", default="8192,16384,32768")
     p.add_argument("--Ts", default="128,256,512,1024")
     p.add_argument("--scheds", default="fork_join,async_dag")
-    p.add_argument("--reps", type=int, default=3)
+    p.add_argument("--reps", type=int, default=20)
     return p.parse_args()
 
 
 def make_input(n: int):
-    import torch
     from paper_2606_11937_amd import inputs
     return inputs.se_kernel_device(n, seed=1, device="cuda")
 
 
-def time_factor(tc, A0, T, sched, reps):
+def update_flops(n: int, T: int) -> float:
+    """Algorithmic flops of all SYRK + GEMM tile operations (T^3 per SYRK,
+    2 T^3 per GEMM, on the tiles' actual sides when T does not divide n)."""
+    M = -(-n // T)
+    side = [min(T, n - I * T) for I in range(M)]
+    f = 0.0
+    for J in range(M):
+        t = side[J]
+        for I in range(J + 1, M):
+            f += side[I] * side[I] * t  # SYRK(I, J)
+            for K in range(J + 1, I):
+                f += 2.0 * side[I] * side[K] * t  # GEMM(I, K, J)
+    return f
+
+
+def time_factor(tc, A0, T, sched, reps, warm=3):
     """Median / min / max device time (ms) of chol_factor on fresh copies."""
     import torch
     n = A0.shape[0]
@@ -67,7 +107,7 @@ def time_factor(tc, A0, T, sched, reps):
     work = tc.factor_workspace(n, T, sched)
     st = torch.cuda.current_stream()
     times = []
-    for r in range(reps + 1):
+    for r in range(reps + warm):
         A.copy_(A0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
@@ -77,7 +117,7 @@ def time_factor(tc, A0, T, sched, reps):
         info = tc.chol_factor_info(work, st)
         if info != 0:
             raise RuntimeError(f"factor failed: info={info} (n={n} T={T} {sched})")
-        if r > 0:  # first call is a warmup
+        if r >= warm:
             times.append(e0.elapsed_time(e1))
     del A
     return statistics.median(times), min(times), max(times)
@@ -93,9 +133,10 @@ def sweep(args):
             for sched in args.scheds.split(","):
                 med, lo, hi = time_factor(tc, A0, T, sched, args.reps)
                 tf = n ** 3 / 3 / (med * 1e-3) / 1e12
-                print(json.dumps({"kind": "sweep", "n": n, "T": T, "sched": sched, "ms_median": round(med, 3),
-                                  "ms_min": round(lo, 3), "ms_max": round(hi, 3), "tflops": round(tf, 2),
-                                  "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)}), flush=True)
+                print(json.dumps({"kind": "sweep", "n": n, "T": T, "sched": sched, "reps": args.reps,
+                                  "ms_median": round(med, 3), "ms_min": round(lo, 3), "ms_max": round(hi, 3),
+                                  "tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)}),
+                      flush=True)
         del A0
         torch.cuda.empty_cache()
 
@@ -134,6 +175,8 @@ def main():
     g = torch.Generator(device="cpu").manual_seed(2)
     rhs = [torch.randn(n, args.nrhs, generator=g, dtype=torch.float64).cuda() for _ in range(K + W)]
     works = [tc.factor_workspace(n, T, sched) for _ in range(K + W)]
+    nb = tc.chol_solve_workspace_size(n, T, args.nrhs)
+    swork = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
     st = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
@@ -143,19 +186,23 @@ def main():
         tc.chol_factor(copies[i], T, sched, work=works[i], stream=st, sync=False)
         if ev is not None:
             ev[1].record(st)
-        tc.chol_solve(copies[i], rhs[i], T, stream=st)
+        tc.chol_solve(copies[i], rhs[i], T, work=swork, stream=st)
 
     for i in range(W):
         step(i)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tc.chol_timing_read(st)  # discard anything recorded before
+    tc.chol_timing_enable(True)
     torch.cuda.synchronize()
     t_start.record(st)
     for k in range(K):
         step(W + k, evs[k])
     t_end.record(st)
     torch.cuda.synchronize()
+    tc.chol_timing_enable(False)
+    launches = tc.chol_timing_read(st)
     total_ms = t_start.elapsed_time(t_end)
     factor_ms = [a.elapsed_time(b) for a, b in evs]
     print(f"[bench] timed {K} steps: {total_ms:.2f} ms; factor ms {['%.2f' % x for x in factor_ms]}",
@@ -167,20 +214,38 @@ def main():
     ms_step = total_ms / K
     flops = n ** 3 / 3
     value = flops / (ms_step * 1e-3) / 1e12
-    fac_avg = sum(factor_ms) / K
-    dominant = "tc_async (persistent DAG kernel)" if sched == "async_dag" else "whole fork-join factorization"
-    achieved = flops / (fac_avg * 1e-3) / 1e12
+
+    if sched == "fork_join":
+        kernel = "tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)"
+        kms, kcount = launches["update"]
+        kflops = update_flops(n, T) * K  # over the K timed factorizations
+    else:
+        kernel = "tc_async (persistent DAG kernel, one launch per factorization)"
+        kms, kcount = launches["persistent"]
+        kflops = flops * K
+    avg_launch_ms = kms / max(kcount, 1)
+    flops_per_launch = kflops / max(kcount, 1)
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    traffic = None
+    rec = TRAFFIC.get((sched, n, T))
+    if rec is not None and rec[1] == sources_sha():
+        traffic = rec[0]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"FP64 tiled Cholesky factor + {args.nrhs}-RHS solve of the SE-kernel SPD matrix "
-                               f"(n={n}, lengthscale 0.1, nugget 1e-2), T={T}, {sched} schedule",
+                               f"(n={n}, points uniform in [0,1]^2, lengthscale 0.1, nugget 1e-2), tile T={T}, "
+                               f"{sched} schedule",
                    "n": n, "T": T, "schedule": sched, "nrhs": args.nrhs},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": dominant, "flops_per_launch": flops, "avg_launch_ms": round(fac_avg, 3)},
-        "factor_ms": [round(x, 3) for x in factor_ms],
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
+                     "kernel": kernel, "launches": kcount, "flops_per_launch": flops_per_launch,
+                     "avg_launch_ms": round(avg_launch_ms, 4)},
+        "factor_ms": {"median": round(statistics.median(factor_ms), 3), "min": round(min(factor_ms), 3),
+                      "max": round(max(factor_ms), 3)},
+        "factor_tflops_median": round(flops / (statistics.median(factor_ms) * 1e-3) / 1e12, 3),
+        "launch_ms": {k: [round(v[0] / K, 3), v[1] // K] for k, v in launches.items()},
     }
     del copies, works, rhs, A0
     torch.cuda.empty_cache()

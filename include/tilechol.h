@@ -182,6 +182,21 @@ int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, 
  * current device (co-resident capacity); < 0 on error.  Touches the device. */
 int64_t chol_async_grid(void);
 
+/* ---- measurement aid ----
+ * Per-launch device time of chol_factor.  When enabled on the calling
+ * thread, each launch chol_factor enqueues for a tile operation, and the
+ * persistent launch of the asynchronous schedule, is bracketed by a pair of
+ * HIP events on the call's stream (events are created on first use and
+ * reused; no device memory is allocated).  chol_timing_read synchronises
+ * `stream`, writes the summed milliseconds and the launch counts per kind
+ * (index CHOL_UNIT_POTRF, CHOL_UNIT_TRSM, CHOL_UNIT_UPDATE, and 3 for the
+ * persistent kernel) recorded since the previous read, and clears them.
+ * The workspace-clearing launch is not timed.  chol_timing_enable returns the
+ * previous state; chol_timing_read returns CHOL_OK, CHOL_EINVAL (NULL
+ * output) or CHOL_EDEVICE. */
+int chol_timing_enable(int on);
+int chol_timing_read(void* stream, double ms[4], int64_t launches[4]);
+
 /* Upper bound in seconds on any single dependency wait of the asynchronous
  * schedule (default 10).  A wait that exceeds it ends the factorization
  * with CHOL_ETIMEOUT instead of a hang.  Process-wide; values < 0 are

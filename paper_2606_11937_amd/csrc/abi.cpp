@@ -258,6 +258,15 @@ int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, 
   return total;
 }
 
+int chol_timing_enable(int on) { return tc_timing_enable(on); }
+
+int chol_timing_read(void* stream, double ms[4], int64_t launches[4]) {
+  g_bad_arg = 0;
+  if (ms == nullptr) return bad(2);
+  if (launches == nullptr) return bad(3);
+  return tc_timing_read((hipStream_t)stream, ms, launches) == 0 ? CHOL_OK : CHOL_EDEVICE;
+}
+
 int64_t chol_async_grid(void) {
   const int64_t g = tc_async_grid_size();
   return g > 0 ? g : CHOL_EDEVICE;

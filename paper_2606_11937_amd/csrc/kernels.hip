@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "dag.h"
 #include "launch.h"
 #include "tile_ops.h"
@@ -290,6 +292,74 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 // ------------------------------------------------------------ host launchers
 static int tc_chk(hipError_t e) { return e == hipSuccess ? 0 : TC_LAUNCH_EDEVICE; }
 
+// Per-launch timing (a measurement aid, off by default): when enabled on the
+// calling thread, every tile-operation launch and the persistent launch are
+// bracketed by a pair of HIP events on the launch stream.  Events are created
+// on first use and reused; they are runtime objects, not device memory.
+namespace {
+struct TcTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+thread_local TcTimer g_timer;
+
+// Launch `fn` on `st`, timed under `kind` when the timer is on.
+template <typename F>
+void tc_timed(int kind, hipStream_t st, F fn) {
+  if (!g_timer.on) {
+    fn();
+    return;
+  }
+  hipEvent_t a = g_timer.next(), b = g_timer.next();
+  if (a == nullptr || b == nullptr) {
+    fn();
+    return;
+  }
+  hipEventRecord(a, st);
+  fn();
+  hipEventRecord(b, st);
+  g_timer.recs.push_back({kind, a, b});
+}
+}  // namespace
+
+int tc_timing_enable(int on) {
+  const int prev = g_timer.on ? 1 : 0;
+  g_timer.on = on != 0;
+  return prev;
+}
+
+int tc_timing_read(hipStream_t st, double ms[4], int64_t cnt[4]) {
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    cnt[k] = 0;
+  }
+  int rc = 0;
+  if (hipStreamSynchronize(st) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
+  for (const TcTimer::Rec& r : g_timer.recs) {
+    float t = 0.0f;
+    if (rc == 0 && hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
+    ms[r.kind] += t;
+    cnt[r.kind] += 1;
+  }
+  g_timer.recs.clear();
+  g_timer.used = 0;
+  return rc;
+}
+
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks) {
   const int64_t Q = 2 * (grid > 0 ? grid : 256);
@@ -301,17 +371,27 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, vo
   if (int e = tc_chk(hipGetLastError())) return e;
   if (sched == 0) {
     for (int32_t J = 0; J < g.M; ++J) {
-      hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      tc_timed(TC_UNIT_POTRF, st, [&] {
+        hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      });
       const int64_t nt = tc_rows_below(g, J);
-      if (nt > 0) hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      if (nt > 0)
+        tc_timed(TC_UNIT_TRSM, st, [&] {
+          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+        });
       const int64_t nu = tc_trailing_units(g, J);
-      if (nu > 0) hipLaunchKernelGGL(tc_fj_update, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      if (nu > 0)
+        tc_timed(TC_UNIT_UPDATE, st, [&] {
+          hipLaunchKernelGGL(tc_fj_update, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+        });
     }
     return tc_chk(hipGetLastError());
   }
   if (g.M > TC_MAX_PHASES) return TC_LAUNCH_EINVAL;
   hipLaunchKernelGGL(tc_phase_offsets, dim3(1), dim3(64), 0, st, g, ws.offs);
-  hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
+  tc_timed(3, st, [&] {
+    hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
+  });
   return tc_chk(hipGetLastError());
 }
 

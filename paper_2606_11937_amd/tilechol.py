@@ -43,6 +43,8 @@ SIGNATURES = [
     ("chol_dag_counts", _int, [_i64, _i64, _pi64]),
     ("chol_dag_enumerate", _i64, [_i64, _i64, _i64, _pi32, _i64]),
     ("chol_dag_forkjoin_update", _i64, [_i64, _i64, _i64, _pi32, _i64]),
+    ("chol_timing_enable", _int, [_int]),
+    ("chol_timing_read", _int, [_vp, ctypes.POINTER(_dbl), _pi64]),
     ("chol_async_grid", _i64, []),
     ("chol_set_wait_limit", _dbl, [_dbl]),
     ("chol_last_bad_arg", _int, []),
@@ -237,6 +239,24 @@ def chol_dag_forkjoin_update(n: int, T: int, J: int):
     out = np.zeros((total, 6), dtype=np.int32)
     lib.chol_dag_forkjoin_update(n, T, J, out.ctypes.data_as(_pi32), total)
     return out
+
+
+def chol_timing_enable(on: bool) -> bool:
+    """Turn per-launch event timing of chol_factor on or off (this thread)."""
+    return bool(lib.chol_timing_enable(1 if on else 0))
+
+
+def chol_timing_read(stream=None):
+    """Summed device milliseconds and launch counts per kernel kind recorded
+    since the last read: {"potrf": (ms, n), "trsm": ..., "update": ...,
+    "persistent": ...}.  Synchronises the stream."""
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    st = lib.chol_timing_read(_stream(stream), ms, cnt)
+    if st != CHOL_OK:
+        raise TileCholError(st, "chol_timing_read", last_bad_arg())
+    names = ("potrf", "trsm", "update", "persistent")
+    return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(4)}
 
 
 def chol_async_grid() -> int:
