@@ -329,9 +329,9 @@ void tc_timed(int kind, hipStream_t st, F fn) {
     fn();
     return;
   }
-  hipEventRecord(a, st);
+  (void)hipEventRecord(a, st);
   fn();
-  hipEventRecord(b, st);
+  (void)hipEventRecord(b, st);
   g_timer.recs.push_back({kind, a, b});
 }
 }  // namespace

@@ -16,7 +16,9 @@
 // right-hand side c, each of the four thread quarters p accumulates its 16
 // columns of every earlier block in ascending order, the quarters are
 // combined in order p = 0..3 and subtracted from B, and the in-block
-// substitution is sequential in the column index.
+// substitution is sequential in the column index, dividing through the
+// reciprocal of the diagonal with one correction step (exact whenever the
+// quotient is representable).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -66,13 +68,47 @@ __device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, SvWs* ws,
   }
 }
 
+// Broadcast lane l's value of v to the whole wave (l wave-uniform).
+__device__ __forceinline__ double sv_readlane(double v, int l) {
+  const int64_t b = __builtin_bit_cast(int64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(uint64_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)b >> 32), l);
+  return __builtin_bit_cast(double, (int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+// x / d from the correctly rounded reciprocal r = 1 / d with one residual
+// correction (Markstein's method): exact whenever x / d is representable,
+// otherwise within one unit in the last place of the rounded quotient.
+__device__ __forceinline__ double sv_div_rcp(double x, double d, double r) {
+  const double q0 = x * r;
+  const double e = __builtin_fma(-q0, d, x);
+  return __builtin_fma(e, r, q0);
+}
+
+// Stage the lower part of the diagonal block and the reciprocals of its
+// diagonal (every thread of the workgroup takes part).
+__device__ __forceinline__ void sv_stage_diag(const double* __restrict__ L, int64_t lda, int64_t r0, int nr,
+                                              double (*Lbb)[SV_NB + 1], double* rdiag) {
+  for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x < SV_NB) rdiag[threadIdx.x] = 1.0 / Lbb[threadIdx.x][threadIdx.x];
+}
+
 // ---------------------------------------------------------------- forward
-// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.
+// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.  The L
+// values of block j + 1 are loaded while block j's contribution is formed, so
+// the load latency of the block that finishes last stays off the chain.  The
+// in-block substitution is one row per lane; each step broadcasts the new
+// unknown with a lane read and divides through the precomputed reciprocal.
 __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                          SvWs* ws, int64_t wait_ticks) {
   __shared__ double part[4][SV_NB][SV_RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_b;
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -80,11 +116,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
   const int32_t b = sv_uniform(s_b);
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  // stage the diagonal block (lower part)
-  for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
-    const int i = e / SV_NB, k = e % SV_NB;
-    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : 0.0;
-  }
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
   // thread (r, p): row r, columns 16p .. 16p+15 of every earlier block
   const int r = tid >> 2, p = tid & 3;
   const bool live = r < nr;
@@ -94,6 +126,11 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
     double acc[SV_RC];
 #pragma unroll
     for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
+    double lc[16];
+    if (b > 0 && live) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lc[k] = lrow[k];
+    }
     int32_t j = 0;
     while (j < b) {
       const int32_t ready = sv_wait_above(&ws->done_f, j, ws, wait_ticks);
@@ -101,15 +138,19 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
       const int32_t jend = ready < b ? ready : b;
       for (; j < jend; ++j) {
         if (!live) continue;
-        const double* lj = lrow + (int64_t)j * SV_NB;
+        double ln[16];
+        const int32_t jn = j + 1 < b ? j + 1 : j;  // the last block re-reads itself
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ln[k] = lrow[(int64_t)jn * SV_NB + k];
         const double* yj = B + ((int64_t)j * SV_NB + 16 * p) * ldb + c0;
-#pragma unroll 4
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
-          const double l = lj[k];
 #pragma unroll
           for (int c = 0; c < SV_RC; ++c)
-            if (c < nc) acc[c] += l * yj[(int64_t)k * ldb + c];
+            if (c < nc) acc[c] += lc[k] * yj[(int64_t)k * ldb + c];
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
       }
     }
 #pragma unroll
@@ -123,12 +164,18 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
         const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
         v = B[(r0 + lane) * ldb + c0 + c] - s;
       }
-      for (int i = 0; i < nr; ++i) {
-        double xi = 0.0;
-        if (lane == i) xi = v / Lbb[i][i];
-        xi = __shfl(xi, i, 64);
+      // lane k keeps row k of the diagonal block, its pivot and reciprocal in
+      // registers; each step is three lane reads and four dependent FP64
+      // operations (rows past nr have a unit diagonal and zero entries)
+      double lr[SV_NB];
+#pragma unroll
+      for (int i = 0; i < SV_NB; ++i) lr[i] = Lbb[lane][i];
+      const double dl = Lbb[lane][lane], rl = rdiag[lane];
+#pragma unroll
+      for (int i = 0; i < SV_NB; ++i) {
+        const double xi = sv_div_rcp(sv_readlane(v, i), sv_readlane(dl, i), sv_readlane(rl, i));
         if (lane == i) v = xi;
-        if (lane > i) v = v - Lbb[lane][i] * xi;
+        else if (lane > i) v = v - lr[i] * xi;
       }
       if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
     }
@@ -146,6 +193,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
                                                           SvWs* ws, int64_t wait_ticks) {
   __shared__ double part[4][SV_NB][SV_RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_t;
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
@@ -155,38 +203,52 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
   const int32_t b = nb - 1 - t;
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
-    const int i = e / SV_NB, k = e % SV_NB;
-    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : 0.0;
-  }
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
   // thread (r, p): output row r of the block (column r of each L_jb), rows
   // 16p .. 16p+15 of every later block; consecutive r are consecutive
   // addresses, so each wave reads 64 contiguous doubles per k
   const int r = tid & 63, p = tid >> 6;
   const bool live = r < nr;
+  // rows of block j this thread reads: 16p .. 16p+15, clipped to the block
+  auto load_col = [&](int32_t j, double* dst) {
+    const int64_t j0 = (int64_t)j * SV_NB;
+    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int kk = 16 * p + k;
+      dst[k] = kk < njr ? L[(j0 + kk) * lda + r0 + r] : 0.0;
+    }
+  };
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
     const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
     double acc[SV_RC];
 #pragma unroll
     for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
-    int32_t d = 0;  // blocks done from the end; block j is done iff j >= nb - d
+    double lc[16];
+    if (b < nb - 1 && live) load_col(nb - 1, lc);
     int32_t j = nb - 1;
     while (j > b) {
       const int32_t ready = sv_wait_above(&ws->done_b, nb - 1 - j, ws, wait_ticks);
       if (ready < 0) break;
-      d = ready;
-      const int32_t jlow = nb - d > b + 1 ? nb - d : b + 1;
+      const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
       for (; j >= jlow; --j) {
+        if (!live) continue;
+        double ln[16];
+        load_col(j - 1 > b ? j - 1 : j, ln);  // the last block re-reads itself
         const int64_t j0 = (int64_t)j * SV_NB;
         const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-        if (!live) continue;
-        for (int k = 16 * p; k < 16 * p + 16 && k < njr; ++k) {
-          const double l = L[(j0 + k) * lda + r0 + r];
-          const double* xk = B + (j0 + k) * ldb + c0;
 #pragma unroll
-          for (int c = 0; c < SV_RC; ++c)
-            if (c < nc) acc[c] += l * xk[c];
+        for (int k = 0; k < 16; ++k) {
+          const int kk = 16 * p + k;
+          if (kk < njr) {
+            const double* xk = B + (j0 + kk) * ldb + c0;
+#pragma unroll
+            for (int c = 0; c < SV_RC; ++c)
+              if (c < nc) acc[c] += lc[k] * xk[c];
+          }
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
       }
     }
 #pragma unroll
@@ -199,12 +261,16 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
         const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
         v = B[(r0 + lane) * ldb + c0 + c] - s;
       }
-      for (int i = nr - 1; i >= 0; --i) {
-        double xi = 0.0;
-        if (lane == i) xi = v / Lbb[i][i];
-        xi = __shfl(xi, i, 64);
+      // lane k keeps column k of the diagonal block (row k of its transpose)
+      double lc2[SV_NB];
+#pragma unroll
+      for (int i = 0; i < SV_NB; ++i) lc2[i] = Lbb[i][lane];
+      const double dl = Lbb[lane][lane], rl = rdiag[lane];
+#pragma unroll
+      for (int i = SV_NB - 1; i >= 0; --i) {
+        const double xi = sv_div_rcp(sv_readlane(v, i), sv_readlane(dl, i), sv_readlane(rl, i));
         if (lane == i) v = xi;
-        if (lane < i) v = v - Lbb[i][lane] * xi;
+        else if (lane < i) v = v - lc2[i] * xi;
       }
       if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
     }
