@@ -148,14 +148,24 @@ int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, 
 int64_t chol_default_tile(int64_t n);
 
 /* ---- introspection of the tile DAG (host only; no device is touched) ----
- * Work units are the pieces the schedules launch: POTRF(J) is one unit;
- * TRSM(I, J) is split into row blocks of CHOL_BLOCK rows; the SYRK/GEMM
- * update of tile (I, K) at step J is split into CHOL_BLOCK x CHOL_BLOCK
- * output blocks (only blocks on or below the diagonal for SYRK). */
+ * Work units are the pieces the schedules launch.  Blocks are CHOL_BLOCK
+ * rows (and columns) inside a tile; sub-block a of tile I is global block
+ * I * ceil(min(T, n) / CHOL_BLOCK) + a.  The panel of tile column J (its
+ * POTRF and TRSM tasks) is factored one CHOL_BLOCK-wide sub-column at a
+ * time, the blocked form of the same operations; the SYRK/GEMM trailing
+ * update of step J keeps K-depth T.  Each unit is 6 int32 {kind, J, I, a,
+ * K, b}:
+ *   POTRF   {0, J, J, s, -1, -1}   diagonal block s of tile J;
+ *   TRSM    {1, J, I, a,  s, -1}   block (I, a) below it against that block;
+ *   UPDATE  {2, J, I, a,  K,  b}   output block (a, b) of tile (I, K) at
+ *                                  step J (SYRK when I == K, only b <= a);
+ *   PANEL   {3, J, I, a,  s, s2}   block (I, a) of panel sub-column s2 of
+ *                                  tile J minus the product of the finished
+ *                                  sub-column s < s2 (rows at or below s2). */
 #define CHOL_BLOCK 128
 
 /* Work-unit kinds as encoded by chol_dag_enumerate. */
-enum { CHOL_UNIT_POTRF = 0, CHOL_UNIT_TRSM = 1, CHOL_UNIT_UPDATE = 2 };
+enum { CHOL_UNIT_POTRF = 0, CHOL_UNIT_TRSM = 1, CHOL_UNIT_UPDATE = 2, CHOL_UNIT_PANEL = 3 };
 
 /* Tile-task counts for (n, T) (Results, "Problem Size Scaling": M POTRF,
  * M(M-1)/2 TRSM and SYRK each, M(M-1)(M-2)/6 GEMM): counts[0..3] =
@@ -163,9 +173,8 @@ enum { CHOL_UNIT_POTRF = 0, CHOL_UNIT_TRSM = 1, CHOL_UNIT_UPDATE = 2 };
  * schedule.  Returns CHOL_OK or CHOL_EINVAL. */
 int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]);
 
-/* Write the asynchronous schedule's work units in dispatch (ticket) order.
- * Each unit is 6 int32 values {kind, J, I, a, K, b}: the tile indices and
- * the CHOL_BLOCK sub-block indices inside them (unused fields are -1).
+/* Write the asynchronous schedule's work units in dispatch (ticket) order,
+ * 6 int32 each as above.
  * `grid` is the number of persistent workgroups the order is tuned for
  * (it sets how far the panel of step J+1 runs ahead of step J's bulk
  * update).  Writes min(cap, total) units; returns the total, or a negative
@@ -183,19 +192,21 @@ int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, 
 int64_t chol_async_grid(void);
 
 /* ---- measurement aid ----
- * Per-launch device time of chol_factor.  When enabled on the calling
- * thread, each launch chol_factor enqueues for a tile operation, and the
- * persistent launch of the asynchronous schedule, is bracketed by a pair of
- * HIP events on the call's stream (events are created on first use and
- * reused; no device memory is allocated).  chol_timing_read synchronises
- * `stream`, writes the summed milliseconds and the launch counts per kind
- * (index CHOL_UNIT_POTRF, CHOL_UNIT_TRSM, CHOL_UNIT_UPDATE, and 3 for the
- * persistent kernel) recorded since the previous read, and clears them.
- * The workspace-clearing launch is not timed.  chol_timing_enable returns the
- * previous state; chol_timing_read returns CHOL_OK, CHOL_EINVAL (NULL
- * output) or CHOL_EDEVICE. */
-int chol_timing_enable(int on);
-int chol_timing_read(void* stream, double ms[4], int64_t launches[4]);
+ * Per-launch device time of chol_factor.  `kinds` is a bit mask: bit k
+ * (k = CHOL_UNIT_POTRF, CHOL_UNIT_TRSM, CHOL_UNIT_UPDATE, CHOL_UNIT_PANEL)
+ * times the fork-join launches of that unit kind, bit 4 the persistent
+ * launch of the asynchronous schedule; 0 turns timing off.  While enabled on
+ * the calling thread, each selected launch chol_factor enqueues is
+ * bracketed by a pair of HIP events on the call's stream (events are
+ * created on first use and reused; no device memory is allocated; each pair
+ * adds a few microseconds to the stream, so time only what is needed).
+ * chol_timing_read synchronises `stream`, writes the summed milliseconds and
+ * the launch counts per kind (same indices) recorded since the previous
+ * read, and clears them.  The workspace-clearing launch is never timed.
+ * chol_timing_enable returns the previous mask; chol_timing_read returns
+ * CHOL_OK, CHOL_EINVAL (NULL output) or CHOL_EDEVICE. */
+int chol_timing_enable(int kinds);
+int chol_timing_read(void* stream, double ms[5], int64_t launches[5]);
 
 /* Upper bound in seconds on any single dependency wait of the asynchronous
  * schedule (default 10).  A wait that exceeds it ends the factorization

@@ -11,6 +11,10 @@
 #include "launch.h"
 
 static_assert(CHOL_BLOCK == TC_BLK, "sub-block size of the ABI and the kernels differ");
+static_assert(CHOL_UNIT_POTRF == TC_UNIT_POTRF && CHOL_UNIT_TRSM == TC_UNIT_TRSM &&
+                  CHOL_UNIT_UPDATE == TC_UNIT_UPDATE && CHOL_UNIT_PANEL == TC_UNIT_PANEL,
+              "unit kinds of the ABI and the kernels differ");
+static_assert(TC_TIMING_KINDS == 5 && TC_TIMING_PERSISTENT == 4, "timing kinds of the ABI and the launcher differ");
 
 namespace {
 thread_local int g_bad_arg = 0;
@@ -226,7 +230,7 @@ int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int
   if (grid < 1) return bad(3);
   if (cap < 0) return bad(5);
   if (cap > 0 && out == nullptr) return bad(4);
-  TcGeom g = tc_geom(n, T, 2 * grid);
+  TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid));
   int64_t k = 0;
   for (int32_t P = 0; P < g.M; ++P) {
     const int64_t sz = tc_phase_size(g, P);
@@ -258,9 +262,9 @@ int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, 
   return total;
 }
 
-int chol_timing_enable(int on) { return tc_timing_enable(on); }
+int chol_timing_enable(int kinds) { return tc_timing_enable(kinds); }
 
-int chol_timing_read(void* stream, double ms[4], int64_t launches[4]) {
+int chol_timing_read(void* stream, double ms[5], int64_t launches[5]) {
   g_bad_arg = 0;
   if (ms == nullptr) return bad(2);
   if (launches == nullptr) return bad(3);

@@ -5,31 +5,41 @@
 //
 // Tiles.  n is split into M = ceil(n/T) tile rows/columns; tile I spans rows
 // [I*T, min(n, (I+1)*T)).  Each tile is further split into sub-blocks of
-// TC_BLK rows; sub-block a of tile I has global row-block id g = I*SB + a.
+// TC_BLK rows; sub-block a of tile I has global block id g = I*SB + a, and
+// the same ids number the block columns.
 //
-// Work units (the pieces the schedules execute):
-//   POTRF(J)              the whole diagonal tile J,
-//   TRSM(I, J, a)         rows of sub-block a of tile I against L_JJ,
-//   UPDATE(I, a, K, b, J) the TC_BLK x TC_BLK output block (a, b) of tile
-//                         (I, K) at step J: SYRK when I == K (only b <= a),
-//                         GEMM when I > K.
+// Work units.  The panel of tile column J (its POTRF and TRSM tasks) is
+// factored one TC_BLK-wide sub-column s at a time, the blocked form of the
+// same operations; the trailing SYRK/GEMM update of step J keeps the full
+// K-depth T:
+//   POTRF(J, s)              the diagonal block gs = gid(J, s),
+//   TRSM(J, s, r)            block (r, gs) against it, for every r > gs,
+//   PANEL(J, s, r, s')       block (r, gid(J, s')) -= (r, gs) (gid(J,s'), gs)^T
+//                            for s < s' and r >= gid(J, s') (the update of the
+//                            panel's later sub-columns, K-depth TC_BLK),
+//   UPDATE(J, r, c)          the TC_BLK x TC_BLK output block (r, c) of the
+//                            step-J trailing update, c beyond tile J, r >= c:
+//                            SYRK when r and c lie in one tile, else GEMM.
+// A block receives its updates in a fixed order: the trailing updates of
+// steps 0, 1, ... and then, inside its own panel, the panel updates of
+// sub-columns 0, 1, ...; both schedules apply exactly these units in that
+// order, so they produce the same bits.
 //
 // Dispatch order of the asynchronous schedule.  Units are grouped in phases
 // P = 0 .. M-1.  Phase P holds, in this order:
-//   [col]   the step-(P-1) updates of tile column P (they feed POTRF(P)),
-//   [potrf] POTRF(P),
-//   [bulk1] the first Q step-(P-1) updates of the columns K > P,
-//   [trsm]  TRSM(I, P, a) for I > P,
-//   [bulk2] the remaining step-(P-1) updates of the columns K > P.
-// Within [col] units go by tile row I, within the bulk by column K then row
-// I, so tile column P+1 is updated first.  Every unit depends only on units
-// of earlier phases or earlier segments (checked by enumeration tests), so
-// ticket order is a topological order of the tile DAG and a worker that
-// waits on a dependency always waits on a unit another running worker holds.
-// Placing [potrf] and [trsm] ahead of the bulk update of the previous step
-// is a one-step lookahead: the panel of step P is factored while the
-// trailing update of step P-1 still runs, the GPU counterpart of removing
-// the per-step barrier of the fork-join variants.
+//   [col]  the step-(P-1) updates of tile column P (they feed its panel),
+//   then for each sub-column s of panel P the chain
+//          POTRF(P, s) [chunk] TRSM(P, s, *) [chunk] PANEL(P, s, *) [chunk]
+//   where every [chunk] is the next (up to) Q step-(P-1) updates of the
+//   columns beyond tile P, and finally
+//   [rest] the remaining step-(P-1) updates.
+// Within [col] units go by tile row, within the bulk by column then row, so
+// tile column P+1 is updated first.  Every unit depends only on units of
+// earlier phases or earlier segments (checked by enumeration tests), so
+// ticket order is a topological order and a worker that waits on a
+// dependency always waits on a unit another running worker holds.  Threading
+// the panel chain of step P through the bulk update of step P-1 is the
+// lookahead that replaces the per-step barrier of the fork-join variants.
 #pragma once
 #include <stdint.h>
 
@@ -41,7 +51,12 @@
 
 #define TC_BLK 128
 
-enum { TC_UNIT_POTRF = 0, TC_UNIT_TRSM = 1, TC_UNIT_UPDATE = 2 };
+// Bulk updates placed after each link of a panel chain, per persistent
+// workgroup: one unit per workgroup keeps every worker busy while one link
+// of the chain (a POTRF, a TRSM column or a panel update) completes.
+TC_HD int64_t tc_lookahead_chunk(int64_t grid) { return grid > 0 ? grid : 256; }
+
+enum { TC_UNIT_POTRF = 0, TC_UNIT_TRSM = 1, TC_UNIT_UPDATE = 2, TC_UNIT_PANEL = 3 };
 
 struct TcGeom {
   int64_t n, T;
@@ -111,23 +126,67 @@ TC_HD int64_t tc_trailing_units(const TcGeom& g, int32_t P) {
 // all step-(P-1) update units of columns K > P (the bulk of phase P)
 TC_HD int64_t tc_bulk(const TcGeom& g, int32_t P) { return P >= 1 ? tc_trailing_units(g, P) : 0; }
 
-struct TcPhase {
-  int64_t col, potrf, bulk1, trsm, bulk2;
-};
-
-TC_HD TcPhase tc_phase(const TcGeom& g, int32_t P) {
-  TcPhase ph;
-  ph.col = P >= 1 ? tc_colsize(g, P) : 0;
-  ph.potrf = 1;
-  int64_t bulk = tc_bulk(g, P);
-  ph.bulk1 = bulk < g.Q ? bulk : g.Q;
-  ph.bulk2 = bulk - ph.bulk1;
-  ph.trsm = tc_rows_below(g, P);
-  return ph;
+// ---- panel chain of tile column P (sub-columns s = 0 .. sb(P)-1)
+// TRSM units of sub-column s: every global block below gid(P, s).
+TC_HD int64_t tc_trsm_count(const TcGeom& g, int32_t P, int32_t s) {
+  return (int64_t)g.NRB - tc_gid(g, P, s) - 1;
 }
+// PANEL units of sub-column s: for each later sub-column s' of the panel,
+// every block row r >= gid(P, s').
+TC_HD int64_t tc_panel_count(const TcGeom& g, int32_t P, int32_t s) {
+  int64_t c = 0;
+  for (int32_t t = s + 1; t < tc_sb(g, P); ++t) c += (int64_t)g.NRB - tc_gid(g, P, t);
+  return c;
+}
+// global block id -> (tile, sub-block)
+TC_HD void tc_split_gid(const TcGeom& g, int64_t r, int32_t& I, int32_t& a) {
+  I = (int32_t)(r / g.SB);
+  a = (int32_t)(r % g.SB);
+}
+TC_HD TcUnit tc_decode_trsm(const TcGeom& g, int32_t P, int32_t s, int64_t k) {
+  TcUnit u;
+  u.kind = TC_UNIT_TRSM;
+  u.J = P;
+  tc_split_gid(g, tc_gid(g, P, s) + 1 + k, u.I, u.a);
+  u.K = s;
+  u.b = -1;
+  return u;
+}
+TC_HD TcUnit tc_decode_panel(const TcGeom& g, int32_t P, int32_t s, int64_t k) {
+  TcUnit u;
+  u.kind = TC_UNIT_PANEL;
+  u.J = P;
+  u.K = s;
+  int32_t t = s + 1;
+  for (;;) {
+    const int64_t rows = (int64_t)g.NRB - tc_gid(g, P, t);
+    if (k < rows || t + 1 >= tc_sb(g, P)) break;
+    k -= rows;
+    ++t;
+  }
+  u.b = t;
+  tc_split_gid(g, tc_gid(g, P, t) + k, u.I, u.a);
+  return u;
+}
+TC_HD TcUnit tc_decode_potrf(int32_t P, int32_t s) {
+  TcUnit u;
+  u.kind = TC_UNIT_POTRF;
+  u.J = P;
+  u.I = P;
+  u.a = s;
+  u.K = -1;
+  u.b = -1;
+  return u;
+}
+// units of the whole panel chain of P
+TC_HD int64_t tc_chain_units(const TcGeom& g, int32_t P) {
+  int64_t c = 0;
+  for (int32_t s = 0; s < tc_sb(g, P); ++s) c += 1 + tc_trsm_count(g, P, s) + tc_panel_count(g, P, s);
+  return c;
+}
+
 TC_HD int64_t tc_phase_size(const TcGeom& g, int32_t P) {
-  TcPhase ph = tc_phase(g, P);
-  return ph.col + ph.potrf + ph.bulk1 + ph.trsm + ph.bulk2;
+  return (P >= 1 ? tc_colsize(g, P) : 0) + tc_chain_units(g, P) + tc_bulk(g, P);
 }
 
 // r-th unit (step J) of tile column K: SYRK sub-blocks (a >= b) of (K, K)
@@ -172,29 +231,24 @@ TC_HD TcUnit tc_decode_bulk(const TcGeom& g, int32_t P, int64_t r) { return tc_d
 
 // Unit at position r within phase P.
 TC_HD TcUnit tc_decode_in_phase(const TcGeom& g, int32_t P, int64_t r) {
-  TcPhase ph = tc_phase(g, P);
-  if (r < ph.col) return tc_decode_col(g, P - 1, P, r);
-  r -= ph.col;
-  if (r < 1) {
-    TcUnit u;
-    u.kind = TC_UNIT_POTRF; u.J = P; u.I = P; u.a = -1; u.K = -1; u.b = -1;
-    return u;
+  const int64_t col = P >= 1 ? tc_colsize(g, P) : 0;
+  if (r < col) return tc_decode_col(g, P - 1, P, r);
+  r -= col;
+  const int64_t bulk = tc_bulk(g, P);
+  int64_t used = 0;  // bulk units placed so far
+  for (int32_t s = 0; s < tc_sb(g, P); ++s) {
+    for (int32_t link = 0; link < 3; ++link) {
+      const int64_t sz = link == 0 ? 1 : link == 1 ? tc_trsm_count(g, P, s) : tc_panel_count(g, P, s);
+      if (r < sz)
+        return link == 0 ? tc_decode_potrf(P, s) : link == 1 ? tc_decode_trsm(g, P, s, r) : tc_decode_panel(g, P, s, r);
+      r -= sz;
+      const int64_t ch = bulk - used < g.Q ? bulk - used : g.Q;
+      if (r < ch) return tc_decode_bulk(g, P, used + r);
+      r -= ch;
+      used += ch;
+    }
   }
-  r -= 1;
-  if (r < ph.bulk1) return tc_decode_bulk(g, P, r);
-  r -= ph.bulk1;
-  if (r < ph.trsm) {
-    TcUnit u;
-    u.kind = TC_UNIT_TRSM;
-    u.J = P;
-    u.I = P + 1 + (int32_t)(r / g.SB);
-    u.a = (int32_t)(r % g.SB);
-    u.K = -1;
-    u.b = -1;
-    return u;
-  }
-  r -= ph.trsm;
-  return tc_decode_bulk(g, P, ph.bulk1 + r);
+  return tc_decode_bulk(g, P, used + r);
 }
 
 // Tile-task counts (Results, problem-size scaling: M POTRF, M(M-1)/2 TRSM

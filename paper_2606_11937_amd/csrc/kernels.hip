@@ -101,56 +101,72 @@ union alignas(512) TcSmem {
   TcUpdSmem upd;
 };
 
-__device__ __forceinline__ void tc_run_potrf(double* A, int64_t lda, const TcGeom& g, int32_t J, TcWsHeader* h,
-                                             TcSmem& sm) {
-  const int64_t d0 = (int64_t)J * g.T;
-  const int td = (int)tc_tdim(g, J);
-  const int bad = tc_potrf_tile(A + d0 * lda + d0, lda, td, sm.potrf);
-  if (bad >= 0 && threadIdx.x == 0) tc_report_fail(h, 1, d0 + bad + 1);
+// POTRF(J, s): the diagonal block gid(J, s).
+__device__ __forceinline__ void tc_run_potrf(double* A, int64_t lda, const TcGeom& g, int32_t J, int32_t s,
+                                             TcWsHeader* h, TcPotrfSmem& sm) {
+  const int64_t d0 = tc_row0(g, J, s);
+  const int bad = tc_potrf_tile(A + d0 * lda + d0, lda, tc_rows(g, J, s), sm);
+  if (bad >= 0 && tc_tid() == 0) tc_report_fail(h, 1, d0 + bad + 1);
 }
 
-__device__ __forceinline__ void tc_run_trsm(double* A, int64_t lda, const TcGeom& g, int32_t I, int32_t a, int32_t J,
-                                            TcSmem& sm) {
+// TRSM(J, s, (I, a)): block (I, a) of sub-column gid(J, s).
+__device__ __forceinline__ void tc_run_trsm(double* A, int64_t lda, const TcGeom& g, int32_t J, int32_t s, int32_t I,
+                                            int32_t a, TcTrsmSmem& sm) {
   const int64_t r0 = tc_row0(g, I, a);
-  const int64_t c0 = (int64_t)J * g.T;
-  tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm.trsm);
+  const int64_t c0 = tc_row0(g, J, s);
+  tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), tc_rows(g, J, s), sm);
 }
 
-__device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u, TcSmem& sm) {
+// UPDATE(J, (I, a), (K, b)): K-depth the whole tile column J.
+__device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u, TcUpdSmem& sm) {
   const int64_t ri = tc_row0(g, u.I, u.a);
   const int64_t rk = tc_row0(g, u.K, u.b);
   const int64_t cj = (int64_t)u.J * g.T;
   tc_update_block(A + ri * lda + rk, A + ri * lda + cj, A + rk * lda + cj, lda, tc_rows(g, u.I, u.a),
-                  tc_rows(g, u.K, u.b), (int)g.T, ri == rk, sm.upd);
+                  tc_rows(g, u.K, u.b), (int)tc_tdim(g, u.J), ri == rk, sm);
+}
+
+// PANEL(J, s, (I, a), s'): block ((I, a), gid(J, s')) minus the product of
+// the finished sub-column s in rows (I, a) and gid(J, s'); K-depth one block.
+__device__ __forceinline__ void tc_run_panel(double* A, int64_t lda, const TcGeom& g, const TcUnit& u, TcUpdSmem& sm) {
+  const int64_t ri = tc_row0(g, u.I, u.a);
+  const int64_t rt = tc_row0(g, u.J, u.b);
+  const int64_t cs = tc_row0(g, u.J, u.K);
+  tc_update_block(A + ri * lda + rt, A + ri * lda + cs, A + rt * lda + cs, lda, tc_rows(g, u.I, u.a),
+                  tc_rows(g, u.J, u.b), tc_rows(g, u.J, u.K), ri == rt, sm);
 }
 
 // ---------------------------------------------------------- fork-join kernels
 // The fork-join kernels declare only the shared memory their body uses (the
 // persistent kernel needs the union of all of them).
-__global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+__global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
+                                                          TcWs ws) {
   __shared__ TcPotrfSmem sm;
   if (tc_err_set(ws.hdr)) return;
-  const int64_t d0 = (int64_t)J * g.T;
-  const int bad = tc_potrf_tile(A + d0 * lda + d0, lda, (int)tc_tdim(g, J), sm);
-  if (bad >= 0 && threadIdx.x == 0) tc_report_fail(ws.hdr, 1, d0 + bad + 1);
+  tc_run_potrf(A, lda, g, J, s, ws.hdr, sm);
 }
 
-__global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
+__global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
+                                                         TcWs ws) {
   __shared__ TcTrsmSmem sm;
   if (tc_err_set(ws.hdr)) return;
-  const int64_t r = blockIdx.x;
-  const int32_t I = J + 1 + (int32_t)(r / g.SB);
-  const int32_t a = (int32_t)(r % g.SB);
-  const int64_t r0 = tc_row0(g, I, a);
-  const int64_t c0 = (int64_t)J * g.T;
-  tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), (int)tc_tdim(g, J), sm);
+  const TcUnit u = tc_decode_trsm(g, J, s, blockIdx.x);
+  tc_run_trsm(A, lda, g, J, s, u.I, u.a, sm);
+}
+
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_panel(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
+                                                             TcWs ws) {
+  __shared__ TcUpdSmem sm;
+  if (tc_err_set(ws.hdr)) return;
+  const TcUnit u = tc_decode_panel(g, J, s, blockIdx.x);
+  tc_run_panel(A, lda, g, u, sm);
 }
 
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
   __shared__ TcUpdSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
-  tc_run_update(A, lda, g, u, *reinterpret_cast<TcSmem*>(&sm));
+  tc_run_update(A, lda, g, u, sm);
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -158,37 +174,39 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update(double* A, int64_t
 
 // Dependency test of unit u (see dag.h): all reads are relaxed agent-scope
 // atomics; the caller issues the acquire fence once the unit is ready.
+//   pdone[r]     finished sub-columns of block row r (they finish in order),
+//   ver[r][c]    updates applied to block (r, c) (trailing ones of steps
+//                0, 1, ..., then the panel ones of sub-columns 0, 1, ...).
 __device__ __forceinline__ bool tc_unit_ready(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
   auto ld = [](const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
   const int64_t NRB = g.NRB;
   if (u.kind == TC_UNIT_UPDATE) {
     const int32_t gi = tc_gid(g, u.I, u.a), gk = tc_gid(g, u.K, u.b);
-    return ld(ws.pdone + gi) > u.J && ld(ws.pdone + gk) > u.J && ld(ws.ver + gi * NRB + gk) >= u.J;
+    const int32_t need = tc_gid(g, u.J, 0) + tc_sb(g, u.J);  // whole panel J finished
+    return ld(ws.pdone + gi) >= need && ld(ws.pdone + gk) >= need && ld(ws.ver + gi * NRB + gk) >= u.J;
+  }
+  if (u.kind == TC_UNIT_PANEL) {
+    const int32_t gs = tc_gid(g, u.J, u.K), gt = tc_gid(g, u.J, u.b), gi = tc_gid(g, u.I, u.a);
+    return ld(ws.pdone + gi) > gs && ld(ws.pdone + gt) > gs && ld(ws.ver + gi * NRB + gt) >= u.J + u.K;
   }
   if (u.kind == TC_UNIT_TRSM) {
-    if (ld(ws.pdone + tc_gid(g, u.J, 0)) <= u.J) return false;
-    const int32_t gi = tc_gid(g, u.I, u.a);
-    const int32_t sj = tc_sb(g, u.J);
-    for (int32_t b = 0; b < sj; ++b)
-      if (ld(ws.ver + gi * NRB + tc_gid(g, u.J, b)) < u.J) return false;
-    return true;
+    const int32_t gs = tc_gid(g, u.J, u.K), gi = tc_gid(g, u.I, u.a);
+    return ld(ws.pdone + gs) > gs && ld(ws.ver + gi * NRB + gs) >= u.J + u.K;
   }
-  const int32_t sj = tc_sb(g, u.J);
-  for (int32_t a = 0; a < sj; ++a)
-    for (int32_t b = 0; b <= a; ++b)
-      if (ld(ws.ver + (int64_t)tc_gid(g, u.J, a) * NRB + tc_gid(g, u.J, b)) < u.J) return false;
-  return true;
+  const int32_t gs = tc_gid(g, u.J, u.a);
+  return ld(ws.ver + (int64_t)gs * NRB + gs) >= u.J + u.a;
 }
 
 __device__ __forceinline__ void tc_unit_publish(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
   auto add = [](int32_t* p) { __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
   if (u.kind == TC_UNIT_UPDATE) {
     add(ws.ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.K, u.b));
+  } else if (u.kind == TC_UNIT_PANEL) {
+    add(ws.ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.J, u.b));
   } else if (u.kind == TC_UNIT_TRSM) {
     add(ws.pdone + tc_gid(g, u.I, u.a));
   } else {
-    const int32_t sj = tc_sb(g, u.J);
-    for (int32_t a = 0; a < sj; ++a) add(ws.pdone + tc_gid(g, u.J, a));
+    add(ws.pdone + tc_gid(g, u.J, u.a));
   }
 }
 
@@ -277,11 +295,13 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                       tc_ctx32(s_unit.a), tc_ctx32(s_unit.K), tc_ctx32(s_unit.b)};
     const TcGeom cg = tc_ctx_geom(s_ctx.g);
     if (u.kind == TC_UNIT_UPDATE) {
-      tc_run_update(A, lda, cg, u, sm);
+      tc_run_update(A, lda, cg, u, sm.upd);
+    } else if (u.kind == TC_UNIT_PANEL) {
+      tc_run_panel(A, lda, cg, u, sm.upd);
     } else if (u.kind == TC_UNIT_TRSM) {
-      tc_run_trsm(A, lda, cg, u.I, u.a, u.J, sm);
+      tc_run_trsm(A, lda, cg, u.J, u.K, u.I, u.a, sm.trsm);
     } else {
-      tc_run_potrf(A, lda, cg, u.J, ws.hdr, sm);
+      tc_run_potrf(A, lda, cg, u.J, u.a, ws.hdr, sm.potrf);
     }
     // every wave makes its stores visible device-wide before the unit is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -298,7 +318,7 @@ static int tc_chk(hipError_t e) { return e == hipSuccess ? 0 : TC_LAUNCH_EDEVICE
 // on first use and reused; they are runtime objects, not device memory.
 namespace {
 struct TcTimer {
-  bool on = false;
+  int mask = 0;  // bit k: time launches of kind k
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {
@@ -320,7 +340,7 @@ thread_local TcTimer g_timer;
 // Launch `fn` on `st`, timed under `kind` when the timer is on.
 template <typename F>
 void tc_timed(int kind, hipStream_t st, F fn) {
-  if (!g_timer.on) {
+  if (!(g_timer.mask >> kind & 1)) {
     fn();
     return;
   }
@@ -336,14 +356,14 @@ void tc_timed(int kind, hipStream_t st, F fn) {
 }
 }  // namespace
 
-int tc_timing_enable(int on) {
-  const int prev = g_timer.on ? 1 : 0;
-  g_timer.on = on != 0;
+int tc_timing_enable(int mask) {
+  const int prev = g_timer.mask;
+  g_timer.mask = mask & ((1 << TC_TIMING_KINDS) - 1);
   return prev;
 }
 
-int tc_timing_read(hipStream_t st, double ms[4], int64_t cnt[4]) {
-  for (int k = 0; k < 4; ++k) {
+int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TIMING_KINDS]) {
+  for (int k = 0; k < TC_TIMING_KINDS; ++k) {
     ms[k] = 0.0;
     cnt[k] = 0;
   }
@@ -362,8 +382,7 @@ int tc_timing_read(hipStream_t st, double ms[4], int64_t cnt[4]) {
 
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks) {
-  const int64_t Q = 2 * (grid > 0 ? grid : 256);
-  TcGeom g = tc_geom(n, T, Q);
+  TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid));
   TcWs ws = tc_ws_map(work, g);
   // clear header and counters with a fill kernel (graph-capture friendly)
   const int64_t words = (tc_ws_bytes(n, T)) / 4;
@@ -371,14 +390,21 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, vo
   if (int e = tc_chk(hipGetLastError())) return e;
   if (sched == 0) {
     for (int32_t J = 0; J < g.M; ++J) {
-      tc_timed(TC_UNIT_POTRF, st, [&] {
-        hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
-      });
-      const int64_t nt = tc_rows_below(g, J);
-      if (nt > 0)
-        tc_timed(TC_UNIT_TRSM, st, [&] {
-          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
+        tc_timed(TC_UNIT_POTRF, st, [&] {
+          hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
         });
+        const int64_t nt = tc_trsm_count(g, J, sc);
+        if (nt > 0)
+          tc_timed(TC_UNIT_TRSM, st, [&] {
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+        const int64_t np = tc_panel_count(g, J, sc);
+        if (np > 0)
+          tc_timed(TC_UNIT_PANEL, st, [&] {
+            hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+      }
       const int64_t nu = tc_trailing_units(g, J);
       if (nu > 0)
         tc_timed(TC_UNIT_UPDATE, st, [&] {
@@ -389,7 +415,7 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, vo
   }
   if (g.M > TC_MAX_PHASES) return TC_LAUNCH_EINVAL;
   hipLaunchKernelGGL(tc_phase_offsets, dim3(1), dim3(64), 0, st, g, ws.offs);
-  tc_timed(3, st, [&] {
+  tc_timed(TC_TIMING_PERSISTENT, st, [&] {
     hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
   });
   return tc_chk(hipGetLastError());

@@ -13,10 +13,14 @@ int64_t tc_ws_bytes(int64_t n, int64_t T);
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks);
 // Per-launch timing of tc_launch_factor on the calling thread (measurement
-// aid): enable returns the previous state; read synchronises `st`, sums the
-// recorded launch times per kind (POTRF, TRSM, UPDATE, persistent) and clears.
-int tc_timing_enable(int on);
-int tc_timing_read(hipStream_t st, double ms[4], int64_t cnt[4]);
+// aid): enable takes a mask of the kinds to time (bit k for kind k) and
+// returns the previous mask; read synchronises `st`, sums the
+// recorded launch times per kind (POTRF, TRSM, UPDATE, PANEL unit launches,
+// then the persistent launch) and clears.
+#define TC_TIMING_KINDS 5
+#define TC_TIMING_PERSISTENT 4
+int tc_timing_enable(int mask);
+int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TIMING_KINDS]);
 // Synchronise the stream and read the error flag / info of a workspace.
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info);
 // Co-resident workgroups of the persistent kernel on the current device.

@@ -241,22 +241,28 @@ def chol_dag_forkjoin_update(n: int, T: int, J: int):
     return out
 
 
-def chol_timing_enable(on: bool) -> bool:
-    """Turn per-launch event timing of chol_factor on or off (this thread)."""
-    return bool(lib.chol_timing_enable(1 if on else 0))
+TIMING_KINDS = {"potrf": 1, "trsm": 2, "update": 4, "panel": 8, "persistent": 16}
+
+
+def chol_timing_enable(kinds) -> int:
+    """Time the chol_factor launches of the given kinds on this thread
+    (an iterable of names from TIMING_KINDS, or an int mask; empty / 0
+    turns timing off).  Returns the previous mask."""
+    mask = kinds if isinstance(kinds, int) else sum(TIMING_KINDS[k] for k in kinds)
+    return int(lib.chol_timing_enable(mask))
 
 
 def chol_timing_read(stream=None):
     """Summed device milliseconds and launch counts per kernel kind recorded
     since the last read: {"potrf": (ms, n), "trsm": ..., "update": ...,
-    "persistent": ...}.  Synchronises the stream."""
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_int64 * 4)()
+    "panel": ..., "persistent": ...}.  Synchronises the stream."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
     st = lib.chol_timing_read(_stream(stream), ms, cnt)
     if st != CHOL_OK:
         raise TileCholError(st, "chol_timing_read", last_bad_arg())
-    names = ("potrf", "trsm", "update", "persistent")
-    return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(4)}
+    names = ("potrf", "trsm", "update", "panel", "persistent")
+    return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(5)}
 
 
 def chol_async_grid() -> int:

@@ -9,7 +9,12 @@ that writer).
 
 Work units refine tile tasks into CHOL_BLOCK-row blocks, exactly as the C ABI
 documents them; their block-level read/write sets follow from the same
-operation definitions.
+operation definitions.  The POTRF and TRSM tasks of a tile column are blocked
+by CHOL_BLOCK-wide sub-columns: the panel of Fig. 1's step J is itself
+factored right-looking with tile side CHOL_BLOCK (POTRF of the diagonal
+block, TRSM of every block below it, update of the panel's later
+sub-columns), after which the step's SYRK/GEMM trailing update runs with
+K-depth T.  program_key gives that blocked program order.
 """
 from __future__ import annotations
 
@@ -17,7 +22,7 @@ import math
 from collections import defaultdict
 
 BLK = 128
-POTRF, TRSM, UPDATE = 0, 1, 2
+POTRF, TRSM, UPDATE, PANEL = 0, 1, 2, 3
 
 
 class Geom:
@@ -35,6 +40,13 @@ class Geom:
 
     def gid(self, I, a):
         return I * self.SB + a
+
+    @property
+    def NRB(self):
+        return (self.M - 1) * self.SB + self.SBL
+
+    def split(self, r):
+        return r // self.SB, r % self.SB
 
 
 # --------------------------------------------------------------- tile level
@@ -89,27 +101,56 @@ def critical_path(tasks, edges) -> int:
 # --------------------------------------------------------------- unit level
 def unit_access(g: Geom, u):
     """Block-level (reads, writes) of a work unit {kind, J, I, a, K, b};
-    a block is a pair of global row-block ids (row block, column block)."""
+    a block is a pair of global block ids (row block, column block)."""
     kind, J, I, a, K, b = (int(x) for x in u)
-    diag = [(g.gid(J, x), g.gid(J, y)) for x in range(g.sb(J)) for y in range(x + 1)]
     if kind == POTRF:
-        return [], diag
+        gs = g.gid(J, a)
+        return [], [(gs, gs)]
     if kind == TRSM:
-        return diag, [(g.gid(I, a), g.gid(J, y)) for y in range(g.sb(J))]
+        gs = g.gid(J, K)
+        return [(gs, gs)], [(g.gid(I, a), gs)]
+    if kind == PANEL:
+        gs, gt, r = g.gid(J, K), g.gid(J, b), g.gid(I, a)
+        return [(r, gs), (gt, gs)], [(r, gt)]
     ri, rk = g.gid(I, a), g.gid(K, b)
     reads = [(ri, g.gid(J, y)) for y in range(g.sb(J))] + [(rk, g.gid(J, y)) for y in range(g.sb(J))]
     return reads, [(ri, rk)]
 
 
 def program_key(g: Geom, u):
-    """Position of a unit's tile task in Fig. 1 program order."""
+    """Position of a unit in the blocked program order of Fig. 1: step J,
+    then its panel sub-columns s in order (POTRF, the TRSMs below, the panel
+    updates), then the step's trailing update."""
     kind, J, I, a, K, b = (int(x) for x in u)
     if kind == POTRF:
-        return (J, 0, 0, 0)
+        return (J, a, 0, 0, 0)
     if kind == TRSM:
-        return (J, 1, I, 0)
-    # SYRK(I) comes before the GEMMs (I, K) of the same I
-    return (J, 2, I, 0 if I == K else 1 + K)
+        return (J, K, 1, g.gid(I, a), 0)
+    if kind == PANEL:
+        return (J, K, 2, b, g.gid(I, a))
+    return (J, g.SB + 1, 3, g.gid(I, a), g.gid(K, b))
+
+
+def program_order_units(g: Geom):
+    """All work units in the blocked program order."""
+    out = []
+    for J in range(g.M):
+        for s in range(g.sb(J)):
+            gs = g.gid(J, s)
+            out.append((POTRF, J, J, s, -1, -1))
+            for r in range(gs + 1, g.NRB):
+                out.append((TRSM, J, *g.split(r), s, -1))
+            for s2 in range(s + 1, g.sb(J)):
+                for r in range(g.gid(J, s2), g.NRB):
+                    out.append((PANEL, J, *g.split(r), s, s2))
+        for I in range(J + 1, g.M):
+            for K in range(J + 1, I + 1):
+                for a in range(g.sb(I)):
+                    for b in range(g.sb(K)):
+                        if I == K and b > a:
+                            continue
+                        out.append((UPDATE, J, I, a, K, b))
+    return out
 
 
 def check_ticket_order(g: Geom, units):

@@ -205,9 +205,10 @@ def test_ticket_order_is_topological(tc, n, T, grid):
 
 @pytest.mark.parametrize("n,T", CASES)
 def test_units_cover_every_block_update_once(tc, n, T):
-    """Each lower output block receives exactly one update per earlier step,
-    each panel row block exactly one TRSM per earlier column, each diagonal
-    tile one POTRF: the decomposition covers Fig. 1 exactly."""
+    """Each diagonal block is factored once, each block below it solved once
+    per sub-column, each later panel block updated once per earlier
+    sub-column of its panel, and each lower trailing block updated once per
+    earlier step: the decomposition covers Fig. 1 exactly."""
     g = dm.Geom(n, T)
     units = tc.chol_dag_enumerate(n, T, grid=16)
     seen = set()
@@ -215,19 +216,12 @@ def test_units_cover_every_block_update_once(tc, n, T):
         key = tuple(int(x) for x in u)
         assert key not in seen
         seen.add(key)
-    expect = set()
-    for J in range(g.M):
-        expect.add((dm.POTRF, J, J, -1, -1, -1))
-        for I in range(J + 1, g.M):
-            for a in range(g.sb(I)):
-                expect.add((dm.TRSM, J, I, a, -1, -1))
-            for K in range(J + 1, I + 1):
-                for a in range(g.sb(I)):
-                    for b in range(g.sb(K)):
-                        if I == K and b > a:
-                            continue
-                        expect.add((dm.UPDATE, J, I, a, K, b))
+    expect = set(dm.program_order_units(g))
     assert seen == expect
+    # hand count of the panel part for the first step
+    G = g.NRB
+    n_panel = sum(1 + (G - s - 1) + sum(G - t for t in range(s + 1, g.sb(0))) for s in range(g.sb(0)))
+    assert sum(1 for u in seen if u[1] == 0 and u[0] != dm.UPDATE) == n_panel
 
 
 def test_dropped_dependency_is_detected():
@@ -236,6 +230,7 @@ def test_dropped_dependency_is_detected():
     g = dm.Geom(512, 128)
     units = [list(u) for u in _program_order_units(g)]
     i_trsm = next(i for i, u in enumerate(units) if u[0] == dm.TRSM and u[2] == 2)
+    assert units[i_trsm][1] == 0
     i_gemm = next(i for i, u in enumerate(units) if u[0] == dm.UPDATE and u[2] == 2 and u[4] == 1)
     assert dm.check_ticket_order(g, units) == []
     units.insert(i_trsm, units.pop(i_gemm))
@@ -243,26 +238,13 @@ def test_dropped_dependency_is_detected():
 
 
 def _program_order_units(g):
-    out = []
-    for J in range(g.M):
-        out.append((dm.POTRF, J, J, -1, -1, -1))
-        for I in range(J + 1, g.M):
-            for a in range(g.sb(I)):
-                out.append((dm.TRSM, J, I, a, -1, -1))
-        for I in range(J + 1, g.M):
-            for K in range(J + 1, I + 1):
-                for a in range(g.sb(I)):
-                    for b in range(g.sb(K)):
-                        if I == K and b > a:
-                            continue
-                        out.append((dm.UPDATE, J, I, a, K, b))
-    return np.array(out, dtype=np.int32)
+    return np.array(dm.program_order_units(g), dtype=np.int32)
 
 
 @pytest.mark.parametrize("n,T", CASES)
 def test_forkjoin_update_launch_covers_each_step(tc, n, T):
-    """The launch order of each fork-join trailing update visits
-    every lower output block of the step's trailing matrix exactly once."""
+    """The launch order of each fork-join trailing update visits every lower
+    output block of the step's trailing matrix exactly once."""
     g = dm.Geom(n, T)
     for J in range(g.M):
         got = tc.chol_dag_forkjoin_update(n, T, J)
@@ -277,3 +259,12 @@ def test_forkjoin_update_launch_covers_each_step(tc, n, T):
                             continue
                         expect.add((dm.UPDATE, J, I, a, K, b))
         assert set(keys) == expect, J
+
+
+def test_timing_read_rejects_null_outputs(tc):
+    import ctypes
+    ms = (ctypes.c_double * 5)()
+    assert tc.lib.chol_timing_read(None, None, None) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 2
+    assert tc.lib.chol_timing_read(None, ms, None) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 3
