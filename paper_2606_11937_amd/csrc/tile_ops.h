@@ -449,14 +449,15 @@ __device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const doub
 //      definition on a 16 x 16 block): lane i holds row i, and the pivot
 //      and the column entries each step needs are read from their owner
 //      lanes;
-//   2. all waves: the rows below, 64 per wave at a time (one per lane):
+//   2. waves 0 and 1: the rows below, 64 per wave at a time (one per lane):
 //      MFMA products, then forward substitution against the new diagonal
 //      block (the in-tile TRSM).
 // A pivot d <= 0 or NaN stops the factorization: returns the 0-based
 // in-tile column, else -1.
 // ---------------------------------------------------------------------------
 struct alignas(16) TcPotrfSmem {
-  double buf[4][64 * 17];
+  double buf[2][64 * 17];    // products of the rows below (waves 0 and 1)
+  double dpart[4][16 * 17];  // partial products of the diagonal group
   double Lt[16 * TC_LT];
   int fail;
 };
@@ -474,7 +475,7 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
 #pragma unroll
     for (int k = 0; k < 16; ++k) a[k] = (own && k <= lane) ? dr[k] : 0.0;
     // diagonal group products, the chunks dealt to the four waves
-    if (c0 > 0) tc_ntg_lds<1>(Dc, nb, Dc, nb, lda, c0, w, 4, sm.buf[w]);
+    if (c0 > 0) tc_ntg_lds<1>(Dc, nb, Dc, nb, lda, c0, w, 4, sm.dpart[w]);
     __syncthreads();
     if (w == 0) {
       if (c0 > 0) {
@@ -482,7 +483,7 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
         for (int k = 0; k < 16; ++k)
           if (own && k <= lane) {
             const int q = lane * 17 + k;
-            a[k] = a[k] - (((sm.buf[0][q] + sm.buf[1][q]) + sm.buf[2][q]) + sm.buf[3][q]);
+            a[k] = a[k] - (((sm.dpart[0][q] + sm.dpart[1][q]) + sm.dpart[2][q]) + sm.dpart[3][q]);
           }
       }
       // unblocked factorization; every branch below is wave-uniform
@@ -525,11 +526,11 @@ __device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda
     __syncthreads();
     const int fail = tc_uniform((int32_t)sm.fail);
     if (fail >= 0) return fail;
-    // rows below the diagonal block, 64 per wave at a time
+    // rows below the diagonal block, 64 per wave of waves 0 and 1 at a time
     const int below = td - c0 - nb;
-    for (int rb = 0; rb < below; rb += 256) {
+    for (int rb = 0; rb < below; rb += 128) {
       const int rw0 = c0 + nb + rb + 64 * w;
-      const int myrows = td - rw0 < 64 ? td - rw0 : 64;
+      const int myrows = w < 2 ? (td - rw0 < 64 ? td - rw0 : 64) : 0;
       if (myrows > 0) {
         const bool mine = lane < myrows;
         double* xr = D + (int64_t)(rw0 + (mine ? lane : 0)) * lda + c0;
