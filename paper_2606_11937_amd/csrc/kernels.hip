@@ -154,19 +154,39 @@ __global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda,
   tc_run_trsm(A, lda, g, J, s, u.I, u.a, sm);
 }
 
+// The panel-update and trailing-update launches each carry the next POTRF:
+// launch index 0 is the update of the next diagonal block (sub-column s+1 of
+// the panel, or sub-column 0 of the next tile column), which is its POTRF's
+// only remaining input, so that workgroup factors the block right after
+// updating it.  The POTRF then overlaps the rest of the launch instead of
+// waiting for all of it plus a launch of its own; the operations and their
+// order per block are unchanged.
+union alignas(512) TcUpdPotrfSmem {
+  TcUpdSmem upd;
+  TcPotrfSmem potrf;
+};
+
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_panel(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                              TcWs ws) {
-  __shared__ TcUpdSmem sm;
+  __shared__ TcUpdPotrfSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const TcUnit u = tc_decode_panel(g, J, s, blockIdx.x);
-  tc_run_panel(A, lda, g, u, sm);
+  tc_run_panel(A, lda, g, u, sm.upd);
+  if (blockIdx.x == 0) {  // the update of diagonal block gid(J, s+1)
+    __syncthreads();
+    tc_run_potrf(A, lda, g, J, s + 1, ws.hdr, sm.potrf);
+  }
 }
 
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
-  __shared__ TcUpdSmem sm;
+  __shared__ TcUpdPotrfSmem sm;
   if (tc_err_set(ws.hdr)) return;
   const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
-  tc_run_update(A, lda, g, u, sm);
+  tc_run_update(A, lda, g, u, sm.upd);
+  if (blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
+    __syncthreads();
+    tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
+  }
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -389,11 +409,13 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, vo
   hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, words);
   if (int e = tc_chk(hipGetLastError())) return e;
   if (sched == 0) {
+    // POTRF(0, 0) is the only POTRF with a launch of its own; every other one
+    // rides at the head of the launch that finishes its input (see above)
+    tc_timed(TC_UNIT_POTRF, st, [&] {
+      hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
+    });
     for (int32_t J = 0; J < g.M; ++J) {
       for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
-        tc_timed(TC_UNIT_POTRF, st, [&] {
-          hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
-        });
         const int64_t nt = tc_trsm_count(g, J, sc);
         if (nt > 0)
           tc_timed(TC_UNIT_TRSM, st, [&] {
