@@ -46,7 +46,10 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
 # the counters were taken with: if the sources differ, the figure no longer
 # describes this kernel and the line reports traffic as null.
 TRAFFIC = {
-    # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources)
+    # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
+    # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
+    ("fork_join", 32768, 1024): (14799465677,
+                                 "af946bf1a24e32cd1ea65095f5193d33cc2d24e00c697422fe31767d0818b508"),
 }
 KERNEL_SOURCES = ["paper_2606_11937_amd/csrc/tile_ops.h", "paper_2606_11937_amd/csrc/kernels.hip",
                   "paper_2606_11937_amd/csrc/dag.h"]
