@@ -13,19 +13,21 @@
 // while the chain of 64 x 64 triangular solves runs.
 //
 // Rounding order, for bitwise reproducibility: for row i of block b and
-// right-hand side c, each of the four thread quarters p accumulates its 16
-// columns of every earlier block in ascending order, the quarters are
-// combined in order p = 0..3 and subtracted from B, and the in-block
-// substitution is sequential in the column index, dividing through the
-// reciprocal of the diagonal with one correction step (exact whenever the
-// quotient is representable).
+// right-hand side c, the forward sweep accumulates per lane over its four
+// columns of every earlier block, in block order, and sums the 16 lanes of
+// a row by a butterfly; the backward sweep accumulates each of four thread
+// quarters p over its 16 rows of every later block in block order and
+// combines the quarters in order p = 0..3.  The sum is subtracted from B and
+// the in-block substitution is sequential in the column index, dividing
+// through the reciprocal of the diagonal with one correction step (exact
+// whenever the quotient is representable).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
-#define SV_RC 16        // right-hand sides per pass
+#define SV_RC 8         // right-hand sides per pass
 #define SV_THREADS 256
 
 struct SvWs {
@@ -58,6 +60,18 @@ __device__ __forceinline__ int32_t sv_wait_above(const int32_t* cnt, int32_t nee
 }
 
 __device__ __forceinline__ int32_t sv_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroup-wide wait: thread 0 alone polls (the other waves sleep in the
+// barrier), and the value it saw reaches every thread through LDS.  One
+// thread-0 branch per call, between barriers, with a wave-uniform result.
+__device__ __forceinline__ int32_t sv_wait_wg(const int32_t* cnt, int32_t need, SvWs* ws, int64_t wait_ticks,
+                                              int32_t* slot) {
+  if (threadIdx.x == 0) *slot = sv_wait_above(cnt, need, ws, wait_ticks);
+  __syncthreads();
+  const int32_t v = sv_uniform(*slot);
+  __syncthreads();  // the slot is rewritten by the next call
+  return v;
+}
 
 // Publish block completion in sweep order: wait until `done` == pos, then
 // set it to pos + 1.  All threads have fenced their stores before.
@@ -98,18 +112,23 @@ __device__ __forceinline__ void sv_stage_diag(const double* __restrict__ L, int6
 }
 
 // ---------------------------------------------------------------- forward
-// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.  The L
-// values of block j + 1 are loaded while block j's contribution is formed, so
-// the load latency of the block that finishes last stays off the chain.  The
-// in-block substitution is one row per lane; each step broadcasts the new
-// unknown with a lane read and divides through the precomputed reciprocal.
+// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.
+// Fold layout: wave w, lane 16 rr + q covers rows 16 s + 4 w + rr (s < 4)
+// and columns 16 m + q (m < 4) of every earlier block, so each load
+// instruction reads four whole 128-byte row segments.  A lane accumulates
+// its 4 x 4 products of every block in block order; the 16 lanes of a row
+// are then summed by a butterfly.  The L values of block j + 1 are loaded
+// while block j is folded, so the load latency of the block that finishes
+// last stays off the chain.  The in-block substitution is one row per lane;
+// each step broadcasts the new unknown with a lane read and divides through
+// the precomputed reciprocal.
 __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                          SvWs* ws, int64_t wait_ticks) {
-  __shared__ double part[4][SV_NB][SV_RC + 1];
+  __shared__ double part[SV_NB][SV_RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_b;
+  __shared__ int32_t s_b, s_ready;
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -117,53 +136,74 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
   sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
-  // thread (r, p): row r, columns 16p .. 16p+15 of every earlier block
-  const int r = tid >> 2, p = tid & 3;
-  const bool live = r < nr;
-  const double* lrow = L + (r0 + (live ? r : 0)) * lda + 16 * p;
+  const int w = tid >> 6, lane = tid & 63, rr = lane >> 4, q = lane & 15;
+  const double* lrow[4];
+  bool live[4];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int row = 16 * s2 + 4 * w + rr;
+    live[s2] = row < nr;
+    lrow[s2] = L + (r0 + (live[s2] ? row : 0)) * lda + q;
+  }
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
     const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
-    double acc[SV_RC];
+    double acc[4][SV_RC];
 #pragma unroll
-    for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
-    double lc[16];
-    if (b > 0 && live) {
+    for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-      for (int k = 0; k < 16; ++k) lc[k] = lrow[k];
-    }
+      for (int c = 0; c < SV_RC; ++c) acc[s2][c] = 0.0;
+    double lc[4][4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) lc[s2][m] = (b > 0 && live[s2]) ? lrow[s2][16 * m] : 0.0;
     int32_t j = 0;
     while (j < b) {
-      const int32_t ready = sv_wait_above(&ws->done_f, j, ws, wait_ticks);
+      const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
       if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
       const int32_t jend = ready < b ? ready : b;
       for (; j < jend; ++j) {
-        if (!live) continue;
-        double ln[16];
         const int32_t jn = j + 1 < b ? j + 1 : j;  // the last block re-reads itself
+        double ln[4][4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) ln[k] = lrow[(int64_t)jn * SV_NB + k];
-        const double* yj = B + ((int64_t)j * SV_NB + 16 * p) * ldb + c0;
+        for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+          for (int m = 0; m < 4; ++m) ln[s2][m] = live[s2] ? lrow[s2][(int64_t)jn * SV_NB + 16 * m] : 0.0;
+        const double* yj = B + ((int64_t)j * SV_NB + q) * ldb + c0;
 #pragma unroll
-          for (int c = 0; c < SV_RC; ++c)
-            if (c < nc) acc[c] += lc[k] * yj[(int64_t)k * ldb + c];
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+          for (int c = 0; c < SV_RC; ++c) {
+            if (c < nc) {
+              const double y = yj[(int64_t)16 * m * ldb + c];
+#pragma unroll
+              for (int s2 = 0; s2 < 4; ++s2) acc[s2][c] += lc[s2][m] * y;
+            }
+          }
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) lc[s2][m] = ln[s2][m];
       }
     }
+    // butterfly over the 16 lanes of each row, then one lane writes the sum
 #pragma unroll
-    for (int c = 0; c < SV_RC; ++c) part[p][r][c] = acc[c];
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int c = 0; c < SV_RC; ++c) {
+        if (c < nc) {
+          double v = acc[s2][c];
+#pragma unroll
+          for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 16);
+          if (q == 0) part[16 * s2 + 4 * w + rr][c] = v;
+        }
+      }
     __syncthreads();
     // one wave per right-hand side: lane k holds row k of the block
-    const int w = tid >> 6, lane = tid & 63;
     for (int c = w; c < nc; c += 4) {
       double v = 0.0;
-      if (lane < nr) {
-        const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
-        v = B[(r0 + lane) * ldb + c0 + c] - s;
-      }
+      if (lane < nr) v = B[(r0 + lane) * ldb + c0 + c] - (b > 0 ? part[lane][c] : 0.0);
       // lane k keeps row k of the diagonal block, its pivot and reciprocal in
       // registers; each step is three lane reads and four dependent FP64
       // operations (rows past nr have a unit diagonal and zero entries)
@@ -194,7 +234,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
   __shared__ double part[4][SV_NB][SV_RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_t;
+  __shared__ int32_t s_t, s_ready;
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -228,7 +268,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
     if (b < nb - 1 && live) load_col(nb - 1, lc);
     int32_t j = nb - 1;
     while (j > b) {
-      const int32_t ready = sv_wait_above(&ws->done_b, nb - 1 - j, ws, wait_ticks);
+      const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
       if (ready < 0) break;
       const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
       for (; j >= jlow; --j) {
