@@ -3,6 +3,8 @@
     python bench.py [--steps K] [--warmup W] [--n 32768] [--T 1024]
                     [--sched fork_join|async_dag] [--no-cpu-baseline]
     python bench.py --sweep [--ns 8192,16384,32768] [--Ts 128,256,512,1024]
+                            [--scheds fork_join,async_dag,fork_join_naive,task_sync]
+                            [--noop]
 
 A step is one pass of the whole hot path over one resident synthetic input:
 chol_factor (tiled right-looking factorization: every POTRF, TRSM, SYRK and
@@ -21,7 +23,11 @@ The default run prints one JSON line (the contract line) with
   cpu_baseline  the CPU oracle timed on this host on a bounded sample.
 --sweep prints one JSON line per (n, T, schedule) with factor-only times
 (3 warm-ups, then the median of --reps runs with min and max); those lines
-are not the contract line.
+are not the contract line.  Schedules: fork_join (collapsed), async_dag,
+fork_join_naive and task_sync (the paper's other two variants).  With
+--noop the schedules run with empty unit bodies and the lines give the
+schedule's own cost per work unit (the per-task overhead of Results,
+"Problem Size Scaling").
 """
 from __future__ import annotations
 
@@ -70,7 +76,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--T", type=int, default=1024)
-    p.add_argument("--sched", default="fork_join", choices=["async_dag", "fork_join"])
+    p.add_argument("--sched", default="fork_join", choices=["async_dag", "fork_join", "fork_join_naive", "task_sync"])
     p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4096, help="order of the oracle's leading-block sample")
@@ -79,6 +85,7 @@ def parse():
     p.add_argument("--Ts", default="128,256,512,1024")
     p.add_argument("--scheds", default="fork_join,async_dag")
     p.add_argument("--reps", type=int, default=20)
+    p.add_argument("--noop", action="store_true", help="sweep with empty unit bodies (schedule overhead)")
     return p.parse_args()
 
 
@@ -102,7 +109,7 @@ def update_flops(n: int, T: int) -> float:
     return f
 
 
-def time_factor(tc, A0, T, sched, reps, warm=3):
+def time_factor(tc, A0, T, sched, reps, warm=3, noop=False):
     """Median / min / max device time (ms) of chol_factor on fresh copies."""
     import torch
     n = A0.shape[0]
@@ -114,7 +121,7 @@ def time_factor(tc, A0, T, sched, reps, warm=3):
         A.copy_(A0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        tc.chol_factor(A, T, sched, work=work, stream=st, sync=False)
+        tc.chol_factor(A, T, sched, work=work, stream=st, sync=False, noop=noop)
         e1.record(st)
         torch.cuda.synchronize()
         info = tc.chol_factor_info(work, st)
@@ -134,12 +141,16 @@ def sweep(args):
         torch.cuda.synchronize()
         for T in [int(x) for x in args.Ts.split(",")]:
             for sched in args.scheds.split(","):
-                med, lo, hi = time_factor(tc, A0, T, sched, args.reps)
-                tf = n ** 3 / 3 / (med * 1e-3) / 1e12
-                print(json.dumps({"kind": "sweep", "n": n, "T": T, "sched": sched, "reps": args.reps,
-                                  "ms_median": round(med, 3), "ms_min": round(lo, 3), "ms_max": round(hi, 3),
-                                  "tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)}),
-                      flush=True)
+                med, lo, hi = time_factor(tc, A0, T, sched, args.reps, noop=args.noop)
+                line = {"kind": "sweep", "n": n, "T": T, "sched": sched, "reps": args.reps,
+                        "ms_median": round(med, 3), "ms_min": round(lo, 3), "ms_max": round(hi, 3)}
+                if args.noop:
+                    units = tc.chol_dag_counts(n, T)["units"]
+                    line.update({"noop": True, "units": units, "us_per_unit": round(med * 1e3 / units, 4)})
+                else:
+                    tf = n ** 3 / 3 / (med * 1e-3) / 1e12
+                    line.update({"tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)})
+                print(json.dumps(line), flush=True)
         del A0
         torch.cuda.empty_cache()
 
@@ -199,7 +210,7 @@ def main():
     tc.chol_timing_read(st)  # discard anything recorded before
     # time the dominant kernel's launches only: every event pair costs a few
     # microseconds on the stream
-    tc.chol_timing_enable(["update"] if sched == "fork_join" else ["persistent"])
+    tc.chol_timing_enable(["update"] if sched in ("fork_join", "fork_join_naive") else ["persistent"])
     torch.cuda.synchronize()
     t_start.record(st)
     for k in range(K):
@@ -220,10 +231,15 @@ def main():
     flops = n ** 3 / 3
     value = flops / (ms_step * 1e-3) / 1e12
 
-    if sched == "fork_join":
-        kernel = "tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)"
+    if sched in ("fork_join", "fork_join_naive"):
+        kernel = ("tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)" if sched == "fork_join"
+                  else "tc_fj_update_naive (trailing update parallel over tile rows, one launch per step)")
         kms, kcount = launches["update"]
         kflops = update_flops(n, T) * K  # over the K timed factorizations
+    elif sched == "task_sync":
+        kernel = "tc_sync (persistent kernel with grid barriers, one launch per factorization)"
+        kms, kcount = launches["persistent"]
+        kflops = flops * K
     else:
         kernel = "tc_async (persistent DAG kernel, one launch per factorization)"
         kms, kcount = launches["persistent"]

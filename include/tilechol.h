@@ -70,8 +70,25 @@ enum {
   /* One persistent launch.  Workgroups take work units in a fixed
    * topological order from an atomic ticket, wait on per-block dependency
    * counters in the workspace, run the unit, and publish its completion. */
-  CHOL_SCHED_ASYNC_DAG = 1
+  CHOL_SCHED_ASYNC_DAG = 1,
+  /* The paper's naive fork-join variant: like CHOL_SCHED_FORK_JOIN, but the
+   * trailing update is parallel over tile rows only (one workgroup walks a
+   * whole tile row) and every POTRF has its own launch. */
+  CHOL_SCHED_FORK_JOIN_NAIVE = 2,
+  /* The paper's synchronous tasking variant: one persistent launch that
+   * walks the phases of the blocked program order (each POTRF, TRSM column,
+   * panel update and trailing update) with a grid-wide barrier after each
+   * phase.  It needs all its workgroups co-resident (it launches exactly
+   * the co-resident capacity); a barrier wait beyond chol_set_wait_limit
+   * ends the call with CHOL_ETIMEOUT instead of hanging. */
+  CHOL_SCHED_TASK_SYNC = 3
 };
+
+/* Flag ORed into `sched` to run the schedule with empty tile-operation
+ * bodies (launches, tickets, waits, barriers and counters only), to measure
+ * the schedule's own per-task cost.  A is left unchanged; the result is not
+ * a factorization. */
+#define CHOL_SCHED_NOOP 0x100
 
 /* Bytes of device workspace chol_factor needs for (n, T, sched); < 0 on
  * invalid arguments.  The workspace holds the dependency counters, the work
@@ -86,9 +103,10 @@ int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched);
 /* Factor A = L L^T in place (Methods, Fig. 1, right-looking tiled order).
  *   A          device pointer, n x n row-major with leading dimension lda.
  *   T          tile side, T >= 1.
- *   sched      CHOL_SCHED_FORK_JOIN or CHOL_SCHED_ASYNC_DAG; both run the
- *              same tile-operation bodies in the same per-tile update order
- *              (ascending J), so they return bit-identical factors.
+ *   sched      one of the CHOL_SCHED_* schedules, optionally ORed with
+ *              CHOL_SCHED_NOOP.  All schedules run the same work units
+ *              with the same bodies in the same per-block update order, so
+ *              they return bit-identical factors.
  *   work       device workspace of at least chol_factor_workspace_size bytes
  *              (may be NULL only when n == 0).
  *   stream     hipStream_t as void*.

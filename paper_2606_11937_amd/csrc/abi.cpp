@@ -14,6 +14,9 @@ static_assert(CHOL_BLOCK == TC_BLK, "sub-block size of the ABI and the kernels d
 static_assert(CHOL_UNIT_POTRF == TC_UNIT_POTRF && CHOL_UNIT_TRSM == TC_UNIT_TRSM &&
                   CHOL_UNIT_UPDATE == TC_UNIT_UPDATE && CHOL_UNIT_PANEL == TC_UNIT_PANEL,
               "unit kinds of the ABI and the kernels differ");
+static_assert(CHOL_SCHED_FORK_JOIN == 0 && CHOL_SCHED_ASYNC_DAG == 1 && CHOL_SCHED_FORK_JOIN_NAIVE == 2 &&
+                  CHOL_SCHED_TASK_SYNC == 3 && CHOL_SCHED_NOOP == TC_SCHED_NOOP,
+              "schedule codes of the ABI and the launcher differ");
 static_assert(TC_TIMING_KINDS == 5 && TC_TIMING_PERSISTENT == 4, "timing kinds of the ABI and the launcher differ");
 
 namespace {
@@ -44,12 +47,17 @@ int status_from(int32_t err, int64_t dinfo, int64_t* info) {
   return CHOL_OK;
 }
 
+bool sched_valid(int sched) {
+  const int base = sched & 0xff, flags = sched & ~0xff;
+  return base >= CHOL_SCHED_FORK_JOIN && base <= CHOL_SCHED_TASK_SYNC && (flags & ~CHOL_SCHED_NOOP) == 0;
+}
+
 int check_factor_args(double* A, int64_t n, int64_t lda, int64_t T, int sched) {
   if (n < 0 || n > kMaxN) return bad(2);
   if (lda < max1(n) || lda > kMaxN) return bad(3);
   if (T < 1) return bad(4);
-  if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(5);
-  if (sched == CHOL_SCHED_ASYNC_DAG && n > 0 && tc_cdiv(n, T) > CHOL_ASYNC_MAX_TILES) return bad(4);
+  if (!sched_valid(sched)) return bad(5);
+  if ((sched & 0xff) == CHOL_SCHED_ASYNC_DAG && n > 0 && tc_cdiv(n, T) > CHOL_ASYNC_MAX_TILES) return bad(4);
   if (n > 0 && A == nullptr) return bad(1);
   return CHOL_OK;
 }
@@ -86,7 +94,7 @@ int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched) {
   g_bad_arg = 0;
   if (n < 0 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
-  if (sched != CHOL_SCHED_FORK_JOIN && sched != CHOL_SCHED_ASYNC_DAG) return bad(3);
+  if (!sched_valid(sched)) return bad(3);
   return tc_ws_bytes(n > 0 ? n : 1, T);
 }
 
@@ -102,8 +110,8 @@ int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* w
   if (work_bytes < tc_ws_bytes(n, T)) return bad(7, CHOL_EWORKSPACE);
   hipStream_t st = (hipStream_t)stream;
   int64_t grid = 0;
-  if (sched == CHOL_SCHED_ASYNC_DAG) {
-    grid = tc_async_grid_size();
+  if ((sched & 0xff) == CHOL_SCHED_ASYNC_DAG || (sched & 0xff) == CHOL_SCHED_TASK_SYNC) {
+    grid = (sched & 0xff) == CHOL_SCHED_ASYNC_DAG ? tc_async_grid_size() : tc_sync_grid_size();
     if (grid <= 0) return CHOL_EDEVICE;
   }
   if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks()) != 0) return CHOL_EDEVICE;

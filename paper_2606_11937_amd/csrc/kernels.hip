@@ -31,6 +31,7 @@ struct TcWsHeader {
   int32_t ticket;
   int32_t error;  // 0 ok, 1 not SPD, 2 dependency-wait timeout
   int64_t info;   // failing global column + 1
+  int32_t bar;    // arrivals at the grid barriers of the synchronous schedule
 };
 
 struct TcWs {
@@ -38,6 +39,7 @@ struct TcWs {
   int64_t* offs;
   int32_t* pdone;
   int32_t* ver;
+  int32_t noop;  // measurement mode: run the schedule with empty unit bodies
 };
 
 static inline int64_t tc_round256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -61,6 +63,7 @@ static TcWs tc_ws_map(void* base, const TcGeom& g) {
   w.pdone = (int32_t*)p;
   p += tc_round256(4 * (int64_t)g.NRB);
   w.ver = (int32_t*)p;
+  w.noop = 0;
   return w;
 }
 
@@ -142,14 +145,14 @@ __device__ __forceinline__ void tc_run_panel(double* A, int64_t lda, const TcGeo
 __global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                           TcWs ws) {
   __shared__ TcPotrfSmem sm;
-  if (tc_err_set(ws.hdr)) return;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
   tc_run_potrf(A, lda, g, J, s, ws.hdr, sm);
 }
 
 __global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                          TcWs ws) {
   __shared__ TcTrsmSmem sm;
-  if (tc_err_set(ws.hdr)) return;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
   const TcUnit u = tc_decode_trsm(g, J, s, blockIdx.x);
   tc_run_trsm(A, lda, g, J, s, u.I, u.a, sm);
 }
@@ -169,7 +172,7 @@ union alignas(512) TcUpdPotrfSmem {
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_panel(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                              TcWs ws) {
   __shared__ TcUpdPotrfSmem sm;
-  if (tc_err_set(ws.hdr)) return;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
   const TcUnit u = tc_decode_panel(g, J, s, blockIdx.x);
   tc_run_panel(A, lda, g, u, sm.upd);
   if (blockIdx.x == 0) {  // the update of diagonal block gid(J, s+1)
@@ -178,15 +181,44 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_panel(double* A, int64_t 
   }
 }
 
+// Panel update without the fused POTRF (the naive variant launches every
+// POTRF on its own).
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_panel_only(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                  int32_t s, TcWs ws) {
+  __shared__ TcUpdSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const TcUnit u = tc_decode_panel(g, J, s, blockIdx.x);
+  tc_run_panel(A, lda, g, u, sm);
+}
+
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws) {
   __shared__ TcUpdPotrfSmem sm;
-  if (tc_err_set(ws.hdr)) return;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
   const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
   tc_run_update(A, lda, g, u, sm.upd);
   if (blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
     __syncthreads();
     tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
   }
+}
+
+// Naive fork-join (the paper's first variant): the trailing update is
+// parallel over tile rows I only; one workgroup walks the whole row, SYRK
+// block (a, b <= a) then the GEMM tiles K = J+1 .. I-1, one block at a time.
+// Same blocks, same arithmetic, far less parallelism.
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_naive(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                    TcWs ws) {
+  __shared__ TcUpdSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const int32_t I = J + 1 + (int32_t)blockIdx.x;
+  for (int32_t K = J + 1; K <= I; ++K)
+    for (int32_t a = 0; a < tc_sb(g, I); ++a)
+      for (int32_t b = 0; b < tc_sb(g, K); ++b) {
+        if (I == K && b > a) continue;
+        const TcUnit u = {TC_UNIT_UPDATE, J, I, a, K, b};
+        tc_run_update(A, lda, g, u, sm);
+        __syncthreads();
+      }
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -314,7 +346,9 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     const TcUnit u = {tc_ctx32(s_unit.kind), tc_ctx32(s_unit.J), tc_ctx32(s_unit.I),
                       tc_ctx32(s_unit.a), tc_ctx32(s_unit.K), tc_ctx32(s_unit.b)};
     const TcGeom cg = tc_ctx_geom(s_ctx.g);
-    if (u.kind == TC_UNIT_UPDATE) {
+    if (ws.noop) {
+      // measurement mode: the schedule's own cost only
+    } else if (u.kind == TC_UNIT_UPDATE) {
       tc_run_update(A, lda, cg, u, sm.upd);
     } else if (u.kind == TC_UNIT_PANEL) {
       tc_run_panel(A, lda, cg, u, sm.upd);
@@ -326,6 +360,76 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // every wave makes its stores visible device-wide before the unit is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
+  }
+}
+
+// Synchronous tasking (the paper's task-synchronous variant, tasks with a
+// taskwait after each phase): one persistent launch walks the phases of the
+// blocked program order, for each step J and sub-column s the POTRF, the
+// TRSM column and the panel update, then the trailing update; inside a phase
+// workgroup w takes units w, w + grid, ...; a grid-wide barrier separates
+// phases.  The units, and each block's update order, are those of the other
+// schedules, so the factor is the same bits.  Every barrier wait is bounded
+// by the wall-clock limit and by the error flag.
+__device__ __forceinline__ int32_t tc_grid_barrier(const TcWs& ws, int64_t target, int64_t wait_ticks,
+                                                   int32_t* s_go) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t go = 1;
+    __hip_atomic_fetch_add(&ws.hdr->bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(&ws.hdr->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (tc_err_set(ws.hdr)) { go = 0; break; }
+      if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(ws.hdr, 2, 0); go = 0; break; }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_go = go;
+  }
+  __syncthreads();
+  return tc_uniform(*s_go);
+}
+
+__global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_sync(
+    double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
+  __shared__ TcSmem sm;
+  __shared__ int32_t s_go;
+  const int64_t grid = gridDim.x;
+  int64_t phase = 0;
+  for (int32_t J = 0; J < g.M; ++J) {
+    const int32_t sbJ = tc_sb(g, J);
+    for (int32_t sc = 0; sc < sbJ; ++sc) {
+      for (int32_t link = 0; link < 3; ++link) {
+        const int64_t cnt = link == 0 ? 1 : link == 1 ? tc_trsm_count(g, J, sc) : tc_panel_count(g, J, sc);
+        for (int64_t i = blockIdx.x; i < cnt && !ws.noop; i += grid) {
+          if (link == 0) {
+            tc_run_potrf(A, lda, g, J, sc, ws.hdr, sm.potrf);
+          } else if (link == 1) {
+            const TcUnit u = tc_decode_trsm(g, J, sc, i);
+            tc_run_trsm(A, lda, g, J, sc, u.I, u.a, sm.trsm);
+          } else {
+            const TcUnit u = tc_decode_panel(g, J, sc, i);
+            tc_run_panel(A, lda, g, u, sm.upd);
+          }
+          __syncthreads();
+        }
+        if (cnt > 0) {
+          ++phase;
+          if (!tc_grid_barrier(ws, phase * grid, wait_ticks, &s_go)) return;
+        }
+      }
+    }
+    const int64_t nu = tc_trailing_units(g, J);
+    for (int64_t i = blockIdx.x; i < nu && !ws.noop; i += grid) {
+      const TcUnit u = tc_decode_trailing(g, J, J, i);
+      tc_run_update(A, lda, g, u, sm.upd);
+      __syncthreads();
+    }
+    if (nu > 0) {
+      ++phase;
+      if (!tc_grid_barrier(ws, phase * grid, wait_ticks, &s_go)) return;
+    }
   }
 }
 
@@ -400,14 +504,49 @@ int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TI
   return rc;
 }
 
-int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
+int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks) {
+  const int sched = sched_flags & 0xff;
   TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid));
   TcWs ws = tc_ws_map(work, g);
+  ws.noop = (sched_flags & TC_SCHED_NOOP) ? 1 : 0;
   // clear header and counters with a fill kernel (graph-capture friendly)
   const int64_t words = (tc_ws_bytes(n, T)) / 4;
   hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, words);
   if (int e = tc_chk(hipGetLastError())) return e;
+  if (sched == 2) {
+    // naive fork-join: a launch per POTRF, per TRSM column and per panel
+    // update of each sub-column, then the row-parallel trailing update
+    for (int32_t J = 0; J < g.M; ++J) {
+      for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
+        tc_timed(TC_UNIT_POTRF, st, [&] {
+          hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+        });
+        const int64_t nt = tc_trsm_count(g, J, sc);
+        if (nt > 0)
+          tc_timed(TC_UNIT_TRSM, st, [&] {
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+        const int64_t np = tc_panel_count(g, J, sc);
+        if (np > 0)
+          tc_timed(TC_UNIT_PANEL, st, [&] {
+            hipLaunchKernelGGL(tc_fj_panel_only, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+      }
+      if (J + 1 < g.M)
+        tc_timed(TC_UNIT_UPDATE, st, [&] {
+          hipLaunchKernelGGL(tc_fj_update_naive, dim3((unsigned)(g.M - 1 - J)), dim3(TC_THREADS), 0, st, A, lda, g, J,
+                             ws);
+        });
+    }
+    return tc_chk(hipGetLastError());
+  }
+  if (sched == 3) {
+    tc_timed(TC_TIMING_PERSISTENT, st, [&] {
+      hipLaunchKernelGGL(tc_sync, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
+    });
+    return tc_chk(hipGetLastError());
+  }
   if (sched == 0) {
     // POTRF(0, 0) is the only POTRF with a launch of its own; every other one
     // rides at the head of the launch that finishes its input (see above)
@@ -452,16 +591,28 @@ int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* in
   return 0;
 }
 
-int64_t tc_async_grid_size() {
-  static int64_t cached[64] = {0};
+// Co-resident workgroups of a persistent kernel on the current device
+// (occupancy x CUs), cached per device and kernel.
+template <typename K>
+static int64_t tc_persistent_grid(K kernel, int64_t* cache) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
-  if (dev >= 0 && dev < 64 && cached[dev] > 0) return cached[dev];
+  if (dev >= 0 && dev < 64 && cache[dev] > 0) return cache[dev];
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tc_async, TC_THREADS, 0) != hipSuccess) return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TC_THREADS, 0) != hipSuccess) return -1;
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, dev) != hipSuccess) return -1;
   int64_t gsz = (int64_t)(per_cu > 0 ? per_cu : 1) * p.multiProcessorCount;
-  if (dev >= 0 && dev < 64) cached[dev] = gsz;
+  if (dev >= 0 && dev < 64) cache[dev] = gsz;
   return gsz;
+}
+
+int64_t tc_async_grid_size() {
+  static int64_t cached[64] = {0};
+  return tc_persistent_grid(tc_async, cached);
+}
+
+int64_t tc_sync_grid_size() {
+  static int64_t cached[64] = {0};
+  return tc_persistent_grid(tc_sync, cached);
 }

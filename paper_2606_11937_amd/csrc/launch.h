@@ -8,9 +8,13 @@
 
 // Workspace bytes chol_factor needs (both schedules use one layout).
 int64_t tc_ws_bytes(int64_t n, int64_t T);
-// Enqueue one factorization.  grid: persistent workgroups (async only);
-// wait_ticks: dependency-wait limit in wall-clock ticks (async only).
-int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* work, hipStream_t st,
+// Enqueue one factorization.  sched_flags: schedule 0 fork-join, 1 async
+// DAG, 2 naive fork-join, 3 synchronous tasking, optionally ORed with
+// TC_SCHED_NOOP (empty unit bodies, for measuring the schedule's own cost).
+// grid: persistent workgroups (1 and 3); wait_ticks: wait limit in
+// wall-clock ticks (1 and 3).
+#define TC_SCHED_NOOP 0x100
+int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks);
 // Per-launch timing of tc_launch_factor on the calling thread (measurement
 // aid): enable takes a mask of the kinds to time (bit k for kind k) and
@@ -23,8 +27,9 @@ int tc_timing_enable(int mask);
 int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TIMING_KINDS]);
 // Synchronise the stream and read the error flag / info of a workspace.
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info);
-// Co-resident workgroups of the persistent kernel on the current device.
+// Co-resident workgroups of the persistent kernels on the current device.
 int64_t tc_async_grid_size();
+int64_t tc_sync_grid_size();
 // Workspace bytes of the solve (block tickets and done counters).
 int64_t tc_solve_ws_bytes();
 // Enqueue forward + backward substitution (64-row blocks).

@@ -24,9 +24,13 @@ CHOL_EWORKSPACE = -3
 CHOL_ETIMEOUT = -4
 CHOL_SCHED_FORK_JOIN = 0
 CHOL_SCHED_ASYNC_DAG = 1
+CHOL_SCHED_FORK_JOIN_NAIVE = 2
+CHOL_SCHED_TASK_SYNC = 3
+CHOL_SCHED_NOOP = 0x100
 CHOL_BLOCK = 128
 CHOL_ASYNC_MAX_TILES = 1024
-SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG}
+SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG,
+             "fork_join_naive": CHOL_SCHED_FORK_JOIN_NAIVE, "task_sync": CHOL_SCHED_TASK_SYNC}
 
 # (name, restype, argtypes) for every symbol of include/tilechol.h
 _i64, _int, _dbl, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -118,17 +122,20 @@ def factor_workspace(n: int, T: int, sched="fork_join", device="cuda"):
 
 
 def chol_factor(A, T: int, sched="fork_join", n: int | None = None, work=None, stream=None,
-                sync: bool = True) -> int:
+                sync: bool = True, noop: bool = False) -> int:
     """Factor A (n x n view of a row-major float64 GPU tensor) in place.
     Returns info (0, or k > 0 for a non-positive-definite leading minor of
-    order k) when sync, else None.  Raises TileCholError on errors."""
+    order k) when sync, else None.  Raises TileCholError on errors.
+    noop=True runs the schedule with empty unit bodies (measurement only;
+    A is left unchanged)."""
     _check_matrix(A)
     n = A.shape[0] if n is None else n
     lda = A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1])
     if work is None:
         work = factor_workspace(n, T, sched, A.device)
     info = ctypes.c_int64(0)
-    st = lib.chol_factor(ctypes.c_void_p(A.data_ptr()), n, lda, T, _sched(sched),
+    code = _sched(sched) | (CHOL_SCHED_NOOP if noop else 0)
+    st = lib.chol_factor(ctypes.c_void_p(A.data_ptr()), n, lda, T, code,
                          ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream),
                          ctypes.byref(info) if sync else None)
     if st not in (CHOL_OK, CHOL_NOT_SPD):

@@ -267,3 +267,70 @@ def test_batched_uneven_sizes(tc):
     bufs = [torch.from_numpy(A).cuda() for A in (As[2], Bad, As[4])]
     infos = tc.chol_factor_batched(bufs, Ts=[64, 64, 64])
     assert infos[0] == 0 and infos[2] == 0 and infos[1] == oracle.potrf(Bad)[1]
+
+
+# ----------------------------------------------- the paper's other variants
+ALL_SCHEDS = ("fork_join", "async_dag", "fork_join_naive", "task_sync")
+
+
+@pytest.mark.parametrize("n,T", [(1000, 128), (777, 256), (1536, 512), (640, 1024), (300, 96)])
+def test_all_schedules_same_bits(tc, n, T):
+    """Naive fork-join and synchronous tasking run the same units with the
+    same bodies in the same per-block order: bit-identical to the other two,
+    and within tolerance of the oracle."""
+    say(f"[all schedules] n={n} T={T}")
+    A = inputs.se_kernel(n, seed=41)
+    Lref, _ = oracle.potrf(A)
+    outs = {}
+    for sched in ALL_SCHEDS:
+        L, info = gpu_factor(tc, A, T, sched)
+        assert info == 0, sched
+        outs[sched] = L
+    for sched in ALL_SCHEDS[1:]:
+        assert lower_equal(outs[sched], outs["fork_join"]), sched
+    assert oracle.row_scaled_error(outs["fork_join"], Lref, A) <= E_ROW_TOL
+
+
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync"])
+def test_variants_integer_factor_bitwise(tc, sched):
+    A, L0 = inputs.integer_factor(640, seed=42)
+    L, info = gpu_factor(tc, A, 256, sched)
+    assert info == 0
+    assert lower_equal(L, L0)
+
+
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync"])
+def test_variants_report_not_spd(tc, sched):
+    n, col = 512, 300
+    A, L0 = inputs.integer_factor(n, seed=43)
+    A[col, col] = float(np.sum(L0[col, :col] ** 2)) - 1.0
+    _, info = gpu_factor(tc, A, 128, sched)
+    assert info == col + 1
+
+
+def test_task_sync_wait_limit_never_hangs(tc):
+    import torch
+    A = inputs.gg_plus_identity(1024, seed=44)
+    prev = tc.chol_set_wait_limit(0.0)
+    try:
+        buf = torch.from_numpy(A).cuda()
+        try:
+            info = tc.chol_factor(buf, 128, "task_sync")
+            assert info == 0
+        except tc.TileCholError as e:
+            assert e.status == tc.CHOL_ETIMEOUT
+    finally:
+        tc.chol_set_wait_limit(prev)
+    L, info = gpu_factor(tc, A, 128, "task_sync")
+    assert info == 0
+
+
+@pytest.mark.parametrize("sched", ALL_SCHEDS)
+def test_noop_mode_leaves_the_matrix(tc, sched):
+    """CHOL_SCHED_NOOP runs only the schedule (launches, tickets, waits,
+    barriers): A must come back untouched and the call must succeed."""
+    import torch
+    A = inputs.gg_plus_identity(768, seed=45)
+    buf = torch.from_numpy(A).cuda()
+    assert tc.chol_factor(buf, 128, sched, noop=True) == 0
+    assert np.array_equal(buf.cpu().numpy(), A)
