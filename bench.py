@@ -86,6 +86,9 @@ def parse():
     p.add_argument("--scheds", default="fork_join,async_dag")
     p.add_argument("--reps", type=int, default=20)
     p.add_argument("--noop", action="store_true", help="sweep with empty unit bodies (schedule overhead)")
+    p.add_argument("--Ms", default=None, help="fixed tile counts per dimension: T = ceil(n / M) (overrides --Ts)")
+    p.add_argument("--lookaheads", default=None,
+                   help="async ticket-order ablation: bulk units per chain link, e.g. -1,0,1000000000")
     return p.parse_args()
 
 
@@ -139,18 +142,25 @@ def sweep(args):
     for n in [int(x) for x in args.ns.split(",")]:
         A0 = make_input(n)
         torch.cuda.synchronize()
-        for T in [int(x) for x in args.Ts.split(",")]:
-            for sched in args.scheds.split(","):
-                med, lo, hi = time_factor(tc, A0, T, sched, args.reps, noop=args.noop)
-                line = {"kind": "sweep", "n": n, "T": T, "sched": sched, "reps": args.reps,
-                        "ms_median": round(med, 3), "ms_min": round(lo, 3), "ms_max": round(hi, 3)}
-                if args.noop:
-                    units = tc.chol_dag_counts(n, T)["units"]
-                    line.update({"noop": True, "units": units, "us_per_unit": round(med * 1e3 / units, 4)})
-                else:
-                    tf = n ** 3 / 3 / (med * 1e-3) / 1e12
-                    line.update({"tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)})
-                print(json.dumps(line), flush=True)
+        Ts = [-(-n // int(M)) for M in args.Ms.split(",")] if args.Ms else [int(x) for x in args.Ts.split(",")]
+        looks = [int(x) for x in args.lookaheads.split(",")] if args.lookaheads else [None]
+        for T, sched, look in [(T, s, l) for T in Ts for s in args.scheds.split(",") for l in looks]:
+            if look is not None:
+                tc.chol_set_lookahead(look)
+            med, lo, hi = time_factor(tc, A0, T, sched, args.reps, noop=args.noop)
+            if look is not None:
+                tc.chol_set_lookahead(-1)
+            line = {"kind": "sweep", "n": n, "T": T, "M": -(-n // T), "sched": sched, "reps": args.reps,
+                    "ms_median": round(med, 3), "ms_min": round(lo, 3), "ms_max": round(hi, 3)}
+            if look is not None:
+                line["lookahead"] = look
+            if args.noop:
+                units = tc.chol_dag_counts(n, T)["units"]
+                line.update({"noop": True, "units": units, "us_per_unit": round(med * 1e3 / units, 4)})
+            else:
+                tf = n ** 3 / 3 / (med * 1e-3) / 1e12
+                line.update({"tflops": round(tf, 2), "frac_fp64_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)})
+            print(json.dumps(line), flush=True)
         del A0
         torch.cuda.empty_cache()
 

@@ -162,7 +162,8 @@ int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, 
                         const int64_t* T, void* work, int64_t work_bytes, void* stream,
                         int64_t* info);
 
-/* Tile side the library picks for order n when the caller passes none. */
+/* Tile side the library picks for order n when the caller passes none
+ * (deterministic in n; from measured factor times). */
 int64_t chol_default_tile(int64_t n);
 
 /* ---- introspection of the tile DAG (host only; no device is touched) ----
@@ -225,6 +226,15 @@ int64_t chol_async_grid(void);
  * CHOL_OK, CHOL_EINVAL (NULL output) or CHOL_EDEVICE. */
 int chol_timing_enable(int kinds);
 int chol_timing_read(void* stream, double ms[5], int64_t launches[5]);
+
+/* Dispatch-order knob of the asynchronous schedule (the paper's task
+ * priorities, here a property of the ticket order): the number of bulk
+ * trailing-update units placed after each link of a panel chain.  Negative
+ * restores the default (one per persistent workgroup); 0 puts each panel's
+ * whole chain ahead of the previous step's bulk update; a value at least
+ * that bulk's size puts the bulk first (no lookahead).  Process-wide; also
+ * used by chol_dag_enumerate.  Returns the previous setting. */
+int64_t chol_set_lookahead(int64_t units);
 
 /* Upper bound in seconds on any single dependency wait of the asynchronous
  * schedule (default 10).  A wait that exceeds it ends the factorization

@@ -22,6 +22,7 @@ static_assert(TC_TIMING_KINDS == 5 && TC_TIMING_PERSISTENT == 4, "timing kinds o
 namespace {
 thread_local int g_bad_arg = 0;
 std::atomic<double> g_wait_limit_s{10.0};
+std::atomic<int64_t> g_lookahead{-1};
 
 int bad(int idx, int code = CHOL_EINVAL) {
   g_bad_arg = idx;
@@ -84,10 +85,13 @@ double chol_set_wait_limit(double seconds) {
   return g_wait_limit_s.exchange(seconds);
 }
 
+int64_t chol_set_lookahead(int64_t units) { return g_lookahead.exchange(units < 0 ? -1 : units); }
+
 int64_t chol_default_tile(int64_t n) {
-  if (n <= 4096) return 128;
-  if (n <= 16384) return 256;
-  return 512;
+  // measured on MI355X (factor time against T, fork-join): small orders are
+  // launch-bound and prefer short panels, large ones deep updates
+  if (n <= 8192) return 128;
+  return 1024;
 }
 
 int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched) {
@@ -114,7 +118,8 @@ int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* w
     grid = (sched & 0xff) == CHOL_SCHED_ASYNC_DAG ? tc_async_grid_size() : tc_sync_grid_size();
     if (grid <= 0) return CHOL_EDEVICE;
   }
-  if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks()) != 0) return CHOL_EDEVICE;
+  if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks(), tc_lookahead_chunk(grid, g_lookahead.load())) != 0)
+    return CHOL_EDEVICE;
   if (info == nullptr) return CHOL_OK;
   int32_t err = 0;
   int64_t dinfo = 0;
@@ -195,7 +200,7 @@ int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, 
   for (int64_t i = 0; i < batch; ++i) {
     const int64_t t = T ? T[i] : chol_default_tile(n[i]);
     const int64_t nb = n[i] > 0 ? n[i] : 1;
-    if (n[i] > 0 && tc_launch_factor(A[i], n[i], lda[i], t, CHOL_SCHED_FORK_JOIN, w, st, 0, 0) != 0)
+    if (n[i] > 0 && tc_launch_factor(A[i], n[i], lda[i], t, CHOL_SCHED_FORK_JOIN, w, st, 0, 0, 0) != 0)
       return CHOL_EDEVICE;
     w += (tc_ws_bytes(nb, t) + 255) & ~(int64_t)255;
   }
@@ -238,7 +243,7 @@ int64_t chol_dag_enumerate(int64_t n, int64_t T, int64_t grid, int32_t* out, int
   if (grid < 1) return bad(3);
   if (cap < 0) return bad(5);
   if (cap > 0 && out == nullptr) return bad(4);
-  TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid));
+  TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid, g_lookahead.load()));
   int64_t k = 0;
   for (int32_t P = 0; P < g.M; ++P) {
     const int64_t sz = tc_phase_size(g, P);

@@ -505,9 +505,9 @@ int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TI
 }
 
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
-                     int64_t grid, int64_t wait_ticks) {
+                     int64_t grid, int64_t wait_ticks, int64_t chunk) {
   const int sched = sched_flags & 0xff;
-  TcGeom g = tc_geom(n, T, tc_lookahead_chunk(grid));
+  TcGeom g = tc_geom(n, T, chunk);
   TcWs ws = tc_ws_map(work, g);
   ws.noop = (sched_flags & TC_SCHED_NOOP) ? 1 : 0;
   // clear header and counters with a fill kernel (graph-capture friendly)

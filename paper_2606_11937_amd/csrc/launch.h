@@ -12,10 +12,11 @@ int64_t tc_ws_bytes(int64_t n, int64_t T);
 // DAG, 2 naive fork-join, 3 synchronous tasking, optionally ORed with
 // TC_SCHED_NOOP (empty unit bodies, for measuring the schedule's own cost).
 // grid: persistent workgroups (1 and 3); wait_ticks: wait limit in
-// wall-clock ticks (1 and 3).
+// wall-clock ticks (1 and 3); chunk: bulk units after each panel-chain link
+// in the ticket order (1).
 #define TC_SCHED_NOOP 0x100
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
-                     int64_t grid, int64_t wait_ticks);
+                     int64_t grid, int64_t wait_ticks, int64_t chunk);
 // Per-launch timing of tc_launch_factor on the calling thread (measurement
 // aid): enable takes a mask of the kinds to time (bit k for kind k) and
 // returns the previous mask; read synchronises `st`, sums the

@@ -51,6 +51,7 @@ SIGNATURES = [
     ("chol_timing_read", _int, [_vp, ctypes.POINTER(_dbl), _pi64]),
     ("chol_async_grid", _i64, []),
     ("chol_set_wait_limit", _dbl, [_dbl]),
+    ("chol_set_lookahead", _i64, [_i64]),
     ("chol_last_bad_arg", _int, []),
     ("chol_status_str", ctypes.c_char_p, [_int]),
 ]
@@ -281,3 +282,9 @@ def chol_async_grid() -> int:
 
 def chol_set_wait_limit(seconds: float) -> float:
     return float(lib.chol_set_wait_limit(seconds))
+
+
+def chol_set_lookahead(units: int) -> int:
+    """Bulk units after each panel-chain link in the asynchronous ticket
+    order (-1 default, 0 chain first, large = no lookahead)."""
+    return int(lib.chol_set_lookahead(units))

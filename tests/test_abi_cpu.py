@@ -270,3 +270,20 @@ def test_timing_read_rejects_null_outputs(tc):
     assert tc.last_bad_arg() == 2
     assert tc.lib.chol_timing_read(None, ms, None) == tc.CHOL_EINVAL
     assert tc.last_bad_arg() == 3
+
+
+@pytest.mark.parametrize("look", [0, 1, 7, 10 ** 9])
+@pytest.mark.parametrize("n,T", [(1000, 96), (2048, 512), (1536, 200)])
+def test_lookahead_setting_keeps_the_order_topological(tc, look, n, T):
+    """Every dispatch-order setting (chain first, bulk first, in between)
+    is still a topological order covering the same units."""
+    prev = tc.chol_set_lookahead(look)
+    try:
+        g = dm.Geom(n, T)
+        units = tc.chol_dag_enumerate(n, T, grid=16)
+        assert dm.check_ticket_order(g, units) == []
+        assert set(tuple(int(x) for x in u) for u in units) == set(dm.program_order_units(g))
+    finally:
+        tc.chol_set_lookahead(prev)
+    assert tc.chol_set_lookahead(-5) == prev  # negative restores the default
+    assert tc.chol_set_lookahead(prev) == -1
