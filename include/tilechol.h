@@ -230,7 +230,7 @@ int chol_timing_read(void* stream, double ms[5], int64_t launches[5]);
 /* Dispatch-order knob of the asynchronous schedule (the paper's task
  * priorities, here a property of the ticket order): the number of bulk
  * trailing-update units placed after each link of a panel chain.  Negative
- * restores the default (one per persistent workgroup); 0 puts each panel's
+ * restores the default (half the persistent grid); 0 puts each panel's
  * whole chain ahead of the previous step's bulk update; a value at least
  * that bulk's size puts the bulk first (no lookahead).  Process-wide; also
  * used by chol_dag_enumerate.  Returns the previous setting. */
