@@ -54,8 +54,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
 TRAFFIC = {
     # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
-    ("fork_join", 32768, 1024): (14799465677,
-                                 "af946bf1a24e32cd1ea65095f5193d33cc2d24e00c697422fe31767d0818b508"),
+    ("fork_join", 32768, 1024): (14799225651,
+                                 "2c8510bb43785aa7fcc6aa855d50bfa15596960a5c2e99bebbb161163d976c55"),
 }
 KERNEL_SOURCES = ["paper_2606_11937_amd/csrc/tile_ops.h", "paper_2606_11937_amd/csrc/kernels.hip",
                   "paper_2606_11937_amd/csrc/dag.h"]
