@@ -13,6 +13,11 @@ recipes below are those workloads at fixed seeds:
   integer_factor(n, seed)     an integer lower-triangular L0 with positive
                               diagonal and A = L0 L0^T computed exactly; every
                               correct FP64 Cholesky returns L0 bit for bit.
+  integer_factor_norm4(n, seed)
+                              the same with every row of L0 of Euclidean
+                              norm 4 (diag(A) = 16), so that diagonal scaling
+                              divides by powers of two and L0 / 4 has
+                              quarter-integer entries: exact in FP32 and BF16.
 
 Both sides of a parity test receive the identical FP64 bytes produced here.
 """
@@ -87,4 +92,27 @@ def integer_factor(n: int, seed: int = 0, diag_max: int = 3, off_max: int = 2,
     L0 += np.diag(rng.integers(1, diag_max + 1, size=n, dtype=np.int64))
     A = L0 @ L0.T
     assert np.abs(A).max() < 2 ** 40
+    return np.ascontiguousarray(A.astype(np.float64)), np.ascontiguousarray(L0.astype(np.float64))
+
+
+# (diagonal, off-diagonal magnitudes) of an integer row with squared norm 16
+_NORM4_ROWS = [(4, ()), (2, (2, 2, 2)), (3, (2, 1, 1, 1)), (3, (1,) * 7), (1, (3, 2, 1, 1)),
+               (2, (1,) * 12), (1, (2, 2, 2, 1, 1, 1))]
+
+
+def integer_factor_norm4(n: int, seed: int = 0):
+    """Return (A, L0) with L0 integer lower triangular, positive diagonal,
+    every row of squared norm 16, off-diagonal entries at random earlier
+    columns with random signs, and A = L0 L0^T exact (so diag(A) = 16 and
+    |A_ij| <= 16)."""
+    rng = np.random.default_rng(seed)
+    L0 = np.zeros((n, n), dtype=np.int64)
+    for i in range(n):
+        fits = [r for r in _NORM4_ROWS if len(r[1]) <= i]
+        dg, offs = fits[int(rng.integers(len(fits)))]
+        L0[i, i] = dg
+        if offs:
+            cols = rng.choice(i, size=len(offs), replace=False)
+            L0[i, cols] = np.array(offs) * rng.choice([-1, 1], size=len(offs))
+    A = L0 @ L0.T
     return np.ascontiguousarray(A.astype(np.float64)), np.ascontiguousarray(L0.astype(np.float64))
