@@ -149,6 +149,82 @@ int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T,
                double* B, int64_t nrhs, int64_t ldb,
                void* work, int64_t work_bytes, void* stream);
 
+/* ---- mixed precision ----------------------------------------------------
+ * The trailing SYRK/GEMM products, which carry almost all of the flops, are
+ * formed from panel entries rounded once to a lower precision and summed in
+ * FP32 on the matrix cores, then subtracted from FP64 storage; POTRF and
+ * TRSM stay in FP64.  Around the factorization the matrix may be scaled
+ * symmetrically to unit diagonal and shifted, and the solve recovers FP64
+ * accuracy by refinement against the original A.  (The paper's algorithm is
+ * FP64 throughout; this is an extension of its tile loop, Fig. 1.) */
+enum {
+  CHOL_PREC_FP64 = 0,  /* the plain FP64 trailing update                        */
+  CHOL_PREC_FP32 = 1,  /* panel rounded to FP32 (nearest even), FP32 sums       */
+  CHOL_PREC_BF16 = 2   /* panel rounded to BF16 (nearest even, no double
+                          rounding), FP32 sums                                  */
+};
+/* Flags of chol_factor_mixed. */
+#define CHOL_MIXED_SCALE 1 /* factor D^-1 A D^-1 with D = diag(A)^(1/2), return D L^ */
+
+/* Bytes of device workspace chol_factor_mixed needs: the fork-join
+ * workspace plus n doubles (D) plus the rounded panel copy (n rows of
+ * ceil(T / 64) * 64 elements of the chosen precision).  < 0 on invalid
+ * arguments. */
+int64_t chol_factor_mixed_workspace_size(int64_t n, int64_t T, int prec);
+
+/* Factor in place with low-precision trailing products (fork-join schedule).
+ *   A, n, lda, T, work, stream, info   as for chol_factor.
+ *   prec    one of CHOL_PREC_*.
+ *   flags   0 or CHOL_MIXED_SCALE.
+ *   shift   >= 0, added to the diagonal of the (scaled) matrix before the
+ *           factorization: the result factors A + shift D^2 with scaling, or
+ *           A + shift I without.  A low-precision factorization of an
+ *           ill-conditioned matrix can meet a non-positive pivot; a shift
+ *           restores positive definiteness at the cost of a worse
+ *           preconditioner (refine with CHOL_REFINE_PCG then).
+ * On return the lower triangle holds L (FP64 storage).  A non-positive
+ * diagonal entry of A itself, or a failed pivot, returns CHOL_NOT_SPD with
+ * *info as for chol_factor; the lower triangle is then unspecified.
+ * prec = CHOL_PREC_FP64 with flags = 0 and shift = 0 is chol_factor with the
+ * fork-join schedule, bit for bit. */
+int chol_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int prec, int flags, double shift,
+                      void* work, int64_t work_bytes, void* stream, int64_t* info);
+
+/* Refinement methods of chol_solve_refine. */
+enum {
+  CHOL_REFINE_IR = 0,  /* classical iterative refinement (FP64 residuals)        */
+  CHOL_REFINE_PCG = 1  /* conjugate gradients preconditioned by L L^T            */
+};
+/* Status of chol_solve_refine when max_iter is reached first. */
+#define CHOL_NOT_CONVERGED 2
+
+/* Bytes of device workspace chol_solve_refine needs: four n x nrhs FP64
+ * blocks, n doubles and a few per-column scalars.  < 0 on invalid
+ * arguments. */
+int64_t chol_refine_workspace_size(int64_t n, int64_t T, int64_t nrhs);
+
+/* Solve A X = B in FP64 to backward error <= tol per column, with a factor
+ * L L^T of A (or of a shifted A) from chol_factor_mixed or chol_factor.
+ * The backward error of column c is ||b - A x||_inf / (||A||_inf ||x||_inf
+ * + ||b||_inf).
+ *   A       device, the original SPD matrix (lower triangle read; lda).
+ *   L       device, the factor (lower triangle read; ldl).
+ *   B       device, n x nrhs row-major (ldb >= nrhs), read only.
+ *   X       device, n x nrhs row-major (ldx >= nrhs), the solution.
+ *   method  CHOL_REFINE_IR or CHOL_REFINE_PCG.
+ *   tol     target backward error (> 0); max_iter >= 0 corrections
+ *           (IR) or iterations (PCG).
+ *   iters   host, or NULL: corrections applied (IR) / iterations of the
+ *           slowest column (PCG).
+ *   eta     host array of nrhs, or NULL: the final backward errors.
+ * The call synchronises `stream` once per iteration (the stopping test).
+ * Returns CHOL_OK, CHOL_NOT_CONVERGED (X holds the last iterate) or a
+ * negative error code. */
+int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T,
+                      const double* B, int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method,
+                      double tol, int64_t max_iter, void* work, int64_t work_bytes, void* stream,
+                      int64_t* iters, double* eta);
+
 /* Batched factorization of `batch` independent SPD matrices of uneven sizes.
  *   A      host array of `batch` device pointers.
  *   n, lda host arrays of `batch` sizes / leading dimensions.

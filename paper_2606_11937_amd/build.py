@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtilechol.so")
-SOURCES = ["kernels.hip", "solve.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "solve.hip", "refine.hip", "abi.cpp"]
 ARCH = os.environ.get("TILECHOL_ARCH", "gfx950")
 
 HIPFLAGS = [

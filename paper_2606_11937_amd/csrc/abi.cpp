@@ -10,6 +10,12 @@
 #include "dag.h"
 #include "launch.h"
 
+#define TC_PREC_FP64 0
+#define TC_PREC_FP32 1
+#define TC_PREC_BF16 2
+
+static_assert(CHOL_PREC_FP64 == TC_PREC_FP64 && CHOL_PREC_FP32 == TC_PREC_FP32 && CHOL_PREC_BF16 == TC_PREC_BF16,
+              "precision codes of the ABI and the kernels differ");
 static_assert(CHOL_BLOCK == TC_BLK, "sub-block size of the ABI and the kernels differ");
 static_assert(CHOL_UNIT_POTRF == TC_UNIT_POTRF && CHOL_UNIT_TRSM == TC_UNIT_TRSM &&
                   CHOL_UNIT_UPDATE == TC_UNIT_UPDATE && CHOL_UNIT_PANEL == TC_UNIT_PANEL,
@@ -76,6 +82,7 @@ const char* chol_status_str(int status) {
     case CHOL_EDEVICE: return "HIP runtime error";
     case CHOL_EWORKSPACE: return "workspace too small";
     case CHOL_ETIMEOUT: return "dependency wait exceeded the wait limit";
+    case CHOL_NOT_CONVERGED: return "refinement did not reach the tolerance within max_iter";
     default: return "unknown status";
   }
 }
@@ -160,6 +167,73 @@ int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, in
   if (work_bytes < tc_solve_ws_bytes()) return bad(9, CHOL_EWORKSPACE);
   return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, work, (hipStream_t)stream, wait_ticks()) == 0 ? CHOL_OK
                                                                                                   : CHOL_EDEVICE;
+}
+
+int64_t chol_factor_mixed_workspace_size(int64_t n, int64_t T, int prec) {
+  g_bad_arg = 0;
+  if (n < 0 || n > kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (prec < CHOL_PREC_FP64 || prec > CHOL_PREC_BF16) return bad(3);
+  return tc_ws_mixed_bytes(n > 0 ? n : 1, T, prec);
+}
+
+int chol_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int prec, int flags, double shift, void* work,
+                      int64_t work_bytes, void* stream, int64_t* info) {
+  g_bad_arg = 0;
+  if (int e = check_factor_args(A, n, lda, T, CHOL_SCHED_FORK_JOIN)) return e;
+  if (prec < CHOL_PREC_FP64 || prec > CHOL_PREC_BF16) return bad(5);
+  if ((flags & ~CHOL_MIXED_SCALE) != 0) return bad(6);
+  if (!(shift >= 0.0) || shift > 1e300) return bad(7);
+  if (n == 0) {
+    if (info) *info = 0;
+    return CHOL_OK;
+  }
+  if (work == nullptr) return bad(8);
+  if (work_bytes < tc_ws_mixed_bytes(n, T, prec)) return bad(9, CHOL_EWORKSPACE);
+  hipStream_t st = (hipStream_t)stream;
+  if (tc_launch_factor_mixed(A, n, lda, T, prec, (flags & CHOL_MIXED_SCALE) ? 1 : 0, shift, work, st) != 0)
+    return CHOL_EDEVICE;
+  if (info == nullptr) return CHOL_OK;
+  int32_t err = 0;
+  int64_t dinfo = 0;
+  if (tc_read_status(work, st, &err, &dinfo) != 0) return CHOL_EDEVICE;
+  return status_from(err, dinfo, info);
+}
+
+int64_t chol_refine_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
+  g_bad_arg = 0;
+  if (n < 0 || n > kMaxN) return bad(1);
+  if (T < 1) return bad(2);
+  if (nrhs < 0) return bad(3);
+  return tc_refine_ws_bytes(n > 0 ? n : 1, nrhs > 0 ? nrhs : 1);
+}
+
+int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T,
+                      const double* B, int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method, double tol,
+                      int64_t max_iter, void* work, int64_t work_bytes, void* stream, int64_t* iters, double* eta) {
+  g_bad_arg = 0;
+  if (n < 0 || n > kMaxN) return bad(5);
+  if (lda < max1(n) || lda > kMaxN) return bad(2);
+  if (ldl < max1(n) || ldl > kMaxN) return bad(4);
+  if (T < 1) return bad(6);
+  if (nrhs < 0) return bad(11);
+  if (ldb < max1(nrhs)) return bad(8);
+  if (ldx < max1(nrhs)) return bad(10);
+  if (method != CHOL_REFINE_IR && method != CHOL_REFINE_PCG) return bad(12);
+  if (!(tol > 0.0)) return bad(13);
+  if (max_iter < 0) return bad(14);
+  if (iters) *iters = 0;
+  if (n == 0 || nrhs == 0) return CHOL_OK;
+  if (A == nullptr) return bad(1);
+  if (L == nullptr) return bad(3);
+  if (B == nullptr) return bad(7);
+  if (X == nullptr) return bad(9);
+  if (work == nullptr) return bad(15);
+  if (work_bytes < tc_refine_ws_bytes(n, nrhs)) return bad(16, CHOL_EWORKSPACE);
+  const int r = tc_refine(A, lda, L, ldl, n, T, B, ldb, X, ldx, nrhs, method, tol, max_iter, work,
+                          (hipStream_t)stream, wait_ticks(), iters, eta);
+  if (r < 0) return CHOL_EDEVICE;
+  return r == 0 ? CHOL_OK : CHOL_NOT_CONVERGED;
 }
 
 int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {

@@ -21,6 +21,7 @@
 #include "dag.h"
 #include "launch.h"
 #include "tile_ops.h"
+#include "tile_ops_lp.h"
 
 // ---------------------------------------------------------------- workspace
 // [0, 256)              TcWsHeader
@@ -219,6 +220,94 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_naive(double* A, i
         tc_run_update(A, lda, g, u, sm);
         __syncthreads();
       }
+}
+
+// ----------------------------------------------- low-precision trailing update
+// Mixed-precision fork-join: after the FP64 panel of step J is final, its
+// rows below the diagonal tile are rounded once into the panel copy P (row r
+// of A at row r of P, column J*T + k at column k); the trailing update then
+// forms its products from P on the FP32 or BF16 matrix cores and subtracts
+// them from the FP64 trailing matrix.  The unit decomposition, the fused
+// POTRF(J+1, 0) and the per-block order of operations are those of the FP64
+// fork-join kernels.
+template <int PREC>
+__global__ __launch_bounds__(TC_THREADS) void tc_round_panel(const double* A, int64_t lda, TcGeom g, int32_t J,
+                                                             typename TcLp<PREC>::elem* P, int64_t ldp, TcWs ws) {
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const int64_t kd = tc_tdim(g, J);
+  const int64_t r0 = (int64_t)(J + 1) * g.T + (int64_t)blockIdx.x * 16;
+  const int64_t c0 = (int64_t)J * g.T;
+  for (int64_t idx = threadIdx.x; idx < 16 * kd; idx += TC_THREADS) {
+    const int64_t rr = idx / kd, k = idx - rr * kd;
+    const int64_t r = r0 + rr;
+    if (r < g.n) P[r * ldp + k] = tc_round_lp<PREC>(A[r * lda + c0 + k]);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws,
+                                                                 const typename TcLp<PREC>::elem* P, int64_t ldp) {
+  __shared__ TcUpdPotrfSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
+  const int64_t ri = tc_row0(g, u.I, u.a);
+  const int64_t rk = tc_row0(g, u.K, u.b);
+  tc_update_block_lp<PREC>(A + ri * lda + rk, P + ri * ldp, P + rk * ldp, lda, ldp, tc_rows(g, u.I, u.a),
+                           tc_rows(g, u.K, u.b), (int)tc_tdim(g, J), ri == rk, sm.upd);
+  if (blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
+    __syncthreads();
+    tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
+  }
+}
+
+// ---------------------------------------------------------- diagonal scaling
+// d_i = sqrt(A_ii) by one workgroup; the first non-positive (or NaN)
+// diagonal entry is reported as a failed pivot at that column.
+__global__ __launch_bounds__(TC_THREADS) void tc_diag_scale(const double* A, int64_t lda, int64_t n, double* d,
+                                                            TcWsHeader* h) {
+  __shared__ int64_t first;
+  if (threadIdx.x == 0) first = n;
+  __syncthreads();
+  int64_t mine = n;
+  for (int64_t i = threadIdx.x; i < n; i += TC_THREADS) {
+    const double a = A[i * lda + i];
+    if (a > 0.0) {
+      d[i] = sqrt(a);
+    } else {
+      d[i] = 1.0;
+      if (i < mine) mine = i;
+    }
+  }
+  if (mine < n) atomicMin((unsigned long long*)&first, (unsigned long long)mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && first < n) tc_report_fail(h, 1, first + 1);
+}
+
+// Row i of the lower triangle: A_ij <- A_ij / (d_i d_j) (when d is given),
+// then A_ii <- A_ii + shift.  One workgroup per row.
+__global__ __launch_bounds__(TC_THREADS) void tc_scale_lower(double* A, int64_t lda, int64_t n, const double* d,
+                                                             double shift, const TcWsHeader* h) {
+  if (tc_err_set(h)) return;
+  const int64_t i = blockIdx.x;
+  double* row = A + i * lda;
+  if (d != nullptr) {
+    const double di = d[i];
+    for (int64_t j = threadIdx.x; j <= i; j += TC_THREADS) row[j] = row[j] / (di * d[j]);
+  }
+  if (shift != 0.0) {
+    __syncthreads();
+    if (threadIdx.x == 0) row[i] = row[i] + shift;
+  }
+}
+
+// Row i of the lower triangle: L_ij <- d_i L_ij (skipped after a failure).
+__global__ __launch_bounds__(TC_THREADS) void tc_unscale_lower(double* A, int64_t lda, int64_t n, const double* d,
+                                                               const TcWsHeader* h) {
+  if (tc_err_set(h)) return;
+  const int64_t i = blockIdx.x;
+  double* row = A + i * lda;
+  const double di = d[i];
+  for (int64_t j = threadIdx.x; j <= i; j += TC_THREADS) row[j] = di * row[j];
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -579,6 +668,74 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
   tc_timed(TC_TIMING_PERSISTENT, st, [&] {
     hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
   });
+  return tc_chk(hipGetLastError());
+}
+
+// Mixed-precision workspace: the fork-join workspace, then d (n doubles),
+// then the panel copy P (n rows of tc_lp_ld(T) elements).
+int64_t tc_lp_ld(int64_t T) { return (T + 63) & ~(int64_t)63; }
+static int64_t tc_lp_elem(int prec) { return prec == TC_PREC_FP32 ? 4 : prec == TC_PREC_BF16 ? 2 : 0; }
+
+int64_t tc_ws_mixed_bytes(int64_t n, int64_t T, int prec) {
+  return tc_ws_bytes(n, T) + tc_round256(8 * n) + tc_round256(n * tc_lp_ld(T) * tc_lp_elem(prec));
+}
+
+template <int PREC>
+static void tc_lp_step(double* A, int64_t lda, const TcGeom& g, int32_t J, TcWs ws, void* P, int64_t ldp,
+                       hipStream_t st) {
+  typedef typename TcLp<PREC>::elem E;
+  const int64_t rows = g.n - (int64_t)(J + 1) * g.T;
+  hipLaunchKernelGGL(tc_round_panel<PREC>, dim3((unsigned)((rows + 15) / 16)), dim3(TC_THREADS), 0, st, A, lda, g,
+                     J, (E*)P, ldp, ws);
+  const int64_t nu = tc_trailing_units(g, J);
+  tc_timed(TC_UNIT_UPDATE, st, [&] {
+    hipLaunchKernelGGL(tc_fj_update_lp<PREC>, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
+                       (const E*)P, ldp);
+  });
+}
+
+int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int prec, int scale, double shift,
+                           void* work, hipStream_t st) {
+  TcGeom g = tc_geom(n, T, 0);
+  TcWs ws = tc_ws_map(work, g);
+  char* tail = (char*)work + tc_ws_bytes(n, T);
+  double* d = (double*)tail;
+  void* P = tail + tc_round256(8 * n);
+  const int64_t ldp = tc_lp_ld(T);
+  hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, tc_ws_bytes(n, T) / 4);
+  if (scale) hipLaunchKernelGGL(tc_diag_scale, dim3(1), dim3(TC_THREADS), 0, st, A, lda, n, d, ws.hdr);
+  if (scale || shift != 0.0)
+    hipLaunchKernelGGL(tc_scale_lower, dim3((unsigned)n), dim3(TC_THREADS), 0, st, A, lda, n,
+                       scale ? (const double*)d : nullptr, shift, ws.hdr);
+  tc_timed(TC_UNIT_POTRF, st, [&] {
+    hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
+  });
+  for (int32_t J = 0; J < g.M; ++J) {
+    for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
+      const int64_t nt = tc_trsm_count(g, J, sc);
+      if (nt > 0)
+        tc_timed(TC_UNIT_TRSM, st, [&] {
+          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+        });
+      const int64_t np = tc_panel_count(g, J, sc);
+      if (np > 0)
+        tc_timed(TC_UNIT_PANEL, st, [&] {
+          hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+        });
+    }
+    if (tc_trailing_units(g, J) <= 0) continue;
+    if (prec == TC_PREC_FP32) {
+      tc_lp_step<TC_PREC_FP32>(A, lda, g, J, ws, P, ldp, st);
+    } else if (prec == TC_PREC_BF16) {
+      tc_lp_step<TC_PREC_BF16>(A, lda, g, J, ws, P, ldp, st);
+    } else {
+      const int64_t nu = tc_trailing_units(g, J);
+      tc_timed(TC_UNIT_UPDATE, st, [&] {
+        hipLaunchKernelGGL(tc_fj_update, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
+      });
+    }
+  }
+  if (scale) hipLaunchKernelGGL(tc_unscale_lower, dim3((unsigned)n), dim3(TC_THREADS), 0, st, A, lda, n, d, ws.hdr);
   return tc_chk(hipGetLastError());
 }
 

@@ -26,6 +26,13 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
 #define TC_TIMING_PERSISTENT 4
 int tc_timing_enable(int mask);
 int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TIMING_KINDS]);
+// Mixed precision (fork-join): prec 0 FP64, 1 FP32, 2 BF16 trailing
+// products; scale: symmetric diagonal scaling around the factorization;
+// shift added to the (scaled) diagonal first.  Workspace: tc_ws_mixed_bytes.
+int64_t tc_ws_mixed_bytes(int64_t n, int64_t T, int prec);
+int64_t tc_lp_ld(int64_t T);
+int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int prec, int scale, double shift,
+                           void* work, hipStream_t st);
 // Synchronise the stream and read the error flag / info of a workspace.
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info);
 // Co-resident workgroups of the persistent kernels on the current device.
@@ -36,3 +43,10 @@ int64_t tc_solve_ws_bytes();
 // Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks);
+// Refinement of A X = B with a (low-precision) factor: method 0 iterative
+// refinement, 1 preconditioned CG.  Synchronises `st` once per iteration.
+// Returns 0 converged, 1 not converged, < 0 device error.
+int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs);
+int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T, const double* B,
+              int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method, double tol, int64_t max_iter, void* work,
+              hipStream_t st, int64_t wait_ticks, int64_t* iters, double* eta_out);

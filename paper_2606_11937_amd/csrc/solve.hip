@@ -27,7 +27,13 @@
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
-#define SV_RC 8         // right-hand sides per pass
+// Right-hand sides are taken in groups: up to 8 by one kernel pair with
+// 8-wide accumulators, more in groups of 16 (one kernel pair per group), so
+// that each sweep folds every block once per group instead of re-folding
+// the whole chain for a second pass.  The arithmetic of a column does not
+// depend on its group.
+#define SV_RC_SMALL 8
+#define SV_RC_LARGE 16
 #define SV_THREADS 256
 
 struct SvWs {
@@ -122,10 +128,11 @@ __device__ __forceinline__ void sv_stage_diag(const double* __restrict__ L, int6
 // last stays off the chain.  The in-block substitution is one row per lane;
 // each step broadcasts the new unknown with a lane read and divides through
 // the precomputed reciprocal.
+template <int RC>
 __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                          SvWs* ws, int64_t wait_ticks) {
-  __shared__ double part[SV_NB][SV_RC + 1];
+  __shared__ double part[SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_b, s_ready;
@@ -145,13 +152,13 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
     live[s2] = row < nr;
     lrow[s2] = L + (r0 + (live[s2] ? row : 0)) * lda + q;
   }
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
-    const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
-    double acc[4][SV_RC];
+  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+    const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
+    double acc[4][RC];
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-      for (int c = 0; c < SV_RC; ++c) acc[s2][c] = 0.0;
+      for (int c = 0; c < RC; ++c) acc[s2][c] = 0.0;
     double lc[4][4];
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2)
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
 #pragma unroll
-          for (int c = 0; c < SV_RC; ++c) {
+          for (int c = 0; c < RC; ++c) {
             if (c < nc) {
               const double y = yj[(int64_t)16 * m * ldb + c];
 #pragma unroll
@@ -191,7 +198,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-      for (int c = 0; c < SV_RC; ++c) {
+      for (int c = 0; c < RC; ++c) {
         if (c < nc) {
           double v = acc[s2][c];
 #pragma unroll
@@ -228,10 +235,11 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
 
 // --------------------------------------------------------------- backward
 // x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j), block b = nb - 1 - ticket.
+template <int RC>
 __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                           double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                           SvWs* ws, int64_t wait_ticks) {
-  __shared__ double part[4][SV_NB][SV_RC + 1];
+  __shared__ double part[4][SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_t, s_ready;
@@ -259,11 +267,11 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
       dst[k] = kk < njr ? L[(j0 + kk) * lda + r0 + r] : 0.0;
     }
   };
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC) {
-    const int nc = nrhs - c0 < SV_RC ? (int)(nrhs - c0) : SV_RC;
-    double acc[SV_RC];
+  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+    const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
+    double acc[RC];
 #pragma unroll
-    for (int c = 0; c < SV_RC; ++c) acc[c] = 0.0;
+    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
     double lc[16];
     if (b < nb - 1 && live) load_col(nb - 1, lc);
     int32_t j = nb - 1;
@@ -283,7 +291,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
           if (kk < njr) {
             const double* xk = B + (j0 + kk) * ldb + c0;
 #pragma unroll
-            for (int c = 0; c < SV_RC; ++c)
+            for (int c = 0; c < RC; ++c)
               if (c < nc) acc[c] += lc[k] * xk[c];
           }
         }
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
       }
     }
 #pragma unroll
-    for (int c = 0; c < SV_RC; ++c) part[p][r][c] = acc[c];
+    for (int c = 0; c < RC; ++c) part[p][r][c] = acc[c];
     __syncthreads();
     const int w = tid >> 6, lane = tid & 63;
     for (int c = w; c < nc; c += 4) {
@@ -332,9 +340,21 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
   (void)T;
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
   SvWs* ws = (SvWs*)work;
-  hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
-  hipLaunchKernelGGL(sv_forward, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb, ws, wait_ticks);
-  hipLaunchKernelGGL(sv_backward, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb, ws,
-                     wait_ticks);
+  if (nrhs <= SV_RC_SMALL) {
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_forward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb,
+                       ws, wait_ticks);
+    hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
+                       ldb, ws, wait_ticks);
+  } else {
+    for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC_LARGE) {
+      const int64_t nc = nrhs - c0 < SV_RC_LARGE ? nrhs - c0 : SV_RC_LARGE;
+      hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+      hipLaunchKernelGGL(sv_forward<SV_RC_LARGE>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc,
+                         ldb, ws, wait_ticks);
+      hipLaunchKernelGGL(sv_backward<SV_RC_LARGE>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0,
+                         nc, ldb, ws, wait_ticks);
+    }
+  }
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }

@@ -28,6 +28,15 @@ CHOL_SCHED_FORK_JOIN_NAIVE = 2
 CHOL_SCHED_TASK_SYNC = 3
 CHOL_SCHED_NOOP = 0x100
 CHOL_BLOCK = 128
+CHOL_NOT_CONVERGED = 2
+CHOL_PREC_FP64 = 0
+CHOL_PREC_FP32 = 1
+CHOL_PREC_BF16 = 2
+CHOL_MIXED_SCALE = 1
+CHOL_REFINE_IR = 0
+CHOL_REFINE_PCG = 1
+PRECISIONS = {"fp64": CHOL_PREC_FP64, "fp32": CHOL_PREC_FP32, "bf16": CHOL_PREC_BF16}
+REFINE_METHODS = {"ir": CHOL_REFINE_IR, "pcg": CHOL_REFINE_PCG}
 CHOL_ASYNC_MAX_TILES = 1024
 SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG,
              "fork_join_naive": CHOL_SCHED_FORK_JOIN_NAIVE, "task_sync": CHOL_SCHED_TASK_SYNC}
@@ -43,6 +52,11 @@ SIGNATURES = [
     ("chol_solve", _int, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp]),
     ("chol_factor_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
     ("chol_factor_batched", _int, [ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp, _i64, _vp, _pi64]),
+    ("chol_factor_mixed_workspace_size", _i64, [_i64, _i64, _int]),
+    ("chol_factor_mixed", _int, [_vp, _i64, _i64, _i64, _int, _int, _dbl, _vp, _i64, _vp, _pi64]),
+    ("chol_refine_workspace_size", _i64, [_i64, _i64, _i64]),
+    ("chol_solve_refine", _int, [_vp, _i64, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int, _dbl, _i64,
+                                 _vp, _i64, _vp, _pi64, ctypes.POINTER(_dbl)]),
     ("chol_default_tile", _i64, [_i64]),
     ("chol_dag_counts", _int, [_i64, _i64, _pi64]),
     ("chol_dag_enumerate", _i64, [_i64, _i64, _i64, _pi32, _i64]),
@@ -176,6 +190,70 @@ def chol_solve(L, B, T: int, n: int | None = None, work=None, stream=None) -> No
                         ctypes.c_void_p(wptr), wbytes, _stream(stream))
     if st != CHOL_OK:
         raise TileCholError(st, "chol_solve", last_bad_arg())
+
+
+# -------------------------------------------------------- mixed precision
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def chol_factor_mixed_workspace_size(n: int, T: int, prec="fp32") -> int:
+    return int(lib.chol_factor_mixed_workspace_size(n, T, _prec(prec)))
+
+
+def chol_factor_mixed(A, T: int, prec="fp32", scale: bool = True, shift: float = 0.0, n: int | None = None,
+                      work=None, stream=None, sync: bool = True):
+    """Factor A in place with low-precision trailing products (FP32 or BF16
+    panel operands, FP32 sums, FP64 storage; FP64 POTRF and TRSM), with
+    optional diagonal scaling and shift.  Returns info when sync."""
+    import torch
+    _check_matrix(A)
+    n = A.shape[0] if n is None else n
+    lda = A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1])
+    if work is None:
+        nb = chol_factor_mixed_workspace_size(n, T, prec)
+        if nb < 0:
+            raise TileCholError(nb, "chol_factor_mixed_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=A.device)
+    info = ctypes.c_int64(0)
+    st = lib.chol_factor_mixed(ctypes.c_void_p(A.data_ptr()), n, lda, T, _prec(prec),
+                               CHOL_MIXED_SCALE if scale else 0, float(shift), ctypes.c_void_p(work.data_ptr()),
+                               work.numel(), _stream(stream), ctypes.byref(info) if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor_mixed", last_bad_arg())
+    return int(info.value) if sync else None
+
+
+def chol_refine_workspace_size(n: int, T: int, nrhs: int) -> int:
+    return int(lib.chol_refine_workspace_size(n, T, nrhs))
+
+
+def chol_solve_refine(A, L, B, X, T: int, method="ir", tol: float = 1e-12, max_iter: int = 30,
+                      n: int | None = None, work=None, stream=None):
+    """Solve A X = B (FP64) with the factor L (of A or of a shifted A) by
+    iterative refinement or PCG.  Returns (converged, iterations, eta per
+    column as a list)."""
+    import torch
+    for t, nm in ((A, "A"), (L, "L"), (B, "B"), (X, "X")):
+        _check_matrix(t, nm)
+    n = A.shape[0] if n is None else n
+    nrhs = B.shape[1]
+    ld = lambda t: t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
+    if work is None:
+        nb = chol_refine_workspace_size(n, T, nrhs)
+        if nb < 0:
+            raise TileCholError(nb, "chol_refine_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=A.device)
+    it = ctypes.c_int64(0)
+    eta = (ctypes.c_double * max(nrhs, 1))()
+    m = REFINE_METHODS[method] if isinstance(method, str) else int(method)
+    st = lib.chol_solve_refine(ctypes.c_void_p(A.data_ptr()), ld(A), ctypes.c_void_p(L.data_ptr()), ld(L), n, T,
+                               ctypes.c_void_p(B.data_ptr()), ld(B), ctypes.c_void_p(X.data_ptr()), ld(X), nrhs, m,
+                               float(tol), int(max_iter), ctypes.c_void_p(work.data_ptr()), work.numel(),
+                               _stream(stream), ctypes.byref(it), eta)
+    if st not in (CHOL_OK, CHOL_NOT_CONVERGED):
+        raise TileCholError(st, "chol_solve_refine", last_bad_arg())
+    return st == CHOL_OK, int(it.value), [float(eta[c]) for c in range(nrhs)]
 
 
 # ---------------------------------------------------------------- batched
