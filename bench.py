@@ -21,6 +21,11 @@ The default run prints one JSON line (the contract line) with
                 HIP events the library records on its own stream around each
                 launch during the timed steps (chol_timing_enable);
   cpu_baseline  the CPU oracle timed on this host on a bounded sample.
+  mixed         time to a solution of backward error <= 1e-12 for 16
+                right-hand sides with FP32 and BF16 trailing products
+                (chol_factor_mixed + chol_solve_refine) against the plain
+                FP64 factor + solve, on the same matrix.
+--mixed prints only that comparison, one JSON line per precision.
 --sweep prints one JSON line per (n, T, schedule) with factor-only times
 (3 warm-ups, then the median of --reps runs with min and max); those lines
 are not the contract line.  Schedules: fork_join (collapsed), async_dag,
@@ -44,6 +49,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Cholesky TFLOP/s (n^3/3) & served solves/s + p99 at bwd err<=1e-12"
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (published)
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense matrix peaks (published)
 
 # HBM traffic of the trailing-update kernel per launch, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over the default configuration, each
@@ -89,6 +95,10 @@ def parse():
     p.add_argument("--Ms", default=None, help="fixed tile counts per dimension: T = ceil(n / M) (overrides --Ts)")
     p.add_argument("--lookaheads", default=None,
                    help="async ticket-order ablation: bulk units per chain link, e.g. -1,0,1000000000")
+    p.add_argument("--mixed", action="store_true",
+                   help="only the mixed-precision comparison (time to a 1e-12 solution, 16 right-hand sides)")
+    p.add_argument("--no-mixed", action="store_true", help="leave the mixed-precision comparison out")
+    p.add_argument("--mixed-T", type=int, default=1024, help="tile side of the mixed-precision factorizations")
     return p.parse_args()
 
 
@@ -180,6 +190,117 @@ def cpu_baseline(block, m: int):
                       f"FP64 oracle; rate = ({m}^3/3)/t"}
 
 
+def mixed_compare(tc, A0, T64: int, T: int, nrhs: int = 16, reps: int = 3, tol: float = 1e-12):
+    """Time to an FP64 solution of A X = B with backward error <= tol.
+
+    fp64: chol_factor (fork-join, T64) + chol_solve; its backward error is
+          then measured (not timed) with chol_solve_refine at max_iter = 0.
+    fp32: chol_factor_mixed (FP32 trailing products, diagonal scaling) +
+          iterative refinement.
+    bf16: chol_factor_mixed with BF16 trailing products and the smallest
+          diagonal shift of the ladder 0, 1e-3 4^k that factors, + PCG;
+          the timed region holds the successful attempt only, the failed
+          attempts are listed.
+    Each line: median of `reps` runs of the whole timed region (device
+    events), iterations, final backward error, forward error and row-scaled
+    factor difference against the FP64 result, and the trailing-update rate
+    of the mixed factorization against its precision's matrix peak."""
+    import numpy as np
+    import torch
+    n = A0.shape[0]
+    g = np.random.default_rng(2)
+    B = torch.from_numpy(g.standard_normal((n, nrhs))).cuda()
+    st = torch.cuda.current_stream()
+    L = torch.empty_like(A0)
+    X = torch.empty_like(B)
+    dsq = torch.sqrt(torch.diagonal(A0)).unsqueeze(1)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {}
+    # ---- FP64 reference path
+    w64 = tc.factor_workspace(n, T64, "fork_join")
+    sw = torch.empty(max(tc.chol_solve_workspace_size(n, T64, nrhs), 8), dtype=torch.uint8, device="cuda")
+    rw = torch.empty(tc.chol_refine_workspace_size(n, T64, nrhs), dtype=torch.uint8, device="cuda")
+    ts = []
+    for r in range(reps + 1):
+        L.copy_(A0)
+        X.copy_(B)
+        torch.cuda.synchronize()
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(st)
+        tc.chol_factor(L, T64, "fork_join", work=w64, stream=st, sync=False)
+        e1.record(st)
+        tc.chol_solve(L, X, T64, work=sw, stream=st)
+        e2.record(st)
+        torch.cuda.synchronize()
+        if r:
+            ts.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    assert tc.chol_factor_info(w64, st) == 0
+    L64 = torch.tril(L)
+    X64 = torch.empty_like(B)
+    ok, it, eta = tc.chol_solve_refine(A0, L, B, X64, T64, "ir", tol, 0, work=rw)
+    tot64 = statistics.median([a + b for a, b in ts])
+    out["fp64"] = {"T": T64, "factor_ms": round(statistics.median([a for a, _ in ts]), 3),
+                   "solve_ms": round(statistics.median([b for _, b in ts]), 3), "total_ms": round(tot64, 3),
+                   "eta": max(eta), "meets_tol": max(eta) <= tol}
+    Xref = X64
+    # ---- mixed paths
+    for prec in ("fp32", "bf16"):
+        wm = torch.empty(tc.chol_factor_mixed_workspace_size(n, T, prec), dtype=torch.uint8, device="cuda")
+        rwm = torch.empty(tc.chol_refine_workspace_size(n, T, nrhs), dtype=torch.uint8, device="cuda")
+        ladder = [0.0] if prec == "fp32" else [0.0] + [1e-3 * 4 ** k for k in range(8)]
+        failed = []
+        shift = None
+        for s_try in ladder:
+            L.copy_(A0)
+            info = tc.chol_factor_mixed(L, T, prec, shift=s_try, work=wm, stream=st)
+            if info == 0:
+                shift = s_try
+                break
+            failed.append({"shift": s_try, "info": info})
+        if shift is None:
+            out[prec] = {"T": T, "failed": failed}
+            continue
+        method = "ir" if prec == "fp32" else "pcg"
+        runs = []
+        for r in range(reps + 1):
+            L.copy_(A0)
+            torch.cuda.synchronize()
+            if r == reps:
+                tc.chol_timing_enable(["update"])
+            e0, e1, e2 = ev(), ev(), ev()
+            e0.record(st)
+            tc.chol_factor_mixed(L, T, prec, shift=shift, work=wm, stream=st, sync=False)
+            e1.record(st)
+            if r == reps:
+                tc.chol_timing_enable(0)
+                upd = tc.chol_timing_read(st)["update"]
+            ok, it, eta = tc.chol_solve_refine(A0, L, B, X, T, method, tol, 200, work=rwm, stream=st)
+            e2.record(st)
+            torch.cuda.synchronize()
+            if r and r < reps:
+                runs.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+            if r == 0:
+                runs_first = (e0.elapsed_time(e1), e1.elapsed_time(e2))
+        if not runs:
+            runs = [runs_first]
+        tot = statistics.median([a + b for a, b in runs])
+        erow = (torch.tril(L) - L64).abs().div(dsq).max().item()
+        fe = ((X - Xref).abs().max() / Xref.abs().max()).item()
+        uflops = update_flops(n, T)
+        urate = uflops / (upd[0] * 1e-3) / 1e12 if upd[0] > 0 else None
+        out[prec] = {"T": T, "shift": shift, "failed_shifts": failed, "method": method,
+                     "factor_ms": round(statistics.median([a for a, _ in runs]), 3),
+                     "refine_ms": round(statistics.median([b for _, b in runs]), 3), "total_ms": round(tot, 3),
+                     "iterations": it, "converged": ok, "eta": max(eta), "forward_err_vs_fp64": fe,
+                     "e_row_vs_fp64": erow, "speedup_vs_fp64": round(tot64 / tot, 3),
+                     "update_tflops": round(urate, 2) if urate else None,
+                     "update_frac_of_peak": round(urate / MFMA_PEAK_TFLOPS[prec], 4) if urate else None}
+        del wm, rwm
+    del L, X, w64, sw, rw
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -190,6 +311,12 @@ def main():
     if args.sweep:
         return sweep(args)
     from paper_2606_11937_amd import tilechol as tc
+    if args.mixed:
+        A0 = make_input(args.n)
+        res = mixed_compare(tc, A0, args.T, args.mixed_T)
+        for prec, r in res.items():
+            print(json.dumps({"kind": "mixed", "n": args.n, "nrhs": 16, "prec": prec, **r}), flush=True)
+        return
 
     n, T, sched, K, W = args.n, args.T, args.sched, args.steps, args.warmup
     print(f"[bench] n={n} T={T} sched={sched} steps={K} warmup={W}", file=sys.stderr, flush=True)
@@ -278,7 +405,12 @@ def main():
         "factor_tflops_median": round(flops / (statistics.median(factor_ms) * 1e-3) / 1e12, 3),
         "launch_ms_per_factor": {k: [round(v[0] / K, 3), v[1] // K] for k, v in launches.items() if v[1]},
     }
-    del copies, works, rhs, A0
+    del copies, works, rhs
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        print("[bench] mixed-precision comparison", file=sys.stderr, flush=True)
+        out["mixed"] = mixed_compare(tc, A0, T, args.mixed_T)
+    del A0
     torch.cuda.empty_cache()
     if sample is not None:
         print(f"[bench] cpu baseline on a {args.cpu_sample}^2 sample", file=sys.stderr, flush=True)

@@ -43,6 +43,13 @@ int64_t tc_solve_ws_bytes();
 // Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks);
+// Repeated solves with one factor: invert the 64 x 64 diagonal blocks once
+// (tc_solve_inv_bytes of storage), then sweep with two matrix-core products
+// per block step.
+int64_t tc_solve_inv_bytes(int64_t n);
+int tc_launch_invert_diag(const double* L, int64_t n, int64_t lda, double* Dinv, hipStream_t st);
+int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* Dinv, double* B, int64_t nrhs,
+                        int64_t ldb, void* work, hipStream_t st, int64_t wait_ticks);
 // Refinement of A X = B with a (low-precision) factor: method 0 iterative
 // refinement, 1 preconditioned CG.  Synchronises `st` once per iteration.
 // Returns 0 converged, 1 not converged, < 0 device error.

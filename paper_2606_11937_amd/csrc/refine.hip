@@ -1,6 +1,10 @@
 // refine.hip -- solving A X = B in FP64 with a factor L L^T of A (or of a
 // shifted A) computed with low-precision trailing products.
 //
+// Every solve with L L^T here runs the sweeps with inverted diagonal blocks
+// (solve.hip): the blocks are inverted once per call, and the small error of
+// the inverses is corrected by the refinement like the factor's own.
+//
 //   iterative refinement   x_0 = (L L^T)^-1 b;  r = b - A x,
 //                          x <- x + (L L^T)^-1 r  until the backward error
 //                          of every column is <= tol;
@@ -15,14 +19,11 @@
 // ||b||_inf).  A is the original symmetric matrix, of which only the lower
 // triangle is read.
 //
-// Products with A: two launches, each streaming the lower triangle once.
-// The first takes the row part (j <= i), the second the transposed part
-// (j > i, read as A_ji).  Every wave owns 16 output rows and 16 columns of
-// X; the contraction runs on the FP64 matrix cores (v_mfma_f64_16x16x4_f64)
-// with each lane loading four consecutive entries of its row (or four
-// entries of its column, for the transposed part) straight from HBM.  The
-// sums of each output entry run in a fixed order, so results are
-// reproducible.  Column reductions (maxima, dot products) are one workgroup
+// Products with A: one launch; every wave owns 16 output rows and 16
+// columns of X and contracts on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64), reading the lower triangle straight from HBM
+// (rows of A left of the diagonal, columns below it).  The sums of each
+// output entry run in a fixed order, so results are reproducible.  Column reductions (maxima, dot products) are one workgroup
 // per column with a fixed partition and a fixed tree.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,65 +42,83 @@ __device__ __forceinline__ rf_v4d rf_mfma(double a, double b, rf_v4d c) {
 }
 
 // ------------------------------------------------------------ A times X
-// Y = S B - A_part X for the row part (LOWER = true: entries j <= i) or
-// Y -= A_part X for the transposed part (LOWER = false: entries j > i, taken
-// as A_ji).  With ABS the entries enter as |A_ij| and X as all ones (row sums
-// of |A|; one column).
-//   row part:        one workgroup per 64 rows; wave w owns rows
-//                    64 blockIdx + 16 w .. +15; contraction over j <= i.
-//   transposed part: one workgroup per 64 rows as well; wave w owns rows
-//                    j = 64 blockIdx + 16 w .. +15 and contracts over i > j
-//                    (column j of the lower triangle, read down the rows).
+// Y = B - A X (Y = -A X when B is null) for symmetric A stored as its lower
+// triangle.  With ABS the entries enter as |A_ij| and X as all ones (row sums
+// of |A|; one column).  One workgroup per 64 rows; wave w owns rows
+// 64 blockIdx + 16 w .. +15 and walks k = 0 .. n - 1 in 16-wide chunks,
+// reading A_ik from row i for k <= i and as A_ki from column i for k > i (so
+// every stored entry is read twice in all, once for each of its rows).
 // MFMA operand layout (measured on gfx950): A-operand lane l holds row
 // l % 16 at k group l / 16, B-operand lane l holds column l % 16 at k group
 // l / 16, output item q of lane l is row 4 q + l / 16, column l % 16.  In a
-// 16-wide k chunk, lane (r, g) brings k = 4 g + m to MFMA m (m = 0..3) for
-// both operands.
-template <bool LOWER, bool ABS>
-__global__ __launch_bounds__(RF_THREADS) void rf_symv(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                      const double* __restrict__ X, int64_t ldx,
-                                                      const double* __restrict__ B, int64_t ldb,
-                                                      double* __restrict__ Y, int64_t ldy, int64_t nrhs) {
+// chunk, lane (r, g) brings k = 4 g + m to MFMA m for both operands.  Each
+// output entry sums its chunks in ascending k, so results are reproducible.
+// Loads are branch-free: indices are clamped into the stored triangle and
+// masked entries are selected away; the next chunk is loaded while the
+// current one is multiplied.
+template <bool ABS>
+__global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                         const double* __restrict__ X, int64_t ldx,
+                                                         const double* __restrict__ B, int64_t ldb,
+                                                         double* __restrict__ Y, int64_t ldy, int64_t nrhs) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = (lane >> 4) * 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;  // first output row of this wave
   if (row0 >= n) return;
-  const int64_t myrow = row0 + r16;  // A-operand row (output row) of this lane
+  const int64_t myrow = row0 + r16;
   const bool rowok = myrow < n;
+  const int64_t rowc = rowok ? myrow : n - 1;
+  const int64_t nch = (n + 15) / 16;
   for (int64_t c0 = 0; c0 < nrhs; c0 += RF_RC) {
-    const int64_t col = c0 + r16;  // B-operand column (right-hand side) of this lane
+    const int64_t col = c0 + r16;
     const bool colok = col < nrhs;
-    rf_v4d acc = {0.0, 0.0, 0.0, 0.0};
-    // contraction range: row part k = 0 .. row0 + 15 (masked to k <= row);
-    // transposed part k = row0 .. n - 1 (masked to k > row)
-    const int64_t k_beg = LOWER ? 0 : row0;
-    const int64_t k_end = LOWER ? (row0 + 16 < n ? row0 + 16 : n) : n;
-    for (int64_t k0 = k_beg; k0 < k_end; k0 += 16) {
-      const int64_t kb = k0 + g4;  // this lane's four k values: kb .. kb + 3
-      double a[4], x[4];
+    const int64_t colc = colok ? col : nrhs - 1;
+    auto load = [&](int64_t ch, double* a, double* x) {
+      const int64_t k0 = 16 * ch;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int64_t k = kb + m;
-        const bool in = rowok && k < n && (LOWER ? k <= myrow : k > myrow);
-        double v = 0.0;
-        if (in) v = LOWER ? A[myrow * lda + k] : A[k * lda + myrow];
-        a[m] = ABS ? fabs(v) : v;
-        if (ABS) x[m] = (colok && k < n) ? 1.0 : 0.0;
-        else x[m] = (colok && k < n) ? X[k * ldx + col] : 0.0;
+        const int64_t k = k0 + g4 + m;
+        const bool kin = k < n;
+        const int64_t kc = kin ? k : n - 1;
+        // k <= row: A[row][k] (row part); k > row: A[k][row] (column part)
+        const bool low = kc <= rowc;
+        const double v = low ? A[rowc * lda + kc] : A[kc * lda + rowc];
+        a[m] = (rowok && kin) ? (ABS ? fabs(v) : v) : 0.0;
+        if (ABS) {
+          x[m] = (colok && kin) ? 1.0 : 0.0;
+        } else {
+          const double xv = X[kc * ldx + colc];
+          x[m] = (colok && kin) ? xv : 0.0;
+        }
       }
+    };
+    // chunks in pairs, the next pair in flight while this one is multiplied
+    // (a chunk index past the end re-reads the last chunk and is not used)
+    rf_v4d acc = {0.0, 0.0, 0.0, 0.0};
+    double a[8], x[8];
+    load(0, a, x);
+    load(nch > 1 ? 1 : 0, a + 4, x + 4);
+    for (int64_t ch = 0; ch < nch; ch += 2) {
+      double an[8], xn[8];
+      load(ch + 2 < nch ? ch + 2 : nch - 1, an, xn);
+      load(ch + 3 < nch ? ch + 3 : nch - 1, an + 4, xn + 4);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc = rf_mfma(a[m], x[m], acc);
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int m = 4; m < 8; ++m) acc = rf_mfma(a[m], x[m], acc);
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        a[m] = an[m];
+        x[m] = xn[m];
+      }
     }
-    // store: item q is row row0 + 4 q + lane / 16, column c0 + lane % 16
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t r = row0 + 4 * q + (lane >> 4);
       const int64_t c = c0 + (lane & 15);
-      if (r < n && c < nrhs) {
-        double* y = Y + r * ldy + c;
-        if (LOWER) *y = (B != nullptr ? B[r * ldb + c] : 0.0) - acc[q];
-        else *y = *y - acc[q];
-      }
+      if (r < n && c < nrhs) Y[r * ldy + c] = (B != nullptr ? B[r * ldb + c] : 0.0) - acc[q];
     }
   }
 }
@@ -204,6 +223,7 @@ inline int64_t rf_r256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 struct RfWs {
   void* solve_ws;
+  double* dinv;                   // inverted 64 x 64 diagonal blocks of L
   double *R, *Z, *P, *Q;          // n x nrhs each, leading dimension nrhs
   double* rowsum;                 // n
   double *anorm, *rmax, *xmax, *bmax, *eta, *rz, *rzn, *pq, *alpha, *beta;  // nrhs each (anorm: 1)
@@ -215,6 +235,8 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
   char* p = (char*)work;
   w.solve_ws = p;
   p += rf_r256(tc_solve_ws_bytes());
+  w.dinv = (double*)p;
+  p += rf_r256(tc_solve_inv_bytes(n));
   const int64_t mat = rf_r256(8 * n * nrhs);
   w.R = (double*)p; p += mat;
   w.Z = (double*)p; p += mat;
@@ -237,11 +259,8 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
 // Y = B - A X  (B null: Y = -A X)
 void rf_residual(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, const double* B, int64_t ldb,
                  double* Y, int64_t ldy, int64_t nrhs, hipStream_t st) {
-  const unsigned nb = rf_blocks(n, 64);
-  hipLaunchKernelGGL((rf_symv<true, false>), dim3(nb), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y, ldy,
-                     nrhs);
-  hipLaunchKernelGGL((rf_symv<false, false>), dim3(nb), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y, ldy,
-                     nrhs);
+  hipLaunchKernelGGL(rf_symv<false>, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y,
+                     ldy, nrhs);
 }
 
 // eta of every column of (R, X, B) into w.eta, copied to host `eta`
@@ -263,7 +282,7 @@ double rf_max(const std::vector<double>& v) {
 }  // namespace
 
 int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs) {
-  return rf_r256(tc_solve_ws_bytes()) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n) + 10 * rf_r256(8 * nrhs) +
+  return rf_r256(tc_solve_ws_bytes()) + rf_r256(tc_solve_inv_bytes(n)) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n) + 10 * rf_r256(8 * nrhs) +
          3 * rf_r256(4 * nrhs);
 }
 
@@ -278,14 +297,13 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
   // update of them follows a stream synchronisation
   std::vector<int32_t> done(nrhs, 0), zero(nrhs, 0), mask(nrhs, 0);
   auto fail = [&]() { return TC_LAUNCH_EDEVICE; };
+  (void)T;
   auto solve = [&](double* Y, int64_t ldy) {
-    return tc_launch_solve(L, n, ldl, T, Y, nrhs, ldy, w.solve_ws, st, wait_ticks);
+    return tc_launch_solve_inv(L, n, ldl, w.dinv, Y, nrhs, ldy, w.solve_ws, st, wait_ticks);
   };
+  if (tc_launch_invert_diag(L, n, ldl, w.dinv, st) != 0) return fail();
   // ||A||_inf from the row sums of |A|, and ||b||_inf per column
-  hipLaunchKernelGGL((rf_symv<true, true>), dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n,
-                     (const double*)nullptr, (int64_t)1, (const double*)nullptr, (int64_t)1, w.rowsum, (int64_t)1,
-                     (int64_t)1);
-  hipLaunchKernelGGL((rf_symv<false, true>), dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n,
+  hipLaunchKernelGGL(rf_symv<true>, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n,
                      (const double*)nullptr, (int64_t)1, (const double*)nullptr, (int64_t)1, w.rowsum, (int64_t)1,
                      (int64_t)1);
   hipLaunchKernelGGL(rf_colmax, dim3(1), dim3(RF_THREADS), 0, st, w.rowsum, (int64_t)1, n, w.anorm);

@@ -27,13 +27,11 @@
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
-// Right-hand sides are taken in groups: up to 8 by one kernel pair with
-// 8-wide accumulators, more in groups of 16 (one kernel pair per group), so
-// that each sweep folds every block once per group instead of re-folding
-// the whole chain for a second pass.  The arithmetic of a column does not
-// depend on its group.
+// One or two right-hand sides go through the kernels with lane-level folds
+// (sv_forward / sv_backward); more are taken in groups of 16 by the kernels
+// whose folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel
+// pair per group.
 #define SV_RC_SMALL 8
-#define SV_RC_LARGE 16
 #define SV_THREADS 256
 
 struct SvWs {
@@ -329,32 +327,548 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
   sv_publish(&ws->done_b, t, ws, wait_ticks);
 }
 
+// ------------------------------------------------ matrix-core fold sweeps
+// The same sweeps with the fold of every finished block done as a 64 x 64
+// by 64 x 16 product on the FP64 matrix cores (v_mfma_f64_16x16x4_f64):
+// wave w owns rows 16 w .. 16 w + 15 of the block and up to 16 right-hand
+// sides.  Operand layout (measured on gfx950): A-operand lane l holds row
+// l % 16 at k group l / 16, B-operand lane l holds column l % 16 at k group
+// l / 16, output item q of lane l is row 4 q + l / 16, column l % 16.  In a
+// 16-wide k chunk ch of a block, lane (r, g) brings k = 16 ch + 4 g + m to
+// MFMA m for both operands.  The factor entries of the next block are
+// loaded while the current block is folded (and its right-hand-side rows
+// too, when that block is already known to be finished).
+//
+// The in-block substitution gives each wave up to four right-hand sides,
+// c = w, w + 4, w + 8, w + 12, whose chains run interleaved: lane k holds
+// row k for all four, and each step broadcasts the pivot data once.
+//
+// Rounding order per output entry: blocks in sweep order; within a block
+// the 16 MFMAs in (chunk, m) order, each adding its four products; then the
+// subtraction from B and the sequential substitution.
+typedef double sv_v4d __attribute__((ext_vector_type(4)));
+#define SV_MF_RC 16
+
+__device__ __forceinline__ sv_v4d sv_mfma(double a, double b, sv_v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// NT interleaved substitution chains of one wave against the staged
+// diagonal block: lane k holds row k of each right-hand side; forward runs
+// with L_bb (lane k keeps row k), backward with L_bb^T (lane k keeps
+// column k).
+template <int NT>
+__device__ __forceinline__ void sv_chains_fwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
+                                              int lane) {
+  double lr[SV_NB];
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) lr[i] = Lbb[lane][i];
+  const double dl = Lbb[lane][lane], rl = rdiag[lane];
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) {
+    const double di = sv_readlane(dl, i), ri = sv_readlane(rl, i);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double xi = sv_div_rcp(sv_readlane(v[t], i), di, ri);
+      if (lane == i) v[t] = xi;
+      else if (lane > i) v[t] = v[t] - lr[i] * xi;
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void sv_chains_bwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
+                                              int lane) {
+  double lc2[SV_NB];
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) lc2[i] = Lbb[i][lane];
+  const double dl = Lbb[lane][lane], rl = rdiag[lane];
+#pragma unroll
+  for (int i = SV_NB - 1; i >= 0; --i) {
+    const double di = sv_readlane(dl, i), ri = sv_readlane(rl, i);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double xi = sv_div_rcp(sv_readlane(v[t], i), di, ri);
+      if (lane == i) v[t] = xi;
+      else if (lane < i) v[t] = v[t] - lc2[i] * xi;
+    }
+  }
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                        double* __restrict__ B, int64_t nc, int64_t ldb, SvWs* ws,
+                                                        int64_t wait_ticks) {
+  __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double rdiag[SV_NB];
+  __shared__ int32_t s_b, s_ready;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t b = sv_uniform(s_b);
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
+  const int arow = 16 * w + r16;
+  const bool alive = arow < nr;
+  const bool bok = r16 < nc;
+  // row arow of the block, columns 4 g .. of every earlier block
+  const double* lrow = L + (r0 + (alive ? arow : 0)) * lda + g4;
+  // right-hand side r16, rows 4 g .. of every earlier block
+  const double* ycol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
+  // the pointers above stay in bounds for idle lanes (row 0 / column 0), so
+  // every lane loads and idle lanes select zero: no branches in the fold
+  auto load_l = [&](int32_t j, double* a) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double v = lrow[(int64_t)j * SV_NB + 16 * ch + m];
+        a[4 * ch + m] = alive ? v : 0.0;
+      }
+  };
+  auto load_y = [&](int32_t j, double* y) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double v = ycol[((int64_t)j * SV_NB + 16 * ch + m) * ldb];
+        y[4 * ch + m] = bok ? v : 0.0;
+      }
+  };
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double la[16], ya[16];
+  bool have_y = false;
+  if (b > 0) load_l(0, la);
+  int32_t j = 0;
+  while (j < b) {
+    const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
+    if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
+    const int32_t jend = ready < b ? ready : b;
+    for (; j < jend; ++j) {
+      if (!have_y) load_y(j, ya);
+      const int32_t jn = j + 1 < b ? j + 1 : j;  // the last block re-reads itself
+      double ln[16], yn[16];
+      load_l(jn, ln);
+      have_y = j + 1 < jend;
+      if (have_y) load_y(j + 1, yn);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) la[k] = ln[k];
+      if (have_y) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ya[k] = yn[k];
+      }
+    }
+  }
+  // item q: row 16 w + 4 q + g, right-hand side r16
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part[16 * w + 4 * q + (lane >> 4)][r16] = acc[q];
+  __syncthreads();
+  {
+    const int ncl = (int)nc;
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = w + 4 * t;
+      v[t] = (c < ncl && lane < nr) ? B[(r0 + lane) * ldb + c] - (b > 0 ? part[lane][c] : 0.0) : 0.0;
+    }
+    // chains with no right-hand side are left out (a wave-uniform choice of
+    // the unrolled loop, so the live chains stay interleaved)
+    const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
+    if (nt >= 4) sv_chains_fwd<4>(v, Lbb, rdiag, lane);
+    else if (nt == 3) sv_chains_fwd<3>(v, Lbb, rdiag, lane);
+    else if (nt == 2) sv_chains_fwd<2>(v, Lbb, rdiag, lane);
+    else if (nt == 1) sv_chains_fwd<1>(v, Lbb, rdiag, lane);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = w + 4 * t;
+      if (c < ncl && lane < nr) B[(r0 + lane) * ldb + c] = v[t];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_f, b, ws, wait_ticks);
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                        double* __restrict__ B, int64_t nc, int64_t ldb, SvWs* ws,
+                                                        int64_t wait_ticks) {
+  __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double rdiag[SV_NB];
+  __shared__ int32_t s_t, s_ready;
+  const int tid = threadIdx.x;
+  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
+  if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t t = sv_uniform(s_t);
+  const int32_t b = nb - 1 - t;
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
+  const int arow = 16 * w + r16;  // output row of the block = column r0 + arow of L
+  const bool alive = arow < nr;
+  const bool bok = r16 < nc;
+  // column r0 + arow of L, rows 4 g .. of every later block
+  const double* lcol = L + (int64_t)g4 * lda + r0 + (alive ? arow : 0);
+  const double* xcol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
+  // rows of block j past n read as zero (only the last block is ragged)
+  // rows past the last row are clamped to it (in bounds) and selected away
+  auto load_l = [&](int32_t j, double* a) {
+    const int64_t j0 = (int64_t)j * SV_NB;
+    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int kk = 16 * ch + g4 + m;
+        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
+        const double v = lcol[(j0 + ks) * lda];
+        a[4 * ch + m] = (alive && kk < njr) ? v : 0.0;
+      }
+  };
+  auto load_x = [&](int32_t j, double* x) {
+    const int64_t j0 = (int64_t)j * SV_NB;
+    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int kk = 16 * ch + g4 + m;
+        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
+        const double v = xcol[(j0 + ks) * ldb];
+        x[4 * ch + m] = (bok && kk < njr) ? v : 0.0;
+      }
+  };
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double la[16], xa[16];
+  bool have_x = false;
+  if (b < nb - 1) load_l(nb - 1, la);
+  int32_t j = nb - 1;
+  while (j > b) {
+    const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
+    if (ready < 0) break;
+    const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
+    for (; j >= jlow; --j) {
+      if (!have_x) load_x(j, xa);
+      const int32_t jn = j - 1 > b ? j - 1 : j;  // the last block re-reads itself
+      double ln[16], xn[16];
+      load_l(jn, ln);
+      have_x = j - 1 >= jlow;
+      if (have_x) load_x(j - 1, xn);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], xa[k], acc);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) la[k] = ln[k];
+      if (have_x) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xa[k] = xn[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) part[16 * w + 4 * q + (lane >> 4)][r16] = acc[q];
+  __syncthreads();
+  {
+    const int ncl = (int)nc;
+    double v[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const int c = w + 4 * tt;
+      v[tt] = (c < ncl && lane < nr) ? B[(r0 + lane) * ldb + c] - (b < nb - 1 ? part[lane][c] : 0.0) : 0.0;
+    }
+    const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
+    if (nt >= 4) sv_chains_bwd<4>(v, Lbb, rdiag, lane);
+    else if (nt == 3) sv_chains_bwd<3>(v, Lbb, rdiag, lane);
+    else if (nt == 2) sv_chains_bwd<2>(v, Lbb, rdiag, lane);
+    else if (nt == 1) sv_chains_bwd<1>(v, Lbb, rdiag, lane);
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const int c = w + 4 * tt;
+      if (c < ncl && lane < nr) B[(r0 + lane) * ldb + c] = v[tt];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_b, t, ws, wait_ticks);
+}
+
+// ------------------------------------------- sweeps with inverted diagonals
+// For repeated solves with one factor (refinement), the 64 x 64 diagonal
+// blocks are inverted once (sv_invert_diag, by substitution against the
+// identity), and each block step of the sweeps becomes two matrix-core
+// products: the fold of the finished blocks as above, then y_b = D_b v
+// (forward) or x_b = D_b^T v (backward) with D_b = L_bb^-1 and v the folded
+// right-hand side.  No sequential substitution remains on the chain.  The
+// inverse is accurate to about kappa(L_bb) u, which the refinement corrects
+// along with the error of the factor itself; the plain solve keeps
+// substitution.
+//
+// D_b is stored row-major, 64 x 64 per block, zero above the diagonal (and
+// the identity on rows past n in the last block).
+__global__ __launch_bounds__(SV_THREADS) void sv_invert_diag(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                             double* __restrict__ Dinv) {
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double rdiag[SV_NB];
+  const int32_t b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* D = Dinv + (int64_t)b * SV_NB * SV_NB;
+  // wave w solves L_bb d = e_c for columns c = w + 4 t, four at a time
+  for (int c0 = 0; c0 < 16; c0 += 4) {
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = lane == w + 4 * (c0 + t) ? 1.0 : 0.0;
+    sv_chains_fwd<4>(v, Lbb, rdiag, lane);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) D[(int64_t)lane * SV_NB + w + 4 * (c0 + t)] = v[t];
+  }
+}
+
+// D_b into LDS (the barrier that follows the fold publishes it).
+__device__ __forceinline__ void sv_stage_inv(const double* __restrict__ D, double (*Ds)[SV_NB + 1]) {
+  for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) Ds[e / SV_NB][e % SV_NB] = D[e];
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                            const double* __restrict__ Dinv, double* __restrict__ B,
+                                                            int64_t nc, int64_t ldb, SvWs* ws, int64_t wait_ticks) {
+  __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double Ds[SV_NB][SV_NB + 1];
+  __shared__ int32_t s_b, s_ready;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t b = sv_uniform(s_b);
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
+  const int arow = 16 * w + r16;
+  const bool alive = arow < nr;
+  const bool bok = r16 < nc;
+  const double* lrow = L + (r0 + (alive ? arow : 0)) * lda + g4;
+  const double* ycol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
+  sv_stage_inv(Dinv + (int64_t)b * SV_NB * SV_NB, Ds);  // D_b, staged before any wait
+  auto load_l = [&](int32_t j, double* a) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double v = lrow[(int64_t)j * SV_NB + 16 * ch + m];
+        a[4 * ch + m] = alive ? v : 0.0;
+      }
+  };
+  auto load_y = [&](int32_t j, double* y) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double v = ycol[((int64_t)j * SV_NB + 16 * ch + m) * ldb];
+        y[4 * ch + m] = bok ? v : 0.0;
+      }
+  };
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double la[16], ya[16];
+  bool have_y = false;
+  if (b > 0) load_l(0, la);
+  int32_t j = 0;
+  while (j < b) {
+    const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
+    if (ready < 0) break;
+    const int32_t jend = ready < b ? ready : b;
+    for (; j < jend; ++j) {
+      if (!have_y) load_y(j, ya);
+      const int32_t jn = j + 1 < b ? j + 1 : j;
+      double ln[16], yn[16];
+      load_l(jn, ln);
+      have_y = j + 1 < jend;
+      if (have_y) load_y(j + 1, yn);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) la[k] = ln[k];
+      if (have_y) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ya[k] = yn[k];
+      }
+    }
+  }
+  // v = B_b - fold, into part (rows past nr and columns past nc are zero)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    const double bv = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
+    part[row][r16] = (row < nr && bok) ? bv - acc[q] : 0.0;
+  }
+  __syncthreads();
+  // y_b = D_b v: rows 16 w .., right-hand side r16
+  sv_v4d y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) y = sv_mfma(Ds[arow][16 * ch + g4 + m], part[16 * ch + g4 + m][r16], y);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    if (row < nr && bok) B[(r0 + row) * ldb + r16] = y[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_f, b, ws, wait_ticks);
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                            const double* __restrict__ Dinv, double* __restrict__ B,
+                                                            int64_t nc, int64_t ldb, SvWs* ws, int64_t wait_ticks) {
+  __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double Ds[SV_NB][SV_NB + 1];
+  __shared__ int32_t s_t, s_ready;
+  const int tid = threadIdx.x;
+  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
+  if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t t = sv_uniform(s_t);
+  const int32_t b = nb - 1 - t;
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
+  const int arow = 16 * w + r16;
+  const bool alive = arow < nr;
+  const bool bok = r16 < nc;
+  const double* lcol = L + (int64_t)g4 * lda + r0 + (alive ? arow : 0);
+  const double* xcol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
+  sv_stage_inv(Dinv + (int64_t)b * SV_NB * SV_NB, Ds);
+  auto load_l = [&](int32_t j, double* a) {
+    const int64_t j0 = (int64_t)j * SV_NB;
+    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int kk = 16 * ch + g4 + m;
+        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
+        const double v = lcol[(j0 + ks) * lda];
+        a[4 * ch + m] = (alive && kk < njr) ? v : 0.0;
+      }
+  };
+  auto load_x = [&](int32_t j, double* x) {
+    const int64_t j0 = (int64_t)j * SV_NB;
+    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int kk = 16 * ch + g4 + m;
+        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
+        const double v = xcol[(j0 + ks) * ldb];
+        x[4 * ch + m] = (bok && kk < njr) ? v : 0.0;
+      }
+  };
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double la[16], xa[16];
+  bool have_x = false;
+  if (b < nb - 1) load_l(nb - 1, la);
+  int32_t j = nb - 1;
+  while (j > b) {
+    const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
+    if (ready < 0) break;
+    const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
+    for (; j >= jlow; --j) {
+      if (!have_x) load_x(j, xa);
+      const int32_t jn = j - 1 > b ? j - 1 : j;
+      double ln[16], xn[16];
+      load_l(jn, ln);
+      have_x = j - 1 >= jlow;
+      if (have_x) load_x(j - 1, xn);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], xa[k], acc);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) la[k] = ln[k];
+      if (have_x) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xa[k] = xn[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    const double bv = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
+    part[row][r16] = (row < nr && bok) ? bv - acc[q] : 0.0;
+  }
+  __syncthreads();
+  // x_b = D_b^T v
+  sv_v4d x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x = sv_mfma(Ds[16 * ch + g4 + m][arow], part[16 * ch + g4 + m][r16], x);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    if (row < nr && bok) B[(r0 + row) * ldb + r16] = x[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  sv_publish(&ws->done_b, t, ws, wait_ticks);
+}
+
 __global__ void sv_clear(SvWs* ws) {
   if (threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)ws)[threadIdx.x] = 0;
 }
 
 int64_t tc_solve_ws_bytes() { return (int64_t)sizeof(SvWs); }
 
+int64_t tc_solve_inv_bytes(int64_t n) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * SV_NB * 8; }
+
+int tc_launch_invert_diag(const double* L, int64_t n, int64_t lda, double* Dinv, hipStream_t st) {
+  const int64_t nb = (n + SV_NB - 1) / SV_NB;
+  hipLaunchKernelGGL(sv_invert_diag, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv);
+  return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}
+
+int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* Dinv, double* B, int64_t nrhs,
+                        int64_t ldb, void* work, hipStream_t st, int64_t wait_ticks) {
+  const int64_t nb = (n + SV_NB - 1) / SV_NB;
+  SvWs* ws = (SvWs*)work;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
+    const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_fwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
+                       wait_ticks);
+    hipLaunchKernelGGL(sv_bwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
+                       wait_ticks);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}
+
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks) {
   (void)T;
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
   SvWs* ws = (SvWs*)work;
-  if (nrhs <= SV_RC_SMALL) {
+  if (nrhs <= 2) {  // measured faster for one or two right-hand sides
     hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
     hipLaunchKernelGGL(sv_forward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb,
                        ws, wait_ticks);
     hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
                        ldb, ws, wait_ticks);
-  } else {
-    for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC_LARGE) {
-      const int64_t nc = nrhs - c0 < SV_RC_LARGE ? nrhs - c0 : SV_RC_LARGE;
-      hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
-      hipLaunchKernelGGL(sv_forward<SV_RC_LARGE>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc,
-                         ldb, ws, wait_ticks);
-      hipLaunchKernelGGL(sv_backward<SV_RC_LARGE>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0,
-                         nc, ldb, ws, wait_ticks);
-    }
+    return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+  }
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
+    const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_fwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,
+                       wait_ticks);
+    hipLaunchKernelGGL(sv_bwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,
+                       wait_ticks);
   }
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }
