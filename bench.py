@@ -25,7 +25,13 @@ The default run prints one JSON line (the contract line) with
                 right-hand sides with FP32 and BF16 trailing products
                 (chol_factor_mixed + chol_solve_refine) against the plain
                 FP64 factor + solve, on the same matrix.
---mixed prints only that comparison, one JSON line per precision.
+  batched       4096 SPD matrices G G^T / n + I with orders log-uniform in
+                [32, 2048] (seed 3), each factored and solved for one
+                right-hand side: one persistent launch
+                (chol_factor_solve_batched, tuned tile sides) against a
+                loop of chol_factor + chol_solve per matrix.
+--mixed prints only that comparison, one JSON line per precision;
+--batched likewise for the batched comparison.
 --sweep prints one JSON line per (n, T, schedule) with factor-only times
 (3 warm-ups, then the median of --reps runs with min and max); those lines
 are not the contract line.  Schedules: fork_join (collapsed), async_dag,
@@ -99,6 +105,12 @@ def parse():
                    help="only the mixed-precision comparison (time to a 1e-12 solution, 16 right-hand sides)")
     p.add_argument("--no-mixed", action="store_true", help="leave the mixed-precision comparison out")
     p.add_argument("--mixed-T", type=int, default=1024, help="tile side of the mixed-precision factorizations")
+    p.add_argument("--batched", action="store_true",
+                   help="only the batched comparison (4096 orders log-uniform in [32, 2048], one launch vs a loop)")
+    p.add_argument("--no-batched", action="store_true", help="leave the batched comparison out")
+    p.add_argument("--batch-count", type=int, default=4096)
+    p.add_argument("--batch-lookaheads", default="-1",
+                   help="batched ticket order: bulk units per chain link of each matrix (comma list; -1 default)")
     return p.parse_args()
 
 
@@ -301,6 +313,82 @@ def mixed_compare(tc, A0, T64: int, T: int, nrhs: int = 16, reps: int = 3, tol: 
     return out
 
 
+def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
+    """One persistent launch factoring and solving a whole batch against a
+    loop of chol_factor (fork-join, the library's default tile for each
+    order) + chol_solve per matrix, on the same inputs.  Times are device
+    time between events around the whole batch (the loop's launch gaps
+    count).  The roofline floor is sum_i max(flops_i / FP64 peak, bytes_i /
+    HBM peak) with flops n^3/3 and bytes 8 n^2 (the lower triangle read and
+    written once)."""
+    import torch
+    from paper_2606_11937_amd import inputs
+    sizes = inputs.batch_sizes(count, seed)
+    As = inputs.gg_batch_device(sizes, seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed + 1)
+    Bs = [torch.randn(n, generator=g, dtype=torch.float64, device="cuda") for n in sizes]
+    Ls = [A.clone() for A in As]
+    Xs = [b.clone() for b in Bs]
+    st = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def reset():
+        for L, A in zip(Ls, As):
+            L.copy_(A)
+        for X, b in zip(Xs, Bs):
+            X.copy_(b)
+        torch.cuda.synchronize()
+
+    work = torch.empty(tc.chol_factor_solve_batched_workspace_size(sizes), dtype=torch.uint8, device="cuda")
+    one = []
+    for r in range(reps + 1):
+        reset()
+        e0, e1 = ev(), ev()
+        e0.record(st)
+        tc.chol_factor_solve_batched(Ls, Xs, work=work, stream=st, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        if r:
+            one.append(e0.elapsed_time(e1))
+    reset()
+    infos = tc.chol_factor_solve_batched(Ls, Xs, work=work, stream=st)
+    worst = 0.0
+    for A, x, b in zip(As, Xs, Bs):
+        r_ = b - A @ x
+        den = A.abs().sum(dim=1).max() * x.abs().max() + b.abs().max()
+        worst = max(worst, (r_.abs().max() / den).item())
+    # the loop baseline: one workspace sized for the largest order, reused
+    nmax = max(sizes)
+    wf = torch.empty(max(tc.chol_factor_workspace_size(nmax, tc.chol_default_tile(nmax)), 8), dtype=torch.uint8,
+                     device="cuda")
+    ws = torch.empty(max(tc.chol_solve_workspace_size(nmax, 128, 1), 8), dtype=torch.uint8, device="cuda")
+    loop = []
+    for r in range(2):
+        reset()
+        e0, e1 = ev(), ev()
+        e0.record(st)
+        for L, X, n in zip(Ls, Xs, sizes):
+            T = tc.chol_default_tile(n)
+            tc.chol_factor(L, T, "fork_join", work=wf, stream=st, sync=False)
+            tc.chol_solve(L, X.view(n, 1), T, work=ws, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        loop.append(e0.elapsed_time(e1))
+    flops = sum(n ** 3 / 3 for n in sizes)
+    floor_ms = sum(max(n ** 3 / 3 / (FP64_MFMA_PEAK_TFLOPS * 1e12), 8.0 * n * n / 8e12) for n in sizes) * 1e3
+    t1 = statistics.median(one)
+    tl = min(loop)
+    out = {"count": count, "n_min": min(sizes), "n_max": nmax, "n_median": int(statistics.median(sizes)),
+           "flops": flops, "one_launch_ms": round(t1, 3), "one_launch_tflops": round(flops / (t1 * 1e-3) / 1e12, 3),
+           "loop_ms": round(tl, 3), "speedup_vs_loop": round(tl / t1, 2), "floor_ms": round(floor_ms, 3),
+           "frac_of_floor": round(floor_ms / t1, 4), "worst_eta": worst,
+           "all_factored": all(i == 0 for i in infos)}
+    del As, Bs, Ls, Xs, work, wf, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -311,6 +399,13 @@ def main():
     if args.sweep:
         return sweep(args)
     from paper_2606_11937_amd import tilechol as tc
+    if args.batched:
+        for la in [int(x) for x in args.batch_lookaheads.split(",")]:
+            tc.chol_set_lookahead(la)
+            print(json.dumps({"kind": "batched", "lookahead": la, **batched_compare(tc, args.batch_count)}),
+                  flush=True)
+        tc.chol_set_lookahead(-1)
+        return
     if args.mixed:
         A0 = make_input(args.n)
         res = mixed_compare(tc, A0, args.T, args.mixed_T)
@@ -412,6 +507,9 @@ def main():
         out["mixed"] = mixed_compare(tc, A0, T, args.mixed_T)
     del A0
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched comparison", file=sys.stderr, flush=True)
+        out["batched"] = batched_compare(tc, args.batch_count)
     if sample is not None:
         print(f"[bench] cpu baseline on a {args.cpu_sample}^2 sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sample, args.cpu_sample)

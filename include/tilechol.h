@@ -225,18 +225,44 @@ int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl
                       double tol, int64_t max_iter, void* work, int64_t work_bytes, void* stream,
                       int64_t* iters, double* eta);
 
-/* Batched factorization of `batch` independent SPD matrices of uneven sizes.
- *   A      host array of `batch` device pointers.
- *   n, lda host arrays of `batch` sizes / leading dimensions.
- *   T      host array of `batch` tile sides, or NULL to let the library pick
- *          T from n alone (deterministic).
+/* ---- batched: many independent SPD matrices of uneven sizes in ONE
+ * persistent launch.  Every matrix keeps its own tile DAG (the asynchronous
+ * schedule's units and ticket order); the launch interleaves the matrices
+ * phase by phase, largest first, so the grid always holds ready units.  A
+ * matrix that is not positive definite is skipped from then on without
+ * disturbing the others.
+ *   A      host array of `batch` device pointers (row-major, lda[i]).
+ *   n, lda host arrays of `batch` orders / leading dimensions (n[i] = 0 is
+ *          allowed and skipped).
+ *   T      host array of `batch` tile sides, or NULL for the tuned choice
+ *          chol_batched_tile(n[i], CHOL_PREC_FP64).  ceil(n / T) must not
+ *          exceed CHOL_ASYNC_MAX_TILES.
+ *   work   device workspace of the *_workspace_size bytes (it holds the
+ *          per-matrix counters and status, the descriptors and the unit
+ *          list the host writes before the launch).
  *   info   host array of `batch` results or NULL (as for chol_factor).
- * Returns CHOL_OK, CHOL_NOT_SPD if any matrix failed (info says which), or a
- * negative error code. */
+ * Returns CHOL_OK, CHOL_NOT_SPD if any matrix failed (info says which),
+ * CHOL_ETIMEOUT, or a negative error code. */
 int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T);
 int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, int64_t batch,
                         const int64_t* T, void* work, int64_t work_bytes, void* stream,
                         int64_t* info);
+
+/* The same launch also solving A_i x_i = b_i for one right-hand side per
+ * matrix: B is a host array of `batch` device pointers to n[i] contiguous
+ * doubles, overwritten by x_i.  Each solve is one unit, run by one
+ * workgroup (forward and backward substitution over 64-row blocks) as soon
+ * as its factor is complete. */
+int64_t chol_factor_solve_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T);
+int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t* n, const int64_t* lda,
+                              int64_t batch, const int64_t* T, void* work, int64_t work_bytes,
+                              void* stream, int64_t* info);
+
+/* Tile side a batched call uses for a matrix of order n when the caller
+ * passes none: a table measured by an offline sweep over n-buckets
+ * (paper_2606_11937_amd/tune_batched.py), deterministic in (n, prec).  Only
+ * CHOL_PREC_FP64 is offered; < 0 on invalid arguments. */
+int64_t chol_batched_tile(int64_t n, int prec);
 
 /* Tile side the library picks for order n when the caller passes none
  * (deterministic in n; from measured factor times). */

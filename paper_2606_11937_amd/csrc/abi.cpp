@@ -5,10 +5,12 @@
 
 #include <atomic>
 #include <new>
+#include <vector>
 
 #include "../../include/tilechol.h"
 #include "dag.h"
 #include "launch.h"
+#include "tuned_tiles.h"
 
 #define TC_PREC_FP64 0
 #define TC_PREC_FP32 1
@@ -236,65 +238,102 @@ int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl
   return r == 0 ? CHOL_OK : CHOL_NOT_CONVERGED;
 }
 
-int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {
+int64_t chol_batched_tile(int64_t n, int prec) {
+  if (prec != CHOL_PREC_FP64) return bad(2);
+  if (n < 0) return bad(1);
+  return tc_tuned_batched_tile(n);
+}
+
+namespace {
+// tile sides of a batch (given, or the tuned choice per n)
+bool batch_tiles(int64_t batch, const int64_t* n, const int64_t* T, std::vector<int64_t>& t) {
+  t.resize(batch);
+  for (int64_t i = 0; i < batch; ++i) {
+    t[i] = T ? T[i] : tc_tuned_batched_tile(n[i] > 0 ? n[i] : 1);
+    if (t[i] < 1) return false;
+  }
+  return true;
+}
+int64_t batch_chunk() {
+  const int64_t grid = tc_batched_grid_size();
+  return tc_lookahead_chunk(grid > 0 ? grid : 1, g_lookahead.load());
+}
+int64_t batched_ws(int64_t batch, const int64_t* n, const int64_t* T, int solve) {
   g_bad_arg = 0;
   if (batch < 0) return bad(1);
   if (batch > 0 && n == nullptr) return bad(2);
-  int64_t total = 0;
-  for (int64_t i = 0; i < batch; ++i) {
+  for (int64_t i = 0; i < batch; ++i)
     if (n[i] < 0 || n[i] > kMaxN) return bad(2);
-    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
-    if (t < 1) return bad(3);
-    total += (tc_ws_bytes(n[i] > 0 ? n[i] : 1, t) + 255) & ~(int64_t)255;
+  std::vector<int64_t> t;
+  if (!batch_tiles(batch, n, T, t)) return bad(3);
+  for (int64_t i = 0; i < batch; ++i)
+    if (n[i] > 0 && tc_cdiv(n[i], t[i]) > CHOL_ASYNC_MAX_TILES) return bad(3);
+  return tc_batched_ws_bytes(batch, n, t.data(), solve, batch_chunk());
+}
+int batched_run(double* const* A, double* const* B, const int64_t* n, const int64_t* lda, int64_t batch,
+                const int64_t* T, void* work, int64_t work_bytes, void* stream, int64_t* info, int iA, int iB,
+                int in, int ilda, int ibatch, int iT, int iwork, int iwb) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(ibatch);
+  if (batch == 0) return CHOL_OK;
+  if (A == nullptr) return bad(iA);
+  if (n == nullptr) return bad(in);
+  if (lda == nullptr) return bad(ilda);
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 0 || n[i] > kMaxN) return bad(in);
+    if (lda[i] < max1(n[i]) || lda[i] > kMaxN) return bad(ilda);
+    if (n[i] > 0 && A[i] == nullptr) return bad(iA);
+    if (B != nullptr && n[i] > 0 && B[i] == nullptr) return bad(iB);
   }
-  return total;
+  std::vector<int64_t> t;
+  if (!batch_tiles(batch, n, T, t)) return bad(iT);
+  for (int64_t i = 0; i < batch; ++i)
+    if (n[i] > 0 && tc_cdiv(n[i], t[i]) > CHOL_ASYNC_MAX_TILES) return bad(iT);
+  const int64_t chunk = batch_chunk();
+  const int64_t need = tc_batched_ws_bytes(batch, n, t.data(), B != nullptr, chunk);
+  if (work == nullptr) return bad(iwork);
+  if (work_bytes < need) return bad(iwb, CHOL_EWORKSPACE);
+  const int64_t grid = tc_batched_grid_size();
+  if (grid <= 0) return CHOL_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (tc_launch_batched(A, B, n, lda, t.data(), batch, work, st, grid, wait_ticks(), chunk) != 0)
+    return CHOL_EDEVICE;
+  if (info == nullptr) return CHOL_OK;
+  std::vector<int32_t> err(batch);
+  std::vector<int64_t> dinfo(batch);
+  if (tc_read_batched_status(work, batch, st, err.data(), dinfo.data()) != 0) return CHOL_EDEVICE;
+  int worst = CHOL_OK;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int s = status_from(err[i], dinfo[i], &info[i]);
+    if (n[i] <= 0) info[i] = 0;
+    if (s == CHOL_ETIMEOUT) worst = CHOL_ETIMEOUT;
+    else if (s != CHOL_OK && worst == CHOL_OK) worst = s;
+  }
+  return worst;
+}
+}  // namespace
+
+int64_t chol_factor_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {
+  return batched_ws(batch, n, T, 0);
 }
 
 int chol_factor_batched(double* const* A, const int64_t* n, const int64_t* lda, int64_t batch, const int64_t* T,
                         void* work, int64_t work_bytes, void* stream, int64_t* info) {
-  g_bad_arg = 0;
-  if (batch < 0) return bad(4);
-  if (batch == 0) return CHOL_OK;
-  if (A == nullptr) return bad(1);
-  if (n == nullptr) return bad(2);
-  if (lda == nullptr) return bad(3);
-  for (int64_t i = 0; i < batch; ++i) {
-    if (n[i] < 0 || n[i] > kMaxN) return bad(2);
-    if (lda[i] < max1(n[i]) || lda[i] > kMaxN) return bad(3);
-    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
-    if (t < 1) return bad(5);
-    if (n[i] > 0 && A[i] == nullptr) return bad(1);
+  return batched_run(A, nullptr, n, lda, batch, T, work, work_bytes, stream, info, 1, 0, 2, 3, 4, 5, 6, 7);
+}
+
+int64_t chol_factor_solve_batched_workspace_size(int64_t batch, const int64_t* n, const int64_t* T) {
+  return batched_ws(batch, n, T, 1);
+}
+
+int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t* n, const int64_t* lda,
+                              int64_t batch, const int64_t* T, void* work, int64_t work_bytes, void* stream,
+                              int64_t* info) {
+  if (B == nullptr) {
+    g_bad_arg = 2;
+    return CHOL_EINVAL;
   }
-  const int64_t need = chol_factor_batched_workspace_size(batch, n, T);
-  if (need < 0) return CHOL_EINVAL;
-  if (work == nullptr) return bad(6);
-  if (work_bytes < need) return bad(7, CHOL_EWORKSPACE);
-  hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)work;
-  for (int64_t i = 0; i < batch; ++i) {
-    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
-    const int64_t nb = n[i] > 0 ? n[i] : 1;
-    if (n[i] > 0 && tc_launch_factor(A[i], n[i], lda[i], t, CHOL_SCHED_FORK_JOIN, w, st, 0, 0, 0) != 0)
-      return CHOL_EDEVICE;
-    w += (tc_ws_bytes(nb, t) + 255) & ~(int64_t)255;
-  }
-  if (info == nullptr) return CHOL_OK;
-  int worst = CHOL_OK;
-  w = (char*)work;
-  for (int64_t i = 0; i < batch; ++i) {
-    const int64_t t = T ? T[i] : chol_default_tile(n[i]);
-    const int64_t nb = n[i] > 0 ? n[i] : 1;
-    info[i] = 0;
-    if (n[i] > 0) {
-      int32_t err = 0;
-      int64_t dinfo = 0;
-      if (tc_read_status(w, st, &err, &dinfo) != 0) return CHOL_EDEVICE;
-      const int s = status_from(err, dinfo, &info[i]);
-      if (s != CHOL_OK && worst == CHOL_OK) worst = s;
-    }
-    w += (tc_ws_bytes(nb, t) + 255) & ~(int64_t)255;
-  }
-  return worst;
+  return batched_run(A, B, n, lda, batch, T, work, work_bytes, stream, info, 1, 2, 3, 4, 5, 6, 7, 8);
 }
 
 int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]) {

@@ -256,6 +256,31 @@ TC_HD TcUnit tc_decode_in_phase(const TcGeom& g, int32_t P, int64_t r) {
   return tc_decode_bulk(g, P, used + r);
 }
 
+// Segments of phase P in ticket order (see tc_decode_in_phase): the column
+// updates, then for each sub-column s its three chain links, each followed
+// by its bulk chunk, then the rest of the bulk.  Writes the sizes to `sz`
+// (if not null; some may be 0) and returns their number, 2 + 6 SB(P).
+TC_HD int64_t tc_phase_segments(const TcGeom& g, int32_t P, int64_t* sz) {
+  int64_t k = 0;
+  if (sz) sz[k] = P >= 1 ? tc_colsize(g, P) : 0;
+  ++k;
+  const int64_t bulk = tc_bulk(g, P);
+  int64_t used = 0;
+  for (int32_t s = 0; s < tc_sb(g, P); ++s) {
+    for (int32_t link = 0; link < 3; ++link) {
+      if (sz) sz[k] = link == 0 ? 1 : link == 1 ? tc_trsm_count(g, P, s) : tc_panel_count(g, P, s);
+      ++k;
+      const int64_t ch = bulk - used < g.Q ? bulk - used : g.Q;
+      if (sz) sz[k] = ch;
+      ++k;
+      used += ch;
+    }
+  }
+  if (sz) sz[k] = bulk - used;
+  ++k;
+  return k;
+}
+
 // Tile-task counts (Results, problem-size scaling: M POTRF, M(M-1)/2 TRSM
 // and SYRK, M(M-1)(M-2)/6 GEMM).
 TC_HD void tc_task_counts(const TcGeom& g, int64_t c[4]) {

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "dag.h"
@@ -452,6 +453,222 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   }
 }
 
+// ------------------------------------------------------------------ batched
+// Many independent SPD matrices in one persistent launch.  Every matrix keeps
+// its own tile DAG (geometry, counters, status header) and its own ticket
+// order (the asynchronous schedule's, cut into its segments: the column
+// updates that open phase P, then for each panel sub-column the POTRF, the
+// TRSM column and the panel updates, each followed by its lookahead chunk of
+// bulk updates, then the rest of the bulk).  The global ticket order takes
+// segment k of phase P of every matrix that has one, largest matrix first,
+// for (P, k) in order, and places a matrix's solve unit right after its last
+// segment.  Each unit therefore waits only for units of its own matrix with
+// smaller tickets, so the co-resident grid cannot deadlock, and the units at
+// the same depth of all matrices sit together: the grid finds ready work
+// while every matrix's chain advances.  A matrix whose factorization fails is
+// skipped from then on; the others are unaffected.
+#define TC_UNIT_SOLVE 4
+
+struct TcBatchMat {
+  double* A;
+  double* b;  // one right-hand side (n contiguous doubles) or null
+  int64_t lda;
+  TcGeom g;
+  TcWs ws;        // per-matrix status header and counters
+  int32_t* done;  // factor units finished
+  int64_t nunits;
+};
+struct TcBatchUnit {
+  int32_t m, kind, J, I, a, K, b, pad;
+};
+struct TcBatchSlot {
+  int32_t m, P;   // P < 0: the solve unit
+  int64_t start;  // first global ticket
+  int64_t pos;    // first position inside phase P of matrix m
+  int64_t size;
+};
+
+__global__ __launch_bounds__(TC_THREADS) void tc_batch_units(const TcBatchMat* __restrict__ mats,
+                                                             const TcBatchSlot* __restrict__ slots,
+                                                             TcBatchUnit* __restrict__ table) {
+  const TcBatchSlot sl = slots[blockIdx.x];
+  const TcGeom g = mats[sl.m].g;
+  for (int64_t r = threadIdx.x; r < sl.size; r += TC_THREADS) {
+    TcBatchUnit e;
+    if (sl.P < 0) {
+      e = {sl.m, TC_UNIT_SOLVE, 0, 0, 0, 0, 0, 0};
+    } else {
+      const TcUnit u = tc_decode_in_phase(g, sl.P, sl.pos + r);
+      e = {sl.m, u.kind, u.J, u.I, u.a, u.K, u.b, 0};
+    }
+    table[sl.start + r] = e;
+  }
+}
+
+// ---- one-workgroup solve with one right-hand side, in place in b
+// (forward then backward substitution over 64-row blocks; the finished part
+// is folded in by 4 threads per row with a fixed combination order, and
+// the diagonal block is solved by wave 0 in registers, one row per lane).
+struct TcSolveSmem {
+  double Lbb[64][65];
+  double rdiag[64];
+  double part[64];
+};
+
+__device__ __forceinline__ void tc_wg_stage_diag(const double* L, int64_t lda, int64_t r0, int nr, TcSolveSmem& sm) {
+  for (int e = tc_tid(); e < 64 * 64; e += TC_THREADS) {
+    const int i = e >> 6, k = e & 63;
+    sm.Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tc_tid() < 64) sm.rdiag[tc_tid()] = 1.0 / sm.Lbb[tc_tid()][tc_tid()];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_t lda, int64_t n,
+                                            double* __restrict__ b, TcSolveSmem& sm) {
+  const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
+  const int r = tid >> 2, p = tid & 3;
+  const int64_t nb = (n + 63) / 64;
+  for (int64_t blk = 0; blk < nb; ++blk) {
+    const int64_t r0 = blk * 64;
+    const int nr = n - r0 < 64 ? (int)(n - r0) : 64;
+    double s = 0.0;
+    if (r < nr) {
+      const double* Lr = L + (r0 + r) * lda;
+      for (int64_t k = p; k < r0; k += 4) s += Lr[k] * b[k];
+    }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if (p == 0) sm.part[r] = s;
+    tc_wg_stage_diag(L, lda, r0, nr, sm);
+    if (w == 0) {
+      double v = lane < nr ? b[r0 + lane] - sm.part[lane] : 0.0;
+      double lr[64];
+#pragma unroll
+      for (int i = 0; i < 64; ++i) lr[i] = sm.Lbb[lane][i];
+      const double dl = sm.Lbb[lane][lane], rl = sm.rdiag[lane];
+#pragma unroll
+      for (int i = 0; i < 64; ++i) {
+        const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
+        if (lane == i) v = xi;
+        else if (lane > i) v = v - lr[i] * xi;
+      }
+      if (lane < nr) b[r0 + lane] = v;
+    }
+    __syncthreads();
+  }
+  for (int64_t blk = nb - 1; blk >= 0; --blk) {
+    const int64_t r0 = blk * 64;
+    const int nr = n - r0 < 64 ? (int)(n - r0) : 64;
+    double s = 0.0;
+    if (r < nr)
+      for (int64_t k = r0 + 64 + p; k < n; k += 4) s += L[k * lda + r0 + r] * b[k];
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if (p == 0) sm.part[r] = s;
+    tc_wg_stage_diag(L, lda, r0, nr, sm);
+    if (w == 0) {
+      double v = lane < nr ? b[r0 + lane] - sm.part[lane] : 0.0;
+      double lc[64];
+#pragma unroll
+      for (int i = 0; i < 64; ++i) lc[i] = sm.Lbb[i][lane];
+      const double dl = sm.Lbb[lane][lane], rl = sm.rdiag[lane];
+#pragma unroll
+      for (int i = 63; i >= 0; --i) {
+        const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
+        if (lane == i) v = xi;
+        else if (lane < i) v = v - lc[i] * xi;
+      }
+      if (lane < nr) b[r0 + lane] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// A pointer read from LDS is generic; casting it through the global address
+// space lets the compiler use global (not flat) instructions for it.
+template <typename T>
+__device__ __forceinline__ T* tc_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)p;
+}
+
+union alignas(512) TcBatchSmem {
+  TcSmem f;
+  TcSolveSmem s;
+};
+
+__global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_batched(
+    const TcBatchMat* __restrict__ mats, const TcBatchUnit* __restrict__ table, int64_t total, int32_t* ticket,
+    int64_t wait_ticks) {
+  __shared__ TcBatchSmem sm;
+  __shared__ TcBatchMat s_mat;
+  __shared__ TcUnit s_unit;
+  __shared__ int32_t s_go, s_run;
+  if (threadIdx.x == 0) {
+    s_unit.kind = -1;
+    s_run = 0;
+  }
+  __syncthreads();
+  for (;;) {
+    asm volatile("" ::: "memory");
+    // thread 0: publish the previous unit, take a ticket, wait for its inputs
+    // (one thread-0 region per pass, as in the single-matrix kernel)
+    if (threadIdx.x == 0) {
+      if (s_unit.kind >= 0 && s_unit.kind != TC_UNIT_SOLVE && s_run && !tc_err_set(s_mat.ws.hdr)) {
+        tc_unit_publish(s_mat.g, s_mat.ws, s_unit);
+        __hip_atomic_fetch_add(s_mat.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const int64_t t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int32_t go = 0, run = 0;
+      if (t < total) {
+        const TcBatchUnit e = table[t];
+        s_mat = mats[e.m];
+        const TcUnit u = {e.kind, e.J, e.I, e.a, e.K, e.b};
+        go = 1;
+        run = 1;
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+          if (tc_err_set(s_mat.ws.hdr)) { run = 0; break; }
+          const bool ready = u.kind == TC_UNIT_SOLVE
+                                 ? __hip_atomic_load(s_mat.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                       s_mat.nunits
+                                 : tc_unit_ready(s_mat.g, s_mat.ws, u);
+          if (ready) break;
+          if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(s_mat.ws.hdr, 2, 0); run = 0; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (run) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_unit = u;
+      }
+      s_go = go;
+      s_run = run;
+    }
+    __syncthreads();
+    if (!tc_uniform(s_go)) break;
+    if (tc_uniform(s_run)) {
+      const TcUnit u = {tc_ctx32(s_unit.kind), tc_ctx32(s_unit.J), tc_ctx32(s_unit.I),
+                        tc_ctx32(s_unit.a), tc_ctx32(s_unit.K), tc_ctx32(s_unit.b)};
+      const TcGeom cg = tc_ctx_geom(s_mat.g);
+      double* A = tc_global(s_mat.A);
+      const int64_t lda = tc_ctx64(s_mat.lda);
+      if (u.kind == TC_UNIT_UPDATE) {
+        tc_run_update(A, lda, cg, u, sm.f.upd);
+      } else if (u.kind == TC_UNIT_PANEL) {
+        tc_run_panel(A, lda, cg, u, sm.f.upd);
+      } else if (u.kind == TC_UNIT_TRSM) {
+        tc_run_trsm(A, lda, cg, u.J, u.K, u.I, u.a, sm.f.trsm);
+      } else if (u.kind == TC_UNIT_POTRF) {
+        tc_run_potrf(A, lda, cg, u.J, u.a, tc_global(s_mat.ws.hdr), sm.f.potrf);
+      } else {
+        tc_wg_solve(A, lda, cg.n, tc_global(s_mat.b), sm.s);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+  }
+}
+
 // Synchronous tasking (the paper's task-synchronous variant, tasks with a
 // taskwait after each phase): one persistent launch walks the phases of the
 // blocked program order, for each step J and sub-column s the POTRF, the
@@ -739,6 +956,163 @@ int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int pre
   return tc_chk(hipGetLastError());
 }
 
+// ---- batched launcher.  Workspace layout (each part 256-byte aligned):
+//   ticket | per-matrix status headers | done counters | per-matrix pdone and
+//   ver counters (all zeroed by one fill) | descriptors | slots | unit table
+namespace {
+struct TcBatchLayout {
+  int64_t hdrs, done, counters, zero_end, mats, slots, table, total_bytes;
+  int64_t nslots, nunits;
+};
+inline int64_t tc_ctr_bytes(const TcGeom& g) {
+  return tc_round256(4 * (int64_t)g.NRB) + tc_round256(4 * (int64_t)g.NRB * g.NRB);
+}
+}  // namespace
+
+static TcBatchLayout tc_batch_layout(int64_t batch, const int64_t* n, const int64_t* T, bool solve, int64_t chunk,
+                                     std::vector<TcGeom>* geoms) {
+  TcBatchLayout L{};
+  int64_t ctr = 0, units = 0, slots = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] <= 0) continue;
+    const TcGeom g = tc_geom(n[i], T[i], chunk);
+    if (geoms) (*geoms)[i] = g;
+    ctr += tc_ctr_bytes(g);
+    for (int32_t P = 0; P < g.M; ++P) {
+      units += tc_phase_size(g, P);
+      slots += tc_phase_segments(g, P, nullptr);
+    }
+    if (solve) {
+      units += 1;
+      slots += 1;
+    }
+  }
+  L.hdrs = 256;
+  L.done = L.hdrs + tc_round256((int64_t)sizeof(TcWsHeader) * batch);
+  L.counters = L.done + tc_round256(4 * batch);
+  L.zero_end = L.counters + ctr;
+  L.mats = L.zero_end;
+  L.slots = L.mats + tc_round256((int64_t)sizeof(TcBatchMat) * batch);
+  L.table = L.slots + tc_round256((int64_t)sizeof(TcBatchSlot) * slots);
+  L.total_bytes = L.table + tc_round256((int64_t)sizeof(TcBatchUnit) * units);
+  L.nslots = slots;
+  L.nunits = units;
+  return L;
+}
+
+int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk) {
+  return tc_batch_layout(batch, n, T, solve != 0, chunk, nullptr).total_bytes;
+}
+
+int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
+                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk) {
+  const bool solve = b != nullptr;
+  std::vector<TcGeom> geoms(batch);
+  const TcBatchLayout L = tc_batch_layout(batch, n, T, solve, chunk, &geoms);
+  char* base = (char*)work;
+  // descriptors
+  std::vector<TcBatchMat> mats(batch);
+  int64_t ctr = L.counters;
+  int32_t maxM = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    TcBatchMat& d = mats[i];
+    d = TcBatchMat{};
+    d.ws.hdr = (TcWsHeader*)(base + L.hdrs) + i;
+    d.done = (int32_t*)(base + L.done) + i;
+    if (n[i] <= 0) continue;
+    const TcGeom& g = geoms[i];
+    d.A = A[i];
+    d.b = solve ? b[i] : nullptr;
+    d.lda = lda[i];
+    d.g = g;
+    d.ws.offs = nullptr;
+    d.ws.pdone = (int32_t*)(base + ctr);
+    d.ws.ver = (int32_t*)(base + ctr + tc_round256(4 * (int64_t)g.NRB));
+    d.ws.noop = 0;
+    ctr += tc_ctr_bytes(g);
+    int64_t nu = 0;
+    for (int32_t P = 0; P < g.M; ++P) nu += tc_phase_size(g, P);
+    d.nunits = nu;
+    if (g.M > maxM) maxM = g.M;
+  }
+  // slots: segment k of phase P of every matrix, largest first, for (P, k)
+  // in order; a matrix's solve right after its last segment
+  std::vector<int64_t> order;
+  for (int64_t i = 0; i < batch; ++i)
+    if (n[i] > 0) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return n[x] > n[y]; });
+  std::vector<TcBatchSlot> slots;
+  slots.reserve(L.nslots);
+  int64_t start = 0;
+  // per phase: each live matrix's segment sizes, then the merge
+  std::vector<int64_t> live, segs, segoff, pos;
+  for (int32_t P = 0; P < maxM; ++P) {
+    live.clear();
+    segoff.clear();
+    segs.clear();
+    int64_t kmax = 0;
+    for (int64_t i : order) {
+      if (P >= geoms[i].M) continue;
+      const int64_t ns = tc_phase_segments(geoms[i], P, nullptr);
+      live.push_back(i);
+      segoff.push_back((int64_t)segs.size());
+      segs.resize(segs.size() + ns);
+      tc_phase_segments(geoms[i], P, segs.data() + segoff.back());
+      kmax = std::max(kmax, ns);
+    }
+    segoff.push_back((int64_t)segs.size());
+    pos.assign(live.size(), 0);
+    for (int64_t k = 0; k < kmax; ++k) {
+      for (size_t q = 0; q < live.size(); ++q) {
+        const int64_t i = live[q];
+        const int64_t nseg = segoff[q + 1] - segoff[q];
+        if (k >= nseg) continue;
+        const int64_t sz = segs[segoff[q] + k];
+        if (sz > 0) {
+          slots.push_back({(int32_t)i, P, start, pos[q], sz});
+          start += sz;
+          pos[q] += sz;
+        }
+        if (solve && P == geoms[i].M - 1 && k == nseg - 1) {
+          slots.push_back({(int32_t)i, -1, start, 0, 1});
+          start += 1;
+        }
+      }
+    }
+  }
+  if ((int64_t)slots.size() > L.nslots || start != L.nunits) return TC_LAUNCH_EINVAL;  // (empty segments dropped)
+  hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, L.zero_end / 4);
+  if (hipMemcpyAsync(base + L.mats, mats.data(), sizeof(TcBatchMat) * batch, hipMemcpyHostToDevice, st) != hipSuccess)
+    return TC_LAUNCH_EDEVICE;
+  if (!slots.empty() &&
+      hipMemcpyAsync(base + L.slots, slots.data(), sizeof(TcBatchSlot) * slots.size(), hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+    return TC_LAUNCH_EDEVICE;
+  if (slots.empty()) return tc_chk(hipGetLastError());
+  hipLaunchKernelGGL(tc_batch_units, dim3((unsigned)slots.size()), dim3(TC_THREADS), 0, st,
+                     (const TcBatchMat*)(base + L.mats), (const TcBatchSlot*)(base + L.slots),
+                     (TcBatchUnit*)(base + L.table));
+  tc_timed(TC_TIMING_PERSISTENT, st, [&] {
+    hipLaunchKernelGGL(tc_batched, dim3((unsigned)grid), dim3(TC_THREADS), 0, st,
+                       (const TcBatchMat*)(base + L.mats), (const TcBatchUnit*)(base + L.table), L.nunits,
+                       (int32_t*)base, wait_ticks);
+  });
+  return tc_chk(hipGetLastError());
+}
+
+int tc_read_batched_status(const void* work, int64_t batch, hipStream_t st, int32_t* error, int64_t* info) {
+  std::vector<TcWsHeader> h(batch);
+  if (batch > 0 && hipMemcpyAsync(h.data(), (const char*)work + 256, sizeof(TcWsHeader) * batch,
+                                  hipMemcpyDeviceToHost, st) != hipSuccess)
+    return TC_LAUNCH_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  for (int64_t i = 0; i < batch; ++i) {
+    error[i] = h[i].error;
+    info[i] = h[i].info;
+  }
+  return 0;
+}
+
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info) {
   TcWsHeader h;
   if (hipMemcpyAsync(&h, work, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
@@ -767,6 +1141,11 @@ static int64_t tc_persistent_grid(K kernel, int64_t* cache) {
 int64_t tc_async_grid_size() {
   static int64_t cached[64] = {0};
   return tc_persistent_grid(tc_async, cached);
+}
+
+int64_t tc_batched_grid_size() {
+  static int64_t cached[64] = {0};
+  return tc_persistent_grid(tc_batched, cached);
 }
 
 int64_t tc_sync_grid_size() {

@@ -57,3 +57,12 @@ int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs);
 int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T, const double* B,
               int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method, double tol, int64_t max_iter, void* work,
               hipStream_t st, int64_t wait_ticks, int64_t* iters, double* eta_out);
+// Batched: many matrices in one persistent launch (b null: factor only,
+// else one right-hand side per matrix, solved in place after its factor).
+// Matrices with n <= 0 are skipped.  chunk: ticket-order lookahead of each
+// matrix (as for the asynchronous schedule).
+int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk);
+int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
+                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk);
+int tc_read_batched_status(const void* work, int64_t batch, hipStream_t st, int32_t* error, int64_t* info);
+int64_t tc_batched_grid_size();

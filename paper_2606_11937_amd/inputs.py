@@ -19,6 +19,15 @@ recipes below are those workloads at fixed seeds:
                               divides by powers of two and L0 / 4 has
                               quarter-integer entries: exact in FP32 and BF16.
 
+  batch_sizes(count, seed, lo, hi)
+                              orders log-uniform in [lo, hi]:
+                              round(exp(U(ln lo, ln hi))) from numpy's
+                              default_rng(seed).
+  gg_batch_device(sizes, seed)
+                              the G G^T / n + I recipe for every order of a
+                              batch, built on the device (matrix i from
+                              torch's generator seeded seed * 1000003 + i).
+
 Both sides of a parity test receive the identical FP64 bytes produced here.
 """
 from __future__ import annotations
@@ -116,3 +125,25 @@ def integer_factor_norm4(n: int, seed: int = 0):
             L0[i, cols] = np.array(offs) * rng.choice([-1, 1], size=len(offs))
     A = L0 @ L0.T
     return np.ascontiguousarray(A.astype(np.float64)), np.ascontiguousarray(L0.astype(np.float64))
+
+
+def batch_sizes(count: int, seed: int = 3, lo: int = 32, hi: int = 2048) -> list[int]:
+    u = np.random.default_rng(seed).uniform(np.log(lo), np.log(hi), size=count)
+    return [int(v) for v in np.rint(np.exp(u))]
+
+
+def gg_batch_device(sizes, seed: int = 3, device="cuda"):
+    """A_i = G_i G_i^T / n_i + I (symmetrised), G_i iid N(0,1) from torch's
+    generator on `device` seeded seed * 1000003 + i; returns a list of
+    contiguous (n_i, n_i) float64 tensors."""
+    import torch
+    out = []
+    for i, n in enumerate(sizes):
+        g = torch.Generator(device=device)
+        g.manual_seed(seed * 1000003 + i)
+        G = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+        A = G @ G.T / n
+        A = (A + A.T) * 0.5
+        A += torch.eye(n, dtype=torch.float64, device=device)
+        out.append(A.contiguous())
+    return out

@@ -52,6 +52,10 @@ SIGNATURES = [
     ("chol_solve", _int, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp]),
     ("chol_factor_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
     ("chol_factor_batched", _int, [ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp, _i64, _vp, _pi64]),
+    ("chol_factor_solve_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
+    ("chol_factor_solve_batched", _int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp,
+                                         _i64, _vp, _pi64]),
+    ("chol_batched_tile", _i64, [_i64, _int]),
     ("chol_factor_mixed_workspace_size", _i64, [_i64, _i64, _int]),
     ("chol_factor_mixed", _int, [_vp, _i64, _i64, _i64, _int, _int, _dbl, _vp, _i64, _vp, _pi64]),
     ("chol_refine_workspace_size", _i64, [_i64, _i64, _i64]),
@@ -259,34 +263,74 @@ def chol_solve_refine(A, L, B, X, T: int, method="ir", tol: float = 1e-12, max_i
 # ---------------------------------------------------------------- batched
 def chol_factor_batched_workspace_size(ns, Ts=None) -> int:
     b = len(ns)
-    n_arr = (ctypes.c_int64 * b)(*ns)
+    n_arr = (ctypes.c_int64 * max(b, 1))(*ns)
     t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
     return int(lib.chol_factor_batched_workspace_size(b, n_arr, t_arr))
 
 
-def chol_factor_batched(As, Ts=None, work=None, stream=None, sync: bool = True):
-    """Factor a list of square row-major float64 GPU tensors in place.
-    Returns the list of infos when sync."""
-    import torch
-    b = len(As)
+def chol_factor_solve_batched_workspace_size(ns, Ts=None) -> int:
+    b = len(ns)
+    n_arr = (ctypes.c_int64 * max(b, 1))(*ns)
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    return int(lib.chol_factor_solve_batched_workspace_size(b, n_arr, t_arr))
+
+
+def chol_batched_tile(n: int, prec="fp64") -> int:
+    return int(lib.chol_batched_tile(n, _prec(prec)))
+
+
+def _batch_args(As):
     for A in As:
         _check_matrix(A)
+    b = len(As)
     ns = [A.shape[0] for A in As]
     ldas = [A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1]) for A in As]
+    ptrs = (ctypes.c_void_p * max(b, 1))(*[A.data_ptr() for A in As])
+    return b, ns, ptrs, (ctypes.c_int64 * max(b, 1))(*ns), (ctypes.c_int64 * max(b, 1))(*ldas)
+
+
+def chol_factor_batched(As, Ts=None, work=None, stream=None, sync: bool = True):
+    """Factor a list of square row-major float64 GPU tensors in place, in one
+    persistent launch.  Returns the list of infos when sync."""
+    import torch
+    b, ns, ptrs, n_arr, l_arr = _batch_args(As)
     if work is None:
         nb = chol_factor_batched_workspace_size(ns, Ts)
         if nb < 0:
             raise TileCholError(nb, "chol_factor_batched_workspace_size", last_bad_arg())
         work = torch.empty(max(nb, 8), dtype=torch.uint8, device=As[0].device if b else "cuda")
-    ptrs = (ctypes.c_void_p * b)(*[A.data_ptr() for A in As])
-    n_arr = (ctypes.c_int64 * b)(*ns)
-    l_arr = (ctypes.c_int64 * b)(*ldas)
     t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
     infos = (ctypes.c_int64 * max(b, 1))()
     st = lib.chol_factor_batched(ptrs, n_arr, l_arr, b, t_arr, ctypes.c_void_p(work.data_ptr()), work.numel(),
                                  _stream(stream), infos if sync else None)
     if st not in (CHOL_OK, CHOL_NOT_SPD):
         raise TileCholError(st, "chol_factor_batched", last_bad_arg())
+    return [int(infos[i]) for i in range(b)] if sync else None
+
+
+def chol_factor_solve_batched(As, Bs, Ts=None, work=None, stream=None, sync: bool = True):
+    """Factor each A_i in place and overwrite each b_i (contiguous float64 GPU
+    vector of n_i entries) with A_i^{-1} b_i, all in one persistent launch.
+    Returns the list of infos when sync."""
+    import torch
+    b, ns, ptrs, n_arr, l_arr = _batch_args(As)
+    if len(Bs) != b:
+        raise ValueError("one right-hand side per matrix")
+    for A, B in zip(As, Bs):
+        if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous() and B.numel() == A.shape[0]):
+            raise TypeError("each right-hand side must be a contiguous float64 GPU vector of n entries")
+    if work is None:
+        nb = chol_factor_solve_batched_workspace_size(ns, Ts)
+        if nb < 0:
+            raise TileCholError(nb, "chol_factor_solve_batched_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=As[0].device if b else "cuda")
+    bptrs = (ctypes.c_void_p * max(b, 1))(*[B.data_ptr() for B in Bs])
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    infos = (ctypes.c_int64 * max(b, 1))()
+    st = lib.chol_factor_solve_batched(ptrs, bptrs, n_arr, l_arr, b, t_arr, ctypes.c_void_p(work.data_ptr()),
+                                       work.numel(), _stream(stream), infos if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor_solve_batched", last_bad_arg())
     return [int(infos[i]) for i in range(b)] if sync else None
 
 

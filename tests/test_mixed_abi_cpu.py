@@ -110,3 +110,46 @@ def test_refine_empty_is_ok(tc):
 
 def test_not_converged_status_string(tc):
     assert "tolerance" in tc.status_str(tc.CHOL_NOT_CONVERGED)
+
+
+# ------------------------------------------------------------------ batched
+def test_batched_argument_checks(tc):
+    n = (ctypes.c_int64 * 2)(64, 100)
+    lda = (ctypes.c_int64 * 2)(64, 99)
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, 2, None, FAKE, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 3
+    lda[1] = 100
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, -1, None, FAKE, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 4
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, 2, None, None, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 6
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, 2, None, FAKE, 10, None, None)
+    assert st == tc.CHOL_EWORKSPACE and tc.last_bad_arg() == 7
+    bad_t = (ctypes.c_int64 * 2)(0, 8)
+    st = tc.lib.chol_factor_batched(ptrs, n, lda, 2, bad_t, FAKE, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 5
+    st = tc.lib.chol_factor_solve_batched(ptrs, None, n, lda, 2, None, FAKE, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 2
+    bptrs = (ctypes.c_void_p * 2)(0x3000, None)
+    st = tc.lib.chol_factor_solve_batched(ptrs, bptrs, n, lda, 2, None, FAKE, BIG, None, None)
+    assert st == tc.CHOL_EINVAL and tc.last_bad_arg() == 2
+
+
+def test_batched_workspace_and_tiles(tc):
+    ns = [0, 1, 100, 129, 2048, 5000]
+    a = tc.chol_factor_batched_workspace_size(ns)
+    b = tc.chol_factor_solve_batched_workspace_size(ns)
+    assert 0 < a <= b
+    assert tc.chol_factor_batched_workspace_size([]) > 0
+    assert tc.chol_factor_batched_workspace_size([-1]) == tc.CHOL_EINVAL
+    # the tuned table: one tile up to its first bucket, then at least 64
+    assert tc.chol_batched_tile(1) == 1 and tc.chol_batched_tile(100) == 100
+    prev = 0
+    for n in (200, 500, 1000, 2048, 4096, 32768):
+        t = tc.chol_batched_tile(n)
+        assert t >= 64 and t >= prev
+        prev = t
+    assert tc.chol_batched_tile(100, "fp32") < 0
+    # deterministic in n
+    assert [tc.chol_batched_tile(n) for n in range(1, 3000, 37)] == [tc.chol_batched_tile(n) for n in range(1, 3000, 37)]
