@@ -30,6 +30,12 @@ The default run prints one JSON line (the contract line) with
                 right-hand side: one persistent launch
                 (chol_factor_solve_batched, tuned tile sides) against a
                 loop of chol_factor + chol_solve per matrix.
+--serve runs the serving comparison: Poisson arrivals of factor + solve
+requests (SE kernel on n points, n log-uniform in [64, 8192], lengthscale
+U[0.05, 0.5], nugget 1e-2, 1-8 right-hand sides, tolerance 1e-6 or 1e-12)
+at each rate, served with continuous batching (chol_server, one tick =
+one batched launch) and by the one-at-a-time FP64 baseline; one JSON line
+per (rate, server) with solves/s and p50/p99 latency.
 --mixed prints only that comparison, one JSON line per precision;
 --batched likewise for the batched comparison.
 --sweep prints one JSON line per (n, T, schedule) with factor-only times
@@ -109,6 +115,11 @@ def parse():
                    help="only the batched comparison (4096 orders log-uniform in [32, 2048], one launch vs a loop)")
     p.add_argument("--no-batched", action="store_true", help="leave the batched comparison out")
     p.add_argument("--batch-count", type=int, default=4096)
+    p.add_argument("--serve", action="store_true",
+                   help="only the serving comparison (Poisson arrivals, continuous batching vs one at a time)")
+    p.add_argument("--rates", default="100,200,500,1000,2000,5000")
+    p.add_argument("--serve-seconds", type=float, default=2.0,
+                   help="arrivals per rate: min(2000, rate x this many seconds)")
     p.add_argument("--batch-lookaheads", default="-1",
                    help="batched ticket order: bulk units per chain link of each matrix (comma list; -1 default)")
     return p.parse_args()
@@ -389,6 +400,56 @@ def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
     return out
 
 
+def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: float = 96.0):
+    """Submit `count` requests with exponential inter-arrival times (rate per
+    second) to a fresh server, from this thread at their scheduled times,
+    then collect every result.  Latency is the server's own: submission to
+    the result in host memory.  solves/s counts requests whose backward error
+    met their tolerance, over the span from the first arrival to the last
+    completion."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, count)
+    arr = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for _ in range(count):
+        n = int(np.rint(np.exp(rng.uniform(np.log(64), np.log(8192)))))
+        nrhs = int(rng.integers(1, 9))
+        reqs.append((rng.random((n, 2)), rng.standard_normal((n, nrhs)), float(rng.uniform(0.05, 0.5)), 1e-2,
+                     1e-6 if rng.random() < 0.5 else 1e-12))
+    arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
+    srv = tc.Server(arena, 8 << 30, mode)
+    ids, lag = [], 0.0
+    t0 = time.perf_counter()
+    for k, (p, B, ell, nug, tol) in enumerate(reqs):
+        target = t0 + arr[k]
+        while time.perf_counter() < target:
+            pass
+        lag = max(lag, time.perf_counter() - target)
+        ids.append(srv.submit(p, B, ell, nug, tol))
+    lat, met, worst = {1e-6: [], 1e-12: []}, 0, 0.0
+    for rid, r in zip(ids, reqs):
+        st, _, eta, latency, info = srv.wait(rid, timeout=600.0, want_x=False)
+        lat[r[4]].append(latency)
+        met += st == tc.CHOL_OK
+        worst = max(worst, eta)
+    t_end = time.perf_counter()
+    ticks = srv.ticks()
+    srv.close()
+    del arena
+    torch.cuda.empty_cache()
+    allv = sorted(lat[1e-6] + lat[1e-12])
+    pct = lambda v, q: round(float(np.percentile(v, q)) * 1e3, 3) if v else None
+    span = t_end - t0  # arrivals start at t0; the last wait returns at the last completion or later
+    return {"rate": rate, "requests": count, "server": mode, "met_tolerance": int(met),
+            "solves_per_s": round(met / span, 1), "span_s": round(span, 3), "ticks": ticks,
+            "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99),
+            "p50_ms_tol1e-6": pct(lat[1e-6], 50), "p99_ms_tol1e-6": pct(lat[1e-6], 99),
+            "p50_ms_tol1e-12": pct(lat[1e-12], 50), "p99_ms_tol1e-12": pct(lat[1e-12], 99),
+            "worst_eta": worst, "max_submit_lag_ms": round(lag * 1e3, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -399,6 +460,12 @@ def main():
     if args.sweep:
         return sweep(args)
     from paper_2606_11937_amd import tilechol as tc
+    if args.serve:
+        for rate in [float(x) for x in args.rates.split(",")]:
+            count = int(min(2000, max(50, rate * args.serve_seconds)))
+            for mode in ("continuous", "fifo"):
+                print(json.dumps({"kind": "serve", **serve_compare(tc, rate, count, 4, mode)}), flush=True)
+        return
     if args.batched:
         for la in [int(x) for x in args.batch_lookaheads.split(",")]:
             tc.chol_set_lookahead(la)

@@ -264,6 +264,56 @@ int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t*
  * CHOL_PREC_FP64 is offered; < 0 on invalid arguments. */
 int64_t chol_batched_tile(int64_t n, int prec);
 
+/* ---- serving with continuous batching ----------------------------------
+ * A server takes factor + solve requests at any time and answers each with
+ * X = A^-1 B and its backward error.  A request is a Gaussian-process style
+ * system: A = k(x_i, x_j) + nugget I with the squared-exponential kernel
+ * k(x, y) = exp(-|x - y|^2 / (2 lengthscale^2)) on n points in the plane,
+ * 1 <= nrhs <= CHOL_SERVE_MAX_RHS right-hand sides, and a target backward
+ * error tol.  A worker thread of the server admits pending requests in
+ * arrival order while their device footprint (8 n^2 + 32 n nrhs + 16 n bytes
+ * plus a small per-tick workspace) fits in the caller's arena, and launches
+ * each group as one tick: matrix assembly on the device, ONE persistent
+ * batched factorization launch (tile side from chol_batched_tile), the
+ * solves as multi-workgroup sweeps (as chol_solve), and a matrix-free
+ * residual giving every request's backward error.  Up to two
+ * ticks are in flight on two streams of the server, so requests that
+ * arrive while a tick runs are admitted and launched meanwhile.  A
+ * request's result does not depend on which other requests shared its tick
+ * (bit for bit).  All arithmetic is FP64.
+ *   CHOL_SERVE_FIFO is the plain baseline: one request at a time, chol_factor
+ *   (fork-join, chol_default_tile) then chol_solve.
+ * Memory: the device arena (arena_bytes) belongs to the caller and is the
+ * server's HBM budget; the server allocates no device memory.  It allocates
+ * pinned_bytes of pinned host memory for staging (inputs and results of the
+ * requests in flight) and frees it in chol_server_destroy.
+ * Threads: submit and wait may be called from any thread.  destroy lets the
+ * admitted and pending requests finish, then stops the worker. */
+typedef struct chol_server chol_server;
+enum { CHOL_SERVE_CONTINUOUS = 0, CHOL_SERVE_FIFO = 1 };
+#define CHOL_SERVE_MAX_RHS 8
+
+/* max_per_tick: requests launched together at most (1 .. 65536). */
+int chol_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int mode,
+                       int64_t max_per_tick, chol_server** server);
+/* points: host, n x 2 row-major (copied); B: host, n x nrhs row-major
+ * (copied); 1 <= n <= 65536.  *id receives the request's handle; the
+ * arrival time is taken here. */
+int chol_server_submit(chol_server* server, const double* points, int64_t n, double lengthscale,
+                       double nugget, const double* B, int64_t nrhs, double tol, int64_t* id);
+/* Wait up to timeout_s seconds for request id.  When it is done: X (host,
+ * n x nrhs, or NULL) receives the solution, *eta the worst column's backward
+ * error, *latency_s the time from submission to the result being in host
+ * memory.  Returns CHOL_OK (eta <= tol), CHOL_NOT_CONVERGED (done, eta >
+ * tol), CHOL_NOT_SPD (*info as for chol_factor), CHOL_EWORKSPACE (the
+ * request can never fit in the arena), CHOL_ETIMEOUT (not done yet), or a
+ * negative error code. */
+int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta,
+                     double* latency_s, int64_t* info);
+/* Ticks launched so far (< 0 on invalid arguments). */
+int64_t chol_server_ticks(chol_server* server);
+int chol_server_destroy(chol_server* server);
+
 /* Tile side the library picks for order n when the caller passes none
  * (deterministic in n; from measured factor times). */
 int64_t chol_default_tile(int64_t n);

@@ -96,12 +96,7 @@ double chol_set_wait_limit(double seconds) {
 
 int64_t chol_set_lookahead(int64_t units) { return g_lookahead.exchange(units < 0 ? -1 : units); }
 
-int64_t chol_default_tile(int64_t n) {
-  // measured on MI355X (factor time against T, fork-join): small orders are
-  // launch-bound and prefer short panels, large ones deep updates
-  if (n <= 8192) return 128;
-  return 1024;
-}
+int64_t chol_default_tile(int64_t n) { return tc_default_tile(n); }
 
 int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched) {
   g_bad_arg = 0;
@@ -334,6 +329,77 @@ int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t*
     return CHOL_EINVAL;
   }
   return batched_run(A, B, n, lda, batch, T, work, work_bytes, stream, info, 1, 2, 3, 4, 5, 6, 7, 8);
+}
+
+// ---------------------------------------------------------------- serving
+struct chol_server {
+  TcServer* s;
+};
+
+int chol_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int mode, int64_t max_per_tick,
+                       chol_server** server) {
+  g_bad_arg = 0;
+  if (arena == nullptr) return bad(1);
+  if (arena_bytes < 4096) return bad(2);
+  if (pinned_bytes < 4096) return bad(3);
+  if (mode != CHOL_SERVE_CONTINUOUS && mode != CHOL_SERVE_FIFO) return bad(4);
+  if (max_per_tick < 1 || max_per_tick > 65536) return bad(5);
+  if (server == nullptr) return bad(6);
+  TcServer* s = nullptr;
+  if (tc_server_create(arena, arena_bytes, pinned_bytes, mode, max_per_tick, wait_ticks(), &s) != 0)
+    return CHOL_EDEVICE;
+  *server = new (std::nothrow) chol_server{s};
+  if (*server == nullptr) {
+    tc_server_destroy(s);
+    return CHOL_EDEVICE;
+  }
+  return CHOL_OK;
+}
+
+int chol_server_submit(chol_server* server, const double* points, int64_t n, double lengthscale, double nugget,
+                       const double* B, int64_t nrhs, double tol, int64_t* id) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  if (points == nullptr) return bad(2);
+  if (n < 1 || n > 65536) return bad(3);
+  if (!(lengthscale > 0.0) || lengthscale > 1e300) return bad(4);
+  if (!(nugget >= 0.0) || nugget > 1e300) return bad(5);
+  if (B == nullptr) return bad(6);
+  if (nrhs < 1 || nrhs > CHOL_SERVE_MAX_RHS) return bad(7);
+  if (!(tol > 0.0)) return bad(8);
+  if (id == nullptr) return bad(9);
+  return tc_server_submit(server->s, points, n, lengthscale, nugget, B, nrhs, tol, id) == 0 ? CHOL_OK
+                                                                                            : CHOL_EDEVICE;
+}
+
+int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta, double* latency_s,
+                     int64_t* info) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  if (!(timeout_s >= 0.0)) return bad(3);
+  const int st = tc_server_wait(server->s, id, timeout_s, X, eta, latency_s, info);
+  switch (st) {
+    case 2: return CHOL_OK;
+    case 5: return CHOL_NOT_CONVERGED;
+    case 3: return CHOL_NOT_SPD;
+    case 4: return CHOL_EWORKSPACE;
+    case 0:
+    case 1: return CHOL_ETIMEOUT;
+    case TC_LAUNCH_EINVAL: return bad(2);
+    default: return CHOL_EDEVICE;
+  }
+}
+
+int64_t chol_server_ticks(chol_server* server) {
+  if (server == nullptr) return bad(1);
+  return tc_server_ticks(server->s);
+}
+
+int chol_server_destroy(chol_server* server) {
+  if (server == nullptr) return CHOL_OK;
+  const int rc = tc_server_destroy(server->s);
+  delete server;
+  return rc == 0 ? CHOL_OK : CHOL_EDEVICE;
 }
 
 int chol_dag_counts(int64_t n, int64_t T, int64_t counts[5]) {

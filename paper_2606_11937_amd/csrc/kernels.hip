@@ -15,6 +15,7 @@
 // work-unit decomposition, so their factors are bit-identical.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -471,8 +472,9 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 
 struct TcBatchMat {
   double* A;
-  double* b;  // one right-hand side (n contiguous doubles) or null
+  double* b;  // right-hand sides (n x nrhs row-major, leading dimension ldb) or null
   int64_t lda;
+  int64_t nrhs, ldb;
   TcGeom g;
   TcWs ws;        // per-matrix status header and counters
   int32_t* done;  // factor units finished
@@ -525,8 +527,9 @@ __device__ __forceinline__ void tc_wg_stage_diag(const double* L, int64_t lda, i
   __syncthreads();
 }
 
+// One column of the right-hand sides: entries b[k * ldb].
 __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_t lda, int64_t n,
-                                            double* __restrict__ b, TcSolveSmem& sm) {
+                                            double* __restrict__ b, int64_t ldb, TcSolveSmem& sm) {
   const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
   const int r = tid >> 2, p = tid & 3;
   const int64_t nb = (n + 63) / 64;
@@ -536,14 +539,14 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     double s = 0.0;
     if (r < nr) {
       const double* Lr = L + (r0 + r) * lda;
-      for (int64_t k = p; k < r0; k += 4) s += Lr[k] * b[k];
+      for (int64_t k = p; k < r0; k += 4) s += Lr[k] * b[k * ldb];
     }
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
     if (p == 0) sm.part[r] = s;
     tc_wg_stage_diag(L, lda, r0, nr, sm);
     if (w == 0) {
-      double v = lane < nr ? b[r0 + lane] - sm.part[lane] : 0.0;
+      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[lane] : 0.0;
       double lr[64];
 #pragma unroll
       for (int i = 0; i < 64; ++i) lr[i] = sm.Lbb[lane][i];
@@ -554,7 +557,7 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
         if (lane == i) v = xi;
         else if (lane > i) v = v - lr[i] * xi;
       }
-      if (lane < nr) b[r0 + lane] = v;
+      if (lane < nr) b[(r0 + lane) * ldb] = v;
     }
     __syncthreads();
   }
@@ -563,13 +566,13 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     const int nr = n - r0 < 64 ? (int)(n - r0) : 64;
     double s = 0.0;
     if (r < nr)
-      for (int64_t k = r0 + 64 + p; k < n; k += 4) s += L[k * lda + r0 + r] * b[k];
+      for (int64_t k = r0 + 64 + p; k < n; k += 4) s += L[k * lda + r0 + r] * b[k * ldb];
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
     if (p == 0) sm.part[r] = s;
     tc_wg_stage_diag(L, lda, r0, nr, sm);
     if (w == 0) {
-      double v = lane < nr ? b[r0 + lane] - sm.part[lane] : 0.0;
+      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[lane] : 0.0;
       double lc[64];
 #pragma unroll
       for (int i = 0; i < 64; ++i) lc[i] = sm.Lbb[i][lane];
@@ -580,7 +583,7 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
         if (lane == i) v = xi;
         else if (lane < i) v = v - lc[i] * xi;
       }
-      if (lane < nr) b[r0 + lane] = v;
+      if (lane < nr) b[(r0 + lane) * ldb] = v;
     }
     __syncthreads();
   }
@@ -661,7 +664,9 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       } else if (u.kind == TC_UNIT_POTRF) {
         tc_run_potrf(A, lda, cg, u.J, u.a, tc_global(s_mat.ws.hdr), sm.f.potrf);
       } else {
-        tc_wg_solve(A, lda, cg.n, tc_global(s_mat.b), sm.s);
+        const int64_t nrhs = tc_ctx64(s_mat.nrhs), ldb = tc_ctx64(s_mat.ldb);
+        double* B = tc_global(s_mat.b);
+        for (int64_t c = 0; c < nrhs; ++c) tc_wg_solve(A, lda, cg.n, B + c, ldb, sm.s);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1005,7 +1010,8 @@ int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, i
 }
 
 int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
-                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk) {
+                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk,
+                      const int64_t* nrhs, const int64_t* ldb) {
   const bool solve = b != nullptr;
   std::vector<TcGeom> geoms(batch);
   const TcBatchLayout L = tc_batch_layout(batch, n, T, solve, chunk, &geoms);
@@ -1024,6 +1030,8 @@ int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, cons
     d.A = A[i];
     d.b = solve ? b[i] : nullptr;
     d.lda = lda[i];
+    d.nrhs = solve ? (nrhs ? nrhs[i] : 1) : 0;
+    d.ldb = solve ? (ldb ? ldb[i] : 1) : 1;
     d.g = g;
     d.ws.offs = nullptr;
     d.ws.pdone = (int32_t*)(base + ctr);
@@ -1111,6 +1119,15 @@ int tc_read_batched_status(const void* work, int64_t batch, hipStream_t st, int3
     info[i] = h[i].info;
   }
   return 0;
+}
+
+int64_t tc_ws_header_bytes() { return (int64_t)sizeof(TcWsHeader); }
+
+void tc_ws_header_read(const void* hdr, int32_t* error, int64_t* info) {
+  TcWsHeader h;
+  memcpy(&h, hdr, sizeof(h));
+  *error = h.error;
+  *info = h.info;
 }
 
 int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* info) {

@@ -4,6 +4,11 @@
 #include <stdint.h>
 
 #define TC_LAUNCH_EDEVICE (-2)
+
+// Tile side of the plain factorization when the caller gives none (measured
+// on MI355X, fork-join: small orders are launch-bound and prefer short
+// panels, large ones deep updates).
+inline int64_t tc_default_tile(int64_t n) { return n <= 8192 ? 128 : 1024; }
 #define TC_LAUNCH_EINVAL (-1)
 
 // Workspace bytes chol_factor needs (both schedules use one layout).
@@ -62,7 +67,25 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
 // Matrices with n <= 0 are skipped.  chunk: ticket-order lookahead of each
 // matrix (as for the asynchronous schedule).
 int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk);
+// nrhs / ldb: right-hand sides per matrix (n x nrhs row-major, leading
+// dimension ldb); null means one right-hand side, contiguous.
 int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
-                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk);
+                      int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk,
+                      const int64_t* nrhs = nullptr, const int64_t* ldb = nullptr);
 int tc_read_batched_status(const void* work, int64_t batch, hipStream_t st, int32_t* error, int64_t* info);
 int64_t tc_batched_grid_size();
+// Status header of a factorization workspace: its size, and decoding a host
+// copy of it.
+int64_t tc_ws_header_bytes();
+void tc_ws_header_read(const void* hdr, int32_t* error, int64_t* info);
+// Serving with continuous batching (serve.hip).  mode 0 continuous batching,
+// 1 one request at a time.
+struct TcServer;
+int tc_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int mode, int64_t max_per_tick,
+                     int64_t wait_ticks, TcServer** out);
+int tc_server_submit(TcServer* S, const double* pts, int64_t n, double lengthscale, double nugget, const double* B,
+                     int64_t nrhs, double tol, int64_t* id);
+int tc_server_wait(TcServer* S, int64_t id, double timeout_s, double* X, double* eta, double* latency_s,
+                   int64_t* info);
+int64_t tc_server_ticks(TcServer* S);
+int tc_server_destroy(TcServer* S);

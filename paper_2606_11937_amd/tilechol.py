@@ -37,6 +37,9 @@ CHOL_REFINE_IR = 0
 CHOL_REFINE_PCG = 1
 PRECISIONS = {"fp64": CHOL_PREC_FP64, "fp32": CHOL_PREC_FP32, "bf16": CHOL_PREC_BF16}
 REFINE_METHODS = {"ir": CHOL_REFINE_IR, "pcg": CHOL_REFINE_PCG}
+CHOL_SERVE_CONTINUOUS = 0
+CHOL_SERVE_FIFO = 1
+CHOL_SERVE_MAX_RHS = 8
 CHOL_ASYNC_MAX_TILES = 1024
 SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG,
              "fork_join_naive": CHOL_SCHED_FORK_JOIN_NAIVE, "task_sync": CHOL_SCHED_TASK_SYNC}
@@ -61,6 +64,11 @@ SIGNATURES = [
     ("chol_refine_workspace_size", _i64, [_i64, _i64, _i64]),
     ("chol_solve_refine", _int, [_vp, _i64, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int, _dbl, _i64,
                                  _vp, _i64, _vp, _pi64, ctypes.POINTER(_dbl)]),
+    ("chol_server_create", _int, [_vp, _i64, _i64, _int, _i64, ctypes.POINTER(_vp)]),
+    ("chol_server_submit", _int, [_vp, _vp, _i64, _dbl, _dbl, _vp, _i64, _dbl, _pi64]),
+    ("chol_server_wait", _int, [_vp, _i64, _dbl, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _pi64]),
+    ("chol_server_ticks", _i64, [_vp]),
+    ("chol_server_destroy", _int, [_vp]),
     ("chol_default_tile", _i64, [_i64]),
     ("chol_dag_counts", _int, [_i64, _i64, _pi64]),
     ("chol_dag_enumerate", _i64, [_i64, _i64, _i64, _pi32, _i64]),
@@ -332,6 +340,68 @@ def chol_factor_solve_batched(As, Bs, Ts=None, work=None, stream=None, sync: boo
     if st not in (CHOL_OK, CHOL_NOT_SPD):
         raise TileCholError(st, "chol_factor_solve_batched", last_bad_arg())
     return [int(infos[i]) for i in range(b)] if sync else None
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Factor + solve server with continuous batching (chol_server_*).
+
+    The device arena (a torch uint8 GPU tensor, the HBM budget) is held for
+    the server's lifetime.  submit() takes numpy inputs and returns a request
+    id; wait() returns (status, X, eta, latency_s, info)."""
+
+    def __init__(self, arena, pinned_bytes: int = 1 << 30, mode: str = "continuous", max_per_tick: int = 4096):
+        import numpy as np  # noqa: F401
+        self.arena = arena
+        self.h = ctypes.c_void_p()
+        m = CHOL_SERVE_CONTINUOUS if mode == "continuous" else CHOL_SERVE_FIFO
+        st = lib.chol_server_create(ctypes.c_void_p(arena.data_ptr()), arena.numel(), pinned_bytes, m, max_per_tick,
+                                    ctypes.byref(self.h))
+        if st != CHOL_OK:
+            raise TileCholError(st, "chol_server_create", last_bad_arg())
+        self.shapes = {}
+
+    def submit(self, points, B, lengthscale: float, nugget: float, tol: float) -> int:
+        import numpy as np
+        P = np.ascontiguousarray(points, dtype=np.float64)
+        Bm = np.ascontiguousarray(B, dtype=np.float64)
+        if Bm.ndim == 1:
+            Bm = Bm.reshape(-1, 1)
+        n, nrhs = Bm.shape
+        rid = ctypes.c_int64(-1)
+        st = lib.chol_server_submit(self.h, P.ctypes.data_as(ctypes.c_void_p), n, float(lengthscale), float(nugget),
+                                    Bm.ctypes.data_as(ctypes.c_void_p), nrhs, float(tol), ctypes.byref(rid))
+        if st != CHOL_OK:
+            raise TileCholError(st, "chol_server_submit", last_bad_arg())
+        self.shapes[rid.value] = (n, nrhs)
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = 60.0, want_x: bool = True):
+        import numpy as np
+        n, nrhs = self.shapes[rid]
+        X = np.empty((n, nrhs)) if want_x else None
+        eta, lat, info = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int64(0)
+        st = lib.chol_server_wait(self.h, rid, float(timeout), X.ctypes.data_as(ctypes.c_void_p) if want_x else None,
+                                  ctypes.byref(eta), ctypes.byref(lat), ctypes.byref(info))
+        if st < 0 and st not in (CHOL_EWORKSPACE, CHOL_ETIMEOUT):
+            raise TileCholError(st, "chol_server_wait", last_bad_arg())
+        return st, X, eta.value, lat.value, info.value
+
+    def ticks(self) -> int:
+        return int(lib.chol_server_ticks(self.h))
+
+    def close(self):
+        if self.h:
+            st = lib.chol_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            if st != CHOL_OK:
+                raise TileCholError(st, "chol_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 # ----------------------------------------------------------- introspection

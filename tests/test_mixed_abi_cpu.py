@@ -153,3 +153,25 @@ def test_batched_workspace_and_tiles(tc):
     assert tc.chol_batched_tile(100, "fp32") < 0
     # deterministic in n
     assert [tc.chol_batched_tile(n) for n in range(1, 3000, 37)] == [tc.chol_batched_tile(n) for n in range(1, 3000, 37)]
+
+
+# ------------------------------------------------------------------ serving
+def test_server_argument_checks(tc):
+    out = ctypes.c_void_p()
+    assert tc.lib.chol_server_create(None, 1 << 30, 1 << 20, 0, 16, ctypes.byref(out)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 1
+    assert tc.lib.chol_server_create(FAKE, 100, 1 << 20, 0, 16, ctypes.byref(out)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 2
+    assert tc.lib.chol_server_create(FAKE, 1 << 30, 10, 0, 16, ctypes.byref(out)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 3
+    assert tc.lib.chol_server_create(FAKE, 1 << 30, 1 << 20, 2, 16, ctypes.byref(out)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 4
+    assert tc.lib.chol_server_create(FAKE, 1 << 30, 1 << 20, 0, 0, ctypes.byref(out)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 5
+    assert tc.lib.chol_server_create(FAKE, 1 << 30, 1 << 20, 0, 16, None) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 6
+    rid = ctypes.c_int64()
+    assert tc.lib.chol_server_submit(None, FAKE, 10, 0.1, 0.01, FAKE, 1, 1e-12, ctypes.byref(rid)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 1
+    assert tc.lib.chol_server_wait(None, 0, 1.0, None, None, None, None) == tc.CHOL_EINVAL
+    assert tc.lib.chol_server_destroy(None) == tc.CHOL_OK
