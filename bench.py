@@ -66,24 +66,33 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense matrix
 # HBM traffic of the trailing-update kernel per launch, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over the default configuration, each
 # scaled by what the same counter reads for a plain copy of known size
-# (fetch x2.0, write x1.0).  `sources` is the SHA-256 of the kernel sources
-# the counters were taken with: if the sources differ, the figure no longer
-# describes this kernel and the line reports traffic as null.
+# (fetch x2.0, write x1.0).  `sources` is the SHA-256 of the kernel's device
+# code (KERNEL_SOURCES) the counters were taken with: if it differs, the
+# figure no longer describes this kernel and the line reports traffic as null.
 TRAFFIC = {
     # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
-    ("fork_join", 32768, 1024): (14799225651,
-                                 "2c8510bb43785aa7fcc6aa855d50bfa15596960a5c2e99bebbb161163d976c55"),
+    ("fork_join", 32768, 1024): (14803277824,
+                                 "d34dce9b4feb02a3cc2ba32a2de0f47f2c6e82098e285e45eb39faadda8277f5"),
 }
-KERNEL_SOURCES = ["paper_2606_11937_amd/csrc/tile_ops.h", "paper_2606_11937_amd/csrc/kernels.hip",
-                  "paper_2606_11937_amd/csrc/dag.h"]
+# the device code the counters describe: the tile bodies, the DAG decode and
+# the fork-join kernels (unit runners up to the naive variant) of kernels.hip
+KERNEL_SOURCES = [("paper_2606_11937_amd/csrc/tile_ops.h", None, None),
+                  ("paper_2606_11937_amd/csrc/dag.h", None, None),
+                  ("paper_2606_11937_amd/csrc/kernels.hip",
+                   "// ------------------------------------------------------------ unit runners",
+                   "// Naive fork-join")]
 
 
 def sources_sha() -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+    for path, start, end in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            text = f.read()
+        if start is not None:
+            i = text.index(start.encode())
+            text = text[i:text.index(end.encode(), i)]
+        h.update(text)
     return h.hexdigest()
 
 
@@ -94,7 +103,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--T", type=int, default=1024)
-    p.add_argument("--sched", default="fork_join", choices=["async_dag", "fork_join", "fork_join_naive", "task_sync"])
+    p.add_argument("--sched", default="fork_join",
+                   choices=["async_dag", "fork_join", "fork_join_naive", "task_sync", "fork_join_lookahead"])
     p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4096, help="order of the oracle's leading-block sample")
@@ -484,7 +494,7 @@ def main():
     print(f"[bench] n={n} T={T} sched={sched} steps={K} warmup={W}", file=sys.stderr, flush=True)
     A0 = make_input(n)
     sample = None if args.no_cpu_baseline else A0[:args.cpu_sample, :args.cpu_sample].cpu()
-    copies = [A0.clone() for _ in range(K + W - 1)] + [A0]
+    copies = [A0.clone() for _ in range(K + W)]  # A0 stays pristine for the comparisons below
     g = torch.Generator(device="cpu").manual_seed(2)
     rhs = [torch.randn(n, args.nrhs, generator=g, dtype=torch.float64).cuda() for _ in range(K + W)]
     works = [tc.factor_workspace(n, T, sched) for _ in range(K + W)]
@@ -509,7 +519,7 @@ def main():
     tc.chol_timing_read(st)  # discard anything recorded before
     # time the dominant kernel's launches only: every event pair costs a few
     # microseconds on the stream
-    tc.chol_timing_enable(["update"] if sched in ("fork_join", "fork_join_naive") else ["persistent"])
+    tc.chol_timing_enable(["update"] if sched.startswith("fork_join") else ["persistent"])
     torch.cuda.synchronize()
     t_start.record(st)
     for k in range(K):
@@ -530,9 +540,11 @@ def main():
     flops = n ** 3 / 3
     value = flops / (ms_step * 1e-3) / 1e12
 
-    if sched in ("fork_join", "fork_join_naive"):
-        kernel = ("tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)" if sched == "fork_join"
-                  else "tc_fj_update_naive (trailing update parallel over tile rows, one launch per step)")
+    if sched.startswith("fork_join"):
+        kernel = {"fork_join": "tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)",
+                  "fork_join_naive": "tc_fj_update_naive (trailing update parallel over tile rows, one launch per step)",
+                  "fork_join_lookahead": "tc_fj_update_range (trailing update in two launches per step, column J+1 "
+                                         "and the rest on a second stream; launch times overlap)"}[sched]
         kms, kcount = launches["update"]
         kflops = update_flops(n, T) * K  # over the K timed factorizations
     elif sched == "task_sync":

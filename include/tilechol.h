@@ -81,7 +81,15 @@ enum {
    * phase.  It needs all its workgroups co-resident (it launches exactly
    * the co-resident capacity); a barrier wait beyond chol_set_wait_limit
    * ends the call with CHOL_ETIMEOUT instead of hanging. */
-  CHOL_SCHED_TASK_SYNC = 3
+  CHOL_SCHED_TASK_SYNC = 3,
+  /* Fork-join with a one-step lookahead: the trailing update of step J is
+   * split into the update of tile column J+1 (on the caller's stream) and
+   * the rest (on a second stream the library keeps per host thread and
+   * device), so the panel of step J+1 is factored while the rest of step J's
+   * update runs.  Events keep every block's updates in step order; the
+   * factor is bit-identical to the other schedules.  The call stays ordered
+   * on the caller's stream. */
+  CHOL_SCHED_FORK_JOIN_LOOKAHEAD = 4
 };
 
 /* Flag ORed into `sched` to run the schedule with empty tile-operation

@@ -224,6 +224,24 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_naive(double* A, i
       }
 }
 
+// ------------------------------------------------- fork-join with lookahead
+// The trailing update of step J split by tile column: units [first, first +
+// gridDim.x) of the launch order (column-major over K).  The first range,
+// column J+1 alone, carries the fused POTRF(J+1, 0) like the whole-update
+// launch; the rest (columns > J+1) runs on a second stream while the panel
+// of step J+1 is factored.
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_range(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                    TcWs ws, int64_t first) {
+  __shared__ TcUpdPotrfSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const TcUnit u = tc_decode_trailing(g, J, J, first + blockIdx.x);
+  tc_run_update(A, lda, g, u, sm.upd);
+  if (first == 0 && blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
+    __syncthreads();
+    tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
+  }
+}
+
 // ----------------------------------------------- low-precision trailing update
 // Mixed-precision fork-join: after the FP64 panel of step J is final, its
 // rows below the diagonal tile are rounded once into the panel copy P (row r
@@ -815,6 +833,38 @@ int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TI
   return rc;
 }
 
+// A second stream and two events per host thread and device for the
+// lookahead schedule (default priority; created on first use and kept).
+namespace {
+struct TcSide {
+  int dev = -1;
+  hipStream_t st = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+thread_local TcSide g_side[8];
+TcSide* tc_side() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 8) return nullptr;
+  TcSide& S = g_side[dev];
+  if (S.st == nullptr) {
+    if (hipStreamCreateWithFlags(&S.st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    for (int k = 0; k < 2; ++k)
+      if (hipEventCreateWithFlags(&S.ev[k], hipEventDisableTiming) != hipSuccess) return nullptr;
+    S.dev = dev;
+  }
+  return &S;
+}
+}  // namespace
+
+static hipStream_t tc_side_stream() {
+  TcSide* S = tc_side();
+  return S ? S->st : nullptr;
+}
+static hipEvent_t tc_side_event(int k) {
+  TcSide* S = tc_side();
+  return S ? S->ev[k] : nullptr;
+}
+
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks, int64_t chunk) {
   const int sched = sched_flags & 0xff;
@@ -856,6 +906,57 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
     tc_timed(TC_TIMING_PERSISTENT, st, [&] {
       hipLaunchKernelGGL(tc_sync, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
     });
+    return tc_chk(hipGetLastError());
+  }
+  if (sched == 4) {
+    // fork-join with a one-step lookahead on two streams: stream A (the
+    // caller's) runs the panel chain and, for step J, the update of column
+    // J+1 only; stream B runs the update of the columns beyond J+1, which
+    // overlaps the panel chain of step J+1.  Each block still receives its
+    // updates in step order: the column-(J+1) update of step J waits for B's
+    // update of step J-1, and B's update of step J waits for A's panel J.
+    hipStream_t sb = tc_side_stream();
+    hipEvent_t ea = tc_side_event(0), eb = tc_side_event(1);
+    if (sb == nullptr || ea == nullptr || eb == nullptr) return TC_LAUNCH_EDEVICE;
+    tc_timed(TC_UNIT_POTRF, st, [&] {
+      hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
+    });
+    if (hipEventRecord(ea, st) != hipSuccess || hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
+    bool b_used = false;
+    for (int32_t J = 0; J < g.M; ++J) {
+      for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
+        const int64_t nt = tc_trsm_count(g, J, sc);
+        if (nt > 0)
+          tc_timed(TC_UNIT_TRSM, st, [&] {
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+        const int64_t np = tc_panel_count(g, J, sc);
+        if (np > 0)
+          tc_timed(TC_UNIT_PANEL, st, [&] {
+            hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          });
+      }
+      const int64_t nu = tc_trailing_units(g, J);
+      if (nu <= 0) continue;
+      const int64_t ncol = tc_colsize(g, J + 1);  // units of tile column J+1 at step J
+      if (hipEventRecord(ea, st) != hipSuccess) return TC_LAUNCH_EDEVICE;  // panel J done
+      if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;  // B's step J-1
+      tc_timed(TC_UNIT_UPDATE, st, [&] {
+        hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)ncol), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
+                           (int64_t)0);
+      });
+      if (nu > ncol) {
+        if (hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
+        tc_timed(TC_UNIT_UPDATE, sb, [&] {
+          hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)(nu - ncol)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
+                             ws, ncol);
+        });
+        if (hipEventRecord(eb, sb) != hipSuccess) return TC_LAUNCH_EDEVICE;
+        b_used = true;
+      }
+    }
+    // the caller's stream covers all of it
+    if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
     return tc_chk(hipGetLastError());
   }
   if (sched == 0) {
@@ -959,6 +1060,45 @@ int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int pre
   }
   if (scale) hipLaunchKernelGGL(tc_unscale_lower, dim3((unsigned)n), dim3(TC_THREADS), 0, st, A, lda, n, d, ws.hdr);
   return tc_chk(hipGetLastError());
+}
+
+// ---- pinned staging for host-to-device copies of launch metadata: one
+// buffer per host thread, grown on demand; before it is rewritten, the event
+// recorded after its last copies is waited for.
+namespace {
+struct TcStaging {
+  char* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+thread_local TcStaging g_staging;
+}  // namespace
+
+static char* tc_staging_acquire(size_t bytes) {
+  TcStaging& S = g_staging;
+  if (S.ev == nullptr && hipEventCreateWithFlags(&S.ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+  if (S.pending) {
+    if (hipEventSynchronize(S.ev) != hipSuccess) return nullptr;
+    S.pending = false;
+  }
+  if (bytes > S.cap) {
+    if (S.buf) (void)hipHostFree(S.buf);
+    S.buf = nullptr;
+    S.cap = 0;
+    size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes * 2;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    S.buf = (char*)p;
+    S.cap = want;
+  }
+  return S.buf;
+}
+
+static int tc_staging_release(hipStream_t st) {
+  if (hipEventRecord(g_staging.ev, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  g_staging.pending = true;
+  return 0;
 }
 
 // ---- batched launcher.  Workspace layout (each part 256-byte aligned):
@@ -1090,12 +1230,18 @@ int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, cons
   }
   if ((int64_t)slots.size() > L.nslots || start != L.nunits) return TC_LAUNCH_EINVAL;  // (empty segments dropped)
   hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, L.zero_end / 4);
-  if (hipMemcpyAsync(base + L.mats, mats.data(), sizeof(TcBatchMat) * batch, hipMemcpyHostToDevice, st) != hipSuccess)
+  // descriptors and slots reach the device through pinned staging: the host
+  // vectors die when this call returns, while the copies may still wait
+  // behind earlier work on the stream
+  const size_t mb = sizeof(TcBatchMat) * batch, sb = sizeof(TcBatchSlot) * slots.size();
+  char* stg = tc_staging_acquire(mb + sb);
+  if (stg == nullptr) return TC_LAUNCH_EDEVICE;
+  memcpy(stg, mats.data(), mb);
+  if (sb) memcpy(stg + mb, slots.data(), sb);
+  if (hipMemcpyAsync(base + L.mats, stg, mb, hipMemcpyHostToDevice, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  if (sb && hipMemcpyAsync(base + L.slots, stg + mb, sb, hipMemcpyHostToDevice, st) != hipSuccess)
     return TC_LAUNCH_EDEVICE;
-  if (!slots.empty() &&
-      hipMemcpyAsync(base + L.slots, slots.data(), sizeof(TcBatchSlot) * slots.size(), hipMemcpyHostToDevice, st) !=
-          hipSuccess)
-    return TC_LAUNCH_EDEVICE;
+  if (tc_staging_release(st) != 0) return TC_LAUNCH_EDEVICE;
   if (slots.empty()) return tc_chk(hipGetLastError());
   hipLaunchKernelGGL(tc_batch_units, dim3((unsigned)slots.size()), dim3(TC_THREADS), 0, st,
                      (const TcBatchMat*)(base + L.mats), (const TcBatchSlot*)(base + L.slots),

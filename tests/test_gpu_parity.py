@@ -270,7 +270,7 @@ def test_batched_uneven_sizes(tc):
 
 
 # ----------------------------------------------- the paper's other variants
-ALL_SCHEDS = ("fork_join", "async_dag", "fork_join_naive", "task_sync")
+ALL_SCHEDS = ("fork_join", "async_dag", "fork_join_naive", "task_sync", "fork_join_lookahead")
 
 
 @pytest.mark.parametrize("n,T", [(1000, 128), (777, 256), (1536, 512), (640, 1024), (300, 96)])
@@ -291,7 +291,7 @@ def test_all_schedules_same_bits(tc, n, T):
     assert oracle.row_scaled_error(outs["fork_join"], Lref, A) <= E_ROW_TOL
 
 
-@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync"])
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead"])
 def test_variants_integer_factor_bitwise(tc, sched):
     A, L0 = inputs.integer_factor(640, seed=42)
     L, info = gpu_factor(tc, A, 256, sched)
@@ -299,7 +299,7 @@ def test_variants_integer_factor_bitwise(tc, sched):
     assert lower_equal(L, L0)
 
 
-@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync"])
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead"])
 def test_variants_report_not_spd(tc, sched):
     n, col = 512, 300
     A, L0 = inputs.integer_factor(n, seed=43)
