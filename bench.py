@@ -74,19 +74,29 @@ TRAFFIC = {
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
     ("fork_join", 32768, 1024): (14803277824,
                                  "d34dce9b4feb02a3cc2ba32a2de0f47f2c6e82098e285e45eb39faadda8277f5"),
+    # per tc_fj_update_range launch, averaged over the column-(J+1) and the
+    # rest launches (profiles/lookahead_n32768_T1024_kernels.md)
+    ("fork_join_lookahead", 32768, 1024): (7507860378,
+                                           "320ab4d4bb6861e459c62b977c32b72d4c1e673a91a0aa4933a5dc7155c41872"),
 }
-# the device code the counters describe: the tile bodies, the DAG decode and
-# the fork-join kernels (unit runners up to the naive variant) of kernels.hip
+# the device code the counters describe: the tile bodies, the DAG decode, the
+# fork-join kernels (unit runners up to the naive variant) of kernels.hip,
+# and for the lookahead schedule its split-update kernel
 KERNEL_SOURCES = [("paper_2606_11937_amd/csrc/tile_ops.h", None, None),
                   ("paper_2606_11937_amd/csrc/dag.h", None, None),
                   ("paper_2606_11937_amd/csrc/kernels.hip",
                    "// ------------------------------------------------------------ unit runners",
                    "// Naive fork-join")]
+KERNEL_SOURCES_EXTRA = {
+    "fork_join_lookahead": [("paper_2606_11937_amd/csrc/kernels.hip",
+                             "// ------------------------------------------------- fork-join with lookahead",
+                             "// ----------------------------------------------- low-precision trailing update")],
+}
 
 
-def sources_sha() -> str:
+def sources_sha(sched: str = "fork_join") -> str:
     h = hashlib.sha256()
-    for path, start, end in KERNEL_SOURCES:
+    for path, start, end in KERNEL_SOURCES + KERNEL_SOURCES_EXTRA.get(sched, []):
         with open(os.path.join(ROOT, path), "rb") as f:
             text = f.read()
         if start is not None:
@@ -103,7 +113,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--T", type=int, default=1024)
-    p.add_argument("--sched", default="fork_join",
+    p.add_argument("--sched", default="fork_join_lookahead",
                    choices=["async_dag", "fork_join", "fork_join_naive", "task_sync", "fork_join_lookahead"])
     p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -560,7 +570,7 @@ def main():
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     traffic = None
     rec = TRAFFIC.get((sched, n, T))
-    if rec is not None and rec[1] == sources_sha():
+    if rec is not None and rec[1] == sources_sha(sched):
         traffic = rec[0]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": W,
