@@ -553,6 +553,12 @@ int tc_server_destroy(TcServer* S) {
   }
   if (S->worker.joinable()) S->worker.join();
   int rc = S->error ? TC_LAUNCH_EDEVICE : 0;
+  // after an error ticks may still be on the device: let them finish before
+  // the pinned staging they copy into is freed
+  for (int k = 0; k < 2; ++k)
+    if (S->st[k] && hipStreamSynchronize(S->st[k]) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
+  for (Tick& t : S->inflight)
+    if (t.done) (void)hipEventDestroy(t.done);
   for (int k = 0; k < 2; ++k)
     if (S->st[k]) (void)hipStreamDestroy(S->st[k]);
   if (S->pinned) (void)hipHostFree(S->pinned);
