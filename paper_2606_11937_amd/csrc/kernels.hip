@@ -123,6 +123,17 @@ __device__ __forceinline__ void tc_run_trsm(double* A, int64_t lda, const TcGeom
   tc_trsm_block(A + r0 * lda + c0, A + c0 * lda + c0, lda, tc_rows(g, I, a), tc_rows(g, J, s), sm);
 }
 
+// Rows [64 h, 64 h + 64) of the same unit (h = 0, 1), for launches that give
+// each half a workgroup of its own.
+__device__ __forceinline__ void tc_run_trsm_half(double* A, int64_t lda, const TcGeom& g, int32_t J, int32_t s,
+                                                 int32_t I, int32_t a, int h, TcTrsmSmem& sm) {
+  const int mr = (int)tc_rows(g, I, a) - 64 * h;
+  if (mr <= 0) return;
+  const int64_t r0 = tc_row0(g, I, a) + 64 * h;
+  const int64_t c0 = tc_row0(g, J, s);
+  tc_trsm_rows(A + r0 * lda + c0, A + c0 * lda + c0, lda, mr < 64 ? mr : 64, tc_rows(g, J, s), sm);
+}
+
 // UPDATE(J, (I, a), (K, b)): K-depth the whole tile column J.
 __device__ __forceinline__ void tc_run_update(double* A, int64_t lda, const TcGeom& g, const TcUnit& u, TcUpdSmem& sm) {
   const int64_t ri = tc_row0(g, u.I, u.a);
@@ -145,19 +156,19 @@ __device__ __forceinline__ void tc_run_panel(double* A, int64_t lda, const TcGeo
 // ---------------------------------------------------------- fork-join kernels
 // The fork-join kernels declare only the shared memory their body uses (the
 // persistent kernel needs the union of all of them).
-__global__ __launch_bounds__(TC_THREADS) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_potrf(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                           TcWs ws) {
   __shared__ TcPotrfSmem sm;
   if (tc_err_set(ws.hdr) || ws.noop) return;
   tc_run_potrf(A, lda, g, J, s, ws.hdr, sm);
 }
 
-__global__ __launch_bounds__(TC_THREADS) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_trsm(double* A, int64_t lda, TcGeom g, int32_t J, int32_t s,
                                                          TcWs ws) {
   __shared__ TcTrsmSmem sm;
   if (tc_err_set(ws.hdr) || ws.noop) return;
-  const TcUnit u = tc_decode_trsm(g, J, s, blockIdx.x);
-  tc_run_trsm(A, lda, g, J, s, u.I, u.a, sm);
+  const TcUnit u = tc_decode_trsm(g, J, s, blockIdx.x >> 1);  // two workgroups per unit
+  tc_run_trsm_half(A, lda, g, J, s, u.I, u.a, (int)(blockIdx.x & 1), sm);
 }
 
 // The panel-update and trailing-update launches each carry the next POTRF:
@@ -403,11 +414,13 @@ __device__ __forceinline__ TcGeom tc_ctx_geom(const TcGeom& s) {
 __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_async(
     double* A, int64_t lda, TcGeom g, TcWs ws, int64_t wait_ticks) {
   __shared__ TcSmem sm;
-  __shared__ int64_t offs[TC_MAX_PHASES + 1];
+  // 32-bit copies of the phase offsets (the launcher checks that the ticket
+  // count fits); 4 KB instead of 8 keeps two workgroups per CU
+  __shared__ int32_t offs[TC_MAX_PHASES + 1];
   __shared__ TcCtx s_ctx;
   __shared__ TcUnit s_unit;
   __shared__ int32_t s_go;
-  for (int i = threadIdx.x; i <= g.M; i += TC_THREADS) offs[i] = ws.offs[i];
+  for (int i = threadIdx.x; i <= g.M; i += TC_THREADS) offs[i] = (int32_t)ws.offs[i];
   if (threadIdx.x == 0) {
     s_ctx.g = g;
     s_ctx.wait_ticks = wait_ticks;
@@ -886,7 +899,7 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
         const int64_t nt = tc_trsm_count(g, J, sc);
         if (nt > 0)
           tc_timed(TC_UNIT_TRSM, st, [&] {
-            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
           });
         const int64_t np = tc_panel_count(g, J, sc);
         if (np > 0)
@@ -928,7 +941,7 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
         const int64_t nt = tc_trsm_count(g, J, sc);
         if (nt > 0)
           tc_timed(TC_UNIT_TRSM, st, [&] {
-            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
           });
         const int64_t np = tc_panel_count(g, J, sc);
         if (np > 0)
@@ -970,7 +983,7 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
         const int64_t nt = tc_trsm_count(g, J, sc);
         if (nt > 0)
           tc_timed(TC_UNIT_TRSM, st, [&] {
-            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
           });
         const int64_t np = tc_panel_count(g, J, sc);
         if (np > 0)
@@ -987,6 +1000,11 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
     return tc_chk(hipGetLastError());
   }
   if (g.M > TC_MAX_PHASES) return TC_LAUNCH_EINVAL;
+  {
+    int64_t tickets = 0;
+    for (int32_t P = 0; P < g.M; ++P) tickets += tc_phase_size(g, P);
+    if (tickets > INT32_MAX) return TC_LAUNCH_EINVAL;
+  }
   hipLaunchKernelGGL(tc_phase_offsets, dim3(1), dim3(64), 0, st, g, ws.offs);
   tc_timed(TC_TIMING_PERSISTENT, st, [&] {
     hipLaunchKernelGGL(tc_async, dim3((unsigned)grid), dim3(TC_THREADS), 0, st, A, lda, g, ws, wait_ticks);
@@ -1038,7 +1056,7 @@ int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int pre
       const int64_t nt = tc_trsm_count(g, J, sc);
       if (nt > 0)
         tc_timed(TC_UNIT_TRSM, st, [&] {
-          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)nt), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
         });
       const int64_t np = tc_panel_count(g, J, sc);
       if (np > 0)

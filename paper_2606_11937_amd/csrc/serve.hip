@@ -359,7 +359,7 @@ void finish_tick(TcServer& S, Tick& t) {
   S.dev.release(t.ws_off, t.ws_bytes);
   S.dev.release(t.meta_dev, t.meta_bytes);
   S.pin.release(t.meta_pin, t.meta_bytes + hb * (int64_t)t.ids.size());
-  hipEventDestroy(t.done);
+  (void)hipEventDestroy(t.done);
 }
 
 void worker_main(TcServer* Sp) {

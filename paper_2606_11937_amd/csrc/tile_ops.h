@@ -66,15 +66,6 @@ __device__ __forceinline__ tc_q4 tc_ld4(const double* p) {
   q.hi = *(const tc_d2*)(p + 2);
   return q;
 }
-// Same, but elements at or beyond `lim` (relative to p) read as zero.
-__device__ __forceinline__ tc_q4 tc_ld4_tail(const double* p, int lim) {
-  tc_q4 q;
-  q.lo.x = lim > 0 ? p[0] : 0.0;
-  q.lo.y = lim > 1 ? p[1] : 0.0;
-  q.hi.x = lim > 2 ? p[2] : 0.0;
-  q.hi.y = lim > 3 ? p[3] : 0.0;
-  return q;
-}
 __device__ __forceinline__ double tc_el(const tc_q4& q, int m) {
   return m == 0 ? q.lo.x : m == 1 ? q.lo.y : m == 2 ? q.hi.x : q.hi.y;
 }
@@ -260,77 +251,8 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
 }
 
 // ---------------------------------------------------------------------------
-// Left-looking MFMA products of G 16-row groups against one 16-row group:
-//   acc[g][r][j] += sum over the 16-wide k chunks c = cs, cs + step, ... < kd/16
-//                   of X[16 g + r][k] Y[j][k],
-// X rows clamped to xr valid rows, Y rows to yr valid rows, kd % 16 == 0.
-// Each group has one accumulator, so a group's sum runs over its chunks in
-// ascending order; splitting the chunks of a product over several waves
-// (cs = wave, step = number of waves) gives partial sums that the caller adds
-// in a fixed order.  The Y fragment is shared by the G groups, whose
-// independent MFMA chains hide one another's latency, and the loads of the
-// next chunk are issued before the MFMAs of the current one.
+// Division and lane reads used by the substitutions.
 // ---------------------------------------------------------------------------
-template <int G>
-__device__ __forceinline__ void tc_ntg(const double* __restrict__ X, int xr, const double* __restrict__ Y, int yr,
-                                       int64_t lda, int kd, int cs, int step, tc_v4d acc[G]) {
-  const int lane = tc_tid() & 63;
-  const int r16 = lane & 15, s4 = (lane >> 4) * 4;
-  const double* py = Y + (int64_t)(r16 < yr ? r16 : yr - 1) * lda + s4;
-  const double* px[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int r = 16 * g + r16;
-    px[g] = X + (int64_t)(r < xr ? r : xr - 1) * lda + s4;
-  }
-  const int nch = kd >> 4;
-  if (cs >= nch) return;
-  tc_q4 y = tc_ld4(py + 16 * cs), x[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) x[g] = tc_ld4(px[g] + 16 * cs);
-  for (int c = cs; c < nch; c += step) {
-    const int cn = c + step < nch ? c + step : c;  // the last pass re-reads its own chunk
-    const tc_q4 yn = tc_ld4(py + 16 * cn);
-    tc_q4 xn[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) xn[g] = tc_ld4(px[g] + 16 * cn);
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int g = 0; g < G; ++g) acc[g] = tc_mfma(tc_el(x[g], m), tc_el(y, m), acc[g]);
-    y = yn;
-#pragma unroll
-    for (int g = 0; g < G; ++g) x[g] = xn[g];
-  }
-}
-
-// Scatter a 16 x 16 MFMA result into a row-major LDS buffer (ld 17).
-__device__ __forceinline__ void tc_acc_to_lds(double* buf, tc_v4d acc) {
-  const int lane = tc_tid() & 63;
-  const int orow = lane >> 4, ocol = lane & 15;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) buf[(4 * q + orow) * 17 + ocol] = acc[q];
-}
-
-// The G-group products of tc_ntg written to LDS as 16 G rows of ld 17.
-template <int G>
-__device__ __forceinline__ void tc_ntg_lds(const double* __restrict__ X, int xr, const double* __restrict__ Y,
-                                           int yr, int64_t lda, int kd, int cs, int step, double* buf) {
-  tc_v4d acc[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = tc_v4d{0.0, 0.0, 0.0, 0.0};
-  tc_ntg<G>(X, xr, Y, yr, lda, kd, cs, step, acc);
-#pragma unroll
-  for (int g = 0; g < G; ++g) tc_acc_to_lds(buf + g * 16 * 17, acc[g]);
-}
-
-// The factored 16 x 16 diagonal block is kept in LDS transposed, one column
-// of L per TC_LT-double row (16-byte aligned): Lt[j * TC_LT + i] = L[i][j]
-// for i >= j, zero above; Lt[j * TC_LT + 16] holds 1 / L[j][j].  Columns j
-// past the block's order nb hold a unit diagonal, so a substitution can run
-// all 16 steps unconditionally (their values stay zero).  The values one
-// step needs are contiguous and every lane reads the same address.
-#define TC_LT 18
 
 // x / d from the correctly rounded reciprocal r = 1 / d and one residual
 // correction (Markstein's method): q0 = x r, e = x - q0 d (exact with an
@@ -343,50 +265,6 @@ __device__ __forceinline__ double tc_div_rcp(double x, double d, double r) {
   return __builtin_fma(e, r, q0);
 }
 
-// Forward substitution of one row against the factored diagonal block:
-//   x_j = (v_j - sum_{q<j} x_q L[j][q]) / L[j][j].
-// v holds the row on entry, x on exit (entries past nb are zero on entry and
-// stay zero).  Column-oriented: step j finishes x_j and then subtracts
-// x_j L[i][j] from every later v_i, so each v_i receives the subtractions of
-// the row-oriented form in the same ascending order of q; the column of L
-// for step j + 1 is read while step j computes.
-__device__ __forceinline__ void tc_subst_row(double v[16], const double* Lt) {
-  double cur[17];
-#pragma unroll
-  for (int i = 0; i < 17; ++i) cur[i] = Lt[i];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    // a compiler-only barrier per step that also pins the previous result:
-    // the LDS loads of column j + 1 may overlap step j, but neither loads are
-    // hoisted nor arithmetic sunk across steps (each column held in registers
-    // costs 34 of them)
-    if (j > 0) asm volatile("" : "+v"(v[j - 1]) : : "memory");
-    double nxt[17];
-    if (j + 1 < 16) {
-#pragma unroll
-      for (int i = j + 1; i < 17; ++i) nxt[i] = Lt[(j + 1) * TC_LT + i];
-    }
-    v[j] = tc_div_rcp(v[j], cur[j], cur[16]);
-#pragma unroll
-    for (int i = j + 1; i < 16; ++i) v[i] = v[i] - v[j] * cur[i];
-    if (j + 1 < 16) {
-#pragma unroll
-      for (int i = j + 1; i < 17; ++i) cur[i] = nxt[i];
-    }
-  }
-}
-
-// Stage the lower nb x nb part of the 16 x 16 block at B (row-major, ld lda)
-// into Lt (transposed, zero-filled, unit diagonal past nb, reciprocals of
-// the diagonal); all TC_THREADS threads take part.
-__device__ __forceinline__ void tc_stage_lt(double* Lt, const double* B, int64_t lda, int nb) {
-  const int tid = tc_tid();
-  const int i = tid >> 4, j = tid & 15;
-  const double val = (i < nb && j <= i) ? B[(int64_t)i * lda + j] : (i == j ? 1.0 : 0.0);
-  Lt[j * TC_LT + i] = val;
-  if (i == j) Lt[j * TC_LT + 16] = 1.0 / val;
-}
-
 __device__ __forceinline__ double tc_readlane(double v, int l) {
   const int64_t b = __builtin_bit_cast(int64_t, v);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(uint64_t)b, l);
@@ -394,172 +272,458 @@ __device__ __forceinline__ double tc_readlane(double v, int l) {
   return __builtin_bit_cast(double, (int64_t)(((uint64_t)hi << 32) | lo));
 }
 
-// ---------------------------------------------------------------------------
-// TRSM work unit: X <- X L^{-T} for mr <= 128 rows of a tile (I, J), I > J,
-// with L = L_JJ (td x td, factored).  Left-looking over 16-column blocks:
-// for each block c0, v = X[:, c0:c0+16] - X[:, :c0] L[c0:c0+16, :c0]^T (MFMA),
-// then forward substitution against the 16 x 16 diagonal block of L.
-// Waves 0 and 1 own rows 0..63 and 64..127: they form the even-chunk part of
-// the products of their rows and substitute them, one row per lane; waves 2
-// and 3 form the odd-chunk part of the same rows.  A row's 16 inputs are
-// fetched before the products so that their latency hides behind them.
-// ---------------------------------------------------------------------------
-struct alignas(16) TcTrsmSmem {
-  double buf[4][64 * 17];  // [wave] products: even chunks (waves 0, 1), odd (2, 3)
-  double Lt[16 * TC_LT];
-};
+// Orders this wave's LDS writes before its later reads of them from other
+// lanes (LDS operations of one wave complete in order; the fences keep the
+// compiler from moving them).
+__device__ __forceinline__ void tc_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr, int td,
-                              TcTrsmSmem& sm) {
-  const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
-  const int half = w & 1;
-  const int row0 = half * 64;
-  const int nrows = mr - row0 < 64 ? mr - row0 : 64;  // rows of this half (may be <= 0)
-  const bool mine = w < 2 && lane < nrows;
-  double* xr0 = X + (int64_t)(row0 + (mine ? lane : 0)) * lda;
-  for (int c0 = 0; c0 < td; c0 += 16) {
-    const int nb = td - c0 < 16 ? td - c0 : 16;
-    double v[16];
+// ---------------------------------------------------------------------------
+// LDS images of 16 x 16 blocks.  A block row is 128 bytes: eight 16-byte
+// slots of two doubles.  Slot s of row r sits at position s ^ (r & 7) of the
+// row (the swizzle of the update kernel), so that one slot read by 16 rows,
+// or whole rows read by 8 lanes, spread over the banks.  `rs` is the row
+// stride in doubles of the array the block sits in.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tc_bo(int r, int c, int rs) { return r * rs + ((((c >> 1) ^ r) & 7) << 1) + (c & 1); }
+
+// Row r of a block (16 doubles), as eight 16-byte accesses.
+__device__ __forceinline__ void tc_row_get(const double* blk, int r, int rs, double v[16]) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr0[c0 + j] : 0.0;
-    tc_stage_lt(sm.Lt, L + (int64_t)c0 * lda + c0, lda, nb);
-    if (nrows > 0 && c0 > 0)
-      tc_ntg_lds<4>(X + (int64_t)row0 * lda, nrows, L + (int64_t)c0 * lda, nb, lda, c0, w >> 1, 2, sm.buf[w]);
-    __syncthreads();
-    if (mine) {
+  for (int s = 0; s < 8; ++s) {
+    const tc_d2a16 p = *(const tc_d2a16*)(blk + r * rs + ((s ^ (r & 7)) << 1));
+    v[2 * s] = p.x;
+    v[2 * s + 1] = p.y;
+  }
+}
+__device__ __forceinline__ void tc_row_put(double* blk, int r, int rs, const double v[16]) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < nb && c0 > 0) v[j] = v[j] - (sm.buf[half][lane * 17 + j] + sm.buf[half + 2][lane * 17 + j]);
-      tc_subst_row(v, sm.Lt);
+  for (int s = 0; s < 8; ++s) {
+    tc_d2a16 p;
+    p.x = v[2 * s];
+    p.y = v[2 * s + 1];
+    *(tc_d2a16*)(blk + r * rs + ((s ^ (r & 7)) << 1)) = p;
+  }
+}
+// MFMA operand fragment of lane (r, s): row r, columns 4 s .. 4 s + 3.
+__device__ __forceinline__ tc_q4 tc_frag_get(const double* blk, int r, int s, int rs) {
+  const tc_d2a16 a = *(const tc_d2a16*)(blk + r * rs + (((2 * s) ^ (r & 7)) << 1));
+  const tc_d2a16 b = *(const tc_d2a16*)(blk + r * rs + (((2 * s + 1) ^ (r & 7)) << 1));
+  tc_q4 q;
+  q.lo = tc_d2{a.x, a.y};
+  q.hi = tc_d2{b.x, b.y};
+  return q;
+}
+// A block in the MFMA result layout: lane l, item q is element (4 q + l / 16, l % 16).
+__device__ __forceinline__ tc_v4d tc_acc_get(const double* blk, int lane, int rs) {
+  tc_v4d a;
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < nb) xr0[c0 + j] = v[j];
+  for (int q = 0; q < 4; ++q) a[q] = blk[tc_bo(4 * q + (lane >> 4), lane & 15, rs)];
+  return a;
+}
+__device__ __forceinline__ void tc_acc_put(double* blk, int lane, int rs, tc_v4d a) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) blk[tc_bo(4 * q + (lane >> 4), lane & 15, rs)] = a[q];
+}
+// c - X Y^T for 16 x 16 blocks and K = 16: x, y are the fragments of lane
+// (l % 16, l / 16) of X and Y, c is in the result layout.  MFMA m sums the
+// k = 4 s + m of the four lane groups s, so the contraction order is fixed.
+__device__ __forceinline__ tc_v4d tc_nt16(const tc_q4& x, const tc_q4& y, tc_v4d c) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) c = tc_mfma(-tc_el(x, m), tc_el(y, m), c);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// A factored 16 x 16 diagonal block packed by columns for the substitutions:
+// column j holds 1 / L[j][j], then L[j+1 .. 15][j], padded to an even count
+// (from offset tc_ltp(j), which is even, so pairs are read 16 bytes at a
+// time; 144 doubles in all).  Columns past the block's order hold a unit
+// diagonal and zeros, so a substitution runs all 16 steps unconditionally
+// (entries past the order stay zero).
+// ---------------------------------------------------------------------------
+#define TC_LTP 144
+__host__ __device__ constexpr int tc_ltp(int j) {
+  int o = 0;
+  for (int q = 0; q < j; ++q) o += (17 - q) & ~1;
+  return o;
+}
+
+// 1 / x from the hardware estimate and two Newton-Raphson steps
+// (r <- r + r (1 - x r)); within one unit in the last place.
+__device__ __forceinline__ double tc_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+// Forward substitution of one row against a packed diagonal block:
+//   x_j = (v_j - sum_{q<j} x_q L[j][q]) (1 / L[j][j]).
+// v holds the row on entry, x on exit.  Column-oriented: step j finishes x_j
+// and then subtracts x_j L[i][j] from every later v_i, so each v_i receives
+// the subtractions of the row-oriented form in ascending order of q; the
+// column for step j + 1 is read while step j computes.  Scaling by the
+// reciprocal of the pivot is the reference BLAS triangular solve's choice.
+__device__ __forceinline__ void tc_subst_row(double v[16], const double* lt) {
+  double cur[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) cur[t] = lt[t];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    // a compiler-only barrier per step that also pins the previous result:
+    // the LDS loads of column j + 1 may overlap step j, but neither loads are
+    // hoisted nor arithmetic sunk across steps
+    if (j > 0) asm volatile("" : "+v"(v[j - 1]) : : "memory");
+    double nxt[16];
+    if (j + 1 < 16) {
+#pragma unroll
+      for (int t = 0; t < 15 - j; ++t) nxt[t] = lt[tc_ltp(j + 1) + t];
     }
-    __syncthreads();
+    v[j] = v[j] * cur[0];
+#pragma unroll
+    for (int i = j + 1; i < 16; ++i) v[i] = v[i] - v[j] * cur[i - j];
+    if (j + 1 < 16) {
+#pragma unroll
+      for (int t = 0; t < 15 - j; ++t) cur[t] = nxt[t];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// POTRF work unit: in-place lower Cholesky of the td x td diagonal tile D.
-// Left-looking over 16-column blocks c0:
-//   1. diagonal group v = D[c0:, c0:] - D[c0:, :c0] D[c0:, :c0]^T (16 x 16,
-//      MFMA, the k chunks dealt to the four waves and their partial sums
-//      added in wave order), then by wave 0 the unblocked factorization in
-//      registers (right-looking, sequential over the column, the POTRF
-//      definition on a 16 x 16 block): lane i holds row i, and the pivot
-//      and the column entries each step needs are read from their owner
-//      lanes;
-//   2. waves 0 and 1: the rows below, 64 per wave at a time (one per lane):
-//      MFMA products, then forward substitution against the new diagonal
-//      block (the in-tile TRSM).
-// A pivot d <= 0 or NaN stops the factorization: returns the 0-based
-// in-tile column, else -1.
+// TRSM work unit: X <- X L^{-T} for mr <= 128 rows of a tile (I, J), I > J,
+// with L = L_JJ (td x td, factored).  Right-looking over 16-column blocks b:
+// forward substitution of X[:, b] against L_bb, then X[:, j] -= X[:, b] L_jb^T
+// for every block j > b (MFMA, K = 16).
+// Rows are independent, so the work is split by rows and kept in LDS, 64
+// rows at a time: wave w owns 16 of them and sweeps them alone (lanes 0..15
+// substitute one row each, all 64 lanes form the products), with no
+// workgroup barrier inside the sweep.  The diagonal blocks of L are staged
+// packed in LDS; the L_jb fragments are read from global memory at the start
+// of each step, behind the substitution (every row block of the sub-column
+// reads them, so they stay in L2).
+// ---------------------------------------------------------------------------
+#define TC_XRS 128  // row stride of the X image, doubles
+struct alignas(16) TcTrsmSmem {
+  double x[64 * TC_XRS];  // 64 rows x 8 column blocks, swizzled within a block
+  double lt[8 * TC_LTP];  // packed diagonal blocks of L
+};
+
+// The packed diagonal blocks of L (td x td, td <= 128); all threads take
+// part, every load issued before the first store.
+__device__ __forceinline__ void tc_trsm_stage_lt(const double* __restrict__ L, int64_t lda, int td, TcTrsmSmem& sm) {
+  const int tot = ((td + 15) >> 4) * TC_LTP;
+  double val[5];
+  bool rcp[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {  // 5 * 256 >= 8 * 144
+    const int e = tc_tid() + k * TC_THREADS;
+    const int b = e / TC_LTP, q = e - b * TC_LTP;
+    int j = 0;
+#pragma unroll
+    for (int t = 1; t < 16; ++t) j += q >= tc_ltp(t);
+    const int i = j + q - tc_ltp(j);  // row of the entry (i == j: the pivot's reciprocal)
+    const int gr = 16 * b + i, gc = 16 * b + j;
+    rcp[k] = i == j;
+    val[k] = (e < tot && i < 16 && gr < td) ? L[(int64_t)gr * lda + gc] : (i == j ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int e = tc_tid() + k * TC_THREADS;
+    if (e < tot) sm.lt[e] = rcp[k] ? 1.0 / val[k] : val[k];
+  }
+}
+
+// Up to 64 rows (mr) of X against the staged diagonal blocks of L.  Starts
+// with a workgroup barrier after staging X (which also publishes the staged
+// diagonal blocks); each wave writes its own rows back at the end.
+__device__ __forceinline__ void tc_trsm_half(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr,
+                                             int td, TcTrsmSmem& sm) {
+  const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, s4 = lane >> 4;
+  const int nbk = (td + 15) >> 4;
+  {  // X rows [0, mr) x columns [0, td), zero elsewhere: 16 slots per thread
+    tc_d2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int row = 4 * k + w, c = 2 * lane;
+      const double* p = X + (int64_t)row * lda + c;
+      v[k].x = (row < mr && c < td) ? p[0] : 0.0;
+      v[k].y = (row < mr && c + 1 < td) ? p[1] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int row = 4 * k + w;
+      tc_d2a16 p;
+      p.x = v[k].x;
+      p.y = v[k].y;
+      *(tc_d2a16*)(sm.x + row * TC_XRS + (lane >> 3) * 16 + (((lane & 7) ^ (row & 7)) << 1)) = p;
+    }
+  }
+  // fragments of L_jb (lane (r16, s4): row 16 j + r16, columns 16 b + 4 s4 ..)
+  tc_q4 lf[7];
+  auto load_frags = [&](tc_q4 f[7], int b) {
+#pragma unroll
+    for (int jj = 0; jj < 7; ++jj) {
+      const int row = 16 * (b + 1 + jj) + r16;
+      if (b + 1 + jj < nbk) {
+        if (row < td) {
+          f[jj] = tc_ld4(L + (int64_t)row * lda + 16 * b + 4 * s4);
+        } else {
+          f[jj].lo = tc_d2{0.0, 0.0};
+          f[jj].hi = tc_d2{0.0, 0.0};
+        }
+      }
+    }
+  };
+  __syncthreads();
+
+  double* xw = sm.x + 16 * w * TC_XRS;  // this wave's 16 rows
+  for (int b = 0; b < nbk; ++b) {
+    // this step's fragments land while the substitution runs
+    if (b + 1 < nbk) load_frags(lf, b);
+    if (lane < 16) {
+      double v[16];
+      tc_row_get(xw + 16 * b, lane, TC_XRS, v);
+      tc_subst_row(v, sm.lt + b * TC_LTP);
+      tc_row_put(xw + 16 * b, lane, TC_XRS, v);
+    }
+    tc_wave_sync();
+    if (b + 1 < nbk) {
+      const tc_q4 xb = tc_frag_get(xw + 16 * b, r16, s4, TC_XRS);
+      // blocks j = b + 1 + jj in two groups (4 + 3), each group's MFMA
+      // chains interleaved
+#pragma unroll
+      for (int g0 = 0; g0 < 7; g0 += 4) {
+        tc_v4d acc[4];
+#pragma unroll
+        for (int jj = g0; jj < g0 + 4 && jj < 7; ++jj)
+          if (b + 1 + jj < nbk) acc[jj - g0] = tc_acc_get(xw + 16 * (b + 1 + jj), lane, TC_XRS);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int jj = g0; jj < g0 + 4 && jj < 7; ++jj)
+            if (b + 1 + jj < nbk) acc[jj - g0] = tc_mfma(-tc_el(xb, m), tc_el(lf[jj], m), acc[jj - g0]);
+#pragma unroll
+        for (int jj = g0; jj < g0 + 4 && jj < 7; ++jj)
+          if (b + 1 + jj < nbk) tc_acc_put(xw + 16 * (b + 1 + jj), lane, TC_XRS, acc[jj - g0]);
+      }
+      tc_wave_sync();
+    }
+  }
+  // this wave's rows back to X
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int row = 16 * w + k, c = 2 * lane;
+    if (row < mr) {
+      const tc_d2a16 p = *(const tc_d2a16*)(sm.x + row * TC_XRS + (lane >> 3) * 16 + (((lane & 7) ^ (row & 7)) << 1));
+      double* g = X + (int64_t)row * lda + c;
+      if (c < td) g[0] = p.x;
+      if (c + 1 < td) g[1] = p.y;
+    }
+  }
+}
+
+// One half (mr <= 64 rows) of a TRSM unit, as a workgroup of its own.
+__device__ __forceinline__ void tc_trsm_rows(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr,
+                                             int td, TcTrsmSmem& sm) {
+  mr = tc_uniform((int32_t)mr);
+  td = tc_uniform((int32_t)td);
+  tc_trsm_stage_lt(L, lda, td, sm);
+  tc_trsm_half(X, L, lda, mr, td, sm);
+}
+
+// A whole TRSM unit (mr <= 128 rows): its halves one after the other.  Each
+// row's arithmetic is the same as in tc_trsm_rows.
+__device__ __forceinline__ void tc_trsm_block(double* __restrict__ X, const double* __restrict__ L, int64_t lda, int mr,
+                                              int td, TcTrsmSmem& sm) {
+  mr = tc_uniform((int32_t)mr);
+  td = tc_uniform((int32_t)td);
+  tc_trsm_stage_lt(L, lda, td, sm);
+  for (int h = 0; h < mr; h += 64) {
+    if (h > 0) __syncthreads();  // the previous half's write-back has read the X image
+    tc_trsm_half(X + (int64_t)h * lda, L, lda, mr - h < 64 ? mr - h : 64, td, sm);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// POTRF work unit: in-place lower Cholesky of the td x td diagonal tile D
+// (td <= 128).  The lower triangle is copied once into LDS as packed 16 x 16
+// blocks (block (i, j), j <= i, at index i (i + 1) / 2 + j), factored there
+// right-looking over 16-column blocks b, and copied back once:
+//   1. diagonal block (b, b): unblocked factorization in registers by wave 0
+//      (lane i holds row i; right-looking over the block's columns, the
+//      POTRF definition on the block; the pivot and the column entries each
+//      step needs are read from their owner lanes);
+//   2. blocks (i, b), i > b: forward substitution against L_bb, one row per
+//      thread;
+//   3. blocks (i, j), b < j <= i: A_ij -= L_ib L_jb^T (MFMA, K = 16).
+// In step 3 wave 0 updates only block (b+1, b+1) and then factors it (step 1
+// of b+1) while waves 1..3 update the other blocks.
+// A pivot d <= 0 or NaN stops the factorization: returns the 0-based in-tile
+// column, else -1 (the tile is then left partly factored).
 // ---------------------------------------------------------------------------
 struct alignas(16) TcPotrfSmem {
-  double buf[2][64 * 17];    // products of the rows below (waves 0 and 1)
-  double dpart[4][16 * 17];  // partial products of the diagonal group
-  double Lt[16 * TC_LT];
+  double blk[36][256];  // packed lower triangle
+  double lt[TC_LTP];    // the current diagonal block, packed by columns
   int fail;
 };
 
-__device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
+__device__ __forceinline__ int tc_pk(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Lower triangle of D (rows and columns < td) into the packed blocks (zeros
+// elsewhere), or (OUT) back into D.  Pass k moves blocks 2 k and 2 k + 1
+// (waves 0-1 and 2-3, 16 rows x 8 slots each), so the block of a pass is
+// uniform per wave; all loads are issued before the first store.
+template <bool OUT>
+__device__ __forceinline__ void tc_pk_copy(double* __restrict__ D, int64_t lda, int td, TcPotrfSmem& sm) {
+  const int tid = tc_tid();
+  const int nbk = (td + 15) >> 4;
+  const int nblk = nbk * (nbk + 1) / 2;
+  const int hi = tc_uniform((int32_t)(tid >> 7));
+  const int r = (tid >> 3) & 15, s = tid & 7;
+  double* const lrow = &sm.blk[0][0] + r * 16 + ((s ^ (r & 7)) << 1);
+  tc_d2 v[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    const int p = 2 * k + hi;
+    if (p < nblk) {
+      int bi = 0;
+#pragma unroll
+      for (int q = 1; q < 8; ++q) bi += p >= q * (q + 1) / 2;
+      const int bj = p - bi * (bi + 1) / 2;
+      const int R = 16 * bi + r, C = 16 * bj + 2 * s;
+      double* g = D + (int64_t)R * lda + C;
+      if (OUT) {
+        if (R < td) {
+          const tc_d2a16 x = *(const tc_d2a16*)(lrow + p * 256);
+          if (C <= R) g[0] = x.x;
+          if (C + 1 <= R) g[1] = x.y;
+        }
+      } else {
+        v[k].x = (R < td && C <= R) ? g[0] : 0.0;
+        v[k].y = (R < td && C + 1 <= R) ? g[1] : 0.0;
+      }
+    }
+  }
+  if (!OUT) {
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+      const int p = 2 * k + hi;
+      if (p < nblk) {
+        tc_d2a16 x;
+        x.x = v[k].x;
+        x.y = v[k].y;
+        *(tc_d2a16*)(lrow + p * 256) = x;
+      }
+    }
+  }
+}
+
+// Step 1 on diagonal block b (nb valid columns, column offset c0 in the
+// tile) by the calling wave: factors the block in place, stages it packed in
+// lt, and records the first failing pivot in fail.  Lane i < 16 holds row i.
+// The 16 steps are free of branches, so the compiler can overlap a step's
+// trailing update with the next pivot: entries above the diagonal are
+// updated too (they never feed an entry on or below it and are never
+// stored), columns past nb take a unit pivot, and after a failing pivot the
+// values are unspecified.
+__device__ __forceinline__ void tc_pk_diag(TcPotrfSmem& sm, int b, int nb, int c0) {
+  const int lane = tc_tid() & 63;
+  double* blk = sm.blk[tc_pk(b, b)];
+  double a[16];
+  tc_row_get(blk, lane & 15, 16, a);
+  int bad = -1;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const bool live = j < nb;
+    const double d = tc_readlane(a[j], j);
+    if (live && bad < 0 && !(d > 0.0)) bad = j;
+    const double ljj = sqrt(live ? d : 1.0);
+    const double rj = tc_rcp(ljj);
+    a[j] = lane == j ? ljj : a[j] * rj;
+    // trailing update a_ik -= l_ij l_kj for k > j
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) a[k] = __builtin_fma(-a[j], tc_readlane(a[j], k), a[k]);
+    if (lane == 0) sm.lt[tc_ltp(j)] = rj;
+  }
+  if (lane == 0 && bad >= 0) sm.fail = c0 + bad;
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 15; ++k)
+      if (k < lane) sm.lt[tc_ltp(k) + (lane - k)] = lane < nb ? a[k] : 0.0;
+  }
+  if (lane < nb) tc_row_put(blk, lane, 16, a);
+}
+
+__device__ __forceinline__ int tc_potrf_tile(double* __restrict__ D, int64_t lda, int td_in, TcPotrfSmem& sm) {
+  const int td = tc_uniform((int32_t)td_in);
   const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
+  const int wu = tc_uniform((int32_t)w);
+  const int r16 = lane & 15, s4 = lane >> 4;
+  const int nbk = (td + 15) >> 4;
+  tc_pk_copy<false>(D, lda, td, sm);
   if (tid == 0) sm.fail = -1;
   __syncthreads();
-  for (int c0 = 0; c0 < td; c0 += 16) {
-    const int nb = td - c0 < 16 ? td - c0 : 16;
-    double* Dc = D + (int64_t)c0 * lda;  // row c0
-    const bool own = w == 0 && lane < nb;
-    const double* dr = Dc + (int64_t)(own ? lane : 0) * lda + c0;
-    double a[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) a[k] = (own && k <= lane) ? dr[k] : 0.0;
-    // diagonal group products, the chunks dealt to the four waves
-    if (c0 > 0) tc_ntg_lds<1>(Dc, nb, Dc, nb, lda, c0, w, 4, sm.dpart[w]);
+  if (wu == 0) tc_pk_diag(sm, 0, td < 16 ? td : 16, 0);
+  __syncthreads();
+  int fail = tc_uniform((int32_t)sm.fail);
+  for (int b = 0; fail < 0 && b + 1 < nbk; ++b) {
+    // 2. the blocks below diagonal block b, one row per thread
+    if (tid < td - 16 * (b + 1)) {
+      double* blk = sm.blk[tc_pk(b + 1 + (tid >> 4), b)];
+      double v[16];
+      tc_row_get(blk, tid & 15, 16, v);
+      tc_subst_row(v, sm.lt);
+      tc_row_put(blk, tid & 15, 16, v);
+    }
     __syncthreads();
-    if (w == 0) {
-      if (c0 > 0) {
+    // 3. the trailing blocks, numbered u = ii (ii + 1) / 2 + jj for block
+    //    (b + 1 + ii, b + 1 + jj), jj <= ii; u = 0 is the next diagonal block
+    if (wu == 0) {
+      double* cb = sm.blk[tc_pk(b + 1, b + 1)];
+      const tc_q4 x = tc_frag_get(sm.blk[tc_pk(b + 1, b)], r16, s4, 16);
+      tc_acc_put(cb, lane, 16, tc_nt16(x, x, tc_acc_get(cb, lane, 16)));
+      tc_wave_sync();
+      const int c1 = 16 * (b + 1);
+      tc_pk_diag(sm, b + 1, td - c1 < 16 ? td - c1 : 16, c1);
+    } else {
+      // wave w takes u = w, w + 3, ..., four blocks at a time with their
+      // MFMA chains interleaved
+      const int m = nbk - 1 - b, cnt = m * (m + 1) / 2;
+      for (int u0 = wu; u0 < cnt; u0 += 12) {
+        int off[4];
+        tc_q4 x[4], y[4];
+        tc_v4d acc[4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (own && k <= lane) {
-            const int q = lane * 17 + k;
-            a[k] = a[k] - (((sm.dpart[0][q] + sm.dpart[1][q]) + sm.dpart[2][q]) + sm.dpart[3][q]);
-          }
-      }
-      // unblocked factorization; every branch below is wave-uniform
-      int bad = -1;
+        for (int q = 0; q < 4; ++q) {
+          const int u = u0 + 3 * q;
+          int ii = 0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        double rj = 1.0;
-        if (j < nb && bad < 0) {
-          const double d = tc_readlane(a[j], j);
-          if (!(d > 0.0)) {
-            bad = j;
-          } else {
-            const double ljj = sqrt(d);
-            rj = 1.0 / ljj;
-            if (lane == j) a[j] = ljj;
-            else if (lane > j) a[j] = tc_div_rcp(a[j], ljj, rj);
-            // trailing update a_ik -= l_ij l_kj for j < k <= i
-#pragma unroll
-            for (int k = j + 1; k < 16; ++k) {
-              const double lkj = tc_readlane(a[j], k);
-              if (lane >= k) a[k] = a[k] - a[j] * lkj;
-            }
+          for (int t = 1; t < 7; ++t) ii += u >= t * (t + 1) / 2;
+          const int i = b + 1 + ii, j = b + 1 + u - ii * (ii + 1) / 2;
+          off[q] = tc_pk(i, j) * 256;
+          if (u < cnt) {
+            x[q] = tc_frag_get(sm.blk[tc_pk(i, b)], r16, s4, 16);
+            y[q] = tc_frag_get(sm.blk[tc_pk(j, b)], r16, s4, 16);
+            acc[q] = tc_acc_get(&sm.blk[0][0] + off[q], lane, 16);
           }
         }
-        if (lane == 0) sm.Lt[j * TC_LT + 16] = rj;
-      }
-      if (lane == 0 && bad >= 0) sm.fail = c0 + bad;
-      if (lane < 16) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          sm.Lt[k * TC_LT + lane] = (own && k <= lane) ? a[k] : (k == lane ? 1.0 : 0.0);
-      }
-      if (own && bad < 0) {
-        double* o = Dc + (int64_t)lane * lda + c0;
+        for (int mm = 0; mm < 4; ++mm)
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (k <= lane) o[k] = a[k];
+          for (int q = 0; q < 4; ++q)
+            if (u0 + 3 * q < cnt) acc[q] = tc_mfma(-tc_el(x[q], mm), tc_el(y[q], mm), acc[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (u0 + 3 * q < cnt) tc_acc_put(&sm.blk[0][0] + off[q], lane, 16, acc[q]);
       }
     }
     __syncthreads();
-    const int fail = tc_uniform((int32_t)sm.fail);
-    if (fail >= 0) return fail;
-    // rows below the diagonal block, 64 per wave of waves 0 and 1 at a time
-    const int below = td - c0 - nb;
-    for (int rb = 0; rb < below; rb += 128) {
-      const int rw0 = c0 + nb + rb + 64 * w;
-      const int myrows = w < 2 ? (td - rw0 < 64 ? td - rw0 : 64) : 0;
-      if (myrows > 0) {
-        const bool mine = lane < myrows;
-        double* xr = D + (int64_t)(rw0 + (mine ? lane : 0)) * lda + c0;
-        double v[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = (mine && j < nb) ? xr[j] : 0.0;
-        if (c0 > 0) {
-          tc_ntg_lds<4>(D + (int64_t)rw0 * lda, myrows, Dc, nb, lda, c0, 0, 1, sm.buf[w]);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        if (mine) {
-          if (c0 > 0) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (j < nb) v[j] = v[j] - sm.buf[w][lane * 17 + j];
-          }
-          tc_subst_row(v, sm.Lt);
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (j < nb) xr[j] = v[j];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    __syncthreads();
+    fail = tc_uniform((int32_t)sm.fail);
   }
-  return -1;
+  tc_pk_copy<true>(D, lda, td, sm);
+  return fail;
 }
