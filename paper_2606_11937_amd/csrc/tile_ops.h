@@ -401,9 +401,8 @@ __device__ __forceinline__ void tc_subst_row(double v[16], const double* lt) {
 // rows at a time: wave w owns 16 of them and sweeps them alone (lanes 0..15
 // substitute one row each, all 64 lanes form the products), with no
 // workgroup barrier inside the sweep.  The diagonal blocks of L are staged
-// packed in LDS; the L_jb fragments are read from global memory at the start
-// of each step, behind the substitution (every row block of the sub-column
-// reads them, so they stay in L2).
+// packed in LDS; the L_jb fragments are read from global memory one step
+// ahead (every row block of the sub-column reads them, so they stay in L2).
 // ---------------------------------------------------------------------------
 #define TC_XRS 128  // row stride of the X image, doubles
 struct alignas(16) TcTrsmSmem {
@@ -463,7 +462,7 @@ __device__ __forceinline__ void tc_trsm_half(double* __restrict__ X, const doubl
     }
   }
   // fragments of L_jb (lane (r16, s4): row 16 j + r16, columns 16 b + 4 s4 ..)
-  tc_q4 lf[7];
+  tc_q4 fa[7], fb[7];
   auto load_frags = [&](tc_q4 f[7], int b) {
 #pragma unroll
     for (int jj = 0; jj < 7; ++jj) {
@@ -478,12 +477,14 @@ __device__ __forceinline__ void tc_trsm_half(double* __restrict__ X, const doubl
       }
     }
   };
+  if (nbk > 1) load_frags(fa, 0);
   __syncthreads();
 
   double* xw = sm.x + 16 * w * TC_XRS;  // this wave's 16 rows
-  for (int b = 0; b < nbk; ++b) {
-    // this step's fragments land while the substitution runs
-    if (b + 1 < nbk) load_frags(lf, b);
+  // step b with its fragments in cur; the next step's are loaded into nxt
+  // between the substitution and the products, so they land behind this
+  // step's products and the next substitution
+  auto step = [&](int b, tc_q4 (&cur)[7], tc_q4 (&nxt)[7]) {
     if (lane < 16) {
       double v[16];
       tc_row_get(xw + 16 * b, lane, TC_XRS, v);
@@ -492,6 +493,7 @@ __device__ __forceinline__ void tc_trsm_half(double* __restrict__ X, const doubl
     }
     tc_wave_sync();
     if (b + 1 < nbk) {
+      if (b + 2 < nbk) load_frags(nxt, b + 1);
       const tc_q4 xb = tc_frag_get(xw + 16 * b, r16, s4, TC_XRS);
       // blocks j = b + 1 + jj in two groups (4 + 3), each group's MFMA
       // chains interleaved
@@ -505,13 +507,17 @@ __device__ __forceinline__ void tc_trsm_half(double* __restrict__ X, const doubl
         for (int m = 0; m < 4; ++m)
 #pragma unroll
           for (int jj = g0; jj < g0 + 4 && jj < 7; ++jj)
-            if (b + 1 + jj < nbk) acc[jj - g0] = tc_mfma(-tc_el(xb, m), tc_el(lf[jj], m), acc[jj - g0]);
+            if (b + 1 + jj < nbk) acc[jj - g0] = tc_mfma(-tc_el(xb, m), tc_el(cur[jj], m), acc[jj - g0]);
 #pragma unroll
         for (int jj = g0; jj < g0 + 4 && jj < 7; ++jj)
           if (b + 1 + jj < nbk) tc_acc_put(xw + 16 * (b + 1 + jj), lane, TC_XRS, acc[jj - g0]);
       }
       tc_wave_sync();
     }
+  };
+  for (int b = 0; b < nbk; b += 2) {
+    step(b, fa, fb);
+    if (b + 1 < nbk) step(b + 1, fb, fa);
   }
   // this wave's rows back to X
 #pragma unroll
