@@ -119,10 +119,16 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
   const int r16 = lane & 15, s2 = (lane >> 4) * 2;
 
   // --- staging: waves 0,1 fetch A rows, waves 2,3 B rows; load q of wave w
-  //     fills LDS slots [(w*8+q)*64, +64) = rows (w&1)*64 + q*8 .. +8
-  const int nrow = w < 2 ? mr : mc;
+  //     fills LDS slots [(w*8+q)*64, +64) = rows (w&1)*64 + q*8 .. +8.
+  //     The operand, its row count and the LDS window depend on the wave
+  //     only: taken as scalars, the buffer resource and the LDS base sit in
+  //     scalar registers (a resource in vector registers would turn every
+  //     load into a loop over the distinct values the lanes hold).
+  const int ws = tc_uniform((int32_t)w);
+  const int nrow = ws < 2 ? tc_uniform((int32_t)mr) : tc_uniform((int32_t)mc);
+  const double* src = (const double*)tc_uniform((int64_t)(ws < 2 ? PA : PB));
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(w < 2 ? PA : PB), (short)0, (int)((int64_t)nrow * lda * 8), 0x00020000);
+      (void*)src, (short)0, (int)((int64_t)nrow * tc_uniform(lda) * 8), 0x00020000);
   const int rl0 = (w & 1) * 64 + (lane >> 3);
   const unsigned vof0 = (unsigned)(rl0 * lda * 8 + 16 * ((lane & 7) ^ tc_swz(rl0)));
   const unsigned rowstep = (unsigned)(8 * lda * 8);
@@ -132,7 +138,7 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rsrc,
           (tc_lds_void*)((char __attribute__((address_space(3)))*)(tc_lds_void*)&sm.tile[st][0][0] +
-                         (w * 8 + q) * 1024),
+                         (ws * 8 + q) * 1024),
           16, vof0 + q * rowstep, (unsigned)(k0 * 8), 0, 0);
   };
   // the ragged last chunk (kd % 16 != 0): ordinary guarded loads, zero past

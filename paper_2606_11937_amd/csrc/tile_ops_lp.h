@@ -120,10 +120,13 @@ __device__ __forceinline__ void tc_update_block_lp(double* __restrict__ C, const
   const int r16 = lane & 15, s2 = (lane >> 4) * 2;
   char* const lds = (char*)&sm.tile[0][0][0];  // [stage][A|B][row][128 bytes]
 
-  const int nrow = w < 2 ? mr : mc;
-  const int64_t rowb = ldp * (int64_t)sizeof(E);  // operand row stride in bytes
+  // operand, row count and LDS window as scalars (see tc_update_block)
+  const int ws = tc_uniform((int32_t)w);
+  const int nrow = ws < 2 ? tc_uniform((int32_t)mr) : tc_uniform((int32_t)mc);
+  const int64_t rowb = tc_uniform(ldp) * (int64_t)sizeof(E);  // operand row stride in bytes
+  const E* src = (const E*)tc_uniform((int64_t)(ws < 2 ? PA : PB));
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(w < 2 ? PA : PB), (short)0, (int)((int64_t)nrow * rowb), 0x00020000);
+      (void*)src, (short)0, (int)((int64_t)nrow * rowb), 0x00020000);
   const int rl0 = (w & 1) * 64 + (lane >> 3);
   const unsigned vof0 = (unsigned)(rl0 * rowb + 16 * ((lane & 7) ^ tc_swz(rl0)));
   const unsigned rowstep = (unsigned)(8 * rowb);
@@ -131,7 +134,7 @@ __device__ __forceinline__ void tc_update_block_lp(double* __restrict__ C, const
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rsrc, (tc_lds_void*)((char __attribute__((address_space(3)))*)(tc_lds_void*)lds + st * 32768 + (w * 8 + q) * 1024),
+          rsrc, (tc_lds_void*)((char __attribute__((address_space(3)))*)(tc_lds_void*)lds + st * 32768 + (ws * 8 + q) * 1024),
           16, vof0 + q * rowstep, (unsigned)(k0 * (int)sizeof(E)), 0, 0);
   };
   // the ragged last chunk: guarded element loads, zero past kd or past the
