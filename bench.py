@@ -72,12 +72,12 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense matrix
 TRAFFIC = {
     # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
-    ("fork_join", 32768, 1024): (14803277824,
-                                 "d34dce9b4feb02a3cc2ba32a2de0f47f2c6e82098e285e45eb39faadda8277f5"),
+    ("fork_join", 32768, 1024): (14851627268,
+                                 "521e1079a7c0f7918a7cc91a4f0ffc031682210e72830943e75f05016b8254f0"),
     # per tc_fj_update_range launch, averaged over the column-(J+1) and the
     # rest launches (profiles/lookahead_n32768_T1024_kernels.md)
-    ("fork_join_lookahead", 32768, 1024): (7507860378,
-                                           "320ab4d4bb6861e459c62b977c32b72d4c1e673a91a0aa4933a5dc7155c41872"),
+    ("fork_join_lookahead", 32768, 1024): (7530060912,
+                                           "76af68270004ca96f533ccb1cb7385166e54335692f3b5d6bc29778679aab06e"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,
@@ -449,11 +449,16 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
         lag = max(lag, time.perf_counter() - target)
         ids.append(srv.submit(p, B, ell, nug, tol))
     lat, met, worst = {1e-6: [], 1e-12: []}, 0, 0.0
+    statuses, missed = {}, []
     for rid, r in zip(ids, reqs):
         st, _, eta, latency, info = srv.wait(rid, timeout=600.0, want_x=False)
         lat[r[4]].append(latency)
         met += st == tc.CHOL_OK
         worst = max(worst, eta)
+        statuses[str(st)] = statuses.get(str(st), 0) + 1
+        if st != tc.CHOL_OK and len(missed) < 8:
+            missed.append({"n": r[1].shape[0], "nrhs": r[1].shape[1], "tol": r[4], "status": st, "info": info,
+                           "eta": eta, "latency_ms": round(latency * 1e3, 1)})
     t_end = time.perf_counter()
     ticks = srv.ticks()
     srv.close()
@@ -467,7 +472,8 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
             "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99),
             "p50_ms_tol1e-6": pct(lat[1e-6], 50), "p99_ms_tol1e-6": pct(lat[1e-6], 99),
             "p50_ms_tol1e-12": pct(lat[1e-12], 50), "p99_ms_tol1e-12": pct(lat[1e-12], 99),
-            "worst_eta": worst, "max_submit_lag_ms": round(lag * 1e3, 3)}
+            "worst_eta": worst, "max_submit_lag_ms": round(lag * 1e3, 3), "statuses": statuses,
+            "missed": missed}
 
 
 def main():

@@ -313,7 +313,9 @@ int chol_server_submit(chol_server* server, const double* points, int64_t n, dou
  * n x nrhs, or NULL) receives the solution, *eta the worst column's backward
  * error, *latency_s the time from submission to the result being in host
  * memory.  Returns CHOL_OK (eta <= tol), CHOL_NOT_CONVERGED (done, eta >
- * tol), CHOL_NOT_SPD (*info as for chol_factor), CHOL_EWORKSPACE (the
+ * tol), CHOL_NOT_SPD (*info as for chol_factor; *info < 0 instead when the
+ * request's factorization was ended by the dependency-wait limit of
+ * chol_set_wait_limit, which then leaves X unspecified), CHOL_EWORKSPACE (the
  * request can never fit in the arena), CHOL_ETIMEOUT (not done yet), or a
  * negative error code. */
 int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta,
