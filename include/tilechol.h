@@ -89,7 +89,15 @@ enum {
    * update runs.  Events keep every block's updates in step order; the
    * factor is bit-identical to the other schedules.  The call stays ordered
    * on the caller's stream. */
-  CHOL_SCHED_FORK_JOIN_LOOKAHEAD = 4
+  CHOL_SCHED_FORK_JOIN_LOOKAHEAD = 4,
+  /* The tile DAG as a HIP graph (the runtime-managed analogue of the
+   * paper's task dependencies): the fork-join launches are graph nodes, the
+   * trailing update of step J is one node per tile column, and the edges
+   * are the dependencies between them, so the runtime overlaps later
+   * columns' updates with the following panels as far as they allow.  The
+   * instantiated graph is cached per (A, lda, n, T, work) and replayed on
+   * `stream`; bit-identical to the other schedules. */
+  CHOL_SCHED_GRAPH_DAG = 5
 };
 
 /* Flag ORed into `sched` to run the schedule with empty tile-operation

@@ -23,7 +23,7 @@ static_assert(CHOL_UNIT_POTRF == TC_UNIT_POTRF && CHOL_UNIT_TRSM == TC_UNIT_TRSM
                   CHOL_UNIT_UPDATE == TC_UNIT_UPDATE && CHOL_UNIT_PANEL == TC_UNIT_PANEL,
               "unit kinds of the ABI and the kernels differ");
 static_assert(CHOL_SCHED_FORK_JOIN == 0 && CHOL_SCHED_ASYNC_DAG == 1 && CHOL_SCHED_FORK_JOIN_NAIVE == 2 &&
-                  CHOL_SCHED_TASK_SYNC == 3 && CHOL_SCHED_FORK_JOIN_LOOKAHEAD == 4 &&
+                  CHOL_SCHED_TASK_SYNC == 3 && CHOL_SCHED_FORK_JOIN_LOOKAHEAD == 4 && CHOL_SCHED_GRAPH_DAG == 5 &&
                   CHOL_SCHED_NOOP == TC_SCHED_NOOP,
               "schedule codes of the ABI and the launcher differ");
 static_assert(TC_TIMING_KINDS == 5 && TC_TIMING_PERSISTENT == 4, "timing kinds of the ABI and the launcher differ");
@@ -59,7 +59,7 @@ int status_from(int32_t err, int64_t dinfo, int64_t* info) {
 
 bool sched_valid(int sched) {
   const int base = sched & 0xff, flags = sched & ~0xff;
-  return base >= CHOL_SCHED_FORK_JOIN && base <= CHOL_SCHED_FORK_JOIN_LOOKAHEAD && (flags & ~CHOL_SCHED_NOOP) == 0;
+  return base >= CHOL_SCHED_FORK_JOIN && base <= CHOL_SCHED_GRAPH_DAG && (flags & ~CHOL_SCHED_NOOP) == 0;
 }
 
 int check_factor_args(double* A, int64_t n, int64_t lda, int64_t T, int sched) {

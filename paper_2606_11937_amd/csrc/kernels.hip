@@ -18,6 +18,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dag.h"
@@ -878,6 +882,125 @@ static hipEvent_t tc_side_event(int k) {
   return S ? S->ev[k] : nullptr;
 }
 
+// ------------------------------------------------- tile DAG as a HIP graph
+// The fork-join launches become the nodes of one HIP graph whose edges are
+// the dependencies between them, with the trailing update of step J split
+// into one node per tile column K > J (units colsum(J, K-J-1) ..
+// + colsize(K) of the step's column-major order):
+//   - TRSM(J, s) and PANEL(J, s) form step J's chain, in sub-column order;
+//   - step J+1's chain starts after the column-(J+1) update of step J, which
+//     carries POTRF(J+1, 0);
+//   - the column-K update of step J waits for step J's chain and for the
+//     column-K update of step J-1.
+// The HIP runtime starts a node when its predecessors have finished, so the
+// updates of later columns overlap the following chains as far as the
+// dependencies allow: a lookahead of any depth, managed by the runtime
+// instead of a ticket order or stream events.  Every block still receives
+// its updates in step order from the same bodies, so the factor is
+// bit-identical to fork-join.  Instantiated graphs are cached per (matrix,
+// workspace, geometry).
+namespace {
+struct TcGraphKey {
+  const void* A;
+  int64_t lda, n, T;
+  const void* work;
+  int noop, dev;
+  bool operator<(const TcGraphKey& o) const {
+    return std::tie(A, lda, n, T, work, noop, dev) < std::tie(o.A, o.lda, o.n, o.T, o.work, o.noop, o.dev);
+  }
+};
+std::mutex g_graph_mu;
+std::map<TcGraphKey, hipGraphExec_t> g_graphs;
+std::deque<TcGraphKey> g_graph_order;  // insertion order, for eviction
+constexpr size_t TC_GRAPH_CACHE = 16;
+}  // namespace
+
+static int tc_graph_node(hipGraph_t gr, hipGraphNode_t* out, const hipGraphNode_t* deps, size_t ndeps,
+                         const void* fn, unsigned grid, void** args) {
+  hipKernelNodeParams p{};
+  p.func = (void*)fn;
+  p.gridDim = dim3(grid);
+  p.blockDim = dim3(TC_THREADS);
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;  // the node copies the argument values
+  p.extra = nullptr;
+  return hipGraphAddKernelNode(out, gr, deps, ndeps, &p) == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}
+
+static int tc_build_factor_graph(double* A, int64_t lda, const TcGeom& g, const TcWs& ws, hipGraphExec_t* exec) {
+  hipGraph_t gr = nullptr;
+  if (hipGraphCreate(&gr, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  TcGeom gv = g;
+  TcWs wv = ws;
+  int rc = 0;
+  hipGraphNode_t prev = nullptr;
+  {
+    int32_t J = 0, sc = 0;
+    void* args[] = {&A, &lda, &gv, &J, &sc, &wv};
+    rc = tc_graph_node(gr, &prev, nullptr, 0, (const void*)tc_fj_potrf, 1, args);
+  }
+  std::vector<hipGraphNode_t> colprev(g.M, nullptr);  // latest update node of each tile column
+  for (int32_t J = 0; J < g.M && rc == 0; ++J) {
+    if (J > 0) prev = colprev[J];
+    for (int32_t sc = 0; sc < tc_sb(g, J) && rc == 0; ++sc) {
+      int32_t Jv = J, sv = sc;
+      void* args[] = {&A, &lda, &gv, &Jv, &sv, &wv};
+      const int64_t nt = tc_trsm_count(g, J, sc);
+      if (nt > 0) {
+        hipGraphNode_t nd = nullptr;
+        rc = tc_graph_node(gr, &nd, &prev, 1, (const void*)tc_fj_trsm, (unsigned)(2 * nt), args);
+        prev = nd;
+      }
+      const int64_t np = tc_panel_count(g, J, sc);
+      if (np > 0 && rc == 0) {
+        hipGraphNode_t nd = nullptr;
+        rc = tc_graph_node(gr, &nd, &prev, 1, (const void*)tc_fj_panel, (unsigned)np, args);
+        prev = nd;
+      }
+    }
+    const hipGraphNode_t chain = prev;
+    for (int32_t K = J + 1; K < g.M && rc == 0; ++K) {
+      int32_t Jv = J;
+      int64_t first = tc_colsum(g, J, K - J - 1);
+      void* args[] = {&A, &lda, &gv, &Jv, &wv, &first};
+      const hipGraphNode_t deps[2] = {chain, colprev[K]};
+      hipGraphNode_t nd = nullptr;
+      rc = tc_graph_node(gr, &nd, deps, colprev[K] ? 2 : 1, (const void*)tc_fj_update_range,
+                         (unsigned)tc_colsize(g, K), args);
+      colprev[K] = nd;
+    }
+  }
+  if (rc == 0 && hipGraphInstantiate(exec, gr, nullptr, nullptr, 0) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
+  (void)hipGraphDestroy(gr);
+  return rc;
+}
+
+static int tc_launch_factor_graph(double* A, int64_t n, int64_t lda, int64_t T, const TcGeom& g, const TcWs& ws,
+                                  void* work, hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  const TcGraphKey key{A, lda, n, T, work, ws.noop, dev};
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    hipGraphExec_t ex = nullptr;
+    if (int e = tc_build_factor_graph(A, lda, g, ws, &ex)) return e;
+    if (g_graphs.size() >= TC_GRAPH_CACHE) {
+      // the oldest graph may still be running on some stream: wait for the
+      // device before releasing it (rare: only when the cache is full)
+      if (hipDeviceSynchronize() != hipSuccess) return TC_LAUNCH_EDEVICE;
+      const TcGraphKey old = g_graph_order.front();
+      g_graph_order.pop_front();
+      (void)hipGraphExecDestroy(g_graphs[old]);
+      g_graphs.erase(old);
+    }
+    it = g_graphs.emplace(key, ex).first;
+    g_graph_order.push_back(key);
+  }
+  if (hipGraphLaunch(it->second, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  return tc_chk(hipGetLastError());
+}
+
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks, int64_t chunk) {
   const int sched = sched_flags & 0xff;
@@ -972,6 +1095,7 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
     if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
     return tc_chk(hipGetLastError());
   }
+  if (sched == 5) return tc_launch_factor_graph(A, n, lda, T, g, ws, work, st);
   if (sched == 0) {
     // POTRF(0, 0) is the only POTRF with a launch of its own; every other one
     // rides at the head of the launch that finishes its input (see above)

@@ -27,6 +27,7 @@ CHOL_SCHED_ASYNC_DAG = 1
 CHOL_SCHED_FORK_JOIN_NAIVE = 2
 CHOL_SCHED_TASK_SYNC = 3
 CHOL_SCHED_FORK_JOIN_LOOKAHEAD = 4
+CHOL_SCHED_GRAPH_DAG = 5
 CHOL_SCHED_NOOP = 0x100
 CHOL_BLOCK = 128
 CHOL_NOT_CONVERGED = 2
@@ -44,7 +45,7 @@ CHOL_SERVE_MAX_RHS = 8
 CHOL_ASYNC_MAX_TILES = 1024
 SCHEDULES = {"fork_join": CHOL_SCHED_FORK_JOIN, "async_dag": CHOL_SCHED_ASYNC_DAG,
              "fork_join_naive": CHOL_SCHED_FORK_JOIN_NAIVE, "task_sync": CHOL_SCHED_TASK_SYNC,
-             "fork_join_lookahead": CHOL_SCHED_FORK_JOIN_LOOKAHEAD}
+             "fork_join_lookahead": CHOL_SCHED_FORK_JOIN_LOOKAHEAD, "graph_dag": CHOL_SCHED_GRAPH_DAG}
 
 # (name, restype, argtypes) for every symbol of include/tilechol.h
 _i64, _int, _dbl, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p

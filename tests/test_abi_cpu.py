@@ -64,7 +64,7 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails val
     ((FAKE, -1, 4, 2, 0), 2, -1),     # n < 0
     ((FAKE, 8, 7, 2, 0), 3, -1),      # lda < n
     ((FAKE, 8, 8, 0, 0), 4, -1),      # T < 1
-    ((FAKE, 8, 8, 4, 5), 5, -1),      # unknown schedule
+    ((FAKE, 8, 8, 4, 6), 5, -1),      # unknown schedule
     ((FAKE, 8, 8, 4, 0x200), 5, -1),  # unknown schedule flag
     ((FAKE, 8, 8, 4, -1), 5, -1),     # negative schedule
     ((None, 8, 8, 4, 0), 1, -1),      # NULL matrix

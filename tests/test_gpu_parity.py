@@ -270,7 +270,7 @@ def test_batched_uneven_sizes(tc):
 
 
 # ----------------------------------------------- the paper's other variants
-ALL_SCHEDS = ("fork_join", "async_dag", "fork_join_naive", "task_sync", "fork_join_lookahead")
+ALL_SCHEDS = ("fork_join", "async_dag", "fork_join_naive", "task_sync", "fork_join_lookahead", "graph_dag")
 
 
 @pytest.mark.parametrize("n,T", [(1000, 128), (777, 256), (1536, 512), (640, 1024), (300, 96)])
@@ -291,7 +291,7 @@ def test_all_schedules_same_bits(tc, n, T):
     assert oracle.row_scaled_error(outs["fork_join"], Lref, A) <= E_ROW_TOL
 
 
-@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead"])
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead", "graph_dag"])
 def test_variants_integer_factor_bitwise(tc, sched):
     A, L0 = inputs.integer_factor(640, seed=42)
     L, info = gpu_factor(tc, A, 256, sched)
@@ -299,13 +299,35 @@ def test_variants_integer_factor_bitwise(tc, sched):
     assert lower_equal(L, L0)
 
 
-@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead"])
+@pytest.mark.parametrize("sched", ["fork_join_naive", "task_sync", "fork_join_lookahead", "graph_dag"])
 def test_variants_report_not_spd(tc, sched):
     n, col = 512, 300
     A, L0 = inputs.integer_factor(n, seed=43)
     A[col, col] = float(np.sum(L0[col, :col] ** 2)) - 1.0
     _, info = gpu_factor(tc, A, 128, sched)
     assert info == col + 1
+
+
+def test_graph_dag_replays(tc):
+    """One instantiated graph, replayed: three factorizations of the same
+    buffer with the same workspace, each followed by eager fork-join work on
+    another buffer, give the fork-join bits every time."""
+    import torch
+    n, T = 1000, 256
+    say(f"[graph replay] n={n} T={T}")
+    A = inputs.se_kernel(n, seed=46)
+    ref, info = gpu_factor(tc, A, T, "fork_join")
+    assert info == 0
+    buf = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    work = tc.factor_workspace(n, T, "graph_dag", buf.device)
+    for rep in range(3):
+        buf.copy_(torch.from_numpy(A))
+        assert tc.chol_factor(buf, T, "graph_dag", work=work) == 0
+        other = torch.from_numpy(A).cuda()
+        assert tc.chol_factor(other, T, "fork_join") == 0
+        torch.cuda.synchronize()
+        assert lower_equal(buf.cpu().numpy(), ref), rep
+        assert lower_equal(other.cpu().numpy(), ref), rep
 
 
 def test_task_sync_wait_limit_never_hangs(tc):
