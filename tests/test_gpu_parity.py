@@ -100,6 +100,33 @@ def test_parity_shapes(tc, n, T):
     assert oracle.scaled_residual(A, Lf) <= RHO_TOL
 
 
+@pytest.mark.parametrize("n,T", [(257, 128), (319, 128), (320, 128), (321, 128), (383, 128), (449, 256),
+                                 (700, 100), (393, 72), (1025, 1024)])
+def test_trsm_halves_and_ragged_blocks(tc, n, T):
+    """Last row blocks of 1, 63, 64, 65 and 127 rows (the TRSM works in 64-row
+    halves, the fork-join launch gives each half a workgroup, the persistent
+    kernels run both halves in one) and tiles whose 16-column blocks are
+    ragged: every schedule gives the same bits, in tolerance of the oracle,
+    and so does the batched launch with the same tile side."""
+    say(f"[ragged] n={n} T={T}")
+    A = inputs.gg_plus_identity(n, seed=n + 7 * T)
+    Lref, _ = oracle.potrf(A)
+    outs = {}
+    for sched in ("fork_join", "fork_join_lookahead", "async_dag", "graph_dag"):
+        L, info = gpu_factor(tc, A, T, sched)
+        assert info == 0, sched
+        outs[sched] = L
+    for sched, L in outs.items():
+        assert lower_equal(L, outs["fork_join"]), sched
+    assert oracle.row_scaled_error(outs["fork_join"], Lref, A) <= E_ROW_TOL
+    assert oracle.scaled_residual(A, outs["fork_join"]) <= RHO_TOL
+    import torch
+    buf = torch.from_numpy(A).cuda()
+    assert tc.chol_factor_batched([buf], Ts=[T]) == [0]
+    torch.cuda.synchronize()
+    assert lower_equal(buf.cpu().numpy(), outs["fork_join"])
+
+
 @pytest.mark.parametrize("n,T", [(384, 128), (600, 256), (1000, 128)])
 def test_parity_se_kernel(tc, n, T):
     """Squared-exponential kernel inputs (lengthscale 0.1, nugget 1e-2)."""
