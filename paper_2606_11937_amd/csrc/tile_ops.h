@@ -647,22 +647,27 @@ __device__ __forceinline__ void tc_pk_diag(TcPotrfSmem& sm, int b, int nb, int c
   double* blk = sm.blk[tc_pk(b, b)];
   double a[16];
   tc_row_get(blk, lane & 15, 16, a);
+  // the 16 steps form one branch-free block (selects only; lane j keeps its
+  // pivot's reciprocal and stores it after the loop), so the scheduler can
+  // run a step's remaining updates under the next pivot's square root
   int bad = -1;
+  double myr = 1.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const bool live = j < nb;
     const double d = tc_readlane(a[j], j);
-    if (live && bad < 0 && !(d > 0.0)) bad = j;
+    bad = (bad < 0 && live && !(d > 0.0)) ? j : bad;
     const double ljj = sqrt(live ? d : 1.0);
     const double rj = tc_rcp(ljj);
     a[j] = lane == j ? ljj : a[j] * rj;
+    myr = lane == j ? rj : myr;
     // trailing update a_ik -= l_ij l_kj for k > j
 #pragma unroll
     for (int k = j + 1; k < 16; ++k) a[k] = __builtin_fma(-a[j], tc_readlane(a[j], k), a[k]);
-    if (lane == 0) sm.lt[tc_ltp(j)] = rj;
   }
   if (lane == 0 && bad >= 0) sm.fail = c0 + bad;
   if (lane < 16) {
+    sm.lt[tc_ltp(lane)] = myr;
 #pragma unroll
     for (int k = 0; k < 15; ++k)
       if (k < lane) sm.lt[tc_ltp(k) + (lane - k)] = lane < nb ? a[k] : 0.0;
