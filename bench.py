@@ -72,12 +72,12 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense matrix
 TRAFFIC = {
     # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
-    ("fork_join", 32768, 1024): (14851627268,
-                                 "521e1079a7c0f7918a7cc91a4f0ffc031682210e72830943e75f05016b8254f0"),
+    ("fork_join", 32768, 1024): (14840737564,
+                                 "edf0e223697f76ccb4261f59af1a4a02bcd3280bb5e66fa497472d8eb731c980"),
     # per tc_fj_update_range launch, averaged over the column-(J+1) and the
     # rest launches (profiles/lookahead_n32768_T1024_kernels.md)
-    ("fork_join_lookahead", 32768, 1024): (7530060912,
-                                           "76af68270004ca96f533ccb1cb7385166e54335692f3b5d6bc29778679aab06e"),
+    ("fork_join_lookahead", 32768, 1024): (7522126878,
+                                           "389687e9dd6de4844a2324ad284059060a3da151e00d2a9cc9148ed7e1abe3be"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,
