@@ -1,5 +1,5 @@
-// kernels.hip -- gfx950 kernels and host launchers of the two factorization
-// schedules and of the triangular solves.
+// kernels.hip -- gfx950 kernels and host launchers of the factorization
+// schedules, the mixed-precision factor and the batched launch.
 //
 //   fork-join  (Methods, "fork-join collapsed"): per step J one launch for
 //              POTRF(J), one for the TRSM panel of column J, one for the
@@ -10,8 +10,11 @@
 //              (a topological order, see dag.h), wait until the per-block
 //              counters say the unit's inputs are final, run it, and publish
 //              its completion.  No global barrier.
+//   the paper's naive fork-join and synchronous tasking variants, fork-join
+//   with a one-step lookahead on two streams, and the fork-join launches as
+//   a HIP graph with explicit dependency edges.
 //
-// Both schedules call the same tile bodies from tile_ops.h with the same
+// Every schedule calls the same tile bodies from tile_ops.h with the same
 // work-unit decomposition, so their factors are bit-identical.
 #include <hip/hip_runtime.h>
 #include <stdint.h>

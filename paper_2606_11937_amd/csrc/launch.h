@@ -11,10 +11,11 @@
 inline int64_t tc_default_tile(int64_t n) { return n <= 8192 ? 128 : 1024; }
 #define TC_LAUNCH_EINVAL (-1)
 
-// Workspace bytes chol_factor needs (both schedules use one layout).
+// Workspace bytes chol_factor needs (every schedule uses one layout).
 int64_t tc_ws_bytes(int64_t n, int64_t T);
 // Enqueue one factorization.  sched_flags: schedule 0 fork-join, 1 async
-// DAG, 2 naive fork-join, 3 synchronous tasking, optionally ORed with
+// DAG, 2 naive fork-join, 3 synchronous tasking, 4 fork-join with lookahead,
+// 5 HIP-graph DAG, optionally ORed with
 // TC_SCHED_NOOP (empty unit bodies, for measuring the schedule's own cost).
 // grid: persistent workgroups (1 and 3); wait_ticks: wait limit in
 // wall-clock ticks (1 and 3); chunk: bulk units after each panel-chain link
