@@ -129,8 +129,11 @@ int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched);
  *   info       host pointer or NULL.  If non-NULL the call synchronises the
  *              stream and stores 0 on success or k > 0 when the leading
  *              minor of order k is not positive definite (a pivot <= 0 or
- *              NaN at global column k - 1, LAPACK potrf convention); columns
- *              before k - 1 then hold L and the rest is unspecified.  If
+ *              NaN at global column k - 1, LAPACK potrf convention); the
+ *              lower triangle is then unspecified (the factorization stops
+ *              inside the 128-column block that holds column k - 1).  With
+ *              CHOL_ETIMEOUT it stores 1 + the ticket of the work unit whose
+ *              dependency wait ran out (asynchronous schedule), or 0.  If
  *              NULL the call is fully asynchronous and its outcome is only
  *              visible through chol_factor_info().
  * Returns CHOL_OK, CHOL_NOT_SPD (only when info != NULL), CHOL_ETIMEOUT
@@ -323,7 +326,8 @@ int chol_server_submit(chol_server* server, const double* points, int64_t n, dou
  * memory.  Returns CHOL_OK (eta <= tol), CHOL_NOT_CONVERGED (done, eta >
  * tol), CHOL_NOT_SPD (*info as for chol_factor; *info < 0 instead when the
  * request's factorization was ended by the dependency-wait limit of
- * chol_set_wait_limit, which then leaves X unspecified), CHOL_EWORKSPACE (the
+ * chol_set_wait_limit, which then leaves X unspecified: -(1 + the ticket of
+ * the unit that waited) within its tick's launch), CHOL_EWORKSPACE (the
  * request can never fit in the arena), CHOL_ETIMEOUT (not done yet), or a
  * negative error code. */
 int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta,

@@ -51,7 +51,9 @@ int64_t wait_ticks() {
 }
 
 int status_from(int32_t err, int64_t dinfo, int64_t* info) {
-  if (info) *info = err == 1 ? dinfo : 0;
+  // err 1: dinfo is the failing column + 1; err 2: 1 + the ticket of the
+  // unit whose dependency wait ran out (persistent schedules), else 0
+  if (info) *info = (err == 1 || err == 2) ? dinfo : 0;
   if (err == 1) return CHOL_NOT_SPD;
   if (err == 2) return CHOL_ETIMEOUT;
   return CHOL_OK;

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const uint64_t t0 = wall_clock64();
         while (!tc_unit_ready(cg, ws, u)) {
           if (tc_err_set(ws.hdr)) { go = 0; break; }
-          if (wall_clock64() - t0 > (uint64_t)s_ctx.wait_ticks) { tc_report_fail(ws.hdr, 2, 0); go = 0; break; }
+          if (wall_clock64() - t0 > (uint64_t)s_ctx.wait_ticks) { tc_report_fail(ws.hdr, 2, t + 1); go = 0; break; }
           __builtin_amdgcn_s_sleep(1);
         }
         if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                                        s_mat.nunits
                                  : tc_unit_ready(s_mat.g, s_mat.ws, u);
           if (ready) break;
-          if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(s_mat.ws.hdr, 2, 0); run = 0; break; }
+          if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(s_mat.ws.hdr, 2, t + 1); run = 0; break; }
           __builtin_amdgcn_s_sleep(1);
         }
         if (run) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -346,7 +346,8 @@ void finish_tick(TcServer& S, Tick& t) {
     int32_t err = 0;
     int64_t info = 0;
     tc_ws_header_read(t.hdr_pin + hb * q, &err, &info);
-    R.info = err == 1 ? info : -(int64_t)err;  // < 0: ended by the dependency-wait limit
+    // < 0: ended by the dependency-wait limit, -(1 + ticket of the unit that waited)
+    R.info = err == 1 ? info : -(info > 0 ? info : (int64_t)err);
     R.state = err ? 3 : 2;
     R.t_done = t_done;
     S.dev.release(R.dev_off, R.dev_bytes);
