@@ -3,24 +3,27 @@
 // L Y = B, then backward substitution L^T X = Y, in place in B.
 //
 // Both sweeps are single launches over 64-row blocks.  Each workgroup takes
-// a block from an atomic ticket (ascending for the forward sweep, descending
-// for the backward one), so a workgroup only ever waits for blocks whose
-// tickets are smaller, all held by running workgroups.  A "done" counter in
-// the workspace records how many blocks, in sweep order, are finished; a
-// workgroup folds in every finished block it sees (no waiting), re-reads the
-// counter, and waits only for the last few blocks before its own.  Blocks
-// finish and publish in sweep order.  The sweep streams L once from HBM
-// while the chain of 64 x 64 triangular solves runs.
+// a group of consecutive blocks from an atomic ticket (ascending for the
+// forward sweep, descending for the backward one), so a workgroup only ever
+// waits for blocks whose tickets are smaller, all held by running
+// workgroups.  A "done" counter in the workspace records how many blocks,
+// in sweep order, are finished; a workgroup folds in every finished block
+// it sees (no waiting), re-reads the counter, and waits only for the last
+// few blocks before its own.  It then solves its own blocks in order,
+// folding each into the later ones of its group, and publishes the group.
+// Blocks finish and publish in sweep order.  The sweep streams L once from
+// HBM while the chain of 64 x 64 triangular solves runs.
 //
 // Rounding order, for bitwise reproducibility: for row i of block b and
 // right-hand side c, the forward sweep accumulates per lane over its four
 // columns of every earlier block, in block order, and sums the 16 lanes of
 // a row by a butterfly; the backward sweep accumulates each of four thread
 // quarters p over its 16 rows of every later block in block order and
-// combines the quarters in order p = 0..3.  The sum is subtracted from B and
-// the in-block substitution is sequential in the column index, dividing
-// through the reciprocal of the diagonal with one correction step (exact
-// whenever the quotient is representable).
+// combines the quarters in order p = 0..3.  The sum is subtracted from B.
+// The in-block substitution scales each row of the diagonal block and the
+// right-hand side by the reciprocal of the row's pivot, then runs
+// sequentially in the column index with one FMA per entry.  None of this
+// depends on the grouping of blocks into workgroups.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,7 +34,11 @@
 // (sv_forward / sv_backward); more are taken in groups of 16 by the kernels
 // whose folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel
 // pair per group.
-#define SV_RC_SMALL 8
+#define SV_RC_SMALL 2
+// 64-row blocks per workgroup in the forward and backward sweeps for one or
+// two right-hand sides
+#define SV_GROUP_F 2
+#define SV_GROUP_B 2
 #define SV_THREADS 256
 
 struct SvWs {
@@ -77,12 +84,13 @@ __device__ __forceinline__ int32_t sv_wait_wg(const int32_t* cnt, int32_t need, 
   return v;
 }
 
-// Publish block completion in sweep order: wait until `done` == pos, then
-// set it to pos + 1.  All threads have fenced their stores before.
-__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, SvWs* ws, int64_t wait_ticks) {
+// Publish the completion of cnt blocks in sweep order: wait until `done` ==
+// pos, then set it to pos + cnt.  All threads have fenced their stores
+// before.
+__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, int32_t cnt, SvWs* ws, int64_t wait_ticks) {
   if (threadIdx.x == 0) {
     if (sv_wait_above(done, pos - 1, ws, wait_ticks) >= 0)
-      __hip_atomic_store(done, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(done, pos + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -94,237 +102,370 @@ __device__ __forceinline__ double sv_readlane(double v, int l) {
   return __builtin_bit_cast(double, (int64_t)(((uint64_t)hi << 32) | lo));
 }
 
-// x / d from the correctly rounded reciprocal r = 1 / d with one residual
-// correction (Markstein's method): exact whenever x / d is representable,
-// otherwise within one unit in the last place of the rounded quotient.
-__device__ __forceinline__ double sv_div_rcp(double x, double d, double r) {
-  const double q0 = x * r;
-  const double e = __builtin_fma(-q0, d, x);
-  return __builtin_fma(e, r, q0);
-}
-
-// Stage the lower part of the diagonal block and the reciprocals of its
-// diagonal (every thread of the workgroup takes part).
+// Stage the diagonal block strictly lower (zero on and above the diagonal)
+// and the reciprocals of its diagonal (every thread of the workgroup takes
+// part).  Rows past nr take a unit pivot.  rdiag is written after the
+// internal barrier: readers need one more barrier.
 __device__ __forceinline__ void sv_stage_diag(const double* __restrict__ L, int64_t lda, int64_t r0, int nr,
                                               double (*Lbb)[SV_NB + 1], double* rdiag) {
   for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) {
     const int i = e / SV_NB, k = e % SV_NB;
-    Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : (i == k ? 1.0 : 0.0);
+    Lbb[i][k] = (i < nr && k < i) ? L[(r0 + i) * lda + r0 + k] : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < SV_NB) rdiag[threadIdx.x] = 1.0 / Lbb[threadIdx.x][threadIdx.x];
+  if (threadIdx.x < SV_NB) {
+    const int i = threadIdx.x;
+    rdiag[i] = i < nr ? 1.0 / L[(r0 + i) * lda + r0 + i] : 1.0;
+  }
+}
+
+// ------------------------------------------------- in-block substitution
+// NT interleaved substitution chains of one wave against the staged
+// diagonal block (strictly lower, with the reciprocals of its diagonal):
+// lane k holds row k of each right-hand side.  Each lane scales its kept
+// row of the block and its values by the reciprocal of its own pivot once,
+// so the chain solves a system with a unit diagonal: step i broadcasts lane
+// i's value, which is x_i, and every lane k subtracts (L[k][i] / L[k][k]) x_i
+// with one FMA.  The kept row is zero on and past the diagonal, so a lane's
+// value stays x_k once its own step has passed.
+// Forward runs with L_bb (lane k keeps row k), backward with L_bb^T (lane k
+// keeps column k).  This is the reference BLAS triangular solve's scaling by
+// reciprocals, done ahead of the chain.
+template <int NT>
+__device__ __forceinline__ void sv_chains_fwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
+                                              int lane) {
+  const double rl = rdiag[lane];
+  double lr[SV_NB];
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) lr[i] = Lbb[lane][i] * rl;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) v[t] = v[t] * rl;
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) v[t] = __builtin_fma(-lr[i], sv_readlane(v[t], i), v[t]);
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void sv_chains_bwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
+                                              int lane) {
+  const double rl = rdiag[lane];
+  double lc[SV_NB];
+#pragma unroll
+  for (int i = 0; i < SV_NB; ++i) lc[i] = Lbb[i][lane] * rl;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) v[t] = v[t] * rl;
+#pragma unroll
+  for (int i = SV_NB - 1; i >= 0; --i) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) v[t] = __builtin_fma(-lc[i], sv_readlane(v[t], i), v[t]);
+  }
 }
 
 // ---------------------------------------------------------------- forward
-// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), row block b = ticket.
+// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j).  A workgroup takes a group of
+// G consecutive blocks b0 .. b0 + G - 1 from the ticket (b0 = G ticket):
+// it folds every earlier group's blocks into all G as they finish, then
+// solves its own blocks in order, folding each into the later ones of the
+// group, and publishes the group at once.  The chain then crosses
+// workgroups once per G blocks.
 // Fold layout: wave w, lane 16 rr + q covers rows 16 s + 4 w + rr (s < 4)
-// and columns 16 m + q (m < 4) of every earlier block, so each load
-// instruction reads four whole 128-byte row segments.  A lane accumulates
-// its 4 x 4 products of every block in block order; the 16 lanes of a row
-// are then summed by a butterfly.  The L values of block j + 1 are loaded
-// while block j is folded, so the load latency of the block that finishes
-// last stays off the chain.  The in-block substitution is one row per lane;
-// each step broadcasts the new unknown with a lane read and divides through
-// the precomputed reciprocal.
-template <int RC>
+// of each block of the group and columns 16 m + q (m < 4) of every earlier
+// block, so each load instruction reads four whole 128-byte row segments.
+// A lane accumulates its 4 x 4 products of every block in block order; the
+// 16 lanes of a row are then summed by a butterfly.  The L values of the
+// next (block, group member) pair are loaded while the current one is
+// folded.  The in-block substitution is one row per lane (sv_chains_fwd).
+template <int RC, int G>
 __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                          SvWs* ws, int64_t wait_ticks) {
   __shared__ double part[SV_NB][RC + 1];
-  __shared__ double Lbb[SV_NB][SV_NB + 1];
-  __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_b, s_ready;
+  __shared__ double ys[SV_NB][RC + 1];
+  __shared__ double Lbb[G][SV_NB][SV_NB + 1];
+  __shared__ double rdiag[G][SV_NB];
+  __shared__ int32_t s_g, s_ready;
   const int tid = threadIdx.x;
-  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
+  if (tid == 0) s_g = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int32_t b = sv_uniform(s_b);
-  const int64_t r0 = (int64_t)b * SV_NB;
-  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  const int32_t b0 = sv_uniform(s_g) * G;
+  const int ns = nb - b0 < G ? (int)(nb - b0) : G;  // blocks in this group
+  const int64_t r0 = (int64_t)b0 * SV_NB;
   const int w = tid >> 6, lane = tid & 63, rr = lane >> 4, q = lane & 15;
-  const double* lrow[4];
-  bool live[4];
+  // row (within its block) of fold slot s2, and the L pointers of block 0 of
+  // the group; member s adds 64 s rows
+  int frow[4];
 #pragma unroll
-  for (int s2 = 0; s2 < 4; ++s2) {
-    const int row = 16 * s2 + 4 * w + rr;
-    live[s2] = row < nr;
-    lrow[s2] = L + (r0 + (live[s2] ? row : 0)) * lda + q;
-  }
+  for (int s2 = 0; s2 < 4; ++s2) frow[s2] = 16 * s2 + 4 * w + rr;
+  // the diagonal blocks of the group, staged before any wait
+#pragma unroll
+  for (int s = 0; s < G; ++s)
+    if (s < ns) {
+      const int64_t rs = r0 + SV_NB * s;
+      sv_stage_diag(L, lda, rs, n - rs < SV_NB ? (int)(n - rs) : SV_NB, Lbb[s], rdiag[s]);
+    }
+  auto lload = [&](int s, int32_t j, double (*dst)[4]) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int64_t R = r0 + SV_NB * s + frow[s2];
+      const bool lv = R < n;
+      const double* p = L + (lv ? R : 0) * lda + q + (int64_t)j * SV_NB;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) dst[s2][m] = lv ? p[16 * m] : 0.0;
+    }
+  };
   for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
     const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
-    double acc[4][RC];
+    double acc[G][4][RC];
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2)
+    for (int s = 0; s < G; ++s)
 #pragma unroll
-      for (int c = 0; c < RC; ++c) acc[s2][c] = 0.0;
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[s][s2][c] = 0.0;
     double lc[4][4];
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) lc[s2][m] = (b > 0 && live[s2]) ? lrow[s2][16 * m] : 0.0;
+    if (b0 > 0) lload(0, 0, lc);
     int32_t j = 0;
-    while (j < b) {
+    while (j < b0) {
       const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
       if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
-      const int32_t jend = ready < b ? ready : b;
+      const int32_t jend = ready < b0 ? ready : b0;
       for (; j < jend; ++j) {
-        const int32_t jn = j + 1 < b ? j + 1 : j;  // the last block re-reads itself
-        double ln[4][4];
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) ln[s2][m] = live[s2] ? lrow[s2][(int64_t)jn * SV_NB + 16 * m] : 0.0;
+        double y[4][RC];
         const double* yj = B + ((int64_t)j * SV_NB + q) * ldb + c0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int c = 0; c < RC; ++c) y[m][c] = c < nc ? yj[(int64_t)16 * m * ldb + c] : 0.0;
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+          // the next pair: member s + 1 of block j, else member 0 of block
+          // j + 1 (the last pair re-reads itself)
+          const int32_t jn = s + 1 < G ? j : (j + 1 < b0 ? j + 1 : j);
+          double ln[4][4];
+          lload(s + 1 < G ? s + 1 : (j + 1 < b0 ? 0 : s), jn, ln);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+              if (c < nc) {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) acc[s][s2][c] += lc[s2][m] * y[m][c];
+              }
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) lc[s2][m] = ln[s2][m];
+        }
+      }
+    }
+    // the group's own blocks, in order
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      if (s < ns) {
+        const int64_t rs = r0 + SV_NB * s;
+        const int nr = n - rs < SV_NB ? (int)(n - rs) : SV_NB;
+        // L of the next member against this block, for the fold after the
+        // substitution (loaded now, used after it)
+        double lg[4][4];
+        if (s + 1 < ns) lload(s + 1, b0 + s, lg);
+        // butterfly over the 16 lanes of each row, then one lane writes the sum
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
           for (int c = 0; c < RC; ++c) {
             if (c < nc) {
-              const double y = yj[(int64_t)16 * m * ldb + c];
+              double v = acc[s][s2][c];
 #pragma unroll
-              for (int s2 = 0; s2 < 4; ++s2) acc[s2][c] += lc[s2][m] * y;
+              for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 16);
+              if (q == 0) part[frow[s2]][c] = v;
             }
           }
+        __syncthreads();
+        for (int c = w; c < nc; c += 4) {
+          double v = 0.0;
+          if (lane < nr) v = B[(rs + lane) * ldb + c0 + c] - (b0 + s > 0 ? part[lane][c] : 0.0);
+          sv_chains_fwd<1>(&v, Lbb[s], rdiag[s], lane);
+          if (lane < nr) B[(rs + lane) * ldb + c0 + c] = v;
+          ys[lane][c] = v;  // zero past nr
         }
+        __syncthreads();
+        // fold this block into the later members: the next one from lg, the
+        // rest with loads of their own
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
+        for (int s3 = s + 1; s3 < G; ++s3) {
+          if (s3 < ns) {
+            double lf[4][4];
+            if (s3 == s + 1) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) lc[s2][m] = ln[s2][m];
+              for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) lf[s2][m] = lg[s2][m];
+            } else {
+              lload(s3, b0 + s, lf);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+              for (int c = 0; c < RC; ++c)
+                if (c < nc) {
+                  const double yv = ys[q + 16 * m][c];
+#pragma unroll
+                  for (int s2 = 0; s2 < 4; ++s2) acc[s3][s2][c] += lf[s2][m] * yv;
+                }
+          }
+        }
+        __syncthreads();  // part and ys are rewritten by the next member
       }
     }
-    // butterfly over the 16 lanes of each row, then one lane writes the sum
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-      for (int c = 0; c < RC; ++c) {
-        if (c < nc) {
-          double v = acc[s2][c];
-#pragma unroll
-          for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 16);
-          if (q == 0) part[16 * s2 + 4 * w + rr][c] = v;
-        }
-      }
-    __syncthreads();
-    // one wave per right-hand side: lane k holds row k of the block
-    for (int c = w; c < nc; c += 4) {
-      double v = 0.0;
-      if (lane < nr) v = B[(r0 + lane) * ldb + c0 + c] - (b > 0 ? part[lane][c] : 0.0);
-      // lane k keeps row k of the diagonal block, its pivot and reciprocal in
-      // registers; each step is three lane reads and four dependent FP64
-      // operations (rows past nr have a unit diagonal and zero entries)
-      double lr[SV_NB];
-#pragma unroll
-      for (int i = 0; i < SV_NB; ++i) lr[i] = Lbb[lane][i];
-      const double dl = Lbb[lane][lane], rl = rdiag[lane];
-#pragma unroll
-      for (int i = 0; i < SV_NB; ++i) {
-        const double xi = sv_div_rcp(sv_readlane(v, i), sv_readlane(dl, i), sv_readlane(rl, i));
-        if (lane == i) v = xi;
-        else if (lane > i) v = v - lr[i] * xi;
-      }
-      if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
-    }
-    __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b, ws, wait_ticks);
+  sv_publish(&ws->done_f, b0, ns, ws, wait_ticks);
 }
 
 // --------------------------------------------------------------- backward
-// x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j), block b = nb - 1 - ticket.
-template <int RC>
+// x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j).  Groups of G blocks in
+// descending order: ticket t takes blocks bh = nb - 1 - G t down to
+// bh - G + 1 (member s is block bh - s), folds every later group's blocks
+// into all of them as they finish, then solves its own blocks from the top,
+// folding each into the members below it, and publishes the group at once.
+template <int RC, int G>
 __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                           double* __restrict__ B, int64_t nrhs, int64_t ldb,
                                                           SvWs* ws, int64_t wait_ticks) {
   __shared__ double part[4][SV_NB][RC + 1];
-  __shared__ double Lbb[SV_NB][SV_NB + 1];
-  __shared__ double rdiag[SV_NB];
+  __shared__ double xs[SV_NB][RC + 1];
+  __shared__ double Lbb[G][SV_NB][SV_NB + 1];
+  __shared__ double rdiag[G][SV_NB];
   __shared__ int32_t s_t, s_ready;
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int32_t t = sv_uniform(s_t);
-  const int32_t b = nb - 1 - t;
-  const int64_t r0 = (int64_t)b * SV_NB;
-  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
-  // thread (r, p): output row r of the block (column r of each L_jb), rows
-  // 16p .. 16p+15 of every later block; consecutive r are consecutive
+  const int32_t bh = nb - 1 - G * t;  // member 0; member s is block bh - s
+  const int ns = bh + 1 < G ? (int)(bh + 1) : G;
+  // thread (r, p): output row r of a member block (column r of each L_jb),
+  // rows 16p .. 16p+15 of every later block; consecutive r are consecutive
   // addresses, so each wave reads 64 contiguous doubles per k
   const int r = tid & 63, p = tid >> 6;
-  const bool live = r < nr;
-  // rows of block j this thread reads: 16p .. 16p+15, clipped to the block
-  auto load_col = [&](int32_t j, double* dst) {
+  // the diagonal blocks of the group, staged before any wait
+#pragma unroll
+  for (int s = 0; s < G; ++s)
+    if (s < ns) {
+      const int64_t rs = (int64_t)(bh - s) * SV_NB;
+      sv_stage_diag(L, lda, rs, n - rs < SV_NB ? (int)(n - rs) : SV_NB, Lbb[s], rdiag[s]);
+    }
+  auto load_col = [&](int s, int32_t j, double* dst) {
     const int64_t j0 = (int64_t)j * SV_NB;
     const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+    const int64_t col = (int64_t)(bh - s) * SV_NB + r;
+    const bool lv = s < ns && col < n;
+    const double* base = L + (lv ? col : 0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int kk = 16 * p + k;
-      dst[k] = kk < njr ? L[(j0 + kk) * lda + r0 + r] : 0.0;
+      dst[k] = (lv && kk < njr) ? base[(j0 + kk) * lda] : 0.0;
     }
   };
   for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
     const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
-    double acc[RC];
+    double acc[G][RC];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+    for (int s = 0; s < G; ++s)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[s][c] = 0.0;
     double lc[16];
-    if (b < nb - 1 && live) load_col(nb - 1, lc);
+    if (bh < nb - 1) load_col(0, nb - 1, lc);
     int32_t j = nb - 1;
-    while (j > b) {
+    while (j > bh) {
       const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
       if (ready < 0) break;
-      const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
+      const int32_t jlow = nb - ready > bh + 1 ? nb - ready : bh + 1;
       for (; j >= jlow; --j) {
-        if (!live) continue;
-        double ln[16];
-        load_col(j - 1 > b ? j - 1 : j, ln);  // the last block re-reads itself
         const int64_t j0 = (int64_t)j * SV_NB;
         const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+        double xv[16][RC];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const int kk = 16 * p + k;
-          if (kk < njr) {
-            const double* xk = B + (j0 + kk) * ldb + c0;
+          const double* xk = B + (j0 + (kk < njr ? kk : 0)) * ldb + c0;
 #pragma unroll
-            for (int c = 0; c < RC; ++c)
-              if (c < nc) acc[c] += lc[k] * xk[c];
-          }
+          for (int c = 0; c < RC; ++c) xv[k][c] = (kk < njr && c < nc) ? xk[c] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
+        for (int s = 0; s < G; ++s) {
+          const int32_t jn = s + 1 < G ? j : (j - 1 > bh ? j - 1 : j);
+          double ln[16];
+          load_col(s + 1 < G ? s + 1 : (j - 1 > bh ? 0 : s), jn, ln);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int kk = 16 * p + k;
+            if (kk < njr) {
+#pragma unroll
+              for (int c = 0; c < RC; ++c)
+                if (c < nc) acc[s][c] += lc[k] * xv[k][c];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 16; ++k) lc[k] = ln[k];
+        }
       }
     }
-#pragma unroll
-    for (int c = 0; c < RC; ++c) part[p][r][c] = acc[c];
-    __syncthreads();
     const int w = tid >> 6, lane = tid & 63;
-    for (int c = w; c < nc; c += 4) {
-      double v = 0.0;
-      if (lane < nr) {
-        const double s = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
-        v = B[(r0 + lane) * ldb + c0 + c] - s;
-      }
-      // lane k keeps column k of the diagonal block (row k of its transpose)
-      double lc2[SV_NB];
 #pragma unroll
-      for (int i = 0; i < SV_NB; ++i) lc2[i] = Lbb[i][lane];
-      const double dl = Lbb[lane][lane], rl = rdiag[lane];
+    for (int s = 0; s < G; ++s) {
+      if (s < ns) {
+        const int32_t b = bh - s;
+        const int64_t r0 = (int64_t)b * SV_NB;
+        const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+        double lg[16];
+        if (s + 1 < ns) load_col(s + 1, b, lg);
 #pragma unroll
-      for (int i = SV_NB - 1; i >= 0; --i) {
-        const double xi = sv_div_rcp(sv_readlane(v, i), sv_readlane(dl, i), sv_readlane(rl, i));
-        if (lane == i) v = xi;
-        else if (lane < i) v = v - lc2[i] * xi;
+        for (int c = 0; c < RC; ++c) part[p][r][c] = acc[s][c];
+        __syncthreads();
+        for (int c = w; c < nc; c += 4) {
+          double v = 0.0;
+          if (lane < nr) {
+            const double sm = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
+            v = B[(r0 + lane) * ldb + c0 + c] - sm;
+          }
+          sv_chains_bwd<1>(&v, Lbb[s], rdiag[s], lane);
+          if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
+          xs[lane][c] = v;  // zero past nr
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s3 = s + 1; s3 < G; ++s3) {
+          if (s3 < ns) {
+            double lf[16];
+            if (s3 == s + 1) {
+#pragma unroll
+              for (int k = 0; k < 16; ++k) lf[k] = lg[k];
+            } else {
+              load_col(s3, b, lf);
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              const int kk = 16 * p + k;
+              if (kk < nr) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c)
+                  if (c < nc) acc[s3][c] += lf[k] * xs[kk][c];
+              }
+            }
+          }
+        }
+        __syncthreads();  // part and xs are rewritten by the next member
       }
-      if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
     }
-    __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, ws, wait_ticks);
+  sv_publish(&ws->done_b, nb - 1 - bh, ns, ws, wait_ticks);
 }
 
 // ------------------------------------------------ matrix-core fold sweeps
@@ -351,48 +492,6 @@ typedef double sv_v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ sv_v4d sv_mfma(double a, double b, sv_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// NT interleaved substitution chains of one wave against the staged
-// diagonal block: lane k holds row k of each right-hand side; forward runs
-// with L_bb (lane k keeps row k), backward with L_bb^T (lane k keeps
-// column k).
-template <int NT>
-__device__ __forceinline__ void sv_chains_fwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
-                                              int lane) {
-  double lr[SV_NB];
-#pragma unroll
-  for (int i = 0; i < SV_NB; ++i) lr[i] = Lbb[lane][i];
-  const double dl = Lbb[lane][lane], rl = rdiag[lane];
-#pragma unroll
-  for (int i = 0; i < SV_NB; ++i) {
-    const double di = sv_readlane(dl, i), ri = sv_readlane(rl, i);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const double xi = sv_div_rcp(sv_readlane(v[t], i), di, ri);
-      if (lane == i) v[t] = xi;
-      else if (lane > i) v[t] = v[t] - lr[i] * xi;
-    }
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void sv_chains_bwd(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
-                                              int lane) {
-  double lc2[SV_NB];
-#pragma unroll
-  for (int i = 0; i < SV_NB; ++i) lc2[i] = Lbb[i][lane];
-  const double dl = Lbb[lane][lane], rl = rdiag[lane];
-#pragma unroll
-  for (int i = SV_NB - 1; i >= 0; --i) {
-    const double di = sv_readlane(dl, i), ri = sv_readlane(rl, i);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const double xi = sv_div_rcp(sv_readlane(v[t], i), di, ri);
-      if (lane == i) v[t] = xi;
-      else if (lane < i) v[t] = v[t] - lc2[i] * xi;
-    }
-  }
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
@@ -490,7 +589,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restr
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b, ws, wait_ticks);
+  sv_publish(&ws->done_f, b, 1, ws, wait_ticks);
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
@@ -594,7 +693,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, ws, wait_ticks);
+  sv_publish(&ws->done_b, t, 1, ws, wait_ticks);
 }
 
 // ------------------------------------------- sweeps with inverted diagonals
@@ -721,7 +820,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b, ws, wait_ticks);
+  sv_publish(&ws->done_f, b, 1, ws, wait_ticks);
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
@@ -817,7 +916,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, ws, wait_ticks);
+  sv_publish(&ws->done_b, t, 1, ws, wait_ticks);
 }
 
 __global__ void sv_clear(SvWs* ws) {
@@ -856,10 +955,11 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
   SvWs* ws = (SvWs*)work;
   if (nrhs <= 2) {  // measured faster for one or two right-hand sides
     hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
-    hipLaunchKernelGGL(sv_forward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs, ldb,
-                       ws, wait_ticks);
-    hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
-                       ldb, ws, wait_ticks);
+    const int64_t ngf = (nb + SV_GROUP_F - 1) / SV_GROUP_F, ngb = (nb + SV_GROUP_B - 1) / SV_GROUP_B;
+    hipLaunchKernelGGL((sv_forward<SV_RC_SMALL, SV_GROUP_F>), dim3((unsigned)ngf), dim3(SV_THREADS), 0, st, L, lda, n,
+                       B, nrhs, ldb, ws, wait_ticks);
+    hipLaunchKernelGGL((sv_backward<SV_RC_SMALL, SV_GROUP_B>), dim3((unsigned)ngb), dim3(SV_THREADS), 0, st, L, lda,
+                       n, B, nrhs, ldb, ws, wait_ticks);
     return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
