@@ -276,6 +276,32 @@ def test_solve_backward_error(tc, n, nrhs, T):
     assert np.abs(X - Xref).max() <= 1e-10 * max(1.0, np.abs(Xref).max())
 
 
+@pytest.mark.parametrize("n", [63, 64, 65, 128, 191, 192, 193, 320, 449, 1000])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_solve_small_rhs_groups(tc, n, nrhs):
+    """The sweeps for one or two right-hand sides take consecutive 64-row
+    blocks in groups per workgroup: block counts that leave a one-block
+    last group, ragged last blocks, and a strided B (ldb > nrhs), against
+    the oracle's factor and solve."""
+    import torch
+    A = inputs.gg_plus_identity(n, seed=61 + n)
+    Lref, info = oracle.potrf(A)
+    assert info == 0
+    B = np.random.default_rng(62 + nrhs).standard_normal((n, nrhs))
+    Lg = torch.from_numpy(np.ascontiguousarray(np.tril(Lref))).cuda()
+    wide = torch.zeros((n, nrhs + 1), dtype=torch.float64, device="cuda")
+    wide[:, :nrhs] = torch.from_numpy(B).cuda()
+    Bg = wide[:, :nrhs]
+    tc.chol_solve(Lg, Bg, 128)
+    X = Bg.cpu().numpy()
+    assert np.array_equal(wide[:, nrhs].cpu().numpy(), np.zeros(n))  # the column past nrhs is untouched
+    Xref = oracle.solve(Lref, B)
+    eta = oracle.backward_error(A, X, B)
+    say(f"solve groups n={n} nrhs={nrhs} eta={eta:.2e}")
+    assert eta <= ETA_TOL
+    assert np.abs(X - Xref).max() <= 1e-10 * max(1.0, np.abs(Xref).max())
+
+
 # ------------------------------------------------------------------ batched
 def test_batched_uneven_sizes(tc):
     import torch
