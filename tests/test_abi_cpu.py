@@ -287,3 +287,16 @@ def test_lookahead_setting_keeps_the_order_topological(tc, look, n, T):
         tc.chol_set_lookahead(prev)
     assert tc.chol_set_lookahead(-5) == prev  # negative restores the default
     assert tc.chol_set_lookahead(prev) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus above 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([_sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
