@@ -84,14 +84,13 @@ __device__ __forceinline__ int32_t sv_wait_wg(const int32_t* cnt, int32_t need, 
   return v;
 }
 
-// Publish the completion of cnt blocks in sweep order: wait until `done` ==
-// pos, then set it to pos + cnt.  All threads have fenced their stores
-// before.
-__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, int32_t cnt, SvWs* ws, int64_t wait_ticks) {
-  if (threadIdx.x == 0) {
-    if (sv_wait_above(done, pos - 1, ws, wait_ticks) >= 0)
-      __hip_atomic_store(done, pos + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+// Publish the completion of cnt blocks in sweep order by setting `done` to
+// pos + cnt.  The caller has seen done == pos: its wait loop ends only when
+// every earlier block is finished, and only the owner of position pos moves
+// the counter on from there.  All threads have fenced their stores before.
+// A workgroup whose wait was aborted publishes nothing.
+__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, int32_t cnt, bool ok) {
+  if (threadIdx.x == 0 && ok) __hip_atomic_store(done, pos + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Broadcast lane l's value of v to the whole wave (l wave-uniform).
@@ -186,6 +185,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
   __shared__ double Lbb[G][SV_NB][SV_NB + 1];
   __shared__ double rdiag[G][SV_NB];
   __shared__ int32_t s_g, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_g = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -230,7 +230,10 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
     int32_t j = 0;
     while (j < b0) {
       const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-      if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
+      if (ready < 0) {  // aborted: finish the barrier sequence, publish nothing
+        ok = false;
+        break;
+      }
       const int32_t jend = ready < b0 ? ready : b0;
       for (; j < jend; ++j) {
         double y[4][RC];
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b0, ns, ws, wait_ticks);
+  sv_publish(&ws->done_f, b0, ns, ok);
 }
 
 // --------------------------------------------------------------- backward
@@ -341,6 +344,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
   __shared__ double Lbb[G][SV_NB][SV_NB + 1];
   __shared__ double rdiag[G][SV_NB];
   __shared__ int32_t s_t, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -383,7 +387,10 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
     int32_t j = nb - 1;
     while (j > bh) {
       const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-      if (ready < 0) break;
+      if (ready < 0) {
+        ok = false;
+        break;
+      }
       const int32_t jlow = nb - ready > bh + 1 ? nb - ready : bh + 1;
       for (; j >= jlow; --j) {
         const int64_t j0 = (int64_t)j * SV_NB;
@@ -465,7 +472,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, nb - 1 - bh, ns, ws, wait_ticks);
+  sv_publish(&ws->done_b, nb - 1 - bh, ns, ok);
 }
 
 // ------------------------------------------------ matrix-core fold sweeps
@@ -501,6 +508,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restr
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_b, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -543,7 +551,10 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restr
   int32_t j = 0;
   while (j < b) {
     const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-    if (ready < 0) break;  // aborted: finish the barrier sequence, publish nothing useful
+    if (ready < 0) {  // aborted: finish the barrier sequence, publish nothing
+        ok = false;
+        break;
+      }
     const int32_t jend = ready < b ? ready : b;
     for (; j < jend; ++j) {
       if (!have_y) load_y(j, ya);
@@ -589,7 +600,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restr
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b, 1, ws, wait_ticks);
+  sv_publish(&ws->done_f, b, 1, ok);
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
@@ -599,6 +610,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
   __shared__ int32_t s_t, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -650,7 +662,10 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
   int32_t j = nb - 1;
   while (j > b) {
     const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-    if (ready < 0) break;
+    if (ready < 0) {
+        ok = false;
+        break;
+      }
     const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
     for (; j >= jlow; --j) {
       if (!have_x) load_x(j, xa);
@@ -693,7 +708,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, 1, ws, wait_ticks);
+  sv_publish(&ws->done_b, t, 1, ok);
 }
 
 // ------------------------------------------- sweeps with inverted diagonals
@@ -742,6 +757,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
   __shared__ double part[SV_NB][SV_MF_RC + 1];
   __shared__ double Ds[SV_NB][SV_NB + 1];
   __shared__ int32_t s_b, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -780,7 +796,10 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
   int32_t j = 0;
   while (j < b) {
     const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-    if (ready < 0) break;
+    if (ready < 0) {
+        ok = false;
+        break;
+      }
     const int32_t jend = ready < b ? ready : b;
     for (; j < jend; ++j) {
       if (!have_y) load_y(j, ya);
@@ -820,7 +839,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_f, b, 1, ws, wait_ticks);
+  sv_publish(&ws->done_f, b, 1, ok);
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
@@ -829,6 +848,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   __shared__ double part[SV_NB][SV_MF_RC + 1];
   __shared__ double Ds[SV_NB][SV_NB + 1];
   __shared__ int32_t s_t, s_ready;
+  bool ok = true;  // no dependency wait aborted
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -877,7 +897,10 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   int32_t j = nb - 1;
   while (j > b) {
     const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-    if (ready < 0) break;
+    if (ready < 0) {
+        ok = false;
+        break;
+      }
     const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
     for (; j >= jlow; --j) {
       if (!have_x) load_x(j, xa);
@@ -916,7 +939,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, 1, ws, wait_ticks);
+  sv_publish(&ws->done_b, t, 1, ok);
 }
 
 __global__ void sv_clear(SvWs* ws) {

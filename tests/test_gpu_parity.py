@@ -302,6 +302,30 @@ def test_solve_small_rhs_groups(tc, n, nrhs):
     assert np.abs(X - Xref).max() <= 1e-10 * max(1.0, np.abs(Xref).max())
 
 
+@pytest.mark.parametrize("nrhs", [1, 20])
+def test_solve_wait_limit_never_hangs(tc, nrhs):
+    """With a zero dependency-wait limit the sweeps give up their waits: the
+    call must return and the stream drain (B is then unspecified).  With the
+    limit restored the same solve must be right, on a fresh workspace."""
+    import torch
+    n = 1000
+    A = inputs.gg_plus_identity(n, seed=71)
+    Lref, _ = oracle.potrf(A)
+    B = np.random.default_rng(72).standard_normal((n, nrhs))
+    Lg = torch.from_numpy(np.ascontiguousarray(np.tril(Lref))).cuda()
+    prev = tc.chol_set_wait_limit(0.0)
+    try:
+        Bg = torch.from_numpy(B).cuda()
+        tc.chol_solve(Lg, Bg, 128)
+        torch.cuda.synchronize()
+    finally:
+        tc.chol_set_wait_limit(prev)
+    Bg = torch.from_numpy(B).cuda()
+    tc.chol_solve(Lg, Bg, 128)
+    X = Bg.cpu().numpy()
+    assert oracle.backward_error(A, X, B) <= ETA_TOL
+
+
 # ------------------------------------------------------------------ batched
 def test_batched_uneven_sizes(tc):
     import torch
