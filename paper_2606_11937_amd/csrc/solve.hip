@@ -216,8 +216,17 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
       for (int m = 0; m < 4; ++m) dst[s2][m] = lv ? p[16 * m] : 0.0;
     }
   };
+  static_assert(RC <= 4, "one right-hand side per wave in the substitutions");
   for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
     const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
+    // the group's own right-hand-side entries, read before any wait (only
+    // this workgroup writes them): wave w substitutes right-hand side w
+    double bown[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int64_t R = r0 + SV_NB * s + lane;
+      bown[s] = (s < ns && w < nc && R < n) ? B[R * ldb + c0 + w] : 0.0;
+    }
     double acc[G][4][RC];
 #pragma unroll
     for (int s = 0; s < G; ++s)
@@ -287,9 +296,10 @@ __global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restric
             }
           }
         __syncthreads();
-        for (int c = w; c < nc; c += 4) {
+        if (w < nc) {
+          const int c = w;
           double v = 0.0;
-          if (lane < nr) v = B[(rs + lane) * ldb + c0 + c] - (b0 + s > 0 ? part[lane][c] : 0.0);
+          if (lane < nr) v = bown[s] - (b0 + s > 0 ? part[lane][c] : 0.0);
           sv_chains_fwd<1>(&v, Lbb[s], rdiag[s], lane);
           if (lane < nr) B[(rs + lane) * ldb + c0 + c] = v;
           ys[lane][c] = v;  // zero past nr
@@ -375,8 +385,18 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
       dst[k] = (lv && kk < njr) ? base[(j0 + kk) * lda] : 0.0;
     }
   };
+  static_assert(RC <= 4, "one right-hand side per wave in the substitutions");
   for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
     const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
+    // the group's own entries of y, read before any wait (only this
+    // workgroup writes them): wave tid / 64 substitutes right-hand side
+    // tid / 64
+    double bown[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int64_t R = (int64_t)(bh - s) * SV_NB + r;
+      bown[s] = (s < ns && p < nc && R < n) ? B[R * ldb + c0 + p] : 0.0;
+    }
     double acc[G][RC];
 #pragma unroll
     for (int s = 0; s < G; ++s)
@@ -434,11 +454,12 @@ __global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restri
 #pragma unroll
         for (int c = 0; c < RC; ++c) part[p][r][c] = acc[s][c];
         __syncthreads();
-        for (int c = w; c < nc; c += 4) {
+        if (w < nc) {
+          const int c = w;
           double v = 0.0;
           if (lane < nr) {
             const double sm = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
-            v = B[(r0 + lane) * ldb + c0 + c] - sm;
+            v = bown[s] - sm;
           }
           sv_chains_bwd<1>(&v, Lbb[s], rdiag[s], lane);
           if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
