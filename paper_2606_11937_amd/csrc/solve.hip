@@ -38,7 +38,7 @@
 // 64-row blocks per workgroup in the forward and backward sweeps for one or
 // two right-hand sides
 #define SV_GROUP_F 2
-#define SV_GROUP_B 2
+#define SV_GROUP_B 1
 #define SV_THREADS 256
 
 struct SvWs {
