@@ -74,10 +74,6 @@ TRAFFIC = {
     # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
     ("fork_join", 32768, 1024): (14840737564,
                                  "edf0e223697f76ccb4261f59af1a4a02bcd3280bb5e66fa497472d8eb731c980"),
-    # per tc_fj_update_range launch, averaged over the column-(J+1) and the
-    # rest launches (profiles/lookahead_n32768_T1024_kernels.md)
-    ("fork_join_lookahead", 32768, 1024): (7522126878,
-                                           "389687e9dd6de4844a2324ad284059060a3da151e00d2a9cc9148ed7e1abe3be"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,
@@ -150,17 +146,20 @@ def make_input(n: int):
     return inputs.se_kernel_device(n, seed=1, device="cuda")
 
 
-def update_flops(n: int, T: int) -> float:
+def update_flops(n: int, T: int, beyond_next: bool = False) -> float:
     """Algorithmic flops of all SYRK + GEMM tile operations (T^3 per SYRK,
-    2 T^3 per GEMM, on the tiles' actual sides when T does not divide n)."""
+    2 T^3 per GEMM, on the tiles' actual sides when T does not divide n).
+    beyond_next: only the output tiles (I, K) with K > J + 1 of each step J,
+    the part the lookahead schedule runs on its second stream."""
     M = -(-n // T)
     side = [min(T, n - I * T) for I in range(M)]
     f = 0.0
     for J in range(M):
         t = side[J]
-        for I in range(J + 1, M):
+        k0 = J + 2 if beyond_next else J + 1
+        for I in range(k0, M):
             f += side[I] * side[I] * t  # SYRK(I, J)
-            for K in range(J + 1, I):
+            for K in range(k0, I):
                 f += 2.0 * side[I] * side[K] * t  # GEMM(I, K, J)
     return f
 
@@ -218,9 +217,25 @@ def sweep(args):
         torch.cuda.empty_cache()
 
 
+def cpu_model() -> str:
+    """Host CPU model name (from /proc/cpuinfo, else the platform string)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(block, m: int):
-    """The CPU oracle (right-looking FP64, all host threads) on the leading
-    m x m principal block of the same input (copied before any factor ran)."""
+    """The CPU oracle (right-looking FP64, OpenMP over the host threads it is
+    given) on the leading m x m principal block of the same input (copied
+    before any factor ran).  `cores` is the thread count the oracle ran with;
+    the host's CPUs available to this process and their model are recorded
+    beside it."""
     import oracle
     a = block.numpy()
     t0 = time.perf_counter()
@@ -229,6 +244,8 @@ def cpu_baseline(block, m: int):
     assert info == 0
     return {"value": round(m ** 3 / 3 / dt / 1e12, 6), "unit": "TFLOP/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
+            "host_cpus_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "omp": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OMP_PROC_BIND", "OMP_PLACES")},
             "sample": f"leading {m}x{m} principal block of the same SE matrix, factored by the right-looking "
                       f"FP64 oracle; rate = ({m}^3/3)/t"}
 
@@ -535,7 +552,8 @@ def main():
     tc.chol_timing_read(st)  # discard anything recorded before
     # time the dominant kernel's launches only: every event pair costs a few
     # microseconds on the stream
-    tc.chol_timing_enable(["update"] if sched.startswith("fork_join") else ["persistent"])
+    tc.chol_timing_enable(["update_rest"] if sched == "fork_join_lookahead" else
+                          ["update"] if sched.startswith("fork_join") else ["persistent"])
     torch.cuda.synchronize()
     t_start.record(st)
     for k in range(K):
@@ -556,11 +574,17 @@ def main():
     flops = n ** 3 / 3
     value = flops / (ms_step * 1e-3) / 1e12
 
-    if sched.startswith("fork_join"):
+    if sched == "fork_join_lookahead":
+        # the bulk of each step's update runs on the second stream, one launch
+        # at a time: its summed launch time fits inside the step
+        kernel = ("tc_fj_update_rest (SYRK+GEMM trailing update of the tile columns beyond J+1, one launch per "
+                  "step on the second stream, concurrent with the next panel chain)")
+        kms, kcount = launches["update_rest"]
+        kflops = update_flops(n, T, beyond_next=True) * K
+    elif sched.startswith("fork_join"):
         kernel = {"fork_join": "tc_fj_update (collapsed SYRK+GEMM trailing update, one launch per step)",
                   "fork_join_naive": "tc_fj_update_naive (trailing update parallel over tile rows, one launch per step)",
-                  "fork_join_lookahead": "tc_fj_update_range (trailing update in two launches per step, column J+1 "
-                                         "and the rest on a second stream; launch times overlap)"}[sched]
+                  }[sched]
         kms, kcount = launches["update"]
         kflops = update_flops(n, T) * K  # over the K timed factorizations
     elif sched == "task_sync":
@@ -589,7 +613,10 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
                      "kernel": kernel, "launches": kcount, "flops_per_launch": flops_per_launch,
-                     "avg_launch_ms": round(avg_launch_ms, 4)},
+                     "avg_launch_ms": round(avg_launch_ms, 4),
+                     # the kernel's summed launch time per step, inside ms_per_step
+                     "kernel_ms_per_step": round(kms / K, 3),
+                     "step_frac": round(value / FP64_MFMA_PEAK_TFLOPS, 4)},
         "factor_ms": {"median": round(statistics.median(factor_ms), 3), "min": round(min(factor_ms), 3),
                       "max": round(max(factor_ms), 3)},
         "factor_tflops_median": round(flops / (statistics.median(factor_ms) * 1e-3) / 1e12, 3),

@@ -56,8 +56,10 @@ enum {
   CHOL_EINVAL = -1,     /* invalid argument (chol_last_bad_arg gives which)     */
   CHOL_EDEVICE = -2,    /* a HIP runtime call failed                             */
   CHOL_EWORKSPACE = -3, /* work_bytes smaller than the *_workspace_size result   */
-  CHOL_ETIMEOUT = -4    /* a dependency wait of the asynchronous schedule
+  CHOL_ETIMEOUT = -4,   /* a dependency wait of the asynchronous schedule
                            exceeded chol_set_wait_limit; factor unspecified     */
+  CHOL_ESTALLED = -5    /* chol_server_wait: a dependency wait of the request's
+                           factorization or solve exceeded the wait limit       */
 };
 
 /* Schedules (Methods, "Implementations", the fork-join collapsed and task
@@ -163,10 +165,16 @@ int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
  *          need not be initialised; calls sharing it must be ordered).
  * Returns CHOL_OK or a negative error code.  Stream-ordered; no host sync.
  * A sweep whose dependency wait exceeds chol_set_wait_limit stops early and
- * leaves B unspecified instead of hanging. */
+ * leaves B unspecified instead of hanging; the workspace then records the
+ * timeout until the next chol_solve with it (chol_solve_info reads it). */
 int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T,
                double* B, int64_t nrhs, int64_t ldb,
                void* work, int64_t work_bytes, void* stream);
+
+/* Outcome of the last chol_solve enqueued with this workspace: synchronises
+ * `stream` and returns CHOL_OK, or CHOL_ETIMEOUT when a dependency wait of
+ * one of its sweeps ran out (B is then unspecified), or CHOL_EDEVICE. */
+int chol_solve_info(const void* work, void* stream);
 
 /* ---- mixed precision ----------------------------------------------------
  * The trailing SYRK/GEMM products, which carry almost all of the flops, are
@@ -237,8 +245,9 @@ int64_t chol_refine_workspace_size(int64_t n, int64_t T, int64_t nrhs);
  *           slowest column (PCG).
  *   eta     host array of nrhs, or NULL: the final backward errors.
  * The call synchronises `stream` once per iteration (the stopping test).
- * Returns CHOL_OK, CHOL_NOT_CONVERGED (X holds the last iterate) or a
- * negative error code. */
+ * Returns CHOL_OK, CHOL_NOT_CONVERGED (X holds the last iterate),
+ * CHOL_ETIMEOUT (a dependency wait of a solve sweep exceeded
+ * chol_set_wait_limit; X unspecified) or a negative error code. */
 int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T,
                       const double* B, int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method,
                       double tol, int64_t max_iter, void* work, int64_t work_bytes, void* stream,
@@ -324,12 +333,12 @@ int chol_server_submit(chol_server* server, const double* points, int64_t n, dou
  * n x nrhs, or NULL) receives the solution, *eta the worst column's backward
  * error, *latency_s the time from submission to the result being in host
  * memory.  Returns CHOL_OK (eta <= tol), CHOL_NOT_CONVERGED (done, eta >
- * tol), CHOL_NOT_SPD (*info as for chol_factor; *info < 0 instead when the
- * request's factorization was ended by the dependency-wait limit of
- * chol_set_wait_limit, which then leaves X unspecified: -(1 + the ticket of
- * the unit that waited) within its tick's launch), CHOL_EWORKSPACE (the
- * request can never fit in the arena), CHOL_ETIMEOUT (not done yet), or a
- * negative error code. */
+ * tol), CHOL_NOT_SPD (*info as for chol_factor), CHOL_ESTALLED (a dependency
+ * wait exceeded chol_set_wait_limit and X is unspecified: *info = 1 + the
+ * ticket, within its tick's launch, of the factorization unit that waited,
+ * or -1 when a solve sweep's wait ran out), CHOL_EWORKSPACE (the request can
+ * never fit in the arena), CHOL_ETIMEOUT (not done yet), or a negative error
+ * code. */
 int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta,
                      double* latency_s, int64_t* info);
 /* Ticks launched so far (< 0 on invalid arguments). */
@@ -388,7 +397,10 @@ int64_t chol_async_grid(void);
  * Per-launch device time of chol_factor.  `kinds` is a bit mask: bit k
  * (k = CHOL_UNIT_POTRF, CHOL_UNIT_TRSM, CHOL_UNIT_UPDATE, CHOL_UNIT_PANEL)
  * times the fork-join launches of that unit kind, bit 4 the persistent
- * launch of the asynchronous schedule; 0 turns timing off.  While enabled on
+ * launch of the asynchronous schedule, bit 5 the trailing-update launches
+ * that CHOL_SCHED_FORK_JOIN_LOOKAHEAD runs on its second stream (the
+ * columns beyond J+1; its column-(J+1) launches count under bit
+ * CHOL_UNIT_UPDATE); 0 turns timing off.  While enabled on
  * the calling thread, each selected launch chol_factor enqueues is
  * bracketed by a pair of HIP events on the call's stream (events are
  * created on first use and reused; no device memory is allocated; each pair
@@ -398,8 +410,9 @@ int64_t chol_async_grid(void);
  * read, and clears them.  The workspace-clearing launch is never timed.
  * chol_timing_enable returns the previous mask; chol_timing_read returns
  * CHOL_OK, CHOL_EINVAL (NULL output) or CHOL_EDEVICE. */
+#define CHOL_TIMING_KINDS 6
 int chol_timing_enable(int kinds);
-int chol_timing_read(void* stream, double ms[5], int64_t launches[5]);
+int chol_timing_read(void* stream, double ms[CHOL_TIMING_KINDS], int64_t launches[CHOL_TIMING_KINDS]);
 
 /* Dispatch-order knob of the asynchronous schedule (the paper's task
  * priorities, here a property of the ticket order): the number of bulk

@@ -26,7 +26,8 @@ static_assert(CHOL_SCHED_FORK_JOIN == 0 && CHOL_SCHED_ASYNC_DAG == 1 && CHOL_SCH
                   CHOL_SCHED_TASK_SYNC == 3 && CHOL_SCHED_FORK_JOIN_LOOKAHEAD == 4 && CHOL_SCHED_GRAPH_DAG == 5 &&
                   CHOL_SCHED_NOOP == TC_SCHED_NOOP,
               "schedule codes of the ABI and the launcher differ");
-static_assert(TC_TIMING_KINDS == 5 && TC_TIMING_PERSISTENT == 4, "timing kinds of the ABI and the launcher differ");
+static_assert(TC_TIMING_KINDS == CHOL_TIMING_KINDS && TC_TIMING_PERSISTENT == 4 && TC_TIMING_REST == 5,
+              "timing kinds of the ABI and the launcher differ");
 
 namespace {
 thread_local int g_bad_arg = 0;
@@ -87,6 +88,7 @@ const char* chol_status_str(int status) {
     case CHOL_EDEVICE: return "HIP runtime error";
     case CHOL_EWORKSPACE: return "workspace too small";
     case CHOL_ETIMEOUT: return "dependency wait exceeded the wait limit";
+    case CHOL_ESTALLED: return "a served request's dependency wait exceeded the wait limit (see info)";
     case CHOL_NOT_CONVERGED: return "refinement did not reach the tolerance within max_iter";
     default: return "unknown status";
   }
@@ -165,8 +167,17 @@ int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, in
   if (B == nullptr) return bad(5);
   if (work == nullptr) return bad(8);
   if (work_bytes < tc_solve_ws_bytes()) return bad(9, CHOL_EWORKSPACE);
-  return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, work, (hipStream_t)stream, wait_ticks()) == 0 ? CHOL_OK
-                                                                                                  : CHOL_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (tc_solve_status_reset(work, st) != 0) return CHOL_EDEVICE;
+  return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, work, st, wait_ticks()) == 0 ? CHOL_OK : CHOL_EDEVICE;
+}
+
+int chol_solve_info(const void* work, void* stream) {
+  g_bad_arg = 0;
+  if (work == nullptr) return bad(1);
+  int32_t err = 0;
+  if (tc_solve_status((void*)work, (hipStream_t)stream, &err) != 0) return CHOL_EDEVICE;
+  return err ? CHOL_ETIMEOUT : CHOL_OK;
 }
 
 int64_t chol_factor_mixed_workspace_size(int64_t n, int64_t T, int prec) {
@@ -232,6 +243,7 @@ int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl
   if (work_bytes < tc_refine_ws_bytes(n, nrhs)) return bad(16, CHOL_EWORKSPACE);
   const int r = tc_refine(A, lda, L, ldl, n, T, B, ldb, X, ldx, nrhs, method, tol, max_iter, work,
                           (hipStream_t)stream, wait_ticks(), iters, eta);
+  if (r == TC_LAUNCH_ETIMEOUT) return CHOL_ETIMEOUT;
   if (r < 0) return CHOL_EDEVICE;
   return r == 0 ? CHOL_OK : CHOL_NOT_CONVERGED;
 }
@@ -386,6 +398,7 @@ int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* 
     case 5: return CHOL_NOT_CONVERGED;
     case 3: return CHOL_NOT_SPD;
     case 4: return CHOL_EWORKSPACE;
+    case 6: return CHOL_ESTALLED;
     case 0:
     case 1: return CHOL_ETIMEOUT;
     case TC_LAUNCH_EINVAL: return bad(2);
@@ -459,7 +472,7 @@ int64_t chol_dag_forkjoin_update(int64_t n, int64_t T, int64_t J, int32_t* out, 
 
 int chol_timing_enable(int kinds) { return tc_timing_enable(kinds); }
 
-int chol_timing_read(void* stream, double ms[5], int64_t launches[5]) {
+int chol_timing_read(void* stream, double ms[CHOL_TIMING_KINDS], int64_t launches[CHOL_TIMING_KINDS]) {
   g_bad_arg = 0;
   if (ms == nullptr) return bad(2);
   if (launches == nullptr) return bad(3);

@@ -260,6 +260,18 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_range(double* A, i
   }
 }
 
+// The rest of step J's update (columns beyond J+1) on the second stream:
+// the same units and bodies as the range kernel, under a name of its own so
+// that traces and counters report the bulk launches apart from the small
+// column-(J+1) launches that overlap them.
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_rest(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                   TcWs ws, int64_t first) {
+  __shared__ TcUpdSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  const TcUnit u = tc_decode_trailing(g, J, J, first + blockIdx.x);
+  tc_run_update(A, lda, g, u, sm);
+}
+
 // ----------------------------------------------- low-precision trailing update
 // Mixed-precision fork-join: after the FP64 panel of step J is final, its
 // rows below the diagonal tile are rounded once into the panel copy P (row r
@@ -1086,8 +1098,8 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
       });
       if (nu > ncol) {
         if (hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
-        tc_timed(TC_UNIT_UPDATE, sb, [&] {
-          hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)(nu - ncol)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
+        tc_timed(TC_TIMING_REST, sb, [&] {
+          hipLaunchKernelGGL(tc_fj_update_rest, dim3((unsigned)(nu - ncol)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
                              ws, ncol);
         });
         if (hipEventRecord(eb, sb) != hipSuccess) return TC_LAUNCH_EDEVICE;

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #define TC_LAUNCH_EDEVICE (-2)
+#define TC_LAUNCH_ETIMEOUT (-4)
 
 // Tile side of the plain factorization when the caller gives none (measured
 // on MI355X, fork-join: small orders are launch-bound and prefer short
@@ -27,9 +28,11 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
 // aid): enable takes a mask of the kinds to time (bit k for kind k) and
 // returns the previous mask; read synchronises `st`, sums the
 // recorded launch times per kind (POTRF, TRSM, UPDATE, PANEL unit launches,
-// then the persistent launch) and clears.
-#define TC_TIMING_KINDS 5
+// then the persistent launch, then the lookahead schedule's second-stream
+// trailing updates) and clears.
+#define TC_TIMING_KINDS 6
 #define TC_TIMING_PERSISTENT 4
+#define TC_TIMING_REST 5
 int tc_timing_enable(int mask);
 int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TIMING_KINDS]);
 // Mixed precision (fork-join): prec 0 FP64, 1 FP32, 2 BF16 trailing
@@ -44,8 +47,16 @@ int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* in
 // Co-resident workgroups of the persistent kernels on the current device.
 int64_t tc_async_grid_size();
 int64_t tc_sync_grid_size();
-// Workspace bytes of the solve (block tickets and done counters).
+// Workspace bytes of the solve (block tickets and done counters, and a
+// status word).
 int64_t tc_solve_ws_bytes();
+// The status word: cleared by tc_solve_status_reset (enqueued), set when a
+// sweep's dependency wait runs out, kept by the launches below (which clear
+// only their counters) until the next reset; tc_solve_status synchronises
+// `st` and reads it; tc_solve_status_offset is its byte offset.
+int tc_solve_status_reset(void* work, hipStream_t st);
+int tc_solve_status(const void* work, hipStream_t st, int32_t* error);
+int64_t tc_solve_status_offset();
 // Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks);
@@ -58,7 +69,8 @@ int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* D
                         int64_t ldb, void* work, hipStream_t st, int64_t wait_ticks);
 // Refinement of A X = B with a (low-precision) factor: method 0 iterative
 // refinement, 1 preconditioned CG.  Synchronises `st` once per iteration.
-// Returns 0 converged, 1 not converged, < 0 device error.
+// Returns 0 converged, 1 not converged, TC_LAUNCH_ETIMEOUT when a sweep's
+// dependency wait ran out (X unspecified), other < 0 device errors.
 int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs);
 int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_t n, int64_t T, const double* B,
               int64_t ldb, double* X, int64_t ldx, int64_t nrhs, int method, double tol, int64_t max_iter, void* work,

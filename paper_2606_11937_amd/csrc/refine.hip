@@ -302,6 +302,8 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
     return tc_launch_solve_inv(L, n, ldl, w.dinv, Y, nrhs, ldy, w.solve_ws, st, wait_ticks);
   };
   if (tc_launch_invert_diag(L, n, ldl, w.dinv, st) != 0) return fail();
+  // one status word for every sweep of the call
+  if (tc_solve_status_reset(w.solve_ws, st) != 0) return fail();
   // ||A||_inf from the row sums of |A|, and ||b||_inf per column
   hipLaunchKernelGGL(rf_symv<true>, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n,
                      (const double*)nullptr, (int64_t)1, (const double*)nullptr, (int64_t)1, w.rowsum, (int64_t)1,
@@ -397,7 +399,10 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
     status = rf_max(eta) <= tol ? 0 : 1;
   }
   if (hipGetLastError() != hipSuccess) return fail();
+  int32_t stalled = 0;
+  if (tc_solve_status(w.solve_ws, st, &stalled) != 0) return fail();
   if (iters) *iters = it;
+  if (stalled) return TC_LAUNCH_ETIMEOUT;
   if (eta_out)
     for (int64_t c = 0; c < nrhs; ++c) eta_out[c] = eta[c];
   return status;

@@ -182,7 +182,8 @@ struct Request {
   std::vector<double> pts, B, X;
   double eta = 0;
   int64_t t_arrive = 0, t_done = 0, info = 0;
-  int state = 0;  // 0 pending, 1 running, 2 done, 3 failed (not SPD), 4 rejected (does not fit)
+  // 0 pending, 1 running, 2 done, 3 failed (not SPD), 4 rejected (does not fit), 6 a dependency wait ran out
+  int state = 0;
   int64_t dev_off = -1, dev_bytes = 0, pin_off = -1, pin_bytes = 0;
 };
 
@@ -191,8 +192,9 @@ struct Tick {
   std::vector<Request*> rq;  // taken under the lock at admission
   int stream = 0;
   hipEvent_t done = nullptr;
-  int64_t ws_off = -1, ws_bytes = 0, meta_dev = -1, meta_bytes = 0, meta_pin = -1;
+  int64_t ws_off = -1, ws_bytes = 0, solve_off = 0, meta_dev = -1, meta_bytes = 0, meta_pin = -1, pin_meta_bytes = 0;
   char* hdr_pin = nullptr;  // per-matrix status headers copied back
+  char* sv_pin = nullptr;   // per-request solve workspaces (status words) copied back
 };
 }  // namespace
 
@@ -284,19 +286,27 @@ bool launch_tick(TcServer& S, Tick& t) {
     if (tc_launch_batched(A.data(), nullptr, n.data(), lda.data(), T.data(), m, S.arena + t.ws_off, st, grid,
                           S.wait_ticks, chunk) != 0)
       return false;
-    char* sws = S.arena + t.ws_off + r256(t.ws_bytes - r256(tc_solve_ws_bytes()));
-    for (int64_t q = 0; q < m; ++q)
-      if (tc_launch_solve(A[q], n[q], n[q], T[q], X[q], nrhs[q], ldb[q], sws, st, S.wait_ticks) != 0) return false;
+    // every request's solve has a workspace (and status word) of its own
+    char* sws = S.arena + t.ws_off + t.solve_off;
+    const int64_t sb = r256(tc_solve_ws_bytes());
+    for (int64_t q = 0; q < m; ++q) {
+      if (tc_solve_status_reset(sws + sb * q, st) != 0) return false;
+      if (tc_launch_solve(A[q], n[q], n[q], T[q], X[q], nrhs[q], ldb[q], sws + sb * q, st, S.wait_ticks) != 0)
+        return false;
+    }
     if (hipMemcpyAsync(t.hdr_pin, S.arena + t.ws_off + 256, tc_ws_header_bytes() * m, hipMemcpyDeviceToHost, st) !=
         hipSuccess)
       return false;
+    if (hipMemcpyAsync(t.sv_pin, sws, sb * m, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
   } else {
     // one request: fork-join factor, then the solve
+    char* sws = S.arena + t.ws_off + t.solve_off;
     if (tc_launch_factor(A[0], n[0], n[0], T[0], 0, S.arena + t.ws_off, st, 0, S.wait_ticks, 0) != 0) return false;
-    if (tc_launch_solve(A[0], n[0], n[0], T[0], X[0], nrhs[0], ldb[0], S.arena + t.ws_off + r256(tc_ws_bytes(n[0], T[0])),
-                        st, S.wait_ticks) != 0)
-      return false;
+    if (tc_solve_status_reset(sws, st) != 0) return false;
+    if (tc_launch_solve(A[0], n[0], n[0], T[0], X[0], nrhs[0], ldb[0], sws, st, S.wait_ticks) != 0) return false;
     if (hipMemcpyAsync(t.hdr_pin, S.arena + t.ws_off, tc_ws_header_bytes(), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return false;
+    if (hipMemcpyAsync(t.sv_pin, sws, r256(tc_solve_ws_bytes()), hipMemcpyDeviceToHost, st) != hipSuccess)
       return false;
   }
   for (int64_t q = 0; q < m; ++q)
@@ -316,9 +326,11 @@ bool launch_tick(TcServer& S, Tick& t) {
   return hipGetLastError() == hipSuccess;
 }
 
-// device bytes of the tick's own workspace (batched counters and unit list,
-// or the fork-join and solve workspaces) and descriptor region
-int64_t tick_ws_bytes(TcServer& S, const std::vector<int64_t>& ids) {
+// device bytes of the tick's own workspace: the batched counters and unit
+// list (or the fork-join workspace), then one solve workspace per request
+// from byte *solve_off on
+int64_t tick_ws_bytes(TcServer& S, const std::vector<int64_t>& ids, int64_t* solve_off) {
+  int64_t head = 0;
   if (S.mode == 0) {
     std::vector<int64_t> n, T;
     for (int64_t id : ids) {
@@ -326,11 +338,13 @@ int64_t tick_ws_bytes(TcServer& S, const std::vector<int64_t>& ids) {
       T.push_back(tc_tuned_batched_tile(S.reqs[id]->n));
     }
     const int64_t grid = tc_batched_grid_size();
-    return r256(tc_batched_ws_bytes((int64_t)ids.size(), n.data(), T.data(), 0, grid > 1 ? grid / 2 : 128)) +
-           r256(tc_solve_ws_bytes());
+    head = r256(tc_batched_ws_bytes((int64_t)ids.size(), n.data(), T.data(), 0, grid > 1 ? grid / 2 : 128));
+  } else {
+    const int64_t n = S.reqs[ids[0]]->n;
+    head = r256(tc_ws_bytes(n, tc_default_tile(n)));
   }
-  const int64_t n = S.reqs[ids[0]]->n;
-  return r256(tc_ws_bytes(n, tc_default_tile(n))) + r256(tc_solve_ws_bytes());
+  *solve_off = head;
+  return head + r256(tc_solve_ws_bytes()) * (int64_t)ids.size();
 }
 
 void finish_tick(TcServer& S, Tick& t) {
@@ -343,12 +357,23 @@ void finish_tick(TcServer& S, Tick& t) {
     const double* he = (const double*)(h + r256(16 * R.n) + 2 * r256(8 * R.n * R.nrhs));
     R.X.assign(hx, hx + R.n * R.nrhs);
     R.eta = *he;
-    int32_t err = 0;
+    int32_t err = 0, serr = 0;
     int64_t info = 0;
     tc_ws_header_read(t.hdr_pin + hb * q, &err, &info);
-    // < 0: ended by the dependency-wait limit, -(1 + ticket of the unit that waited)
-    R.info = err == 1 ? info : -(info > 0 ? info : (int64_t)err);
-    R.state = err ? 3 : 2;
+    memcpy(&serr, t.sv_pin + r256(tc_solve_ws_bytes()) * q + tc_solve_status_offset(), sizeof(serr));
+    if (err == 1) {  // not positive definite: the failing column + 1
+      R.info = info;
+      R.state = 3;
+    } else if (err) {  // the factorization's dependency wait ran out: 1 + its unit's ticket
+      R.info = info > 0 ? info : 1;
+      R.state = 6;
+    } else if (serr) {  // a solve sweep's dependency wait ran out
+      R.info = -1;
+      R.state = 6;
+    } else {
+      R.info = 0;
+      R.state = 2;
+    }
     R.t_done = t_done;
     S.dev.release(R.dev_off, R.dev_bytes);
     S.pin.release(R.pin_off, R.pin_bytes);
@@ -359,7 +384,7 @@ void finish_tick(TcServer& S, Tick& t) {
   }
   S.dev.release(t.ws_off, t.ws_bytes);
   S.dev.release(t.meta_dev, t.meta_bytes);
-  S.pin.release(t.meta_pin, t.meta_bytes + hb * (int64_t)t.ids.size());
+  S.pin.release(t.meta_pin, t.pin_meta_bytes);
   (void)hipEventDestroy(t.done);
 }
 
@@ -430,14 +455,17 @@ void worker_main(TcServer* Sp) {
         // fewer; a lone request that cannot get them with nothing in flight
         // is rejected
         while (!t.ids.empty()) {
-          t.ws_bytes = tick_ws_bytes(S, t.ids);
-          t.meta_bytes = r256((int64_t)sizeof(SrvDesc) * (int64_t)t.ids.size());
-          const int64_t pin_meta = t.meta_bytes + tc_ws_header_bytes() * (int64_t)t.ids.size();
+          const int64_t m = (int64_t)t.ids.size();
+          t.ws_bytes = tick_ws_bytes(S, t.ids, &t.solve_off);
+          t.meta_bytes = r256((int64_t)sizeof(SrvDesc) * m);
+          const int64_t hdr_bytes = r256(tc_ws_header_bytes() * m);
+          t.pin_meta_bytes = t.meta_bytes + hdr_bytes + r256(tc_solve_ws_bytes()) * m;
           t.ws_off = S.dev.alloc(t.ws_bytes);
           t.meta_dev = t.ws_off >= 0 ? S.dev.alloc(t.meta_bytes) : -1;
-          t.meta_pin = t.meta_dev >= 0 ? S.pin.alloc(pin_meta) : -1;
+          t.meta_pin = t.meta_dev >= 0 ? S.pin.alloc(t.pin_meta_bytes) : -1;
           if (t.meta_pin >= 0) {
             t.hdr_pin = S.pinned + t.meta_pin + t.meta_bytes;
+            t.sv_pin = t.hdr_pin + hdr_bytes;
             t.stream = S.next_stream;
             S.next_stream ^= 1;
             break;
@@ -523,8 +551,10 @@ int tc_server_submit(TcServer* S, const double* pts, int64_t n, double lengthsca
 }
 
 // Returns the request state after waiting up to timeout_s (2 done within its
-// tolerance, 5 done but above it, 3 not SPD, 4 rejected, 0/1 still pending /
-// running), or < 0 on a device error.
+// tolerance, 5 done but above it, 3 not SPD, 4 rejected, 6 a dependency wait
+// of its factorization (info = 1 + the unit's ticket) or of a solve sweep
+// (info = -1) ran out, 0/1 still pending / running), or < 0 on a device
+// error.
 int tc_server_wait(TcServer* S, int64_t id, double timeout_s, double* X, double* eta, double* latency_s,
                    int64_t* info) {
   std::unique_lock<std::mutex> lk(S->mu);

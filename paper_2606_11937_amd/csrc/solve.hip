@@ -25,6 +25,7 @@
 // sequentially in the column index with one FMA per entry.  None of this
 // depends on the grouping of blocks into workgroups.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "launch.h"
@@ -41,10 +42,15 @@
 #define SV_GROUP_B 1
 #define SV_THREADS 256
 
+// Per-call counters of the two sweeps, then the call's status word: `error`
+// is set when a dependency wait ran out, cleared only when a call (or a
+// caller that groups several solves under one status) starts, so that the
+// counter reset before each 16-column group of right-hand sides keeps it.
 struct SvWs {
   int32_t ticket_f, done_f, ticket_b, done_b;
   int32_t error, pad[59];
 };
+#define SV_COUNTER_WORDS 4
 
 __device__ __forceinline__ int32_t sv_ld(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -963,11 +969,28 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   sv_publish(&ws->done_b, t, 1, ok);
 }
 
-__global__ void sv_clear(SvWs* ws) {
-  if (threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)ws)[threadIdx.x] = 0;
+// words: SV_COUNTER_WORDS clears the sweep counters only, the whole struct
+// clears the status too
+__global__ void sv_clear(SvWs* ws, int words) {
+  if ((int)threadIdx.x < words) ((int32_t*)ws)[threadIdx.x] = 0;
 }
 
 int64_t tc_solve_ws_bytes() { return (int64_t)sizeof(SvWs); }
+
+int tc_solve_status_reset(void* work, hipStream_t st) {
+  hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, (SvWs*)work, (int)(sizeof(SvWs) / 4));
+  return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}
+
+int tc_solve_status(const void* work, hipStream_t st, int32_t* error) {
+  SvWs h;
+  if (hipMemcpyAsync(&h, work, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  *error = h.error;
+  return 0;
+}
+
+int64_t tc_solve_status_offset() { return (int64_t)offsetof(SvWs, error); }
 
 int64_t tc_solve_inv_bytes(int64_t n) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * SV_NB * 8; }
 
@@ -983,7 +1006,7 @@ int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* D
   SvWs* ws = (SvWs*)work;
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
     const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
     hipLaunchKernelGGL(sv_fwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
                        wait_ticks);
     hipLaunchKernelGGL(sv_bwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
@@ -998,7 +1021,7 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
   SvWs* ws = (SvWs*)work;
   if (nrhs <= 2) {  // measured faster for one or two right-hand sides
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
     const int64_t ngf = (nb + SV_GROUP_F - 1) / SV_GROUP_F, ngb = (nb + SV_GROUP_B - 1) / SV_GROUP_B;
     hipLaunchKernelGGL((sv_forward<SV_RC_SMALL, SV_GROUP_F>), dim3((unsigned)ngf), dim3(SV_THREADS), 0, st, L, lda, n,
                        B, nrhs, ldb, ws, wait_ticks);
@@ -1008,7 +1031,7 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
     const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
     hipLaunchKernelGGL(sv_fwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,
                        wait_ticks);
     hipLaunchKernelGGL(sv_bwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,

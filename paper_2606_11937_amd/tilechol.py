@@ -22,6 +22,7 @@ CHOL_EINVAL = -1
 CHOL_EDEVICE = -2
 CHOL_EWORKSPACE = -3
 CHOL_ETIMEOUT = -4
+CHOL_ESTALLED = -5
 CHOL_SCHED_FORK_JOIN = 0
 CHOL_SCHED_ASYNC_DAG = 1
 CHOL_SCHED_FORK_JOIN_NAIVE = 2
@@ -56,6 +57,7 @@ SIGNATURES = [
     ("chol_factor_info", _int, [_vp, _vp, _pi64]),
     ("chol_solve_workspace_size", _i64, [_i64, _i64, _i64]),
     ("chol_solve", _int, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp]),
+    ("chol_solve_info", _int, [_vp, _vp]),
     ("chol_factor_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
     ("chol_factor_batched", _int, [ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp, _i64, _vp, _pi64]),
     ("chol_factor_solve_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
@@ -205,6 +207,15 @@ def chol_solve(L, B, T: int, n: int | None = None, work=None, stream=None) -> No
                         ctypes.c_void_p(wptr), wbytes, _stream(stream))
     if st != CHOL_OK:
         raise TileCholError(st, "chol_solve", last_bad_arg())
+
+
+def chol_solve_info(work, stream=None) -> int:
+    """Status of the last chol_solve with this workspace: CHOL_OK or
+    CHOL_ETIMEOUT (synchronises the stream)."""
+    st = lib.chol_solve_info(ctypes.c_void_p(work.data_ptr()), _stream(stream))
+    if st not in (CHOL_OK, CHOL_ETIMEOUT):
+        raise TileCholError(st, "chol_solve_info", last_bad_arg())
+    return st
 
 
 # -------------------------------------------------------- mixed precision
@@ -386,7 +397,7 @@ class Server:
         eta, lat, info = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int64(0)
         st = lib.chol_server_wait(self.h, rid, float(timeout), X.ctypes.data_as(ctypes.c_void_p) if want_x else None,
                                   ctypes.byref(eta), ctypes.byref(lat), ctypes.byref(info))
-        if st < 0 and st not in (CHOL_EWORKSPACE, CHOL_ETIMEOUT):
+        if st < 0 and st not in (CHOL_EWORKSPACE, CHOL_ETIMEOUT, CHOL_ESTALLED):
             raise TileCholError(st, "chol_server_wait", last_bad_arg())
         return st, X, eta.value, lat.value, info.value
 
@@ -444,7 +455,8 @@ def chol_dag_forkjoin_update(n: int, T: int, J: int):
     return out
 
 
-TIMING_KINDS = {"potrf": 1, "trsm": 2, "update": 4, "panel": 8, "persistent": 16}
+TIMING_KINDS = {"potrf": 1, "trsm": 2, "update": 4, "panel": 8, "persistent": 16, "update_rest": 32}
+_TIMING_NAMES = ("potrf", "trsm", "update", "panel", "persistent", "update_rest")
 
 
 def chol_timing_enable(kinds) -> int:
@@ -458,14 +470,15 @@ def chol_timing_enable(kinds) -> int:
 def chol_timing_read(stream=None):
     """Summed device milliseconds and launch counts per kernel kind recorded
     since the last read: {"potrf": (ms, n), "trsm": ..., "update": ...,
-    "panel": ..., "persistent": ...}.  Synchronises the stream."""
-    ms = (ctypes.c_double * 5)()
-    cnt = (ctypes.c_int64 * 5)()
+    "panel": ..., "persistent": ..., "update_rest": ...}.  Synchronises the
+    stream."""
+    k = len(_TIMING_NAMES)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
     st = lib.chol_timing_read(_stream(stream), ms, cnt)
     if st != CHOL_OK:
         raise TileCholError(st, "chol_timing_read", last_bad_arg())
-    names = ("potrf", "trsm", "update", "panel", "persistent")
-    return {names[k]: (float(ms[k]), int(cnt[k])) for k in range(5)}
+    return {_TIMING_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(k)}
 
 
 def chol_async_grid() -> int:

@@ -305,23 +305,32 @@ def test_solve_small_rhs_groups(tc, n, nrhs):
 @pytest.mark.parametrize("nrhs", [1, 20])
 def test_solve_wait_limit_never_hangs(tc, nrhs):
     """With a zero dependency-wait limit the sweeps give up their waits: the
-    call must return and the stream drain (B is then unspecified).  With the
-    limit restored the same solve must be right, on a fresh workspace."""
+    call must return, the stream drain, and chol_solve_info must report
+    CHOL_ETIMEOUT (B is then unspecified) -- or CHOL_OK with a correct B if
+    no block ever had to wait.  The status survives the per-group counter
+    resets of the 20-column case.  With the limit restored, the same
+    workspace must give a correct solve and report CHOL_OK."""
     import torch
     n = 1000
     A = inputs.gg_plus_identity(n, seed=71)
     Lref, _ = oracle.potrf(A)
     B = np.random.default_rng(72).standard_normal((n, nrhs))
     Lg = torch.from_numpy(np.ascontiguousarray(np.tril(Lref))).cuda()
+    work = torch.empty(tc.chol_solve_workspace_size(n, 128, nrhs), dtype=torch.uint8, device="cuda")
     prev = tc.chol_set_wait_limit(0.0)
     try:
         Bg = torch.from_numpy(B).cuda()
-        tc.chol_solve(Lg, Bg, 128)
-        torch.cuda.synchronize()
+        tc.chol_solve(Lg, Bg, 128, work=work)
+        status = tc.chol_solve_info(work)
     finally:
         tc.chol_set_wait_limit(prev)
+    say(f"zero wait limit solve nrhs={nrhs}: status {status}")
+    assert status in (tc.CHOL_OK, tc.CHOL_ETIMEOUT)
+    if status == tc.CHOL_OK:
+        assert oracle.backward_error(A, Bg.cpu().numpy(), B) <= ETA_TOL
     Bg = torch.from_numpy(B).cuda()
-    tc.chol_solve(Lg, Bg, 128)
+    tc.chol_solve(Lg, Bg, 128, work=work)
+    assert tc.chol_solve_info(work) == tc.CHOL_OK
     X = Bg.cpu().numpy()
     assert oracle.backward_error(A, X, B) <= ETA_TOL
 
