@@ -143,6 +143,27 @@ int64_t chol_factor_workspace_size(int64_t n, int64_t T, int sched);
 int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched,
                 void* work, int64_t work_bytes, void* stream, int64_t* info);
 
+/* chol_factor for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same factorization, bit for bit, with the workspace taken from a
+ * fixed array that the library keeps in each device's memory
+ * (CHOL_NOALLOC_WORKSPACE bytes per device, held until the process ends)
+ * instead of a caller's buffer.  The call allocates and frees nothing.
+ *   A, n, lda, T, stream, info   as for chol_factor.
+ *   sched      CHOL_SCHED_FORK_JOIN or CHOL_SCHED_ASYNC_DAG, optionally ORed
+ *              with CHOL_SCHED_NOOP; other schedules give CHOL_EINVAL
+ *              naming sched.
+ * A problem whose workspace (chol_factor_workspace_size) exceeds
+ * CHOL_NOALLOC_WORKSPACE returns CHOL_EWORKSPACE naming n (argument 2)
+ * before anything is enqueued; with T >= 128 every n up to 131072 fits.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (concurrent streams or threads) race and must be ordered by
+ * the caller.  The array's contents are cleared on the stream at the start
+ * of each call.  With info == NULL the call is fully stream-ordered and its
+ * outcome is not reported. */
+#define CHOL_NOALLOC_WORKSPACE ((4 << 20) + (64 << 10))
+int chol_factor_noalloc(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* stream, int64_t* info);
+
 /* Read the outcome of the last chol_factor enqueued with this workspace:
  * synchronises `stream`, stores info as above, and returns CHOL_OK,
  * CHOL_NOT_SPD or CHOL_ETIMEOUT. */

@@ -19,6 +19,7 @@
 static_assert(CHOL_PREC_FP64 == TC_PREC_FP64 && CHOL_PREC_FP32 == TC_PREC_FP32 && CHOL_PREC_BF16 == TC_PREC_BF16,
               "precision codes of the ABI and the kernels differ");
 static_assert(CHOL_BLOCK == TC_BLK, "sub-block size of the ABI and the kernels differ");
+static_assert(CHOL_NOALLOC_WORKSPACE == TC_SCRATCH_BYTES, "no-allocation workspace sizes of the ABI and the library differ");
 static_assert(CHOL_UNIT_POTRF == TC_UNIT_POTRF && CHOL_UNIT_TRSM == TC_UNIT_TRSM &&
                   CHOL_UNIT_UPDATE == TC_UNIT_UPDATE && CHOL_UNIT_PANEL == TC_UNIT_PANEL,
               "unit kinds of the ABI and the kernels differ");
@@ -125,6 +126,33 @@ int chol_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* w
   int64_t grid = 0;
   if ((sched & 0xff) == CHOL_SCHED_ASYNC_DAG || (sched & 0xff) == CHOL_SCHED_TASK_SYNC) {
     grid = (sched & 0xff) == CHOL_SCHED_ASYNC_DAG ? tc_async_grid_size() : tc_sync_grid_size();
+    if (grid <= 0) return CHOL_EDEVICE;
+  }
+  if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks(), tc_lookahead_chunk(grid, g_lookahead.load())) != 0)
+    return CHOL_EDEVICE;
+  if (info == nullptr) return CHOL_OK;
+  int32_t err = 0;
+  int64_t dinfo = 0;
+  if (tc_read_status(work, st, &err, &dinfo) != 0) return CHOL_EDEVICE;
+  return status_from(err, dinfo, info);
+}
+
+int chol_factor_noalloc(double* A, int64_t n, int64_t lda, int64_t T, int sched, void* stream, int64_t* info) {
+  g_bad_arg = 0;
+  if (int e = check_factor_args(A, n, lda, T, sched)) return e;
+  const int base = sched & 0xff;
+  if (base != CHOL_SCHED_FORK_JOIN && base != CHOL_SCHED_ASYNC_DAG) return bad(5);
+  if (n == 0) {
+    if (info) *info = 0;
+    return CHOL_OK;
+  }
+  if (tc_ws_bytes(n, T) > tc_scratch_bytes()) return bad(2, CHOL_EWORKSPACE);
+  void* work = tc_scratch_ptr();
+  if (work == nullptr) return CHOL_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t grid = 0;
+  if (base == CHOL_SCHED_ASYNC_DAG) {
+    grid = tc_async_grid_size();
     if (grid <= 0) return CHOL_EDEVICE;
   }
   if (tc_launch_factor(A, n, lda, T, sched, work, st, grid, wait_ticks(), tc_lookahead_chunk(grid, g_lookahead.load())) != 0)

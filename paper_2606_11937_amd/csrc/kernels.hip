@@ -1472,3 +1472,33 @@ int64_t tc_sync_grid_size() {
   static int64_t cached[64] = {0};
   return tc_persistent_grid(tc_sync, cached);
 }
+
+// ------------------------------------------ factorization without allocation
+// A fixed device-resident workspace for callers that cannot allocate device
+// memory (HIP graph capture, tight serving loops): each device holds its own
+// copy of this array for the life of the process.  Host code never uses the
+// array's name as an address: the address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.  The factorization clears
+// the part it uses with a fill kernel before every run, so a call needs no
+// state from the previous one; calls that overlap on one device share the
+// array and race.
+static __device__ __align__(256) char scratch[TC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+}  // namespace
+
+int64_t tc_scratch_bytes() { return TC_SCRATCH_BYTES; }
+
+void* tc_scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}

@@ -14,6 +14,12 @@ inline int64_t tc_default_tile(int64_t n) { return n <= 8192 ? 128 : 1024; }
 
 // Workspace bytes chol_factor needs (every schedule uses one layout).
 int64_t tc_ws_bytes(int64_t n, int64_t T);
+// The device-resident factorization workspace of chol_factor_noalloc: its
+// size, and its address on the current device (looked up once per device;
+// nullptr on a runtime error).
+#define TC_SCRATCH_BYTES ((4 << 20) + (64 << 10))
+int64_t tc_scratch_bytes();
+void* tc_scratch_ptr();
 // Enqueue one factorization.  sched_flags: schedule 0 fork-join, 1 async
 // DAG, 2 naive fork-join, 3 synchronous tasking, 4 fork-join with lookahead,
 // 5 HIP-graph DAG, optionally ORed with

@@ -55,6 +55,7 @@ SIGNATURES = [
     ("chol_factor_workspace_size", _i64, [_i64, _i64, _int]),
     ("chol_factor", _int, [_vp, _i64, _i64, _i64, _int, _vp, _i64, _vp, _pi64]),
     ("chol_factor_info", _int, [_vp, _vp, _pi64]),
+    ("chol_factor_noalloc", _int, [_vp, _i64, _i64, _i64, _int, _vp, _pi64]),
     ("chol_solve_workspace_size", _i64, [_i64, _i64, _i64]),
     ("chol_solve", _int, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp]),
     ("chol_solve_info", _int, [_vp, _vp]),
@@ -172,6 +173,20 @@ def chol_factor(A, T: int, sched="fork_join", n: int | None = None, work=None, s
                          ctypes.byref(info) if sync else None)
     if st not in (CHOL_OK, CHOL_NOT_SPD):
         raise TileCholError(st, "chol_factor", last_bad_arg())
+    return int(info.value) if sync else None
+
+
+def chol_factor_noalloc(A, T: int, sched="fork_join", n: int | None = None, stream=None, sync: bool = True) -> int:
+    """chol_factor with the library's fixed device workspace (no allocation by
+    the library or here).  Returns info when sync."""
+    _check_matrix(A)
+    n = A.shape[0] if n is None else n
+    lda = A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1])
+    info = ctypes.c_int64(0)
+    st = lib.chol_factor_noalloc(ctypes.c_void_p(A.data_ptr()), n, lda, T, _sched(sched), _stream(stream),
+                                 ctypes.byref(info) if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD):
+        raise TileCholError(st, "chol_factor_noalloc", last_bad_arg())
     return int(info.value) if sync else None
 
 
