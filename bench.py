@@ -423,15 +423,46 @@ def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
         e1.record(st)
         torch.cuda.synchronize()
         loop.append(e0.elapsed_time(e1))
+    # the FP32 variant: FP32 trailing products, the originals kept, every
+    # solution refined in FP64 to eta <= 1e-12 inside the same launch
+    Ls32 = [torch.empty_like(A) for A in As]
+    wm = torch.empty(tc.chol_factor_solve_batched_mixed_workspace_size(sizes, None, ["fp32"] * len(sizes)),
+                     dtype=torch.uint8, device="cuda")
+    fp32 = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(st)
+        tc.chol_factor_solve_batched_mixed(As, Ls32, Bs, Xs, precs=["fp32"] * len(sizes), tol=1e-12, max_iter=10,
+                                           work=wm, stream=st, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        if r:
+            fp32.append(e0.elapsed_time(e1))
+    inf32, it32, eta32 = tc.chol_factor_solve_batched_mixed(As, Ls32, Bs, Xs, precs=["fp32"] * len(sizes),
+                                                            tol=1e-12, max_iter=10, work=wm, stream=st)
+    worst32 = 0.0
+    for A, x, b in zip(As, Xs, Bs):
+        r_ = b - A @ x
+        den = A.abs().sum(dim=1).max() * x.abs().max() + b.abs().max()
+        worst32 = max(worst32, (r_.abs().max() / den).item())
+    del Ls32, wm
     flops = sum(n ** 3 / 3 for n in sizes)
     floor_ms = sum(max(n ** 3 / 3 / (FP64_MFMA_PEAK_TFLOPS * 1e12), 8.0 * n * n / 8e12) for n in sizes) * 1e3
     t1 = statistics.median(one)
     tl = min(loop)
+    t32 = statistics.median(fp32)
     out = {"count": count, "n_min": min(sizes), "n_max": nmax, "n_median": int(statistics.median(sizes)),
            "flops": flops, "one_launch_ms": round(t1, 3), "one_launch_tflops": round(flops / (t1 * 1e-3) / 1e12, 3),
            "loop_ms": round(tl, 3), "speedup_vs_loop": round(tl / t1, 2), "floor_ms": round(floor_ms, 3),
            "frac_of_floor": round(floor_ms / t1, 4), "worst_eta": worst,
-           "all_factored": all(i == 0 for i in infos)}
+           "all_factored": all(i == 0 for i in infos),
+           "fp32": {"one_launch_ms": round(t32, 3), "one_launch_tflops": round(flops / (t32 * 1e-3) / 1e12, 3),
+                    "speedup_vs_fp64_launch": round(t1 / t32, 3), "speedup_vs_loop": round(tl / t32, 2),
+                    "frac_of_floor": round(floor_ms / t32, 4), "worst_eta": worst32,
+                    "reported_eta_max": max(eta32), "corrections_max": max(it32),
+                    "corrections_mean": round(sum(it32) / len(it32), 3), "all_factored": all(i == 0 for i in inf32),
+                    "what": "FP32 trailing products, originals kept, FP64 refinement to 1e-12 in the same launch"}}
     del As, Bs, Ls, Xs, work, wf, ws
     torch.cuda.empty_cache()
     return out

@@ -307,10 +307,42 @@ int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t*
                               int64_t batch, const int64_t* T, void* work, int64_t work_bytes,
                               void* stream, int64_t* info);
 
+/* The same launch with a per-matrix precision of the trailing products and
+ * a refined solve (the mixed-precision extension of the tile loop, Fig. 1,
+ * applied to a batch): matrix i is factored into L[i] from its original
+ * A[i], which stays untouched, with its SYRK/GEMM products formed from panel
+ * entries rounded once to FP32 and summed in FP32 (prec[i] =
+ * CHOL_PREC_FP32; POTRF and TRSM stay FP64) or in FP64 (CHOL_PREC_FP64),
+ * and its solve unit then computes x_i = (L L^T)^-1 b_i and refines it,
+ * x_i += (L L^T)^-1 (b_i - A_i x_i) in FP64, until the backward error
+ * ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf) is <= tol or max_iter
+ * corrections were applied.
+ *   A, B    host arrays of device pointers: the originals (lower triangle of
+ *           A[i] read, lda[i]; b_i of n[i] contiguous doubles), read only.
+ *   L, X    host arrays of device pointers: the factor (lower triangle of
+ *           L[i] written, ldl[i]; L[i] must differ from A[i]) and x_i (n[i]
+ *           contiguous doubles).
+ *   T       host array of tile sides or NULL (chol_batched_tile(n, prec));
+ *           an FP32 matrix of more than one tile needs T % 4 == 0.
+ *   prec    host array of CHOL_PREC_FP64 / CHOL_PREC_FP32, or NULL (FP64).
+ *   info    host array or NULL as for chol_factor_batched; iters, eta: host
+ *           arrays (or NULL) of the corrections applied and the final
+ *           backward error per matrix, filled only when info != NULL.
+ * Returns CHOL_OK, CHOL_NOT_SPD, CHOL_ETIMEOUT, CHOL_NOT_CONVERGED (a
+ * matrix ended above tol), or a negative error code. */
+int64_t chol_factor_solve_batched_mixed_workspace_size(int64_t batch, const int64_t* n, const int64_t* T,
+                                                       const int* prec);
+int chol_factor_solve_batched_mixed(const double* const* A, double* const* L, const double* const* B,
+                                    double* const* X, const int64_t* n, const int64_t* lda, const int64_t* ldl,
+                                    int64_t batch, const int64_t* T, const int* prec, double tol, int64_t max_iter,
+                                    void* work, int64_t work_bytes, void* stream, int64_t* info, int64_t* iters,
+                                    double* eta);
+
 /* Tile side a batched call uses for a matrix of order n when the caller
- * passes none: a table measured by an offline sweep over n-buckets
- * (paper_2606_11937_amd/tune_batched.py), deterministic in (n, prec).  Only
- * CHOL_PREC_FP64 is offered; < 0 on invalid arguments. */
+ * passes none: tables measured by an offline sweep over n-buckets for each
+ * precision of the trailing products (paper_2606_11937_amd/tune_batched.py),
+ * deterministic in (n, prec); prec is CHOL_PREC_FP64 or CHOL_PREC_FP32; < 0
+ * on invalid arguments. */
 int64_t chol_batched_tile(int64_t n, int prec);
 
 /* ---- serving with continuous batching ----------------------------------

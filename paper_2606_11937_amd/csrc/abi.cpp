@@ -277,9 +277,10 @@ int chol_solve_refine(const double* A, int64_t lda, const double* L, int64_t ldl
 }
 
 int64_t chol_batched_tile(int64_t n, int prec) {
-  if (prec != CHOL_PREC_FP64) return bad(2);
+  g_bad_arg = 0;
+  if (prec != CHOL_PREC_FP64 && prec != CHOL_PREC_FP32) return bad(2);
   if (n < 0) return bad(1);
-  return tc_tuned_batched_tile(n);
+  return tc_tuned_batched_tile_prec(n, prec);
 }
 
 namespace {
@@ -372,6 +373,114 @@ int chol_factor_solve_batched(double* const* A, double* const* B, const int64_t*
     return CHOL_EINVAL;
   }
   return batched_run(A, B, n, lda, batch, T, work, work_bytes, stream, info, 1, 2, 3, 4, 5, 6, 7, 8);
+}
+
+namespace {
+// per-matrix precision and tile side of a mixed batched call (given, or the
+// tuned choice per (n, precision))
+bool mixed_plan(int64_t batch, const int64_t* n, const int64_t* T, const int* prec, std::vector<int32_t>& p,
+                std::vector<int64_t>& t) {
+  p.resize(batch);
+  t.resize(batch);
+  for (int64_t i = 0; i < batch; ++i) {
+    p[i] = prec ? prec[i] : CHOL_PREC_FP64;
+    if (p[i] != CHOL_PREC_FP64 && p[i] != CHOL_PREC_FP32) return false;
+    t[i] = T ? T[i] : tc_tuned_batched_tile_prec(n[i] > 0 ? n[i] : 1, p[i]);
+  }
+  return true;
+}
+bool mixed_tiles_ok(int64_t batch, const int64_t* n, const std::vector<int32_t>& p, const std::vector<int64_t>& t) {
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] <= 0) continue;
+    if (t[i] < 1 || tc_cdiv(n[i], t[i]) > CHOL_ASYNC_MAX_TILES) return false;
+    // the FP32 panel copy is read in 16-byte pieces from column J T on
+    if (p[i] == CHOL_PREC_FP32 && t[i] < n[i] && t[i] % 4 != 0) return false;
+  }
+  return true;
+}
+}  // namespace
+
+int64_t chol_factor_solve_batched_mixed_workspace_size(int64_t batch, const int64_t* n, const int64_t* T,
+                                                       const int* prec) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(1);
+  if (batch > 0 && n == nullptr) return bad(2);
+  for (int64_t i = 0; i < batch; ++i)
+    if (n[i] < 0 || n[i] > kMaxN) return bad(2);
+  std::vector<int32_t> p;
+  std::vector<int64_t> t;
+  if (!mixed_plan(batch, n, T, prec, p, t)) return bad(4);
+  if (!mixed_tiles_ok(batch, n, p, t)) return bad(3);
+  return tc_batched_ws_bytes(batch, n, t.data(), 1, batch_chunk(), p.data(), true);
+}
+
+int chol_factor_solve_batched_mixed(const double* const* A, double* const* L, const double* const* B,
+                                    double* const* X, const int64_t* n, const int64_t* lda, const int64_t* ldl,
+                                    int64_t batch, const int64_t* T, const int* prec, double tol, int64_t max_iter,
+                                    void* work, int64_t work_bytes, void* stream, int64_t* info, int64_t* iters,
+                                    double* eta) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(8);
+  if (!(tol > 0.0)) return bad(11);
+  if (max_iter < 0) return bad(12);
+  if (batch == 0) return CHOL_OK;
+  if (A == nullptr) return bad(1);
+  if (L == nullptr) return bad(2);
+  if (B == nullptr) return bad(3);
+  if (X == nullptr) return bad(4);
+  if (n == nullptr) return bad(5);
+  if (lda == nullptr) return bad(6);
+  if (ldl == nullptr) return bad(7);
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n[i] < 0 || n[i] > kMaxN) return bad(5);
+    if (lda[i] < max1(n[i]) || lda[i] > kMaxN) return bad(6);
+    if (ldl[i] < max1(n[i]) || ldl[i] > kMaxN) return bad(7);
+    if (n[i] == 0) continue;
+    if (A[i] == nullptr) return bad(1);
+    if (L[i] == nullptr || (const double*)L[i] == A[i]) return bad(2);  // the original stays for the residuals
+    if (B[i] == nullptr) return bad(3);
+    if (X[i] == nullptr) return bad(4);
+  }
+  std::vector<int32_t> p;
+  std::vector<int64_t> t;
+  if (!mixed_plan(batch, n, T, prec, p, t)) return bad(10);
+  if (!mixed_tiles_ok(batch, n, p, t)) return bad(9);
+  const int64_t chunk = batch_chunk();
+  const int64_t need = tc_batched_ws_bytes(batch, n, t.data(), 1, chunk, p.data(), true);
+  if (work == nullptr) return bad(13);
+  if (work_bytes < need) return bad(14, CHOL_EWORKSPACE);
+  const int64_t grid = tc_batched_grid_size();
+  if (grid <= 0) return CHOL_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  TcBatchMixed mx;
+  mx.prec = p.data();
+  mx.A0 = A;
+  mx.lda0 = lda;
+  mx.b0 = B;
+  mx.tol = tol;
+  mx.max_iter = max_iter;
+  if (tc_launch_batched(L, X, n, ldl, t.data(), batch, work, st, grid, wait_ticks(), chunk, nullptr, nullptr, &mx) != 0)
+    return CHOL_EDEVICE;
+  if (info == nullptr) return CHOL_OK;
+  std::vector<int32_t> err(batch);
+  std::vector<int64_t> dinfo(batch);
+  if (tc_read_batched_status(work, batch, st, err.data(), dinfo.data()) != 0) return CHOL_EDEVICE;
+  std::vector<double> e(batch);
+  std::vector<int64_t> it(batch);
+  if (tc_read_batched_stats(work, batch, n, t.data(), chunk, p.data(), st, e.data(), it.data()) != 0)
+    return CHOL_EDEVICE;
+  int worst = CHOL_OK;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int s = status_from(err[i], dinfo[i], &info[i]);
+    if (n[i] <= 0) info[i] = 0;
+    const bool solved = n[i] <= 0 || s == CHOL_OK;
+    if (iters) iters[i] = n[i] > 0 && solved ? it[i] : 0;
+    if (eta) eta[i] = n[i] > 0 && solved ? e[i] : 0.0;
+    if (s == CHOL_ETIMEOUT) worst = CHOL_ETIMEOUT;
+    else if (s != CHOL_OK && worst == CHOL_OK) worst = s;
+    else if (s == CHOL_OK && worst == CHOL_OK && n[i] > 0 && !(e[i] <= tol)) worst = CHOL_NOT_CONVERGED;
+  }
+  return worst;
 }
 
 // ---------------------------------------------------------------- serving

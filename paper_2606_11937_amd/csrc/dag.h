@@ -291,3 +291,44 @@ TC_HD void tc_task_counts(const TcGeom& g, int64_t c[4]) {
   c[3] = M * (M - 1) * (M - 2) / 6;
 }
 
+
+// ---- dependency counters (the asynchronous schedule and the batched launch)
+// pdone[r]     sub-columns of block row r finished (they finish in order:
+//              the POTRF or TRSM of sub-column s is the (s+1)-th);
+// ver[r][c]    updates applied to block (r, c): the trailing updates of
+//              steps 0, 1, ... and then, inside its own panel, the panel
+//              updates of sub-columns 0, 1, ....
+// `ld(p)` reads a counter (an atomic load on the device, a plain read in the
+// host emulation) and `add(p)` increments one.
+template <typename Ld>
+TC_HD bool tc_unit_ready_with(const TcGeom& g, const int32_t* pdone, const int32_t* ver, const TcUnit& u, Ld ld) {
+  const int64_t NRB = g.NRB;
+  if (u.kind == TC_UNIT_UPDATE) {
+    const int32_t gi = tc_gid(g, u.I, u.a), gk = tc_gid(g, u.K, u.b);
+    const int32_t need = tc_gid(g, u.J, 0) + tc_sb(g, u.J);  // whole panel J finished
+    return ld(pdone + gi) >= need && ld(pdone + gk) >= need && ld(ver + gi * NRB + gk) >= u.J;
+  }
+  if (u.kind == TC_UNIT_PANEL) {
+    const int32_t gs = tc_gid(g, u.J, u.K), gt = tc_gid(g, u.J, u.b), gi = tc_gid(g, u.I, u.a);
+    return ld(pdone + gi) > gs && ld(pdone + gt) > gs && ld(ver + gi * NRB + gt) >= u.J + u.K;
+  }
+  if (u.kind == TC_UNIT_TRSM) {
+    const int32_t gs = tc_gid(g, u.J, u.K), gi = tc_gid(g, u.I, u.a);
+    return ld(pdone + gs) > gs && ld(ver + gi * NRB + gs) >= u.J + u.K;
+  }
+  const int32_t gs = tc_gid(g, u.J, u.a);
+  return ld(ver + (int64_t)gs * NRB + gs) >= u.J + u.a;
+}
+
+template <typename Add>
+TC_HD void tc_unit_publish_with(const TcGeom& g, int32_t* pdone, int32_t* ver, const TcUnit& u, Add add) {
+  if (u.kind == TC_UNIT_UPDATE) {
+    add(ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.K, u.b));
+  } else if (u.kind == TC_UNIT_PANEL) {
+    add(ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.J, u.b));
+  } else if (u.kind == TC_UNIT_TRSM) {
+    add(pdone + tc_gid(g, u.I, u.a));
+  } else {
+    add(pdone + tc_gid(g, u.J, u.a));
+  }
+}

@@ -27,33 +27,17 @@
 #include <tuple>
 #include <vector>
 
+#include "batch_plan.h"
 #include "dag.h"
 #include "launch.h"
 #include "tile_ops.h"
 #include "tile_ops_lp.h"
 
 // ---------------------------------------------------------------- workspace
-// [0, 256)              TcWsHeader
+// [0, 256)              TcWsHeader (batch_plan.h)
 // [256, +8*(M+1))       phase offsets (async only), rounded to 256 bytes
 // then int32 pdone[NRB] (panel columns finalised per row block)
 // then int32 ver[NRB*NRB] (updates applied per output block)
-struct TcWsHeader {
-  int32_t ticket;
-  int32_t error;  // 0 ok, 1 not SPD, 2 dependency-wait timeout
-  int64_t info;   // failing global column + 1
-  int32_t bar;    // arrivals at the grid barriers of the synchronous schedule
-};
-
-struct TcWs {
-  TcWsHeader* hdr;
-  int64_t* offs;
-  int32_t* pdone;
-  int32_t* ver;
-  int32_t noop;  // measurement mode: run the schedule with empty unit bodies
-};
-
-static inline int64_t tc_round256(int64_t x) { return (x + 255) & ~(int64_t)255; }
-
 int64_t tc_ws_bytes(int64_t n, int64_t T) {
   TcGeom g = tc_geom(n, T, 0);
   int64_t b = 256;
@@ -363,42 +347,20 @@ __global__ __launch_bounds__(TC_THREADS) void tc_unscale_lower(double* A, int64_
 // ------------------------------------------------------- persistent kernel
 #define TC_MAX_PHASES 1024
 
-// Dependency test of unit u (see dag.h): all reads are relaxed agent-scope
-// atomics; the caller issues the acquire fence once the unit is ready.
-//   pdone[r]     finished sub-columns of block row r (they finish in order),
-//   ver[r][c]    updates applied to block (r, c) (trailing ones of steps
-//                0, 1, ..., then the panel ones of sub-columns 0, 1, ...).
+// Dependency test and completion of unit u (the counter rules are in dag.h):
+// the counters are read with relaxed agent-scope atomic loads (the caller
+// issues the acquire fence once the unit is ready) and incremented with
+// relaxed agent-scope atomic adds (after the workgroup's release fence).
 __device__ __forceinline__ bool tc_unit_ready(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
-  auto ld = [](const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  const int64_t NRB = g.NRB;
-  if (u.kind == TC_UNIT_UPDATE) {
-    const int32_t gi = tc_gid(g, u.I, u.a), gk = tc_gid(g, u.K, u.b);
-    const int32_t need = tc_gid(g, u.J, 0) + tc_sb(g, u.J);  // whole panel J finished
-    return ld(ws.pdone + gi) >= need && ld(ws.pdone + gk) >= need && ld(ws.ver + gi * NRB + gk) >= u.J;
-  }
-  if (u.kind == TC_UNIT_PANEL) {
-    const int32_t gs = tc_gid(g, u.J, u.K), gt = tc_gid(g, u.J, u.b), gi = tc_gid(g, u.I, u.a);
-    return ld(ws.pdone + gi) > gs && ld(ws.pdone + gt) > gs && ld(ws.ver + gi * NRB + gt) >= u.J + u.K;
-  }
-  if (u.kind == TC_UNIT_TRSM) {
-    const int32_t gs = tc_gid(g, u.J, u.K), gi = tc_gid(g, u.I, u.a);
-    return ld(ws.pdone + gs) > gs && ld(ws.ver + gi * NRB + gs) >= u.J + u.K;
-  }
-  const int32_t gs = tc_gid(g, u.J, u.a);
-  return ld(ws.ver + (int64_t)gs * NRB + gs) >= u.J + u.a;
+  return tc_unit_ready_with(g, ws.pdone, ws.ver, u, [](const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  });
 }
 
 __device__ __forceinline__ void tc_unit_publish(const TcGeom& g, const TcWs& ws, const TcUnit& u) {
-  auto add = [](int32_t* p) { __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  if (u.kind == TC_UNIT_UPDATE) {
-    add(ws.ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.K, u.b));
-  } else if (u.kind == TC_UNIT_PANEL) {
-    add(ws.ver + (int64_t)tc_gid(g, u.I, u.a) * g.NRB + tc_gid(g, u.J, u.b));
-  } else if (u.kind == TC_UNIT_TRSM) {
-    add(ws.pdone + tc_gid(g, u.I, u.a));
-  } else {
-    add(ws.pdone + tc_gid(g, u.J, u.a));
-  }
+  tc_unit_publish_with(g, ws.pdone, ws.ver, u, [](int32_t* p) {
+    __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  });
 }
 
 // Loop-invariant launch state of the persistent kernel that is not a pointer.
@@ -518,43 +480,14 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 // the same depth of all matrices sit together: the grid finds ready work
 // while every matrix's chain advances.  A matrix whose factorization fails is
 // skipped from then on; the others are unaffected.
-#define TC_UNIT_SOLVE 4
-
-struct TcBatchMat {
-  double* A;
-  double* b;  // right-hand sides (n x nrhs row-major, leading dimension ldb) or null
-  int64_t lda;
-  int64_t nrhs, ldb;
-  TcGeom g;
-  TcWs ws;        // per-matrix status header and counters
-  int32_t* done;  // factor units finished
-  int64_t nunits;
-};
-struct TcBatchUnit {
-  int32_t m, kind, J, I, a, K, b, pad;
-};
-struct TcBatchSlot {
-  int32_t m, P;   // P < 0: the solve unit
-  int64_t start;  // first global ticket
-  int64_t pos;    // first position inside phase P of matrix m
-  int64_t size;
-};
+// (descriptor, unit and slot records: batch_plan.h)
 
 __global__ __launch_bounds__(TC_THREADS) void tc_batch_units(const TcBatchMat* __restrict__ mats,
                                                              const TcBatchSlot* __restrict__ slots,
                                                              TcBatchUnit* __restrict__ table) {
   const TcBatchSlot sl = slots[blockIdx.x];
   const TcGeom g = mats[sl.m].g;
-  for (int64_t r = threadIdx.x; r < sl.size; r += TC_THREADS) {
-    TcBatchUnit e;
-    if (sl.P < 0) {
-      e = {sl.m, TC_UNIT_SOLVE, 0, 0, 0, 0, 0, 0};
-    } else {
-      const TcUnit u = tc_decode_in_phase(g, sl.P, sl.pos + r);
-      e = {sl.m, u.kind, u.J, u.I, u.a, u.K, u.b, 0};
-    }
-    table[sl.start + r] = e;
-  }
+  for (int64_t r = threadIdx.x; r < sl.size; r += TC_THREADS) table[sl.start + r] = tc_batch_slot_unit(sl, g, r);
 }
 
 // ---- one-workgroup solve with one right-hand side, in place in b
@@ -646,10 +579,124 @@ __device__ __forceinline__ T* tc_global(T* p) {
   return (T*)(__attribute__((address_space(1))) T*)p;
 }
 
+// ---- one-workgroup residual r = b0 - A0 x of one matrix (A0 symmetric, its
+// lower triangle read), with the norms of the backward error.  Rows go in
+// 64-row blocks; for each block the 64 x 64 tiles of the symmetric matrix
+// are staged in LDS in column-block order (a tile above the diagonal is read
+// transposed from the lower triangle), and thread (row r, part p) sums its
+// 16 columns of every tile in order; the four parts are added in order
+// p = 0..3.  Deterministic.  Returns, in red[0..3] (LDS, after a barrier),
+// max |r_i|, max |x_i|, max |b0_i| and max_i sum_j |A0_ij|.
+struct TcResSmem {
+  double t[64][65];
+  double xs[64];
+  double part[4][64];
+  double apart[4][64];
+  double red[4][TC_THREADS];
+};
+
+__device__ __forceinline__ void tc_wg_residual(const double* __restrict__ A0, int64_t lda0, int64_t n,
+                                               const double* __restrict__ x, const double* __restrict__ b0,
+                                               double* __restrict__ r, TcResSmem& sm) {
+  const int tid = tc_tid(), rr = tid >> 2, p = tid & 3;
+  double rmax = 0.0, xmax = 0.0, bmax = 0.0, amax = 0.0;
+  for (int64_t R0 = 0; R0 < n; R0 += 64) {
+    double acc = 0.0, asum = 0.0;
+    for (int64_t C0 = 0; C0 < n; C0 += 64) {
+      if (tid < 64) sm.xs[tid] = C0 + tid < n ? x[C0 + tid] : 0.0;
+      for (int e = tid; e < 64 * 64; e += TC_THREADS) {
+        // coalesced: along the stored row of the lower triangle
+        const int i = C0 > R0 ? (e & 63) : (e >> 6), k = C0 > R0 ? (e >> 6) : (e & 63);
+        const int64_t gi = R0 + i, gj = C0 + k;
+        double v = 0.0;
+        if (gi < n && gj < n) v = gj <= gi ? A0[gi * lda0 + gj] : A0[gj * lda0 + gi];
+        sm.t[i][k] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const double v = sm.t[rr][16 * p + kk];
+        acc += v * sm.xs[16 * p + kk];
+        asum += fabs(v);
+      }
+      __syncthreads();
+    }
+    sm.part[p][rr] = acc;
+    sm.apart[p][rr] = asum;
+    __syncthreads();
+    if (p == 0 && R0 + rr < n) {
+      const int64_t i = R0 + rr;
+      const double sum = sm.part[0][rr] + sm.part[1][rr] + sm.part[2][rr] + sm.part[3][rr];
+      const double as = sm.apart[0][rr] + sm.apart[1][rr] + sm.apart[2][rr] + sm.apart[3][rr];
+      const double bi = b0[i], ri = bi - sum;
+      r[i] = ri;
+      rmax = fmax(rmax, fabs(ri));
+      xmax = fmax(xmax, fabs(x[i]));
+      bmax = fmax(bmax, fabs(bi));
+      amax = fmax(amax, as);
+    }
+    __syncthreads();
+  }
+  sm.red[0][tid] = rmax;
+  sm.red[1][tid] = xmax;
+  sm.red[2][tid] = bmax;
+  sm.red[3][tid] = amax;
+  __syncthreads();
+  if (tid < 4) {
+    double m = 0.0;
+    for (int t = 0; t < TC_THREADS; ++t) m = fmax(m, sm.red[tid][t]);
+    sm.red[tid][0] = m;
+  }
+  __syncthreads();
+}
+
 union alignas(512) TcBatchSmem {
   TcSmem f;
   TcSolveSmem s;
+  TcResSmem r;
 };
+
+// Solve with refinement of one matrix (one right-hand side, in place in x,
+// which holds b0 on entry): x = (L L^T)^-1 b0, then while the backward error
+// ||b0 - A0 x||_inf / (||A0||_inf ||x||_inf + ||b0||_inf) exceeds tol and
+// fewer than max_iter corrections were applied, x += (L L^T)^-1 (b0 - A0 x).
+// Writes {eta, corrections} to stat.
+__device__ __forceinline__ void tc_wg_solve_refine(const double* __restrict__ L, int64_t lda, int64_t n, double* x,
+                                                   const double* A0, int64_t lda0, const double* b0, double* R,
+                                                   double tol, int64_t max_iter, double* stat, TcBatchSmem& sm) {
+  tc_wg_solve(L, lda, n, x, 1, sm.s);
+  int64_t it = 0;
+  double eta = 0.0;
+  for (;;) {
+    tc_wg_residual(A0, lda0, n, x, b0, R, sm.r);
+    const double den = sm.r.red[3][0] * sm.r.red[1][0] + sm.r.red[2][0];
+    eta = tc_uniform(den > 0.0 ? sm.r.red[0][0] / den : 0.0);
+    __syncthreads();
+    if (!(eta > tol) || it >= max_iter) break;
+    tc_wg_solve(L, lda, n, R, 1, sm.s);
+    for (int64_t i = tc_tid(); i < n; i += TC_THREADS) x[i] = x[i] + R[i];
+    __syncthreads();
+    ++it;
+  }
+  if (tc_tid() == 0) {
+    stat[0] = eta;
+    stat[1] = (double)it;
+  }
+}
+
+// Round row block (I, a)'s finished panel strip of tile column J to FP32 into
+// P (same row and column indices, leading dimension ldp).  Called by the
+// workgroup that just ran the strip's last TRSM, after a barrier.
+__device__ __forceinline__ void tc_round_strip(const double* __restrict__ A, int64_t lda, const TcGeom& g,
+                                               int32_t J, int32_t I, int32_t a, float* __restrict__ P, int64_t ldp) {
+  const int64_t r0 = tc_row0(g, I, a), c0 = (int64_t)J * g.T;
+  const int mr = tc_rows(g, I, a);
+  const int64_t kd = tc_tdim(g, J);
+  for (int64_t e = tc_tid(); e < (int64_t)mr * kd; e += TC_THREADS) {
+    const int64_t rr = e / kd, k = e - rr * kd;
+    P[(r0 + rr) * ldp + c0 + k] = tc_round_lp<TC_PREC_FP32>(A[(r0 + rr) * lda + c0 + k]);
+  }
+}
 
 __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_batched(
     const TcBatchMat* __restrict__ mats, const TcBatchUnit* __restrict__ table, int64_t total, int32_t* ticket,
@@ -705,14 +752,32 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       const TcGeom cg = tc_ctx_geom(s_mat.g);
       double* A = tc_global(s_mat.A);
       const int64_t lda = tc_ctx64(s_mat.lda);
+      const int32_t prec = tc_ctx32(s_mat.prec);
       if (u.kind == TC_UNIT_UPDATE) {
-        tc_run_update(A, lda, cg, u, sm.f.upd);
+        if (prec == TC_PREC_FP32) {
+          const float* P = tc_global(s_mat.P);
+          const int64_t ldp = tc_ctx64(s_mat.ldp);
+          const int64_t ri = tc_row0(cg, u.I, u.a), rk = tc_row0(cg, u.K, u.b), cj = (int64_t)u.J * cg.T;
+          tc_update_block_lp<TC_PREC_FP32>(A + ri * lda + rk, P + ri * ldp + cj, P + rk * ldp + cj, lda, ldp,
+                                           tc_rows(cg, u.I, u.a), tc_rows(cg, u.K, u.b), (int)tc_tdim(cg, u.J),
+                                           ri == rk, sm.f.upd);
+        } else {
+          tc_run_update(A, lda, cg, u, sm.f.upd);
+        }
       } else if (u.kind == TC_UNIT_PANEL) {
         tc_run_panel(A, lda, cg, u, sm.f.upd);
       } else if (u.kind == TC_UNIT_TRSM) {
         tc_run_trsm(A, lda, cg, u.J, u.K, u.I, u.a, sm.f.trsm);
+        if (prec == TC_PREC_FP32 && u.K == tc_sb(cg, u.J) - 1 && u.I > u.J) {
+          __syncthreads();  // the strip's new block is visible to the whole workgroup
+          tc_round_strip(A, lda, cg, u.J, u.I, u.a, tc_global(s_mat.P), tc_ctx64(s_mat.ldp));
+        }
       } else if (u.kind == TC_UNIT_POTRF) {
         tc_run_potrf(A, lda, cg, u.J, u.a, tc_global(s_mat.ws.hdr), sm.f.potrf);
+      } else if (tc_ctx32(s_mat.refine)) {
+        tc_wg_solve_refine(A, lda, cg.n, tc_global(s_mat.b), tc_global(s_mat.A0), tc_ctx64(s_mat.lda0),
+                           tc_global(s_mat.b0), tc_global(s_mat.R), tc_uniform(s_mat.tol), tc_ctx64(s_mat.max_iter),
+                           tc_global(s_mat.stat), sm);
       } else {
         const int64_t nrhs = tc_ctx64(s_mat.nrhs), ldb = tc_ctx64(s_mat.ldb);
         double* B = tc_global(s_mat.b);
@@ -1258,65 +1323,54 @@ static int tc_staging_release(hipStream_t st) {
   return 0;
 }
 
-// ---- batched launcher.  Workspace layout (each part 256-byte aligned):
-//   ticket | per-matrix status headers | done counters | per-matrix pdone and
-//   ver counters (all zeroed by one fill) | descriptors | slots | unit table
-namespace {
-struct TcBatchLayout {
-  int64_t hdrs, done, counters, zero_end, mats, slots, table, total_bytes;
-  int64_t nslots, nunits;
-};
-inline int64_t tc_ctr_bytes(const TcGeom& g) {
-  return tc_round256(4 * (int64_t)g.NRB) + tc_round256(4 * (int64_t)g.NRB * g.NRB);
+// ---- batched launcher (workspace layout and ticket order: batch_plan.h)
+int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk,
+                            const int32_t* prec, bool refine) {
+  return tc_batch_layout(batch, n, T, solve != 0, chunk, nullptr, prec, refine).total_bytes;
 }
-}  // namespace
 
-static TcBatchLayout tc_batch_layout(int64_t batch, const int64_t* n, const int64_t* T, bool solve, int64_t chunk,
-                                     std::vector<TcGeom>* geoms) {
-  TcBatchLayout L{};
-  int64_t ctr = 0, units = 0, slots = 0;
-  for (int64_t i = 0; i < batch; ++i) {
-    if (n[i] <= 0) continue;
-    const TcGeom g = tc_geom(n[i], T[i], chunk);
-    if (geoms) (*geoms)[i] = g;
-    ctr += tc_ctr_bytes(g);
-    for (int32_t P = 0; P < g.M; ++P) {
-      units += tc_phase_size(g, P);
-      slots += tc_phase_segments(g, P, nullptr);
-    }
-    if (solve) {
-      units += 1;
-      slots += 1;
-    }
+// Copies of the refined batched launch: the lower triangle of A0 into the
+// factor's storage A, and b0 into x (one matrix per blockIdx.x, rows strided
+// over blockIdx.y).
+__global__ __launch_bounds__(TC_THREADS) void tc_batch_copy(const TcBatchMat* __restrict__ mats) {
+  const TcBatchMat& d = mats[blockIdx.x];
+  const int64_t n = d.g.n;
+  if (d.A0 == nullptr || n <= 0) return;
+  for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+    if (d.A != d.A0)
+      for (int64_t j = threadIdx.x; j <= i; j += TC_THREADS) d.A[i * d.lda + j] = d.A0[i * d.lda0 + j];
+    if (threadIdx.x == 0) d.b[i] = d.b0[i];
   }
-  L.hdrs = 256;
-  L.done = L.hdrs + tc_round256((int64_t)sizeof(TcWsHeader) * batch);
-  L.counters = L.done + tc_round256(4 * batch);
-  L.zero_end = L.counters + ctr;
-  L.mats = L.zero_end;
-  L.slots = L.mats + tc_round256((int64_t)sizeof(TcBatchMat) * batch);
-  L.table = L.slots + tc_round256((int64_t)sizeof(TcBatchSlot) * slots);
-  L.total_bytes = L.table + tc_round256((int64_t)sizeof(TcBatchUnit) * units);
-  L.nslots = slots;
-  L.nunits = units;
-  return L;
 }
 
-int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk) {
-  return tc_batch_layout(batch, n, T, solve != 0, chunk, nullptr).total_bytes;
+int tc_read_batched_stats(const void* work, int64_t batch, const int64_t* n, const int64_t* T, int64_t chunk,
+                          const int32_t* prec, hipStream_t st, double* eta, int64_t* iters) {
+  const TcBatchLayout L = tc_batch_layout(batch, n, T, true, chunk, nullptr, prec, true);
+  std::vector<double> h(2 * batch);
+  if (batch > 0 && hipMemcpyAsync(h.data(), (const char*)work + L.stats, 16 * batch, hipMemcpyDeviceToHost, st) !=
+                       hipSuccess)
+    return TC_LAUNCH_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  for (int64_t i = 0; i < batch; ++i) {
+    eta[i] = h[2 * i];
+    iters[i] = (int64_t)h[2 * i + 1];
+  }
+  return 0;
 }
 
 int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
                       int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk,
-                      const int64_t* nrhs, const int64_t* ldb) {
+                      const int64_t* nrhs, const int64_t* ldb, const TcBatchMixed* mx) {
   const bool solve = b != nullptr;
+  const int32_t* prec = mx ? mx->prec : nullptr;
+  const bool refine = solve && mx && mx->A0;
   std::vector<TcGeom> geoms(batch);
-  const TcBatchLayout L = tc_batch_layout(batch, n, T, solve, chunk, &geoms);
+  const TcBatchLayout L = tc_batch_layout(batch, n, T, solve, chunk, &geoms, prec, refine);
   char* base = (char*)work;
   // descriptors
   std::vector<TcBatchMat> mats(batch);
-  int64_t ctr = L.counters;
-  int32_t maxM = 0;
+  int64_t ctr = L.counters, extra = L.extra;
+  int64_t nmax = 0;
   for (int64_t i = 0; i < batch; ++i) {
     TcBatchMat& d = mats[i];
     d = TcBatchMat{};
@@ -1335,56 +1389,31 @@ int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, cons
     d.ws.ver = (int32_t*)(base + ctr + tc_round256(4 * (int64_t)g.NRB));
     d.ws.noop = 0;
     ctr += tc_ctr_bytes(g);
+    d.prec = prec ? prec[i] : TC_PREC_FP64;
+    if (d.prec == TC_PREC_FP32 && g.M > 1) {
+      d.P = (float*)(base + extra);
+      d.ldp = tc_batch_ldp(g.n);
+      extra += tc_round256(4 * g.n * d.ldp);
+    }
+    if (refine) {
+      d.refine = 1;
+      d.A0 = mx->A0[i];
+      d.lda0 = mx->lda0[i];
+      d.b0 = mx->b0[i];
+      d.R = (double*)(base + extra);
+      extra += tc_round256(8 * g.n);
+      d.stat = (double*)(base + L.stats) + 2 * i;
+      d.tol = mx->tol;
+      d.max_iter = mx->max_iter;
+      nmax = std::max(nmax, g.n);
+    }
     int64_t nu = 0;
     for (int32_t P = 0; P < g.M; ++P) nu += tc_phase_size(g, P);
     d.nunits = nu;
-    if (g.M > maxM) maxM = g.M;
   }
-  // slots: segment k of phase P of every matrix, largest first, for (P, k)
-  // in order; a matrix's solve right after its last segment
-  std::vector<int64_t> order;
-  for (int64_t i = 0; i < batch; ++i)
-    if (n[i] > 0) order.push_back(i);
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return n[x] > n[y]; });
   std::vector<TcBatchSlot> slots;
   slots.reserve(L.nslots);
-  int64_t start = 0;
-  // per phase: each live matrix's segment sizes, then the merge
-  std::vector<int64_t> live, segs, segoff, pos;
-  for (int32_t P = 0; P < maxM; ++P) {
-    live.clear();
-    segoff.clear();
-    segs.clear();
-    int64_t kmax = 0;
-    for (int64_t i : order) {
-      if (P >= geoms[i].M) continue;
-      const int64_t ns = tc_phase_segments(geoms[i], P, nullptr);
-      live.push_back(i);
-      segoff.push_back((int64_t)segs.size());
-      segs.resize(segs.size() + ns);
-      tc_phase_segments(geoms[i], P, segs.data() + segoff.back());
-      kmax = std::max(kmax, ns);
-    }
-    segoff.push_back((int64_t)segs.size());
-    pos.assign(live.size(), 0);
-    for (int64_t k = 0; k < kmax; ++k) {
-      for (size_t q = 0; q < live.size(); ++q) {
-        const int64_t i = live[q];
-        const int64_t nseg = segoff[q + 1] - segoff[q];
-        if (k >= nseg) continue;
-        const int64_t sz = segs[segoff[q] + k];
-        if (sz > 0) {
-          slots.push_back({(int32_t)i, P, start, pos[q], sz});
-          start += sz;
-          pos[q] += sz;
-        }
-        if (solve && P == geoms[i].M - 1 && k == nseg - 1) {
-          slots.push_back({(int32_t)i, -1, start, 0, 1});
-          start += 1;
-        }
-      }
-    }
-  }
+  const int64_t start = tc_batch_slots(batch, n, geoms, solve, slots);
   if ((int64_t)slots.size() > L.nslots || start != L.nunits) return TC_LAUNCH_EINVAL;  // (empty segments dropped)
   hipLaunchKernelGGL(tc_fill_zero, dim3(256), dim3(256), 0, st, (int32_t*)work, L.zero_end / 4);
   // descriptors and slots reach the device through pinned staging: the host
@@ -1400,6 +1429,9 @@ int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, cons
     return TC_LAUNCH_EDEVICE;
   if (tc_staging_release(st) != 0) return TC_LAUNCH_EDEVICE;
   if (slots.empty()) return tc_chk(hipGetLastError());
+  if (refine)
+    hipLaunchKernelGGL(tc_batch_copy, dim3((unsigned)batch, (unsigned)std::min<int64_t>(nmax, 16)), dim3(TC_THREADS),
+                       0, st, (const TcBatchMat*)(base + L.mats));
   hipLaunchKernelGGL(tc_batch_units, dim3((unsigned)slots.size()), dim3(TC_THREADS), 0, st,
                      (const TcBatchMat*)(base + L.mats), (const TcBatchSlot*)(base + L.slots),
                      (TcBatchUnit*)(base + L.table));

@@ -85,12 +85,31 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
 // else one right-hand side per matrix, solved in place after its factor).
 // Matrices with n <= 0 are skipped.  chunk: ticket-order lookahead of each
 // matrix (as for the asynchronous schedule).
-int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk);
+// Mixed precision and refinement of a batched launch (all optional):
+//   prec      per-matrix trailing-product precision (TC_PREC_FP64 / FP32),
+//             null = FP64;
+//   A0, lda0  originals: with them the launch first copies each lower
+//             triangle A0 -> A (A is then the factor's storage) and b0 -> b,
+//             and every solve unit refines against A0 and b0 to tol (at most
+//             max_iter corrections).
+struct TcBatchMixed {
+  const int32_t* prec = nullptr;
+  const double* const* A0 = nullptr;
+  const int64_t* lda0 = nullptr;
+  const double* const* b0 = nullptr;
+  double tol = 0.0;
+  int64_t max_iter = 0;
+};
+int64_t tc_batched_ws_bytes(int64_t batch, const int64_t* n, const int64_t* T, int solve, int64_t chunk,
+                            const int32_t* prec = nullptr, bool refine = false);
 // nrhs / ldb: right-hand sides per matrix (n x nrhs row-major, leading
 // dimension ldb); null means one right-hand side, contiguous.
 int tc_launch_batched(double* const* A, double* const* b, const int64_t* n, const int64_t* lda, const int64_t* T,
                       int64_t batch, void* work, hipStream_t st, int64_t grid, int64_t wait_ticks, int64_t chunk,
-                      const int64_t* nrhs = nullptr, const int64_t* ldb = nullptr);
+                      const int64_t* nrhs = nullptr, const int64_t* ldb = nullptr, const TcBatchMixed* mx = nullptr);
+// Refinement statistics {eta, corrections} of every matrix (synchronises).
+int tc_read_batched_stats(const void* work, int64_t batch, const int64_t* n, const int64_t* T, int64_t chunk,
+                          const int32_t* prec, hipStream_t st, double* eta, int64_t* iters);
 int tc_read_batched_status(const void* work, int64_t batch, hipStream_t st, int32_t* error, int64_t* info);
 int64_t tc_batched_grid_size();
 // Status header of a factorization workspace: its size, and decoding a host

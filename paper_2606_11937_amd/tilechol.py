@@ -64,6 +64,10 @@ SIGNATURES = [
     ("chol_factor_solve_batched_workspace_size", _i64, [_i64, _pi64, _pi64]),
     ("chol_factor_solve_batched", _int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _pi64, _pi64, _i64, _pi64, _vp,
                                          _i64, _vp, _pi64]),
+    ("chol_factor_solve_batched_mixed_workspace_size", _i64, [_i64, _pi64, _pi64, _pi32]),
+    ("chol_factor_solve_batched_mixed", _int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                               ctypes.POINTER(_vp), _pi64, _pi64, _pi64, _i64, _pi64, _pi32, _dbl,
+                                               _i64, _vp, _i64, _vp, _pi64, _pi64, ctypes.POINTER(_dbl)]),
     ("chol_batched_tile", _i64, [_i64, _int]),
     ("chol_factor_mixed_workspace_size", _i64, [_i64, _i64, _int]),
     ("chol_factor_mixed", _int, [_vp, _i64, _i64, _i64, _int, _int, _dbl, _vp, _i64, _vp, _pi64]),
@@ -369,6 +373,55 @@ def chol_factor_solve_batched(As, Bs, Ts=None, work=None, stream=None, sync: boo
     if st not in (CHOL_OK, CHOL_NOT_SPD):
         raise TileCholError(st, "chol_factor_solve_batched", last_bad_arg())
     return [int(infos[i]) for i in range(b)] if sync else None
+
+
+def chol_factor_solve_batched_mixed_workspace_size(ns, Ts=None, precs=None) -> int:
+    b = len(ns)
+    n_arr = (ctypes.c_int64 * max(b, 1))(*ns)
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    p_arr = (ctypes.c_int32 * b)(*[_prec(p) for p in precs]) if precs is not None else None
+    return int(lib.chol_factor_solve_batched_mixed_workspace_size(b, n_arr, t_arr, p_arr))
+
+
+def chol_factor_solve_batched_mixed(As, Ls, Bs, Xs, Ts=None, precs=None, tol: float = 1e-12, max_iter: int = 10,
+                                    work=None, stream=None, sync: bool = True):
+    """Factor each original A_i (left untouched) into L_i with FP32 or FP64
+    trailing products (precs: list of "fp32"/"fp64", None = FP64), then solve
+    A_i x_i = b_i into X_i with FP64 refinement to tol, all in one persistent
+    launch.  Returns (infos, corrections, etas) when sync."""
+    import torch
+    b = len(As)
+    for A in As:
+        _check_matrix(A)
+    for L in Ls:
+        _check_matrix(L, "L")
+    ns = [A.shape[0] for A in As]
+    ld = lambda t: t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
+    for n, B, X in zip(ns, Bs, Xs):
+        for v in (B, X):
+            if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous() and v.numel() == n):
+                raise TypeError("right-hand sides and solutions must be contiguous float64 GPU vectors of n entries")
+    if work is None:
+        nb = chol_factor_solve_batched_mixed_workspace_size(ns, Ts, precs)
+        if nb < 0:
+            raise TileCholError(nb, "chol_factor_solve_batched_mixed_workspace_size", last_bad_arg())
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=As[0].device if b else "cuda")
+    vp = lambda ts: (ctypes.c_void_p * max(b, 1))(*[t.data_ptr() for t in ts])
+    i64 = lambda v: (ctypes.c_int64 * max(b, 1))(*v)
+    t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
+    p_arr = (ctypes.c_int32 * b)(*[_prec(p) for p in precs]) if precs is not None else None
+    infos, its = (ctypes.c_int64 * max(b, 1))(), (ctypes.c_int64 * max(b, 1))()
+    etas = (ctypes.c_double * max(b, 1))()
+    st = lib.chol_factor_solve_batched_mixed(vp(As), vp(Ls), vp(Bs), vp(Xs), i64(ns), i64([ld(A) for A in As]),
+                                             i64([ld(L) for L in Ls]), b, t_arr, p_arr, float(tol), int(max_iter),
+                                             ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream),
+                                             infos if sync else None, its if sync else None,
+                                             etas if sync else None)
+    if st not in (CHOL_OK, CHOL_NOT_SPD, CHOL_NOT_CONVERGED):
+        raise TileCholError(st, "chol_factor_solve_batched_mixed", last_bad_arg())
+    if not sync:
+        return None
+    return [int(infos[i]) for i in range(b)], [int(its[i]) for i in range(b)], [float(etas[i]) for i in range(b)]
 
 
 # ---------------------------------------------------------------- serving

@@ -300,3 +300,27 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_batched_mixed_argument_checks(tc):
+    """chol_factor_solve_batched_mixed validates everything before touching
+    the device: the factor must not overwrite the original, precisions and
+    tile sides must be usable, and the workspace must be large enough."""
+    vp = lambda *p: (ctypes.c_void_p * len(p))(*p)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    A, L, B, X = vp(FAKE.value), vp(0x2000), vp(0x3000), vp(0x4000)
+    n, ld = i64(300), i64(300)
+    call = lambda A_, L_, T_, p_, tol, it, wb: tc.lib.chol_factor_solve_batched_mixed(
+        A_, L_, B, X, n, ld, ld, 1, T_, p_, tol, it, FAKE, wb, None, None, None, None)
+    assert call(A, vp(FAKE.value), None, None, 1e-12, 5, 1 << 40) == tc.CHOL_EINVAL and tc.last_bad_arg() == 2
+    assert call(A, L, None, None, 0.0, 5, 1 << 40) == tc.CHOL_EINVAL and tc.last_bad_arg() == 11
+    assert call(A, L, None, None, 1e-12, -1, 1 << 40) == tc.CHOL_EINVAL and tc.last_bad_arg() == 12
+    assert call(A, L, None, (ctypes.c_int32 * 1)(2), 1e-12, 5, 1 << 40) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 10  # BF16 is not offered in the batched launch
+    assert call(A, L, i64(126), (ctypes.c_int32 * 1)(1), 1e-12, 5, 1 << 40) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 9  # FP32 products read the panel copy in 4-float pieces
+    need = tc.chol_factor_solve_batched_mixed_workspace_size([300], [128], ["fp32"])
+    assert need > tc.chol_factor_solve_batched_mixed_workspace_size([300], [128], ["fp64"]) > 0
+    assert call(A, L, i64(128), (ctypes.c_int32 * 1)(1), 1e-12, 5, need - 1) == tc.CHOL_EWORKSPACE
+    assert tc.last_bad_arg() == 14
+    assert tc.chol_batched_tile(1000, "fp32") > 0 and tc.chol_batched_tile(1000, "bf16") == tc.CHOL_EINVAL

@@ -42,6 +42,10 @@ def _dev(A):
     return torch.from_numpy(np.ascontiguousarray(A)).cuda()
 
 
+def lower_equal(X, Y):
+    return np.array_equal(np.tril(X), np.tril(Y))
+
+
 EDGE = [1, 2, 31, 64, 65, 127, 128, 129, 200, 255, 256, 257, 383, 640, 1000]
 
 
@@ -157,3 +161,85 @@ def test_batched_full_workload_sampled(tc):
         Lref, info = oracle.potrf(keepA[i])
         assert info == 0
         assert oracle.row_scaled_error(Ls[i].cpu().numpy(), Lref, keepA[i]) <= E_ROW_TOL, sizes[i]
+
+
+# ------------------------------------------------ FP32 products + refinement
+def _mixed_batch(tc, As, precs, Ts, tol=1e-12, max_iter=10, seed=0):
+    import torch
+    dA = [torch.from_numpy(A).cuda() for A in As]
+    dL = [torch.full_like(a, float("nan")) for a in dA]
+    rng = np.random.default_rng(seed)
+    Bs = [rng.standard_normal(A.shape[0]) for A in As]
+    dB = [torch.from_numpy(b).cuda() for b in Bs]
+    dX = [torch.zeros_like(b) for b in dB]
+    infos, its, etas = tc.chol_factor_solve_batched_mixed(dA, dL, dB, dX, Ts=Ts, precs=precs, tol=tol,
+                                                          max_iter=max_iter)
+    torch.cuda.synchronize()
+    # the originals are read only
+    for A, a, b, B in zip(As, dA, dB, Bs):
+        assert np.array_equal(a.cpu().numpy(), A) and np.array_equal(b.cpu().numpy(), B)
+    return infos, its, etas, [l.cpu().numpy() for l in dL], [x.cpu().numpy() for x in dX], Bs
+
+
+@pytest.mark.parametrize("T", [128, 256])
+def test_batched_fp32_matches_single_matrix_mixed(tc, T):
+    """FP32 trailing products in the batched launch: each factor equals, bit
+    for bit, the single-matrix mixed factorization with FP32 products (same
+    tile bodies, same panel rounding, no scaling, no shift); every refined
+    solution meets eta <= 1e-12 (checked by the oracle's measure) and agrees
+    with the oracle's FP64 solve."""
+    import torch
+    ns = [1, 17, 100, 128, 129, 300, 513, 700, 1000]
+    rng = np.random.default_rng(91)
+    As = [inputs.gg_plus_identity(n, seed=int(rng.integers(1 << 30))) for n in ns]
+    say(f"[batched fp32] T={T} sizes={ns}")
+    infos, its, etas, Ls, Xs, Bs = _mixed_batch(tc, As, ["fp32"] * len(ns), [T] * len(ns), seed=92)
+    assert infos == [0] * len(ns)
+    for A, L, X, b, it, eta in zip(As, Ls, Xs, Bs, its, etas):
+        n = A.shape[0]
+        d = torch.from_numpy(A).cuda()
+        assert tc.chol_factor_mixed(d, T, "fp32", scale=False) == 0
+        assert lower_equal(L, d.cpu().numpy()), n
+        e = oracle.backward_error(A, X, b)
+        Lref, _ = oracle.potrf(A)
+        xr = oracle.solve(Lref, b)
+        say(f"  n={n} corrections={it} eta={eta:.2e} (oracle {e:.2e})")
+        assert e <= ETA_TOL and eta <= ETA_TOL
+        # the two residuals sum in different orders: they agree to about
+        # n u relative to ||A|| ||x||, the denominator of eta
+        assert abs(e - eta) <= 2.0 * n * 2.0 ** -53 + 1e-3 * e
+        assert np.abs(X - xr).max() <= 1e-10 * max(1.0, np.abs(xr).max())
+        if n > T:
+            assert it >= 1  # the FP32 factor alone does not reach 1e-12
+
+
+def test_batched_mixed_fp64_members_equal_the_fp64_launch(tc):
+    import torch
+    ns = [64, 300, 777]
+    As = [inputs.gg_plus_identity(n, seed=93 + n) for n in ns]
+    infos, its, etas, Ls, Xs, Bs = _mixed_batch(tc, As, ["fp64", "fp32", "fp64"], [128, 128, 256], seed=94)
+    assert infos == [0, 0, 0]
+    ref = [torch.from_numpy(A).cuda() for A in As]
+    assert tc.chol_factor_batched(ref, Ts=[128, 128, 256]) == [0, 0, 0]
+    for k in (0, 2):
+        assert lower_equal(Ls[k], ref[k].cpu().numpy())
+        assert its[k] == 0 and etas[k] <= ETA_TOL
+
+
+def test_batched_fp32_integer_exact(tc):
+    """Rows of norm 4: every panel entry is exact in FP32 and so is every
+    product sum, so the FP32 batched factor is L0 bit for bit."""
+    mats = [inputs.integer_factor_norm4(n, seed=95 + n) for n in (200, 333, 700)]
+    infos, its, etas, Ls, Xs, Bs = _mixed_batch(tc, [A for A, _ in mats], ["fp32"] * 3, [128, 100, 256], seed=96)
+    assert infos == [0, 0, 0]
+    for (A, L0), L in zip(mats, Ls):
+        assert lower_equal(L, L0)
+
+
+def test_batched_fp32_failure_is_isolated(tc):
+    good = inputs.gg_plus_identity(400, seed=97)
+    bad = inputs.gg_plus_identity(400, seed=98)
+    bad[250, 250] = -1.0
+    infos, its, etas, Ls, Xs, Bs = _mixed_batch(tc, [good, bad, good], ["fp32"] * 3, [128] * 3, seed=99)
+    assert infos[0] == 0 and infos[2] == 0 and infos[1] == oracle.potrf(bad)[1]
+    assert oracle.backward_error(good, Xs[0], Bs[0]) <= ETA_TOL
