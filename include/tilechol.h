@@ -58,8 +58,10 @@ enum {
   CHOL_EWORKSPACE = -3, /* work_bytes smaller than the *_workspace_size result   */
   CHOL_ETIMEOUT = -4,   /* a dependency wait of the asynchronous schedule
                            exceeded chol_set_wait_limit; factor unspecified     */
-  CHOL_ESTALLED = -5    /* chol_server_wait: a dependency wait of the request's
+  CHOL_ESTALLED = -5,   /* chol_server_wait: a dependency wait of the request's
                            factorization or solve exceeded the wait limit       */
+  CHOL_ENOFACTOR = -6   /* serving: no such resident factor (never kept,
+                           released, or evicted to make room)                    */
 };
 
 /* Schedules (Methods, "Implementations", the fork-join collapsed and task
@@ -351,37 +353,57 @@ int64_t chol_batched_tile(int64_t n, int prec);
  * system: A = k(x_i, x_j) + nugget I with the squared-exponential kernel
  * k(x, y) = exp(-|x - y|^2 / (2 lengthscale^2)) on n points in the plane,
  * 1 <= nrhs <= CHOL_SERVE_MAX_RHS right-hand sides, and a target backward
- * error tol.  A worker thread of the server admits pending requests in
- * arrival order while their device footprint (8 n^2 + 32 n nrhs + 16 n bytes
- * plus a small per-tick workspace) fits in the caller's arena, and launches
- * each group as one tick: matrix assembly on the device, ONE persistent
- * batched factorization launch (tile side from chol_batched_tile), the
- * solves as multi-workgroup sweeps (as chol_solve), and a matrix-free
- * residual giving every request's backward error.  Up to two
- * ticks are in flight on two streams of the server, so requests that
- * arrive while a tick runs are admitted and launched meanwhile.  A
- * request's result does not depend on which other requests shared its tick
- * (bit for bit).  All arithmetic is FP64.
+ * error tol.  It may ask for its factor to stay resident (CHOL_SERVE_KEEP);
+ * later solves against a resident factor (chol_server_submit_solve) skip
+ * the factorization.
+ * A worker thread admits pending requests in arrival order while their
+ * device footprint fits in the caller's arena (8 n^2 + 16 n bytes for the
+ * factor and the points, 24 n nrhs + 8 (3 nrhs + 2) for right-hand sides,
+ * solution, residual and statistics, plus a per-tick workspace), evicting
+ * resident factors that no request is using, least recently used first,
+ * when the arena is short.  Each admitted group is one tick: matrix assembly
+ * on the device, ONE persistent batched factorization launch, the solves as
+ * multi-workgroup sweeps (as chol_solve), and a matrix-free residual giving
+ * every request's backward error.  Up to two ticks are in flight on two
+ * streams, so requests that arrive while a tick runs are admitted and
+ * launched meanwhile.
+ * Precision per request, from (n, tol) only: FP32 trailing products
+ * (CHOL_PREC_FP32, tile side chol_batched_tile(n, CHOL_PREC_FP32)) from an
+ * order on that depends on the tolerance class (tol >= 1e-8 or below, a
+ * table measured offline), FP64 otherwise.  A request whose backward error
+ * after its solve exceeds tol gets FP64 refinement corrections in later
+ * ticks, x += (L L^T)^-1 (b - A x) with the residual formed matrix-free in
+ * FP64; an FP32 factor whose corrections run out is refactored in FP64.
+ * A request's result does not depend on which other requests shared its
+ * ticks (bit for bit).
  *   CHOL_SERVE_FIFO is the plain baseline: one request at a time, chol_factor
- *   (fork-join, chol_default_tile) then chol_solve.
+ *   (fork-join, chol_default_tile) in FP64 then chol_solve.
  * Memory: the device arena (arena_bytes) belongs to the caller and is the
  * server's HBM budget; the server allocates no device memory.  It allocates
  * pinned_bytes of pinned host memory for staging (inputs and results of the
  * requests in flight) and frees it in chol_server_destroy.
- * Threads: submit and wait may be called from any thread.  destroy lets the
- * admitted and pending requests finish, then stops the worker. */
+ * Threads: every call may come from any thread.  destroy lets the admitted
+ * and pending requests finish, then stops the worker. */
 typedef struct chol_server chol_server;
 enum { CHOL_SERVE_CONTINUOUS = 0, CHOL_SERVE_FIFO = 1 };
 #define CHOL_SERVE_MAX_RHS 8
+#define CHOL_SERVE_KEEP 1 /* flag of chol_server_submit: keep the factor resident */
 
-/* max_per_tick: requests launched together at most (1 .. 65536). */
+/* max_per_tick: work items launched together at most (1 .. 65536). */
 int chol_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int mode,
                        int64_t max_per_tick, chol_server** server);
 /* points: host, n x 2 row-major (copied); B: host, n x nrhs row-major
- * (copied); 1 <= n <= 65536.  *id receives the request's handle; the
- * arrival time is taken here. */
+ * (copied); 1 <= n <= 65536; flags 0 or CHOL_SERVE_KEEP.  *id receives the
+ * request's handle; the arrival time is taken here. */
 int chol_server_submit(chol_server* server, const double* points, int64_t n, double lengthscale,
-                       double nugget, const double* B, int64_t nrhs, double tol, int64_t* id);
+                       double nugget, const double* B, int64_t nrhs, double tol, int flags, int64_t* id);
+/* A solve with resident factor `factor` (from chol_server_request_info of a
+ * request submitted with CHOL_SERVE_KEEP): B host, n x nrhs row-major
+ * (copied), n must be the factor's order.  The factor cannot be evicted
+ * while such a request is pending or running.  Returns CHOL_ENOFACTOR if
+ * the factor is not resident (never kept, released, or evicted). */
+int chol_server_submit_solve(chol_server* server, int64_t factor, const double* B, int64_t n, int64_t nrhs,
+                             double tol, int64_t* id);
 /* Wait up to timeout_s seconds for request id.  When it is done: X (host,
  * n x nrhs, or NULL) receives the solution, *eta the worst column's backward
  * error, *latency_s the time from submission to the result being in host
@@ -394,8 +416,22 @@ int chol_server_submit(chol_server* server, const double* points, int64_t n, dou
  * code. */
 int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta,
                      double* latency_s, int64_t* info);
-/* Ticks launched so far (< 0 on invalid arguments). */
+/* How request id was served (any argument but server may be NULL): *factor
+ * the handle of its resident factor (CHOL_SERVE_KEEP, once done; -1
+ * otherwise, and for a solve request the factor it used), *prec the
+ * precision of the factor that produced the result (CHOL_PREC_*),
+ * *corrections the refinement corrections of that factor, *refactors 1 if
+ * an FP32 factor was replaced by an FP64 one.  Returns CHOL_OK or
+ * CHOL_EINVAL (unknown id). */
+int chol_server_request_info(chol_server* server, int64_t id, int64_t* factor, int* prec, int* corrections,
+                             int* refactors);
+/* Drop a resident factor; CHOL_ENOFACTOR if it is not resident or a pending
+ * or running request still uses it. */
+int chol_server_release_factor(chol_server* server, int64_t factor);
+/* Ticks launched so far, and resident factors evicted so far (< 0 on invalid
+ * arguments). */
 int64_t chol_server_ticks(chol_server* server);
+int64_t chol_server_evictions(chol_server* server);
 int chol_server_destroy(chol_server* server);
 
 /* Tile side the library picks for order n when the caller passes none

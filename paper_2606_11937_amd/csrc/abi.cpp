@@ -90,6 +90,7 @@ const char* chol_status_str(int status) {
     case CHOL_EWORKSPACE: return "workspace too small";
     case CHOL_ETIMEOUT: return "dependency wait exceeded the wait limit";
     case CHOL_ESTALLED: return "a served request's dependency wait exceeded the wait limit (see info)";
+    case CHOL_ENOFACTOR: return "no such resident factor (never kept, released or evicted)";
     case CHOL_NOT_CONVERGED: return "refinement did not reach the tolerance within max_iter";
     default: return "unknown status";
   }
@@ -509,7 +510,7 @@ int chol_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, i
 }
 
 int chol_server_submit(chol_server* server, const double* points, int64_t n, double lengthscale, double nugget,
-                       const double* B, int64_t nrhs, double tol, int64_t* id) {
+                       const double* B, int64_t nrhs, double tol, int flags, int64_t* id) {
   g_bad_arg = 0;
   if (server == nullptr) return bad(1);
   if (points == nullptr) return bad(2);
@@ -519,9 +520,46 @@ int chol_server_submit(chol_server* server, const double* points, int64_t n, dou
   if (B == nullptr) return bad(6);
   if (nrhs < 1 || nrhs > CHOL_SERVE_MAX_RHS) return bad(7);
   if (!(tol > 0.0)) return bad(8);
-  if (id == nullptr) return bad(9);
-  return tc_server_submit(server->s, points, n, lengthscale, nugget, B, nrhs, tol, id) == 0 ? CHOL_OK
-                                                                                            : CHOL_EDEVICE;
+  if ((flags & ~CHOL_SERVE_KEEP) != 0) return bad(9);
+  if (id == nullptr) return bad(10);
+  return tc_server_submit(server->s, points, n, lengthscale, nugget, B, nrhs, tol, flags & CHOL_SERVE_KEEP, id) == 0
+             ? CHOL_OK
+             : CHOL_EDEVICE;
+}
+
+int chol_server_submit_solve(chol_server* server, int64_t factor, const double* B, int64_t n, int64_t nrhs,
+                             double tol, int64_t* id) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  if (B == nullptr) return bad(3);
+  if (n < 1 || n > 65536) return bad(4);
+  if (nrhs < 1 || nrhs > CHOL_SERVE_MAX_RHS) return bad(5);
+  if (!(tol > 0.0)) return bad(6);
+  if (id == nullptr) return bad(7);
+  const int r = tc_server_submit_solve(server->s, factor, B, n, nrhs, tol, id);
+  if (r == TC_LAUNCH_ENOFACTOR) return CHOL_ENOFACTOR;
+  if (r == TC_LAUNCH_EINVAL) return bad(4);
+  return r == 0 ? CHOL_OK : CHOL_EDEVICE;
+}
+
+int chol_server_request_info(chol_server* server, int64_t id, int64_t* factor, int* prec, int* corrections,
+                             int* refactors) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  const int st = tc_server_request_info(server->s, id, factor, prec, corrections, refactors);
+  return st == TC_LAUNCH_EINVAL ? bad(2) : CHOL_OK;
+}
+
+
+int chol_server_release_factor(chol_server* server, int64_t factor) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  return tc_server_release_factor(server->s, factor) == 0 ? CHOL_OK : CHOL_ENOFACTOR;
+}
+
+int64_t chol_server_evictions(chol_server* server) {
+  if (server == nullptr) return bad(1);
+  return tc_server_evictions(server->s);
 }
 
 int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* X, double* eta, double* latency_s,

@@ -5,6 +5,7 @@
 
 #define TC_LAUNCH_EDEVICE (-2)
 #define TC_LAUNCH_ETIMEOUT (-4)
+#define TC_LAUNCH_ENOFACTOR (-6)
 
 // Tile side of the plain factorization when the caller gives none (measured
 // on MI355X, fork-join: small orders are launch-bound and prefer short
@@ -116,14 +117,19 @@ int64_t tc_batched_grid_size();
 // copy of it.
 int64_t tc_ws_header_bytes();
 void tc_ws_header_read(const void* hdr, int32_t* error, int64_t* info);
-// Serving with continuous batching (serve.hip).  mode 0 continuous batching,
-// 1 one request at a time.
+// Serving with continuous batching (serve.hip; bookkeeping in serve_core.h).
+// mode 0 continuous batching, 1 one request at a time.
 struct TcServer;
 int tc_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int mode, int64_t max_per_tick,
                      int64_t wait_ticks, TcServer** out);
 int tc_server_submit(TcServer* S, const double* pts, int64_t n, double lengthscale, double nugget, const double* B,
-                     int64_t nrhs, double tol, int64_t* id);
+                     int64_t nrhs, double tol, int keep, int64_t* id);
+int tc_server_submit_solve(TcServer* S, int64_t factor, const double* B, int64_t n, int64_t nrhs, double tol,
+                           int64_t* id);
 int tc_server_wait(TcServer* S, int64_t id, double timeout_s, double* X, double* eta, double* latency_s,
                    int64_t* info);
+int tc_server_request_info(TcServer* S, int64_t id, int64_t* factor, int* prec, int* corrections, int* refactors);
+int tc_server_release_factor(TcServer* S, int64_t factor);
 int64_t tc_server_ticks(TcServer* S);
+int64_t tc_server_evictions(TcServer* S);
 int tc_server_destroy(TcServer* S);

@@ -23,6 +23,8 @@ CHOL_EDEVICE = -2
 CHOL_EWORKSPACE = -3
 CHOL_ETIMEOUT = -4
 CHOL_ESTALLED = -5
+CHOL_ENOFACTOR = -6
+CHOL_SERVE_KEEP = 1
 CHOL_SCHED_FORK_JOIN = 0
 CHOL_SCHED_ASYNC_DAG = 1
 CHOL_SCHED_FORK_JOIN_NAIVE = 2
@@ -75,7 +77,12 @@ SIGNATURES = [
     ("chol_solve_refine", _int, [_vp, _i64, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _int, _dbl, _i64,
                                  _vp, _i64, _vp, _pi64, ctypes.POINTER(_dbl)]),
     ("chol_server_create", _int, [_vp, _i64, _i64, _int, _i64, ctypes.POINTER(_vp)]),
-    ("chol_server_submit", _int, [_vp, _vp, _i64, _dbl, _dbl, _vp, _i64, _dbl, _pi64]),
+    ("chol_server_submit", _int, [_vp, _vp, _i64, _dbl, _dbl, _vp, _i64, _dbl, _int, _pi64]),
+    ("chol_server_submit_solve", _int, [_vp, _i64, _vp, _i64, _i64, _dbl, _pi64]),
+    ("chol_server_request_info", _int, [_vp, _i64, _pi64, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                        ctypes.POINTER(_int)]),
+    ("chol_server_release_factor", _int, [_vp, _i64]),
+    ("chol_server_evictions", _i64, [_vp]),
     ("chol_server_wait", _int, [_vp, _i64, _dbl, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _pi64]),
     ("chol_server_ticks", _i64, [_vp]),
     ("chol_server_destroy", _int, [_vp]),
@@ -443,7 +450,7 @@ class Server:
             raise TileCholError(st, "chol_server_create", last_bad_arg())
         self.shapes = {}
 
-    def submit(self, points, B, lengthscale: float, nugget: float, tol: float) -> int:
+    def submit(self, points, B, lengthscale: float, nugget: float, tol: float, keep: bool = False) -> int:
         import numpy as np
         P = np.ascontiguousarray(points, dtype=np.float64)
         Bm = np.ascontiguousarray(B, dtype=np.float64)
@@ -452,11 +459,43 @@ class Server:
         n, nrhs = Bm.shape
         rid = ctypes.c_int64(-1)
         st = lib.chol_server_submit(self.h, P.ctypes.data_as(ctypes.c_void_p), n, float(lengthscale), float(nugget),
-                                    Bm.ctypes.data_as(ctypes.c_void_p), nrhs, float(tol), ctypes.byref(rid))
+                                    Bm.ctypes.data_as(ctypes.c_void_p), nrhs, float(tol),
+                                    CHOL_SERVE_KEEP if keep else 0, ctypes.byref(rid))
         if st != CHOL_OK:
             raise TileCholError(st, "chol_server_submit", last_bad_arg())
         self.shapes[rid.value] = (n, nrhs)
         return rid.value
+
+    def submit_solve(self, factor: int, B, tol: float) -> int:
+        """A solve with a resident factor; raises TileCholError with status
+        CHOL_ENOFACTOR if it is no longer resident."""
+        import numpy as np
+        Bm = np.ascontiguousarray(B, dtype=np.float64)
+        if Bm.ndim == 1:
+            Bm = Bm.reshape(-1, 1)
+        n, nrhs = Bm.shape
+        rid = ctypes.c_int64(-1)
+        st = lib.chol_server_submit_solve(self.h, int(factor), Bm.ctypes.data_as(ctypes.c_void_p), n, nrhs,
+                                          float(tol), ctypes.byref(rid))
+        if st != CHOL_OK:
+            raise TileCholError(st, "chol_server_submit_solve", last_bad_arg())
+        self.shapes[rid.value] = (n, nrhs)
+        return rid.value
+
+    def request_info(self, rid: int):
+        """(factor handle or -1, precision, corrections, refactors) of a request."""
+        f, p, c, r = ctypes.c_int64(-1), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        st = lib.chol_server_request_info(self.h, rid, ctypes.byref(f), ctypes.byref(p), ctypes.byref(c),
+                                          ctypes.byref(r))
+        if st != CHOL_OK:
+            raise TileCholError(st, "chol_server_request_info", last_bad_arg())
+        return f.value, p.value, c.value, r.value
+
+    def release_factor(self, factor: int) -> bool:
+        return lib.chol_server_release_factor(self.h, int(factor)) == CHOL_OK
+
+    def evictions(self) -> int:
+        return int(lib.chol_server_evictions(self.h))
 
     def wait(self, rid: int, timeout: float = 60.0, want_x: bool = True):
         import numpy as np

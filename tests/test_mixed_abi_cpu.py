@@ -171,7 +171,12 @@ def test_server_argument_checks(tc):
     assert tc.lib.chol_server_create(FAKE, 1 << 30, 1 << 20, 0, 16, None) == tc.CHOL_EINVAL
     assert tc.last_bad_arg() == 6
     rid = ctypes.c_int64()
-    assert tc.lib.chol_server_submit(None, FAKE, 10, 0.1, 0.01, FAKE, 1, 1e-12, ctypes.byref(rid)) == tc.CHOL_EINVAL
+    assert tc.lib.chol_server_submit(None, FAKE, 10, 0.1, 0.01, FAKE, 1, 1e-12, 0, ctypes.byref(rid)) == tc.CHOL_EINVAL
     assert tc.last_bad_arg() == 1
+    assert tc.lib.chol_server_submit_solve(None, 0, FAKE, 10, 1, 1e-12, ctypes.byref(rid)) == tc.CHOL_EINVAL
+    assert tc.last_bad_arg() == 1
+    assert tc.lib.chol_server_request_info(None, 0, None, None, None, None) == tc.CHOL_EINVAL
+    assert tc.lib.chol_server_release_factor(None, 0) == tc.CHOL_EINVAL
+    assert tc.lib.chol_server_evictions(None) == tc.CHOL_EINVAL
     assert tc.lib.chol_server_wait(None, 0, 1.0, None, None, None, None) == tc.CHOL_EINVAL
     assert tc.lib.chol_server_destroy(None) == tc.CHOL_OK
