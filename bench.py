@@ -126,7 +126,10 @@ def parse():
     p.add_argument("--mixed", action="store_true",
                    help="only the mixed-precision comparison (time to a 1e-12 solution, 16 right-hand sides)")
     p.add_argument("--no-mixed", action="store_true", help="leave the mixed-precision comparison out")
-    p.add_argument("--mixed-T", type=int, default=1024, help="tile side of the mixed-precision factorizations")
+    p.add_argument("--mixed-T", type=int, default=512,
+                   help="tile side of the mixed-precision factorizations (the mixed workload's T=512)")
+    p.add_argument("--mixed-T2", type=int, default=1024,
+                   help="a second tile side for the mixed comparison in the contract line (0: none)")
     p.add_argument("--batched", action="store_true",
                    help="only the batched comparison (4096 orders log-uniform in [32, 2048], one launch vs a loop)")
     p.add_argument("--no-batched", action="store_true", help="leave the batched comparison out")
@@ -136,6 +139,9 @@ def parse():
     p.add_argument("--rates", default="100,200,500,1000,2000,5000")
     p.add_argument("--serve-seconds", type=float, default=2.0,
                    help="arrivals per rate: min(2000, rate x this many seconds)")
+    p.add_argument("--serve-resident", type=float, default=0.3,
+                   help="--serve: also a stream where this fraction of arrivals are solves against resident factors")
+    p.add_argument("--no-serve", action="store_true", help="leave the serving figures out of the contract line")
     p.add_argument("--batch-lookaheads", default="-1",
                    help="batched ticket order: bulk units per chain link of each matrix (comma list; -1 default)")
     return p.parse_args()
@@ -259,8 +265,8 @@ def mixed_compare(tc, A0, T64: int, T: int, nrhs: int = 16, reps: int = 3, tol: 
           iterative refinement.
     bf16: chol_factor_mixed with BF16 trailing products and the smallest
           diagonal shift of the ladder 0, 1e-3 4^k that factors, + PCG;
-          the timed region holds the successful attempt only, the failed
-          attempts are listed.
+          the timed region holds the whole ladder: the failed attempts
+          (each a factorization and a copy of A) and the successful one.
     Each line: median of `reps` runs of the whole timed region (device
     events), iterations, final backward error, forward error and row-scaled
     factor difference against the FP64 result, and the trailing-update rate
@@ -329,6 +335,12 @@ def mixed_compare(tc, A0, T64: int, T: int, nrhs: int = 16, reps: int = 3, tol: 
                 tc.chol_timing_enable(["update"])
             e0, e1, e2 = ev(), ev(), ev()
             e0.record(st)
+            # the timed region holds the whole shift ladder: every failed
+            # attempt (a factorization that meets a non-positive pivot, then a
+            # fresh copy of A) before the one that succeeds
+            for f in failed:
+                tc.chol_factor_mixed(L, T, prec, shift=f["shift"], work=wm, stream=st, sync=False)
+                L.copy_(A0)
             tc.chol_factor_mixed(L, T, prec, shift=shift, work=wm, stream=st, sync=False)
             e1.record(st)
             if r == reps:
@@ -468,13 +480,20 @@ def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
     return out
 
 
-def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: float = 96.0):
+def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: float = 96.0,
+                  resident: float = 0.0):
     """Submit `count` requests with exponential inter-arrival times (rate per
     second) to a fresh server, from this thread at their scheduled times,
     then collect every result.  Latency is the server's own: submission to
     the result in host memory.  solves/s counts requests whose backward error
     met their tolerance, over the span from the first arrival to the last
-    completion."""
+    completion.
+    resident > 0: the stream also holds solves against resident factors:
+    every factor + solve request asks to keep its factor, and each arrival is,
+    with probability `resident`, a solve (new right-hand sides, same
+    tolerance class) against the factor of a random earlier request whose
+    result is already in (factors the server evicted are refused and counted).
+    """
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
@@ -486,42 +505,107 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
         nrhs = int(rng.integers(1, 9))
         reqs.append((rng.random((n, 2)), rng.standard_normal((n, nrhs)), float(rng.uniform(0.05, 0.5)), 1e-2,
                      1e-6 if rng.random() < 0.5 else 1e-12))
+    solve_draw = rng.random(count)
     arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
     srv = tc.Server(arena, 8 << 30, mode)
-    ids, lag = [], 0.0
+    ids, lag, kinds = [], 0.0, []
+    done_factors = []  # (factor handle, n, tol) of finished keep requests
+    refused = 0
+    import collections
+    watch = collections.deque()  # indices of keep requests not yet seen finished
     t0 = time.perf_counter()
     for k, (p, B, ell, nug, tol) in enumerate(reqs):
         target = t0 + arr[k]
         while time.perf_counter() < target:
             pass
         lag = max(lag, time.perf_counter() - target)
-        ids.append(srv.submit(p, B, ell, nug, tol))
+        if resident > 0 and solve_draw[k] < resident:
+            # harvest finished keep requests without blocking (they finish
+            # roughly in arrival order: stop at the first one still running)
+            while watch:
+                j = watch[0]
+                if srv.wait(ids[j], timeout=0.0, want_x=False)[0] == tc.CHOL_ETIMEOUT:
+                    break  # still running
+                f = srv.request_info(ids[j])[0]
+                if f >= 0:
+                    done_factors.append((f, reqs[j][1].shape[0], reqs[j][4]))
+                watch.popleft()
+            if done_factors:
+                f, n, tol0 = done_factors[int(rng.integers(len(done_factors)))]
+                try:
+                    ids.append(srv.submit_solve(f, rng.standard_normal((n, B.shape[1])), tol0))
+                    kinds.append("solve")
+                    reqs[k] = (None, np.empty((n, B.shape[1])), ell, nug, tol0)
+                    continue
+                except tc.TileCholError:
+                    refused += 1
+        ids.append(srv.submit(p, B, ell, nug, tol, keep=resident > 0))
+        kinds.append("factor")
+        if resident > 0:
+            watch.append(len(ids) - 1)
     lat, met, worst = {1e-6: [], 1e-12: []}, 0, 0.0
-    statuses, missed = {}, []
-    for rid, r in zip(ids, reqs):
+    lat_solve = []
+    statuses, missed, precs, corr = {}, [], {}, 0
+    for rid, r, kind in zip(ids, reqs, kinds):
         st, _, eta, latency, info = srv.wait(rid, timeout=600.0, want_x=False)
         lat[r[4]].append(latency)
+        if kind == "solve":
+            lat_solve.append(latency)
         met += st == tc.CHOL_OK
         worst = max(worst, eta)
         statuses[str(st)] = statuses.get(str(st), 0) + 1
+        _, pr, c, _ = srv.request_info(rid)
+        precs[str(pr)] = precs.get(str(pr), 0) + 1
+        corr += c
         if st != tc.CHOL_OK and len(missed) < 8:
             missed.append({"n": r[1].shape[0], "nrhs": r[1].shape[1], "tol": r[4], "status": st, "info": info,
                            "eta": eta, "latency_ms": round(latency * 1e3, 1)})
     t_end = time.perf_counter()
     ticks = srv.ticks()
+    evictions = srv.evictions()
     srv.close()
     del arena
     torch.cuda.empty_cache()
     allv = sorted(lat[1e-6] + lat[1e-12])
     pct = lambda v, q: round(float(np.percentile(v, q)) * 1e3, 3) if v else None
     span = t_end - t0  # arrivals start at t0; the last wait returns at the last completion or later
-    return {"rate": rate, "requests": count, "server": mode, "met_tolerance": int(met),
-            "solves_per_s": round(met / span, 1), "span_s": round(span, 3), "ticks": ticks,
-            "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99),
-            "p50_ms_tol1e-6": pct(lat[1e-6], 50), "p99_ms_tol1e-6": pct(lat[1e-6], 99),
-            "p50_ms_tol1e-12": pct(lat[1e-12], 50), "p99_ms_tol1e-12": pct(lat[1e-12], 99),
-            "worst_eta": worst, "max_submit_lag_ms": round(lag * 1e3, 3), "statuses": statuses,
-            "missed": missed}
+    out = {"rate": rate, "requests": count, "server": mode, "met_tolerance": int(met),
+           "solves_per_s": round(met / span, 1), "span_s": round(span, 3), "ticks": ticks,
+           "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99),
+           "p50_ms_tol1e-6": pct(lat[1e-6], 50), "p99_ms_tol1e-6": pct(lat[1e-6], 99),
+           "p50_ms_tol1e-12": pct(lat[1e-12], 50), "p99_ms_tol1e-12": pct(lat[1e-12], 99),
+           "worst_eta": worst, "max_submit_lag_ms": round(lag * 1e3, 3), "statuses": statuses,
+           "precisions": precs, "corrections": corr, "missed": missed}
+    if resident > 0:
+        out.update({"resident_solves": len(lat_solve), "refused_evicted": refused, "evictions": evictions,
+                    "p50_ms_resident_solve": pct(lat_solve, 50), "p99_ms_resident_solve": pct(lat_solve, 99)})
+    return out
+
+
+def serve_summary(tc, rates=(500.0, 2000.0), seconds: float = 1.0):
+    """The serving figures of the contract line: for each rate, continuous
+    batching and the one-at-a-time FP64 baseline on the same Poisson stream
+    (min(2000, rate x seconds) requests), and at the highest rate the stream
+    with solves against resident factors."""
+    out = {"workload": "Poisson arrivals of factor + solve requests: SE kernel on n points uniform in [0,1]^2, "
+                       "n log-uniform in [64, 8192], lengthscale U[0.05, 0.5], nugget 1e-2, 1-8 right-hand "
+                       "sides, tolerance 1e-6 or 1e-12 (1/2 each); seed 4",
+           "rates": []}
+    for rate in rates:
+        count = int(min(2000, max(50, rate * seconds)))
+        row = {"rate": rate}
+        for mode in ("continuous", "fifo"):
+            r = serve_compare(tc, rate, count, 4, mode)
+            row[mode] = {k: r[k] for k in ("requests", "met_tolerance", "solves_per_s", "p50_ms", "p99_ms",
+                                          "p99_ms_tol1e-6", "p99_ms_tol1e-12", "worst_eta", "ticks",
+                                          "precisions", "corrections", "statuses")}
+        row["throughput_vs_fifo"] = round(row["continuous"]["solves_per_s"] / row["fifo"]["solves_per_s"], 2)
+        out["rates"].append(row)
+    r = serve_compare(tc, max(rates), int(min(2000, max(rates) * seconds)), 5, "continuous", resident=0.3)
+    out["resident"] = {k: r[k] for k in ("rate", "requests", "met_tolerance", "solves_per_s", "p50_ms", "p99_ms",
+                                         "resident_solves", "p50_ms_resident_solve", "p99_ms_resident_solve",
+                                         "refused_evicted", "evictions", "worst_eta")}
+    return out
 
 
 def main():
@@ -539,6 +623,9 @@ def main():
             count = int(min(2000, max(50, rate * args.serve_seconds)))
             for mode in ("continuous", "fifo"):
                 print(json.dumps({"kind": "serve", **serve_compare(tc, rate, count, 4, mode)}), flush=True)
+            if args.serve_resident > 0:
+                r = serve_compare(tc, rate, count, 5, "continuous", resident=args.serve_resident)
+                print(json.dumps({"kind": "serve_resident", **r}), flush=True)
         return
     if args.batched:
         for la in [int(x) for x in args.batch_lookaheads.split(",")]:
@@ -658,11 +745,16 @@ def main():
     if not args.no_mixed:
         print("[bench] mixed-precision comparison", file=sys.stderr, flush=True)
         out["mixed"] = mixed_compare(tc, A0, T, args.mixed_T)
+        if args.mixed_T2 and args.mixed_T2 != args.mixed_T:
+            out[f"mixed_T{args.mixed_T2}"] = mixed_compare(tc, A0, T, args.mixed_T2)
     del A0
     torch.cuda.empty_cache()
     if not args.no_batched:
         print("[bench] batched comparison", file=sys.stderr, flush=True)
         out["batched"] = batched_compare(tc, args.batch_count)
+    if not args.no_serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serve"] = serve_summary(tc)
     if sample is not None:
         print(f"[bench] cpu baseline on a {args.cpu_sample}^2 sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sample, args.cpu_sample)
