@@ -142,6 +142,8 @@ def parse():
     p.add_argument("--serve-resident", type=float, default=0.3,
                    help="--serve: also a stream where this fraction of arrivals are solves against resident factors")
     p.add_argument("--no-serve", action="store_true", help="leave the serving figures out of the contract line")
+    p.add_argument("--serve-plans", default=None,
+                   help="measure serving precision plans: 'loose,strict;...' (FP32 from these orders on)")
     p.add_argument("--batch-lookaheads", default="-1",
                    help="batched ticket order: bulk units per chain link of each matrix (comma list; -1 default)")
     return p.parse_args()
@@ -481,7 +483,7 @@ def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
 
 
 def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: float = 96.0,
-                  resident: float = 0.0):
+                  resident: float = 0.0, plan=None):
     """Submit `count` requests with exponential inter-arrival times (rate per
     second) to a fresh server, from this thread at their scheduled times,
     then collect every result.  Latency is the server's own: submission to
@@ -508,6 +510,8 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
     solve_draw = rng.random(count)
     arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
     srv = tc.Server(arena, 8 << 30, mode)
+    if plan is not None:
+        srv.set_plan(*plan)
     ids, lag, kinds = [], 0.0, []
     done_factors = []  # (factor handle, n, tol) of finished keep requests
     refused = 0
@@ -618,6 +622,15 @@ def main():
     if args.sweep:
         return sweep(args)
     from paper_2606_11937_amd import tilechol as tc
+    if args.serve_plans:
+        # the precision plan's thresholds, measured: (FP32 from n, loose; strict)
+        for pl in args.serve_plans.split(";"):
+            plan = tuple(int(x) for x in pl.split(","))
+            for rate in [float(x) for x in args.rates.split(",")]:
+                count = int(min(2000, max(50, rate * args.serve_seconds)))
+                r = serve_compare(tc, rate, count, 4, "continuous", plan=plan)
+                print(json.dumps({"kind": "serve_plan", "plan": plan, **r}), flush=True)
+        return
     if args.serve:
         for rate in [float(x) for x in args.rates.split(",")]:
             count = int(min(2000, max(50, rate * args.serve_seconds)))

@@ -425,6 +425,12 @@ int chol_server_wait(chol_server* server, int64_t id, double timeout_s, double* 
  * CHOL_EINVAL (unknown id). */
 int chol_server_request_info(chol_server* server, int64_t id, int64_t* factor, int* prec, int* corrections,
                              int* refactors);
+/* The precision plan of requests submitted from now on: FP32 trailing
+ * products for orders n >= fp32_min_n_loose when tol >= 1e-8, and for
+ * n >= fp32_min_n_strict below; FP64 otherwise (a value above 65536 turns
+ * FP32 off for that class).  The default is the measured table the library
+ * compiles in; this call is for measuring other plans. */
+int chol_server_set_plan(chol_server* server, int64_t fp32_min_n_loose, int64_t fp32_min_n_strict);
 /* Drop a resident factor; CHOL_ENOFACTOR if it is not resident or a pending
  * or running request still uses it. */
 int chol_server_release_factor(chol_server* server, int64_t factor);

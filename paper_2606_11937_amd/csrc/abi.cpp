@@ -557,6 +557,14 @@ int chol_server_release_factor(chol_server* server, int64_t factor) {
   return tc_server_release_factor(server->s, factor) == 0 ? CHOL_OK : CHOL_ENOFACTOR;
 }
 
+int chol_server_set_plan(chol_server* server, int64_t fp32_min_n_loose, int64_t fp32_min_n_strict) {
+  g_bad_arg = 0;
+  if (server == nullptr) return bad(1);
+  if (fp32_min_n_loose < 1) return bad(2);
+  if (fp32_min_n_strict < 1) return bad(3);
+  return tc_server_set_plan(server->s, fp32_min_n_loose, fp32_min_n_strict) == 0 ? CHOL_OK : CHOL_EDEVICE;
+}
+
 int64_t chol_server_evictions(chol_server* server) {
   if (server == nullptr) return bad(1);
   return tc_server_evictions(server->s);

@@ -130,6 +130,7 @@ int tc_server_wait(TcServer* S, int64_t id, double timeout_s, double* X, double*
                    int64_t* info);
 int tc_server_request_info(TcServer* S, int64_t id, int64_t* factor, int* prec, int* corrections, int* refactors);
 int tc_server_release_factor(TcServer* S, int64_t factor);
+int tc_server_set_plan(TcServer* S, int64_t fp32_min_n_loose, int64_t fp32_min_n_strict);
 int64_t tc_server_ticks(TcServer* S);
 int64_t tc_server_evictions(TcServer* S);
 int tc_server_destroy(TcServer* S);

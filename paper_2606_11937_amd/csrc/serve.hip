@@ -478,6 +478,15 @@ int tc_server_release_factor(TcServer* S, int64_t factor) {
   return S->core->release_factor(factor) ? 0 : TC_LAUNCH_ENOFACTOR;
 }
 
+int tc_server_set_plan(TcServer* S, int64_t fp32_min_n_loose, int64_t fp32_min_n_strict) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  tcs::PlanTable p = S->core->plans();
+  p.fp32_min_n_loose = fp32_min_n_loose;
+  p.fp32_min_n_strict = fp32_min_n_strict;
+  S->core->set_plans(p);
+  return 0;
+}
+
 int64_t tc_server_ticks(TcServer* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   return S->ticks;

@@ -241,6 +241,9 @@ class Core {
     pending_.push_back(id);
     return id;
   }
+  // The precision plan of requests submitted from now on.
+  void set_plans(const PlanTable& p) { plans_ = p; }
+  const PlanTable& plans() const { return plans_; }
   Request& req(int64_t id) { return *reqs_[id]; }
   const Request& req(int64_t id) const { return *reqs_[id]; }
   int64_t num_requests() const { return (int64_t)reqs_.size(); }

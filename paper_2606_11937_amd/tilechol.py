@@ -82,6 +82,7 @@ SIGNATURES = [
     ("chol_server_request_info", _int, [_vp, _i64, _pi64, ctypes.POINTER(_int), ctypes.POINTER(_int),
                                         ctypes.POINTER(_int)]),
     ("chol_server_release_factor", _int, [_vp, _i64]),
+    ("chol_server_set_plan", _int, [_vp, _i64, _i64]),
     ("chol_server_evictions", _i64, [_vp]),
     ("chol_server_wait", _int, [_vp, _i64, _dbl, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _pi64]),
     ("chol_server_ticks", _i64, [_vp]),
@@ -493,6 +494,13 @@ class Server:
 
     def release_factor(self, factor: int) -> bool:
         return lib.chol_server_release_factor(self.h, int(factor)) == CHOL_OK
+
+    def set_plan(self, fp32_min_n_loose: int, fp32_min_n_strict: int) -> None:
+        """FP32 trailing products from these orders on (per tolerance class)
+        for requests submitted from now on."""
+        st = lib.chol_server_set_plan(self.h, int(fp32_min_n_loose), int(fp32_min_n_strict))
+        if st != CHOL_OK:
+            raise TileCholError(st, "chol_server_set_plan", last_bad_arg())
 
     def evictions(self) -> int:
         return int(lib.chol_server_evictions(self.h))
