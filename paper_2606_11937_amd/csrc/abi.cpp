@@ -180,7 +180,7 @@ int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs) {
   if (n < 0 || n > kMaxN) return bad(1);
   if (T < 1) return bad(2);
   if (nrhs < 0) return bad(3);
-  return tc_solve_ws_bytes();
+  return tc_solve_ws_bytes(n, nrhs, false);
 }
 
 int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb, void* work,
@@ -195,7 +195,7 @@ int chol_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, in
   if (L == nullptr) return bad(1);
   if (B == nullptr) return bad(5);
   if (work == nullptr) return bad(8);
-  if (work_bytes < tc_solve_ws_bytes()) return bad(9, CHOL_EWORKSPACE);
+  if (work_bytes < tc_solve_ws_bytes(n, nrhs, false)) return bad(9, CHOL_EWORKSPACE);
   hipStream_t st = (hipStream_t)stream;
   if (tc_solve_status_reset(work, st) != 0) return CHOL_EDEVICE;
   return tc_launch_solve(L, n, lda, T, B, nrhs, ldb, work, st, wait_ticks()) == 0 ? CHOL_OK : CHOL_EDEVICE;

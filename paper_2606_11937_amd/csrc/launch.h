@@ -54,9 +54,10 @@ int tc_read_status(const void* work, hipStream_t st, int32_t* error, int64_t* in
 // Co-resident workgroups of the persistent kernels on the current device.
 int64_t tc_async_grid_size();
 int64_t tc_sync_grid_size();
-// Workspace bytes of the solve (block tickets and done counters, and a
-// status word).
-int64_t tc_solve_ws_bytes();
+// Workspace bytes of the solve of nrhs right-hand sides of order n: block
+// tickets, done counters and a status word, then the two sweeps' payloads
+// (inv: the sweeps with inverted diagonal blocks).
+int64_t tc_solve_ws_bytes(int64_t n, int64_t nrhs, bool inv);
 // The status word: cleared by tc_solve_status_reset (enqueued), set when a
 // sweep's dependency wait runs out, kept by the launches below (which clear
 // only their counters) until the next reset; tc_solve_status synchronises
@@ -67,9 +68,10 @@ int64_t tc_solve_status_offset();
 // Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks);
-// Repeated solves with one factor: invert the 64 x 64 diagonal blocks once
-// (tc_solve_inv_bytes of storage), then sweep with two matrix-core products
-// per block step.
+// Repeated solves with one factor: invert the 64 x 64 diagonal blocks and
+// form the coupling blocks of neighbouring block rows once
+// (tc_solve_inv_bytes of storage), then sweep with one matrix-core product
+// per block step on the chain.
 int64_t tc_solve_inv_bytes(int64_t n);
 int tc_launch_invert_diag(const double* L, int64_t n, int64_t lda, double* Dinv, hipStream_t st);
 int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* Dinv, double* B, int64_t nrhs,

@@ -43,8 +43,7 @@ __device__ __forceinline__ rf_v4d rf_mfma(double a, double b, rf_v4d c) {
 
 // ------------------------------------------------------------ A times X
 // Y = B - A X (Y = -A X when B is null) for symmetric A stored as its lower
-// triangle.  With ABS the entries enter as |A_ij| and X as all ones (row sums
-// of |A|; one column).  One workgroup per 64 rows; wave w owns rows
+// triangle.  One workgroup per 64 rows; wave w owns rows
 // 64 blockIdx + 16 w .. +15 and walks k = 0 .. n - 1 in 16-wide chunks,
 // reading A_ik from row i for k <= i and as A_ki from column i for k > i (so
 // every stored entry is read twice in all, once for each of its rows).
@@ -56,7 +55,6 @@ __device__ __forceinline__ rf_v4d rf_mfma(double a, double b, rf_v4d c) {
 // Loads are branch-free: indices are clamped into the stored triangle and
 // masked entries are selected away; the next chunk is loaded while the
 // current one is multiplied.
-template <bool ABS>
 __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restrict__ A, int64_t lda, int64_t n,
                                                          const double* __restrict__ X, int64_t ldx,
                                                          const double* __restrict__ B, int64_t ldb,
@@ -83,13 +81,9 @@ __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restric
         // k <= row: A[row][k] (row part); k > row: A[k][row] (column part)
         const bool low = kc <= rowc;
         const double v = low ? A[rowc * lda + kc] : A[kc * lda + rowc];
-        a[m] = (rowok && kin) ? (ABS ? fabs(v) : v) : 0.0;
-        if (ABS) {
-          x[m] = (colok && kin) ? 1.0 : 0.0;
-        } else {
-          const double xv = X[kc * ldx + colc];
-          x[m] = (colok && kin) ? xv : 0.0;
-        }
+        a[m] = (rowok && kin) ? v : 0.0;
+        const double xv = X[kc * ldx + colc];
+        x[m] = (colok && kin) ? xv : 0.0;
       }
     };
     // chunks in pairs, the next pair in flight while this one is multiplied
@@ -123,6 +117,81 @@ __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restric
   }
 }
 
+// ------------------------------------------------------- ||A||_inf
+// Row sums of |A| for symmetric A stored as its lower triangle:
+// s_i = sum_{k <= i} |A_ik| + sum_{k > i} |A_ki|.  Grid (64-row blocks I,
+// RF_SEG segments of the 64-wide k tiles); workgroup (I, g) adds the tiles
+// K of its segment: K <= I row-wise (entries k <= i of rows of block I,
+// lanes along k), K >= I column-wise (entries k > i of rows of block K,
+// lanes along i).  Each entry of the stored triangle is read once for each
+// row it belongs to.  Sums run in a fixed order: per lane over the tiles in
+// the workgroup's order, then the 64 lanes of a row by a butterfly (row side) or the
+// four waves in order (column side); the segments are added in order by
+// rf_rowabs_max.  Partial sums go to part[g * n + i].
+#define RF_SEG 8
+__global__ __launch_bounds__(RF_THREADS) void rf_rowabs(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                        double* __restrict__ part) {
+  __shared__ double colp[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t nb = (n + 63) / 64;
+  const int64_t I = blockIdx.x, i0 = I * 64;
+  const int64_t per = (nb + RF_SEG - 1) / RF_SEG;
+  const int64_t K0 = blockIdx.y * per, K1 = K0 + per < nb ? K0 + per : nb;
+  double racc[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) racc[rr] = 0.0;
+  double cacc = 0.0;
+  const int64_t ic = i0 + lane;  // column side: this lane's row i
+  // the segment's tiles from a start that depends on I, so that the
+  // workgroups running at one time read different column offsets
+  const int64_t len = K1 > K0 ? K1 - K0 : 0;
+  for (int64_t t = 0; t < len; ++t) {
+    const int64_t K = K0 + (t + I) % len;
+    const int64_t k0 = K * 64;
+    if (K <= I) {  // row side: rows i = i0 + 16 w + rr, k = k0 + lane
+      const int64_t k = k0 + lane;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int64_t i = i0 + 16 * w + rr;
+        const bool in = i < n && k <= i;
+        const double v = A[(in ? i : 0) * lda + (in ? k : 0)];
+        racc[rr] += in ? fabs(v) : 0.0;
+      }
+    }
+    if (K >= I) {  // column side: rows k = k0 + 16 w + rr, column i = ic
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int64_t k = k0 + 16 * w + rr;
+        const bool in = k < n && ic < n && k > ic;
+        const double v = A[(in ? k : 0) * lda + (in ? ic : 0)];
+        cacc += in ? fabs(v) : 0.0;
+      }
+    }
+  }
+  colp[w][lane] = cacc;
+  // row side: the 64 lanes of each row, butterfly
+  double mine = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    double v = racc[rr];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+    if (lane == rr) mine = v;  // row 16 w + rr
+  }
+  __syncthreads();
+  // thread (w, lane < 16) holds row 16 w + lane of the row side
+  if (lane < 16) {
+    const int r = 16 * w + lane;
+    const double c = ((colp[0][r] + colp[1][r]) + colp[2][r]) + colp[3][r];
+    if (i0 + r < n) part[blockIdx.y * n + i0 + r] = mine + c;
+  }
+}
+
+// anorm[0] = max_i sum_g part[g * n + i] (one workgroup; segments added in
+// order, then the fixed max tree)
+__global__ __launch_bounds__(RF_THREADS) void rf_rowabs_max(const double* __restrict__ part, int64_t n,
+                                                            double* anorm);
+
 // ------------------------------------------------------- column reductions
 // Fixed-order tree over the 256 threads of the workgroup.
 __device__ __forceinline__ double rf_block_reduce(double v, bool take_max) {
@@ -139,6 +208,18 @@ __device__ __forceinline__ double rf_block_reduce(double v, bool take_max) {
   const double r = red[0];
   __syncthreads();
   return r;
+}
+
+__global__ __launch_bounds__(RF_THREADS) void rf_rowabs_max(const double* __restrict__ part, int64_t n,
+                                                            double* anorm) {
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += RF_THREADS) {
+    double t = 0.0;
+    for (int g = 0; g < RF_SEG; ++g) t += part[g * n + i];
+    m = fmax(m, t);
+  }
+  m = rf_block_reduce(m, true);
+  if (threadIdx.x == 0) anorm[0] = m;
 }
 
 // out[c] = max_i |U[i][c]| (one workgroup per column c).
@@ -225,7 +306,7 @@ struct RfWs {
   void* solve_ws;
   double* dinv;                   // inverted 64 x 64 diagonal blocks of L
   double *R, *Z, *P, *Q;          // n x nrhs each, leading dimension nrhs
-  double* rowsum;                 // n
+  double* rowsum;                 // RF_SEG x n partial row sums of |A|
   double *anorm, *rmax, *xmax, *bmax, *eta, *rz, *rzn, *pq, *alpha, *beta;  // nrhs each (anorm: 1)
   int32_t *done, *zero, *mask;    // nrhs each
 };
@@ -234,7 +315,7 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
   RfWs w;
   char* p = (char*)work;
   w.solve_ws = p;
-  p += rf_r256(tc_solve_ws_bytes());
+  p += rf_r256(tc_solve_ws_bytes(n, nrhs, true));
   w.dinv = (double*)p;
   p += rf_r256(tc_solve_inv_bytes(n));
   const int64_t mat = rf_r256(8 * n * nrhs);
@@ -242,7 +323,7 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
   w.Z = (double*)p; p += mat;
   w.P = (double*)p; p += mat;
   w.Q = (double*)p; p += mat;
-  w.rowsum = (double*)p; p += rf_r256(8 * n);
+  w.rowsum = (double*)p; p += rf_r256(8 * n * RF_SEG);
   double** vecs[] = {&w.anorm, &w.rmax, &w.xmax, &w.bmax, &w.eta, &w.rz, &w.rzn, &w.pq, &w.alpha, &w.beta};
   for (double** v : vecs) {
     *v = (double*)p;
@@ -259,7 +340,7 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
 // Y = B - A X  (B null: Y = -A X)
 void rf_residual(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, const double* B, int64_t ldb,
                  double* Y, int64_t ldy, int64_t nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(rf_symv<false>, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y,
+  hipLaunchKernelGGL(rf_symv, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y,
                      ldy, nrhs);
 }
 
@@ -282,7 +363,7 @@ double rf_max(const std::vector<double>& v) {
 }  // namespace
 
 int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs) {
-  return rf_r256(tc_solve_ws_bytes()) + rf_r256(tc_solve_inv_bytes(n)) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n) + 10 * rf_r256(8 * nrhs) +
+  return rf_r256(tc_solve_ws_bytes(n, nrhs, true)) + rf_r256(tc_solve_inv_bytes(n)) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n * RF_SEG) + 10 * rf_r256(8 * nrhs) +
          3 * rf_r256(4 * nrhs);
 }
 
@@ -305,10 +386,8 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
   // one status word for every sweep of the call
   if (tc_solve_status_reset(w.solve_ws, st) != 0) return fail();
   // ||A||_inf from the row sums of |A|, and ||b||_inf per column
-  hipLaunchKernelGGL(rf_symv<true>, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n,
-                     (const double*)nullptr, (int64_t)1, (const double*)nullptr, (int64_t)1, w.rowsum, (int64_t)1,
-                     (int64_t)1);
-  hipLaunchKernelGGL(rf_colmax, dim3(1), dim3(RF_THREADS), 0, st, w.rowsum, (int64_t)1, n, w.anorm);
+  hipLaunchKernelGGL(rf_rowabs, dim3(rf_blocks(n, 64), RF_SEG), dim3(RF_THREADS), 0, st, A, lda, n, w.rowsum);
+  hipLaunchKernelGGL(rf_rowabs_max, dim3(1), dim3(RF_THREADS), 0, st, (const double*)w.rowsum, n, w.anorm);
   hipLaunchKernelGGL(rf_colmax, dim3((unsigned)nrhs), dim3(RF_THREADS), 0, st, B, ldb, n, w.bmax);
   // x0 = (L L^T)^-1 b
   hipLaunchKernelGGL(rf_copy, dim3(eb), dim3(256), 0, st, X, ldx, B, ldb, (const int32_t*)nullptr, n, nrhs);

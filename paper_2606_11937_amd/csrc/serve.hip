@@ -53,7 +53,8 @@ struct SrvDesc {
   const double* B;    // n x nrhs, the right-hand sides (kept)
   double* X;          // n x nrhs, the solution
   double* R;          // n x nrhs, residual / correction
-  double* stats;      // ||A||_inf, then per column max|r|, max|x|, max|b|, then eta
+  double* stats;      // ||A||_inf, then per column max|r|, max|x|, max|b|, then eta and the solve status
+  const int32_t* serr;  // the status word of the item's solve workspace
   int64_t n, nrhs;
   double inv2l2, nugget;
   int32_t item;       // tcs::ITEM_*
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(SRV_THREADS) void srv_prepare(const SrvDesc* __rest
   const SrvDesc d = items[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * SRV_THREADS + threadIdx.x;
   if (d.fresh && e < d.n * d.nrhs) d.X[e] = d.B[e];
-  if (blockIdx.x == 0 && threadIdx.x < 3 * d.nrhs + 2) d.stats[threadIdx.x] = 0.0;  // tcs::stats_doubles
+  if (blockIdx.x == 0 && threadIdx.x < 3 * d.nrhs + 3) d.stats[threadIdx.x] = 0.0;  // tcs::stats_doubles
 }
 
 // After a correction's solve: X += R.  Grid (row blocks of 256, items).
@@ -145,6 +146,7 @@ __global__ void srv_eta(const SrvDesc* __restrict__ items, int64_t count) {
     worst = e > worst || e != e ? e : worst;
   }
   d.stats[1 + 3 * d.nrhs] = worst;
+  d.stats[2 + 3 * d.nrhs] = (double)*d.serr;
 }
 
 // ------------------------------------------------------------ host runtime
@@ -212,6 +214,7 @@ bool launch_tick(TcServer& S, Flight& f) {
     D.nugget = R.nugget;
     D.item = it.item;
     D.fresh = it.item != tcs::ITEM_CORRECT;
+    D.serr = (const int32_t*)(S.arena + t.ws_off + t.solve_off[q] + tc_solve_status_offset());
     nmax = std::max(nmax, R.n);
     emax = std::max(emax, R.n * R.nrhs);
     // inputs of a request's first item through its pinned staging
@@ -258,21 +261,19 @@ bool launch_tick(TcServer& S, Flight& f) {
                      dim3(SRV_THREADS), 0, st, meta_d);
   // each item's solve, with a solve workspace (and status word) of its own:
   // of B (in X) for a new solution, of the residual R for a correction
-  char* sws = ws + t.solve_off;
-  const int64_t sb = r256(tc_solve_ws_bytes());
   for (int64_t q = 0; q < m; ++q) {
     const tcs::Request& R = *f.rq[q];
     double* rhs = desc[q].fresh ? desc[q].X : desc[q].R;
-    if (tc_solve_status_reset(sws + sb * q, st) != 0) return false;
-    if (tc_launch_solve(desc[q].L, R.n, R.n, 128, rhs, R.nrhs, R.nrhs, sws + sb * q, st, S.wait_ticks) != 0)
-      return false;
+    char* sws = ws + t.solve_off[q];
+    if (tc_solve_status_reset(sws, st) != 0) return false;
+    if (tc_launch_solve(desc[q].L, R.n, R.n, 128, rhs, R.nrhs, R.nrhs, sws, st, S.wait_ticks) != 0) return false;
   }
   hipLaunchKernelGGL(srv_apply, dim3((unsigned)((emax + SRV_THREADS - 1) / SRV_THREADS), (unsigned)m),
                      dim3(SRV_THREADS), 0, st, (const SrvDesc*)meta_d);
   hipLaunchKernelGGL(srv_residual, dim3((unsigned)((nmax + 63) / 64), (unsigned)m), dim3(SRV_THREADS), 0, st,
                      (const SrvDesc*)meta_d);
   hipLaunchKernelGGL(srv_eta, dim3((unsigned)((m + 63) / 64)), dim3(64), 0, st, (const SrvDesc*)meta_d, m);
-  // results: status headers of the factorizations, solve statuses, X and eta
+  // results: status headers of the factorizations, X, eta and the solve status
   char* hdr_pin = S.pinned + t.meta_pin + t.hdr_off;
   if (!A.empty()) {
     const char* hdr_dev = S.mode == 0 ? ws + 256 : ws;  // batched: per-matrix headers after the ticket
@@ -280,15 +281,13 @@ bool launch_tick(TcServer& S, Flight& f) {
         hipSuccess)
       return false;
   }
-  if (hipMemcpyAsync(S.pinned + t.meta_pin + t.sv_off, sws, sb * m, hipMemcpyDeviceToHost, st) != hipSuccess)
-    return false;
   for (int64_t q = 0; q < m; ++q) {
     const tcs::Request& R = *f.rq[q];
     char* h = S.pinned + R.pin_off;
     double* hx = (double*)(h + r256(16 * R.n) + r256(8 * R.n * R.nrhs));
     double* he = (double*)(h + r256(16 * R.n) + 2 * r256(8 * R.n * R.nrhs));
     if (hipMemcpyAsync(hx, desc[q].X, 8 * R.n * R.nrhs, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
-    if (hipMemcpyAsync(he, desc[q].stats + 1 + 3 * R.nrhs, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+    if (hipMemcpyAsync(he, desc[q].stats + 1 + 3 * R.nrhs, 16, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
   }
   if (hipEventRecord(f.done, st) != hipSuccess) return false;
   return hipGetLastError() == hipSuccess;
@@ -296,19 +295,19 @@ bool launch_tick(TcServer& S, Flight& f) {
 
 void finish_tick(TcServer& S, Flight& f) {
   const tcs::Tick& t = f.t;
-  const int64_t hb = tc_ws_header_bytes(), sb = r256(tc_solve_ws_bytes()), m = (int64_t)t.items.size();
+  const int64_t hb = tc_ws_header_bytes(), m = (int64_t)t.items.size();
   std::vector<tcs::ItemResult> res(m);
   for (int64_t q = 0; q < m; ++q) {
     tcs::Request& R = S.core->req(t.items[q].req);
     const char* h = S.pinned + R.pin_off;
     const double* hx = (const double*)(h + r256(16 * R.n) + r256(8 * R.n * R.nrhs));
     const double* he = (const double*)(h + r256(16 * R.n) + 2 * r256(8 * R.n * R.nrhs));
-    res[q].eta = *he;
+    res[q].eta = he[0];
+    res[q].solve_err = (int32_t)he[1];
     R.X.assign(hx, hx + R.n * R.nrhs);
     if (f.fac_index[q] >= 0)
       tc_ws_header_read(S.pinned + t.meta_pin + t.hdr_off + hb * f.fac_index[q], &res[q].factor_err,
                         &res[q].factor_info);
-    memcpy(&res[q].solve_err, S.pinned + t.meta_pin + t.sv_off + sb * q + tc_solve_status_offset(), 4);
   }
   S.core->finish(t, res, now_ns());
   for (int64_t id : S.core->take_finished()) {
@@ -329,7 +328,7 @@ tcs::WsSizer make_sizer() {
   };
   z.fifo = [](int64_t n) { return tc_ws_bytes(n, tc_default_tile(n)); };
   z.tile = [](int64_t n, int prec) { return tc_tuned_batched_tile_prec(n, prec); };
-  z.solve_ws = tc_solve_ws_bytes();
+  z.solve_ws = [](int64_t n, int64_t nrhs) { return tc_solve_ws_bytes(n, nrhs, false); };
   z.header = tc_ws_header_bytes();
   z.desc = (int64_t)sizeof(SrvDesc);
   return z;

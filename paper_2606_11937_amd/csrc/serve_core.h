@@ -116,11 +116,12 @@ struct PlanTable {
 
 // Device bytes of the pieces of a request.
 inline int64_t factor_bytes(int64_t n) { return r256(8 * n * n) + r256(16 * n); }  // L (n x n) + points
-inline int64_t stats_doubles(int64_t nrhs) { return 1 + 3 * nrhs + 1; }
+// ||A||_inf, per column max|r|, max|x|, max|b|, then eta and the solve's status word
+inline int64_t stats_doubles(int64_t nrhs) { return 1 + 3 * nrhs + 2; }
 inline int64_t work_bytes(int64_t n, int64_t nrhs) {  // B, X, R, stats
   return 3 * r256(8 * n * nrhs) + r256(8 * stats_doubles(nrhs));
 }
-// pinned bytes: points and B in, X and eta out
+// pinned bytes: points and B in, X, eta and the solve status out
 inline int64_t pin_bytes(int64_t n, int64_t nrhs) { return r256(16 * n) + 2 * r256(8 * n * nrhs) + r256(8); }
 
 struct Request {
@@ -160,8 +161,9 @@ struct TickItem {
 struct Tick {
   std::vector<TickItem> items;
   int stream = 0;
-  int64_t ws_off = -1, ws_bytes = 0, solve_off = 0, meta_dev = -1, meta_bytes = 0;
-  int64_t meta_pin = -1, pin_meta_bytes = 0, hdr_off = 0, sv_off = 0;
+  int64_t ws_off = -1, ws_bytes = 0, meta_dev = -1, meta_bytes = 0;
+  int64_t meta_pin = -1, pin_meta_bytes = 0, hdr_off = 0;
+  std::vector<int64_t> solve_off;  // per item: its solve workspace, from ws_off
   int64_t seq = 0;
 };
 
@@ -181,7 +183,8 @@ struct WsSizer {
       batched;
   std::function<int64_t(int64_t)> fifo;  // one-at-a-time factorization workspace of order n
   std::function<int64_t(int64_t, int)> tile;  // tile side of order n and precision
-  int64_t solve_ws = 256;   // one solve workspace
+  // one item's solve workspace, of order n with nrhs right-hand sides
+  std::function<int64_t(int64_t, int64_t)> solve_ws = [](int64_t, int64_t) { return (int64_t)256; };
   int64_t header = 24;      // one factorization status header
   int64_t desc = 128;       // one item descriptor
 };
@@ -488,12 +491,17 @@ class Core {
       }
     int64_t head = 0;
     if (!n.empty()) head = r256(mode_ == 0 ? sz_.batched(n, T, p) : sz_.fifo(n[0]));
-    t.solve_off = head;
-    t.ws_bytes = head + r256(sz_.solve_ws) * m;
+    t.solve_off.assign(m, 0);
+    int64_t off = head;
+    for (int64_t q = 0; q < m; ++q) {
+      const Request& R = *reqs_[t.items[q].req];
+      t.solve_off[q] = off;
+      off += r256(sz_.solve_ws(R.n, R.nrhs));
+    }
+    t.ws_bytes = off;
     t.meta_bytes = r256(sz_.desc * m);
     t.hdr_off = t.meta_bytes;
-    t.sv_off = t.hdr_off + r256(sz_.header * std::max<int64_t>(m, 1));
-    t.pin_meta_bytes = t.sv_off + r256(sz_.solve_ws) * m;
+    t.pin_meta_bytes = t.hdr_off + r256(sz_.header * std::max<int64_t>(m, 1));
     if (!fits_or_evict(dev_, t.ws_bytes, &t.ws_off)) t.ws_off = -1;
     if (t.ws_off >= 0 && !fits_or_evict(dev_, t.meta_bytes, &t.meta_dev)) t.meta_dev = -1;
     t.meta_pin = t.meta_dev >= 0 ? pin_.alloc(t.pin_meta_bytes) : -1;

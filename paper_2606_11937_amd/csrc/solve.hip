@@ -107,6 +107,61 @@ __device__ __forceinline__ double sv_readlane(double v, int l) {
   return __builtin_bit_cast(double, (int64_t)(((uint64_t)hi << 32) | lo));
 }
 
+// ------------------------------------------------------------ hand-off
+// The solved entries of a block reach the workgroups that fold them as data,
+// not behind a counter: the owner stores them as relaxed device-scope 64-bit
+// atomics into a payload buffer that held a sentinel, and a reader loads
+// them the same way until none is the sentinel.  Each entry is written once
+// per sweep, so an entry that is not the sentinel is final; no fence is
+// needed on either side (with a counter the publisher must write back its
+// L2 and the reader invalidate its own).  The sentinel is a signalling NaN,
+// which no arithmetic result is; an entry with its bit pattern is stored as
+// the default quiet NaN instead.
+// Payload layout: block-major, [block][64 rows][PW columns], PW = 2 for the
+// one- and two-column sweeps and 16 for the others; rows past n and columns
+// past the right-hand sides are stored as zero.
+#define SV_SENTINEL 0x7FF4A5A5A5A5A5A5ull
+#define SV_QNAN 0x7FF8000000000000ull
+
+__device__ __forceinline__ double sv_pay_ld(const double* p) {
+  return __builtin_bit_cast(double,
+                            __hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void sv_pay_st(double* p, double v) {
+  uint64_t b = __builtin_bit_cast(uint64_t, v);
+  b = b == SV_SENTINEL ? SV_QNAN : b;
+  __hip_atomic_store((uint64_t*)p, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool sv_pending(double v) { return __builtin_bit_cast(uint64_t, v) == SV_SENTINEL; }
+
+// Wave-level wait for a payload block: while `pending` (this lane still
+// holds a sentinel) is true for some lane, the wave polls one entry of the
+// block (`probe`, the same address in every lane) until it is no longer the
+// sentinel, then reissues `load` and checks again.  Returns false when the
+// status word is set or the wait limit runs out (which sets it).  Every lane
+// of the wave takes the same path.
+template <class Load, class Pending>
+__device__ __forceinline__ bool sv_wave_wait(const double* probe, Load load, Pending pending, SvWs* ws,
+                                             int64_t wait_ticks) {
+  if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t it = 0;; ++it) {
+    // the status word and the clock every 16th poll (every waiting wave
+    // reads the same status word)
+    if ((it & 15) == 0) {
+      if (sv_ld(&ws->error)) return false;
+      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
+        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (sv_pending(sv_pay_ld(probe))) continue;
+    load();
+    if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  }
+}
+
 // Stage the diagonal block strictly lower (zero on and above the diagonal)
 // and the reciprocals of its diagonal (every thread of the workgroup takes
 // part).  Rows past nr take a unit pivot.  rdiag is written after the
@@ -740,17 +795,25 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
 
 // ------------------------------------------- sweeps with inverted diagonals
 // For repeated solves with one factor (refinement), the 64 x 64 diagonal
-// blocks are inverted once (sv_invert_diag, by substitution against the
-// identity), and each block step of the sweeps becomes two matrix-core
-// products: the fold of the finished blocks as above, then y_b = D_b v
-// (forward) or x_b = D_b^T v (backward) with D_b = L_bb^-1 and v the folded
-// right-hand side.  No sequential substitution remains on the chain.  The
-// inverse is accurate to about kappa(L_bb) u, which the refinement corrects
-// along with the error of the factor itself; the plain solve keeps
+// blocks are inverted once per call (sv_invert_diag, by substitution
+// against the identity), D_b = L_bb^-1, and so are the coupling blocks of
+// neighbouring block rows (sv_couple):
+//   P_b = -D_b L_{b,b-1}          (forward),
+//   Q_b = -D_b^T L_{b+1,b}^T      (backward).
+// The forward sweep then takes y_b = c_b + P_b y_{b-1} with
+// c_b = D_b (B_b - sum_{j < b-1} L_bj y_j), and the backward sweep
+// x_b = d_b + Q_b x_{b+1} with d_b = D_b^T (y_b - sum_{j > b+1} L_jb^T x_j).
+// A workgroup computes c_b (or d_b) while it still waits for its neighbour,
+// so a block step on the chain is one 64 x 64 by 64 x 16 product per wave
+// (each wave its 16 rows), with no workgroup barrier.  The inverses and
+// couplings are accurate to about kappa(L_bb) u, which the refinement
+// corrects along with the error of the factor itself; the plain solve keeps
 // substitution.
 //
-// D_b is stored row-major, 64 x 64 per block, zero above the diagonal (and
-// the identity on rows past n in the last block).
+// Storage (tc_solve_inv_bytes): D, then P, then Q, each 64 x 64 row-major per
+// block.  D is zero above the diagonal and the identity on rows past n in
+// the last block; P and Q are zero where the factor has no entries (P_0,
+// Q_{nb-1}, rows or columns past n).
 __global__ __launch_bounds__(SV_THREADS) void sv_invert_diag(const double* __restrict__ L, int64_t lda, int64_t n,
                                                              double* __restrict__ Dinv) {
   __shared__ double Lbb[SV_NB][SV_NB + 1];
@@ -773,18 +836,96 @@ __global__ __launch_bounds__(SV_THREADS) void sv_invert_diag(const double* __res
   }
 }
 
+// P_b and Q_b from D (sv_invert_diag's output, an earlier launch) and L.
+// One workgroup per block; thread (w, lane) computes entries (row r, column
+// lane) for r = w, w + 4, ..., each a 64-term sum in ascending k.
+__global__ __launch_bounds__(SV_THREADS) void sv_couple(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                        const double* __restrict__ Dinv, double* __restrict__ P,
+                                                        double* __restrict__ Q) {
+  __shared__ double Db[SV_NB][SV_NB + 1];
+  __shared__ double Lc[SV_NB][SV_NB + 1];
+  const int32_t b = blockIdx.x;
+  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* D = Dinv + (int64_t)b * SV_NB * SV_NB;
+  for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) Db[e / SV_NB][e % SV_NB] = D[e];
+  // Lc = L_{b,b-1} (rows past n zero)
+  for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    Lc[i][k] = (b > 0 && r0 + i < n) ? L[(r0 + i) * lda + r0 - SV_NB + k] : 0.0;
+  }
+  __syncthreads();
+  double* Pb = P + (int64_t)b * SV_NB * SV_NB;
+  for (int r = w; r < SV_NB; r += 4) {
+    double acc = 0.0;
+    for (int k = 0; k < SV_NB; ++k) acc = fma(Db[r][k], Lc[k][lane], acc);
+    Pb[r * SV_NB + lane] = -acc;
+  }
+  __syncthreads();
+  // Lc = L_{b+1,b} (rows past n zero)
+  for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    const int64_t row = r0 + SV_NB + i;
+    Lc[i][k] = (b + 1 < nb && row < n) ? L[row * lda + r0 + k] : 0.0;
+  }
+  __syncthreads();
+  // Q_b[r][c] = -sum_k D_b[k][r] L_{b+1,b}[c][k]
+  double* Qb = Q + (int64_t)b * SV_NB * SV_NB;
+  for (int r = w; r < SV_NB; r += 4) {
+    double acc = 0.0;
+    for (int k = 0; k < SV_NB; ++k) acc = fma(Db[k][r], Lc[lane][k], acc);
+    Qb[r * SV_NB + lane] = -acc;
+  }
+}
+
 // D_b into LDS (the barrier that follows the fold publishes it).
 __device__ __forceinline__ void sv_stage_inv(const double* __restrict__ D, double (*Ds)[SV_NB + 1]) {
   for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) Ds[e / SV_NB][e % SV_NB] = D[e];
 }
 
+// Wave-level wait for a whole payload block by reloading it (one round trip
+// per check; used for the one block on the chain, which one workgroup at a
+// time waits for).  Same contract as sv_wave_wait.
+template <class Load, class Pending>
+__device__ __forceinline__ bool sv_wave_wait_full(Load load, Pending pending, SvWs* ws, int64_t wait_ticks) {
+  if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t it = 0;; ++it) {
+    if ((it & 15) == 0) {
+      if (sv_ld(&ws->error)) return false;
+      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
+        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    load();
+    if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  }
+}
+
+// The forward sweep reads its own rows of the right-hand side from B and
+// publishes y_b into the payload Ypay (it does not write B); the backward
+// sweep reads y_b from Ypay, publishes x_b into Xpay and writes it to B.
+// Both payloads have 16 columns.  The forward sweep also resets its block of
+// Xpay to the sentinel for the backward sweep (a later launch).
+// Fold layout (matrix cores): wave w owns rows 16 w .. 16 w + 15 of the block
+// and the 16 payload columns, so it reads whole 512-byte row segments of L;
+// in a 16-wide k chunk ch, lane (r, g) brings k = 16 ch + 4 g + m to MFMA m
+// for both operands.  Rounding order per output entry: the folded blocks in
+// sweep order, each as 16 MFMAs in (chunk, m) order; the subtraction from B;
+// the product with D_b; then the product with the coupling block added to
+// it.
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                            const double* __restrict__ Dinv, double* __restrict__ B,
-                                                            int64_t nc, int64_t ldb, SvWs* ws, int64_t wait_ticks) {
+                                                            const double* __restrict__ Dinv,
+                                                            const double* __restrict__ P,
+                                                            const double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                            double* Ypay, double* __restrict__ Xpay, SvWs* ws,
+                                                            int64_t wait_ticks) {
   __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double yl[SV_NB][SV_MF_RC + 1];  // y_{b-1}, handed over by wave 0
   __shared__ double Ds[SV_NB][SV_NB + 1];
-  __shared__ int32_t s_b, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ int32_t s_b, s_ok;
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -796,8 +937,12 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
   const bool alive = arow < nr;
   const bool bok = r16 < nc;
   const double* lrow = L + (r0 + (alive ? arow : 0)) * lda + g4;
-  const double* ycol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
+  // payload column r16, rows 4 g .. of every earlier block (columns past nc
+  // are published as zero)
+  const double* ypay = Ypay + (int64_t)g4 * SV_MF_RC + r16;
   sv_stage_inv(Dinv + (int64_t)b * SV_NB * SV_NB, Ds);  // D_b, staged before any wait
+  for (int e = tid; e < SV_NB * SV_MF_RC; e += SV_THREADS)
+    Xpay[(int64_t)b * SV_NB * SV_MF_RC + e] = __builtin_bit_cast(double, SV_SENTINEL);
   auto load_l = [&](int32_t j, double* a) {
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
@@ -811,71 +956,139 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const double v = ycol[((int64_t)j * SV_NB + 16 * ch + m) * ldb];
-        y[4 * ch + m] = bok ? v : 0.0;
-      }
+      for (int m = 0; m < 4; ++m) y[4 * ch + m] = sv_pay_ld(ypay + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
   };
-  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  double la[16], ya[16];
-  bool have_y = false;
-  if (b > 0) load_l(0, la);
-  int32_t j = 0;
-  while (j < b) {
-    const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-    if (ready < 0) {
-        ok = false;
-        break;
-      }
-    const int32_t jend = ready < b ? ready : b;
-    for (; j < jend; ++j) {
-      if (!have_y) load_y(j, ya);
-      const int32_t jn = j + 1 < b ? j + 1 : j;
-      double ln[16], yn[16];
-      load_l(jn, ln);
-      have_y = j + 1 < jend;
-      if (have_y) load_y(j + 1, yn);
+  // read before any wait: the own rows of the right-hand side, the coupling
+  // block P_b (row arow), and the last folded tile L_{b,b-2}
+  double bown[4];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    bown[q] = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
+  }
+  double pc[16];
+  {
+    const double* pr = P + (int64_t)b * SV_NB * SV_NB + (int64_t)arow * SV_NB + g4;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) pc[4 * ch + m] = pr[16 * ch + m];
+  }
+  const int32_t nfold = b > 1 ? b - 1 : 0;  // blocks 0 .. b - 2 are folded
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double lt[16], la[16], ya[16];
+  bool ok = true;  // no wait of this wave aborted
+  if (nfold > 0) {
+    load_l(nfold - 1, lt);
+    load_y(0, ya);
+  }
+  if (nfold > 1) load_l(0, la);
+  auto pending = [&] {
+    bool p = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) p = p || sv_pending(ya[k]);
+    return p;
+  };
+  // the probe: the block's last entry
+  auto probe = [&](int32_t j) { return Ypay + ((int64_t)j * SV_NB + SV_NB - 1) * SV_MF_RC + SV_MF_RC - 1; };
+  // the folded blocks but the last, in order; the next block's tile (unless
+  // it is the last) and its payload are loaded while this one is folded
+  for (int32_t j = 0; j + 1 < nfold; ++j) {
+    if (!sv_wave_wait(probe(j), [&] { load_y(j, ya); }, pending, ws, wait_ticks)) {
+      ok = false;
+      break;
+    }
+    const int32_t jn = j + 1;
+    const bool more = jn + 1 < nfold;
+    double ln[16], yn[16];
+    if (more) load_l(jn, ln);
+    load_y(jn, yn);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+    if (more) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) la[k] = ln[k];
-      if (have_y) {
+    }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) ya[k] = yn[k];
-      }
+    for (int k = 0; k < 16; ++k) ya[k] = yn[k];
+  }
+  if (ok && nfold > 0) {
+    if (sv_wave_wait(probe(nfold - 1), [&] { load_y(nfold - 1, ya); }, pending, ws, wait_ticks)) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(lt[k], ya[k], acc);
+    } else {
+      ok = false;
     }
   }
+  // the previous block's payload (wave 0), speculatively (checked below)
+  if (ok && b > 0 && w == 0) load_y(b - 1, ya);
   // v = B_b - fold, into part (rows past nr and columns past nc are zero)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int row = 16 * w + 4 * q + (lane >> 4);
-    const double bv = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
-    part[row][r16] = (row < nr && bok) ? bv - acc[q] : 0.0;
+    part[row][r16] = (row < nr && bok) ? bown[q] - acc[q] : 0.0;
   }
   __syncthreads();
-  // y_b = D_b v: rows 16 w .., right-hand side r16
+  // c_b = D_b v: rows 16 w .., right-hand side r16
   sv_v4d y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
     for (int m = 0; m < 4; ++m) y = sv_mfma(Ds[arow][16 * ch + g4 + m], part[16 * ch + g4 + m][r16], y);
+  // the chain: y_b = c_b + P_b y_{b-1}.  Every wave needs the same operand
+  // fragments of y_{b-1}; wave 0 alone waits for them and hands them over
+  // through LDS, so the waves finish (and publish) together.
+  if (b > 0) {
+    if (w == 0) {
+      bool got = ok && sv_wave_wait_full([&] { load_y(b - 1, ya); }, pending, ws, wait_ticks);
+      if (got) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4);
-    if (row < nr && bok) B[(r0 + row) * ldb + r16] = y[q];
+        for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) yl[16 * ch + g4 + m][r16] = ya[4 * ch + m];
+      }
+      if (lane == 0) s_ok = got;
+    }
+    __syncthreads();
+    ok = ok && s_ok;
+    if (ok) {
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) y = sv_mfma(pc[4 * ch + m], yl[16 * ch + g4 + m][r16], y);
+    }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  sv_publish(&ws->done_f, b, 1, ok);
+  // the waves publish their rows unless a wait aborted (then the status
+  // word is set and every waiter leaves)
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * w + 4 * q + (lane >> 4);
+      sv_pay_st(Ypay + ((int64_t)b * SV_NB + row) * SV_MF_RC + r16, (row < nr && bok) ? y[q] : 0.0);
+    }
+  }
 }
 
+// The backward sweep's fold splits k across the waves: wave w takes rows
+// 16 w .. 16 w + 15 of every later block j, for all 64 output rows (columns
+// r0 .. r0 + 63 of L), so it reads whole 512-byte row segments of L and only
+// the 16 payload rows that wave w of block j's workgroup publishes.  MFMA
+// (o, kc): output rows 16 o .., k rows 16 w + 4 kc + g; A lane (r, g) holds
+// L[j0 + 16 w + 4 kc + g][r0 + 16 o + r], B lane (r, g) holds
+// x_j[16 w + 4 kc + g][r].  Rounding order per output entry: each wave sums
+// its blocks in sweep order, each as 4 MFMAs in kc order; the waves' sums
+// are combined as (w0 + w2) + (w1 + w3); then the subtraction from y_b, the
+// product with D_b^T, and the coupling product added to it.
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                            const double* __restrict__ Dinv, double* __restrict__ B,
-                                                            int64_t nc, int64_t ldb, SvWs* ws, int64_t wait_ticks) {
-  __shared__ double part[SV_NB][SV_MF_RC + 1];
+                                                            const double* __restrict__ Dinv,
+                                                            const double* __restrict__ Q, double* __restrict__ B,
+                                                            int64_t nc, int64_t ldb, const double* __restrict__ Ypay,
+                                                            double* Xpay, SvWs* ws, int64_t wait_ticks) {
+  __shared__ double red[2][SV_NB][SV_MF_RC + 1];  // partial sums; red[0] then holds v
+  __shared__ double xl[SV_NB][SV_MF_RC + 1];      // x_{b+1}, handed over by wave 0
   __shared__ double Ds[SV_NB][SV_NB + 1];
-  __shared__ int32_t s_t, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ int32_t s_t, s_ok;
+  double(*part)[SV_MF_RC + 1] = red[0];
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -884,89 +1097,177 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
   const int32_t b = nb - 1 - t;
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4, g = lane >> 4;
   const int arow = 16 * w + r16;
-  const bool alive = arow < nr;
   const bool bok = r16 < nc;
-  const double* lcol = L + (int64_t)g4 * lda + r0 + (alive ? arow : 0);
-  const double* xcol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
   sv_stage_inv(Dinv + (int64_t)b * SV_NB * SV_NB, Ds);
+  // tile of block j: a[4 o + kc] (rows past n and columns past n read as zero)
   auto load_l = [&](int32_t j, double* a) {
     const int64_t j0 = (int64_t)j * SV_NB;
     const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kr = 16 * w + 4 * kc + g;
+      const bool kin = kr < njr;
+      const double* rowp = L + (j0 + (kin ? kr : 0)) * lda + r0;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int kk = 16 * ch + g4 + m;
-        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
-        const double v = lcol[(j0 + ks) * lda];
-        a[4 * ch + m] = (alive && kk < njr) ? v : 0.0;
-      }
-  };
-  auto load_x = [&](int32_t j, double* x) {
-    const int64_t j0 = (int64_t)j * SV_NB;
-    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int kk = 16 * ch + g4 + m;
-        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
-        const double v = xcol[(j0 + ks) * ldb];
-        x[4 * ch + m] = (bok && kk < njr) ? v : 0.0;
-      }
-  };
-  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  double la[16], xa[16];
-  bool have_x = false;
-  if (b < nb - 1) load_l(nb - 1, la);
-  int32_t j = nb - 1;
-  while (j > b) {
-    const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-    if (ready < 0) {
-        ok = false;
-        break;
-      }
-    const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
-    for (; j >= jlow; --j) {
-      if (!have_x) load_x(j, xa);
-      const int32_t jn = j - 1 > b ? j - 1 : j;
-      double ln[16], xn[16];
-      load_l(jn, ln);
-      have_x = j - 1 >= jlow;
-      if (have_x) load_x(j - 1, xn);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], xa[k], acc);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) la[k] = ln[k];
-      if (have_x) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) xa[k] = xn[k];
+      for (int o = 0; o < 4; ++o) {
+        const int col = 16 * o + r16;
+        const bool cin = col < nr;
+        const double v = rowp[cin ? col : 0];
+        a[4 * o + kc] = (kin && cin) ? v : 0.0;
       }
     }
-  }
+  };
+  // this wave's payload rows of block j: x[kc]
+  auto load_xk = [&](int32_t j, double* x) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+      x[kc] = sv_pay_ld(Xpay + ((int64_t)j * SV_NB + 16 * w + 4 * kc + g) * SV_MF_RC + r16);
+  };
+  // the whole payload of block j in the chain product's layout (wave 0)
+  auto load_x = [&](int32_t j, double* x) {
+    const double* xp = Xpay + (int64_t)g4 * SV_MF_RC + r16;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[4 * ch + m] = sv_pay_ld(xp + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
+  };
+  // read before any wait: the own rows of y (published by the forward sweep,
+  // an earlier launch), the coupling block Q_b (row arow), and the last
+  // folded tile, rows of block b + 2
+  double yown[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4);
-    const double bv = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
-    part[row][r16] = (row < nr && bok) ? bv - acc[q] : 0.0;
+    const int row = 16 * w + 4 * q + g;
+    yown[q] = Ypay[((int64_t)b * SV_NB + row) * SV_MF_RC + r16];
+  }
+  double qc[16];
+  {
+    const double* qr = Q + (int64_t)b * SV_NB * SV_NB + (int64_t)arow * SV_NB + g4;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) qc[4 * ch + m] = qr[16 * ch + m];
+  }
+  const int32_t jlast = b + 2;  // blocks nb - 1 down to b + 2 are folded
+  sv_v4d acc[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) acc[o] = (sv_v4d){0.0, 0.0, 0.0, 0.0};
+  double lt[16], la[16], xa[4];
+  bool ok = true;
+  if (jlast < nb) {
+    load_l(jlast, lt);
+    load_xk(nb - 1, xa);
+  }
+  if (jlast < nb - 1) load_l(nb - 1, la);
+  auto pending = [&] { return sv_pending(xa[0]) || sv_pending(xa[1]) || sv_pending(xa[2]) || sv_pending(xa[3]); };
+  // the probe: the last entry of this wave's payload rows
+  auto probe = [&](int32_t j) { return Xpay + ((int64_t)j * SV_NB + 16 * w + 15) * SV_MF_RC + SV_MF_RC - 1; };
+  auto fold = [&](const double* a, const double* x) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc[o] = sv_mfma(a[4 * o + kc], x[kc], acc[o]);
+  };
+  for (int32_t j = nb - 1; j > jlast; --j) {
+    if (!sv_wave_wait(probe(j), [&] { load_xk(j, xa); }, pending, ws, wait_ticks)) {
+      ok = false;
+      break;
+    }
+    const int32_t jn = j - 1;
+    const bool more = jn > jlast;
+    double ln[16], xn[4];
+    if (more) load_l(jn, ln);
+    load_xk(jn, xn);
+    fold(la, xa);
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) la[k] = ln[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xa[k] = xn[k];
+  }
+  if (ok && jlast < nb) {
+    if (sv_wave_wait(probe(jlast), [&] { load_xk(jlast, xa); }, pending, ws, wait_ticks))
+      fold(lt, xa);
+    else
+      ok = false;
+  }
+  double xc[16];  // the chain's operand (wave 0), loaded speculatively
+  if (ok && b + 1 < nb && w == 0) load_x(b + 1, xc);
+  // combine the waves' sums: red[0] = w0 + w2, red[1] = w1 + w3
+  if (w < 2) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[w][16 * o + 4 * q + g][r16] = acc[o][q];
   }
   __syncthreads();
-  // x_b = D_b^T v
+  if (w >= 2) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[w - 2][16 * o + 4 * q + g][r16] += acc[o][q];
+  }
+  __syncthreads();
+  // v = y_b - fold into part (= red[0]; each entry read and rewritten by the
+  // same thread; rows past nr and columns past nc are zero)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + g;
+    const double f = red[0][row][r16] + red[1][row][r16];
+    part[row][r16] = (row < nr && bok) ? yown[q] - f : 0.0;
+  }
+  __syncthreads();
+  // d_b = D_b^T v
   sv_v4d x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
     for (int m = 0; m < 4; ++m) x = sv_mfma(Ds[16 * ch + g4 + m][arow], part[16 * ch + g4 + m][r16], x);
+  // the chain: x_b = d_b + Q_b x_{b+1}, x_{b+1} handed over by wave 0
+  if (b + 1 < nb) {
+    if (w == 0) {
+      auto pend16 = [&] {
+        bool p = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p = p || sv_pending(xc[k]);
+        return p;
+      };
+      bool got = ok && sv_wave_wait_full([&] { load_x(b + 1, xc); }, pend16, ws, wait_ticks);
+      if (got) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) xl[16 * ch + g4 + m][r16] = xc[4 * ch + m];
+      }
+      if (lane == 0) s_ok = got;
+    }
+    __syncthreads();
+    ok = ok && s_ok;
+    if (ok) {
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x = sv_mfma(qc[4 * ch + m], xl[16 * ch + g4 + m][r16], x);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4);
+    const int row = 16 * w + 4 * q + g;
     if (row < nr && bok) B[(r0 + row) * ldb + r16] = x[q];
+    if (ok) sv_pay_st(Xpay + ((int64_t)b * SV_NB + row) * SV_MF_RC + r16, (row < nr && bok) ? x[q] : 0.0);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  sv_publish(&ws->done_b, t, 1, ok);
+}
+
+// Clear the first `words` words of the workspace header and set `count`
+// payload entries to the sentinel.
+__global__ void sv_fill(SvWs* ws, int words, double* pay, int64_t count) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < words) ((int32_t*)ws)[threadIdx.x] = 0;
+  const double s = __builtin_bit_cast(double, SV_SENTINEL);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    pay[i] = s;
 }
 
 // words: SV_COUNTER_WORDS clears the sweep counters only, the whole struct
@@ -975,7 +1276,35 @@ __global__ void sv_clear(SvWs* ws, int words) {
   if ((int)threadIdx.x < words) ((int32_t*)ws)[threadIdx.x] = 0;
 }
 
-int64_t tc_solve_ws_bytes() { return (int64_t)sizeof(SvWs); }
+namespace {
+inline int64_t sv_r256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+// payload columns: 2 for the one- and two-column sweeps, 16 otherwise
+inline int64_t sv_pay_width(int64_t nrhs, bool inv) { return (!inv && nrhs <= SV_RC_SMALL) ? SV_RC_SMALL : SV_MF_RC; }
+inline int64_t sv_pay_entries(int64_t n, int64_t pw) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * pw; }
+// header, then the forward and the backward payloads
+struct SvMap {
+  SvWs* ws;
+  double *ypay, *xpay;
+  int64_t entries;
+};
+SvMap sv_map(void* work, int64_t n, int64_t pw) {
+  SvMap m;
+  m.ws = (SvWs*)work;
+  m.entries = sv_pay_entries(n, pw);
+  m.ypay = (double*)((char*)work + sv_r256(sizeof(SvWs)));
+  m.xpay = (double*)((char*)m.ypay + sv_r256(8 * m.entries));
+  return m;
+}
+void sv_launch_fill(const SvMap& m, hipStream_t st) {
+  int64_t blocks = (m.entries + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(sv_fill, dim3((unsigned)blocks), dim3(256), 0, st, m.ws, SV_COUNTER_WORDS, m.ypay, m.entries);
+}
+}  // namespace
+
+int64_t tc_solve_ws_bytes(int64_t n, int64_t nrhs, bool inv) {
+  return sv_r256(sizeof(SvWs)) + 2 * sv_r256(8 * sv_pay_entries(n, sv_pay_width(nrhs, inv)));
+}
 
 int tc_solve_status_reset(void* work, hipStream_t st) {
   hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, (SvWs*)work, (int)(sizeof(SvWs) / 4));
@@ -992,25 +1321,31 @@ int tc_solve_status(const void* work, hipStream_t st, int32_t* error) {
 
 int64_t tc_solve_status_offset() { return (int64_t)offsetof(SvWs, error); }
 
-int64_t tc_solve_inv_bytes(int64_t n) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * SV_NB * 8; }
+// D, P and Q: three arrays of 64 x 64 blocks
+int64_t tc_solve_inv_bytes(int64_t n) { return 3 * ((n + SV_NB - 1) / SV_NB) * SV_NB * SV_NB * 8; }
 
 int tc_launch_invert_diag(const double* L, int64_t n, int64_t lda, double* Dinv, hipStream_t st) {
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
+  double* P = Dinv + nb * SV_NB * SV_NB;
+  double* Q = P + nb * SV_NB * SV_NB;
   hipLaunchKernelGGL(sv_invert_diag, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv);
+  hipLaunchKernelGGL(sv_couple, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, (const double*)Dinv, P, Q);
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }
 
 int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* Dinv, double* B, int64_t nrhs,
                         int64_t ldb, void* work, hipStream_t st, int64_t wait_ticks) {
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
-  SvWs* ws = (SvWs*)work;
+  const double* P = Dinv + nb * SV_NB * SV_NB;
+  const double* Q = P + nb * SV_NB * SV_NB;
+  const SvMap m = sv_map(work, n, SV_MF_RC);
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
     const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
-    hipLaunchKernelGGL(sv_fwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
-                       wait_ticks);
-    hipLaunchKernelGGL(sv_bwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, B + c0, nc, ldb, ws,
-                       wait_ticks);
+    sv_launch_fill(m, st);
+    hipLaunchKernelGGL(sv_fwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, P,
+                       (const double*)(B + c0), nc, ldb, m.ypay, m.xpay, m.ws, wait_ticks);
+    hipLaunchKernelGGL(sv_bwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, Q, B + c0, nc, ldb,
+                       (const double*)m.ypay, m.xpay, m.ws, wait_ticks);
   }
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }
