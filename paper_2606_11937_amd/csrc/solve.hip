@@ -36,10 +36,6 @@
 // whose folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel
 // pair per group.
 #define SV_RC_SMALL 2
-// 64-row blocks per workgroup in the forward and backward sweeps for one or
-// two right-hand sides
-#define SV_GROUP_F 2
-#define SV_GROUP_B 1
 #define SV_THREADS 256
 
 // Per-call counters of the two sweeps, then the call's status word: `error`
@@ -224,337 +220,324 @@ __device__ __forceinline__ void sv_chains_bwd(double* v, const double (*Lbb)[SV_
 }
 
 // ---------------------------------------------------------------- forward
-// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j).  A workgroup takes a group of
-// G consecutive blocks b0 .. b0 + G - 1 from the ticket (b0 = G ticket):
-// it folds every earlier group's blocks into all G as they finish, then
-// solves its own blocks in order, folding each into the later ones of the
-// group, and publishes the group at once.  The chain then crosses
-// workgroups once per G blocks.
+// y_b = L_bb^{-1} (B_b - sum_{j<b} L_bj y_j), one block per workgroup, one
+// or two right-hand sides (payload width 2).  The four waves fold the blocks
+// j <= b - 2 as their payloads arrive; then wave c (c < nc) takes
+// right-hand side c alone: it waits for y_{b-1}, subtracts the fold and
+// L_{b,b-1} y_{b-1} (the tile staged in LDS at the start), substitutes, and
+// publishes its column, so the chain step involves one wave and no
+// workgroup barrier.
 // Fold layout: wave w, lane 16 rr + q covers rows 16 s + 4 w + rr (s < 4)
-// of each block of the group and columns 16 m + q (m < 4) of every earlier
-// block, so each load instruction reads four whole 128-byte row segments.
-// A lane accumulates its 4 x 4 products of every block in block order; the
-// 16 lanes of a row are then summed by a butterfly.  The L values of the
-// next (block, group member) pair are loaded while the current one is
-// folded.  The in-block substitution is one row per lane (sv_chains_fwd).
-template <int RC, int G>
-__global__ __launch_bounds__(SV_THREADS) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                         double* __restrict__ B, int64_t nrhs, int64_t ldb,
-                                                         SvWs* ws, int64_t wait_ticks) {
+// of the block and columns 16 m + q (m < 4) of every folded block, so each
+// load instruction reads four whole 128-byte row segments.  A lane
+// accumulates its 4 x 4 products of every block in block order; the 16
+// lanes of a row are then summed by a butterfly.
+// Rounding order per entry (row i, right-hand side c): the fold as above;
+// B minus it; minus L_{b,b-1} y_{b-1} as four partial sums (columns
+// k = 4 i + r, ascending) added as (d0 + d1) + (d2 + d3); then the
+// substitution (sv_chains_fwd).  The forward sweep does not write
+// B: the backward sweep reads y_b from the payload.
+template <int RC>
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                         const double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                         double* Ypay, double* __restrict__ Xpay, SvWs* ws,
+                                                         int64_t wait_ticks) {
   __shared__ double part[SV_NB][RC + 1];
-  __shared__ double ys[SV_NB][RC + 1];
-  __shared__ double Lbb[G][SV_NB][SV_NB + 1];
-  __shared__ double rdiag[G][SV_NB];
-  __shared__ int32_t s_g, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double LsubT[SV_NB][SV_NB + 1];  // L_{b,b-1}, transposed
+  __shared__ double ylds[RC][SV_NB];          // y_{b-1}, broadcast to the chain wave's lanes
+  __shared__ double rdiag[SV_NB];
+  __shared__ int32_t s_b;
   const int tid = threadIdx.x;
-  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
-  if (tid == 0) s_g = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int32_t b0 = sv_uniform(s_g) * G;
-  const int ns = nb - b0 < G ? (int)(nb - b0) : G;  // blocks in this group
-  const int64_t r0 = (int64_t)b0 * SV_NB;
+  const int32_t b = sv_uniform(s_b);
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
   const int w = tid >> 6, lane = tid & 63, rr = lane >> 4, q = lane & 15;
-  // row (within its block) of fold slot s2, and the L pointers of block 0 of
-  // the group; member s adds 64 s rows
+  // the backward sweep's payload of this block starts as the sentinel
+  for (int e = tid; e < SV_NB * RC; e += SV_THREADS)
+    Xpay[(int64_t)b * SV_NB * RC + e] = __builtin_bit_cast(double, SV_SENTINEL);
+  // a payload column with no right-hand side is published as zero at once
+  if (w >= nc && w < RC) sv_pay_st(Ypay + ((int64_t)b * SV_NB + lane) * RC + w, 0.0);
+  // the chain wave's own entries of B, read before any wait
+  const double bown = (w < nc && lane < nr) ? B[(r0 + lane) * ldb + w] : 0.0;
+  // staged before any wait: the diagonal block, and L_{b,b-1}
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
+    const int i = e / SV_NB, k = e % SV_NB;
+    LsubT[k][i] = (b > 0 && i < nr) ? L[(r0 + i) * lda + r0 - SV_NB + k] : 0.0;
+  }
   int frow[4];
 #pragma unroll
   for (int s2 = 0; s2 < 4; ++s2) frow[s2] = 16 * s2 + 4 * w + rr;
-  // the diagonal blocks of the group, staged before any wait
-#pragma unroll
-  for (int s = 0; s < G; ++s)
-    if (s < ns) {
-      const int64_t rs = r0 + SV_NB * s;
-      sv_stage_diag(L, lda, rs, n - rs < SV_NB ? (int)(n - rs) : SV_NB, Lbb[s], rdiag[s]);
-    }
-  auto lload = [&](int s, int32_t j, double (*dst)[4]) {
+  auto lload = [&](int32_t j, double (*dst)[4]) {
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const int64_t R = r0 + SV_NB * s + frow[s2];
+      const int64_t R = r0 + frow[s2];
       const bool lv = R < n;
       const double* p = L + (lv ? R : 0) * lda + q + (int64_t)j * SV_NB;
 #pragma unroll
       for (int m = 0; m < 4; ++m) dst[s2][m] = lv ? p[16 * m] : 0.0;
     }
   };
-  static_assert(RC <= 4, "one right-hand side per wave in the substitutions");
-  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
-    const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
-    // the group's own right-hand-side entries, read before any wait (only
-    // this workgroup writes them): wave w substitutes right-hand side w
-    double bown[G];
+  auto yload = [&](int32_t j, double (*y)[RC]) {
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int64_t R = r0 + SV_NB * s + lane;
-      bown[s] = (s < ns && w < nc && R < n) ? B[R * ldb + c0 + w] : 0.0;
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) y[m][c] = sv_pay_ld(Ypay + ((int64_t)j * SV_NB + 16 * m + q) * RC + c);
+  };
+  const int32_t nfold = b > 1 ? b - 1 : 0;  // blocks 0 .. b - 2
+  double acc[4][RC];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[s2][c] = 0.0;
+  // the last folded tile (block b - 2) is read before any wait: its fold
+  // runs one step before the chain step
+  double lt[4][4], lc[4][4], ya[4][RC];
+  bool ok = true;
+  if (nfold > 0) {
+    lload(nfold - 1, lt);
+    yload(0, ya);
+  }
+  if (nfold > 1) lload(0, lc);
+  auto pending = [&] {
+    bool p = false;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) p = p || sv_pending(ya[m][c]);
+    return p;
+  };
+  // the probe: the last row of column 0
+  auto probe = [&](int32_t j) { return Ypay + ((int64_t)j * SV_NB + SV_NB - 1) * RC; };
+  auto fold = [&](const double (*l)[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) {
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) acc[s2][c] += l[s2][m] * ya[m][c];
+        }
+  };
+  for (int32_t j = 0; j < nfold; ++j) {
+    if (!sv_wave_wait(probe(j), [&] { yload(j, ya); }, pending, ws, wait_ticks)) {
+      ok = false;
+      break;
     }
-    double acc[G][4][RC];
-#pragma unroll
-    for (int s = 0; s < G; ++s)
+    if (j + 1 == nfold) {
+      fold(lt);
+      break;
+    }
+    // the next block, while this one is folded (its tile unless it is the last)
+    const bool more = j + 2 < nfold;
+    double ln[4][4], yn[4][RC];
+    if (more) lload(j + 1, ln);
+    yload(j + 1, yn);
+    fold(lc);
+    if (more) {
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-        for (int c = 0; c < RC; ++c) acc[s][s2][c] = 0.0;
-    double lc[4][4];
-    if (b0 > 0) lload(0, 0, lc);
-    int32_t j = 0;
-    while (j < b0) {
-      const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-      if (ready < 0) {  // aborted: finish the barrier sequence, publish nothing
-        ok = false;
-        break;
-      }
-      const int32_t jend = ready < b0 ? ready : b0;
-      for (; j < jend; ++j) {
-        double y[4][RC];
-        const double* yj = B + ((int64_t)j * SV_NB + q) * ldb + c0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int c = 0; c < RC; ++c) y[m][c] = c < nc ? yj[(int64_t)16 * m * ldb + c] : 0.0;
-#pragma unroll
-        for (int s = 0; s < G; ++s) {
-          // the next pair: member s + 1 of block j, else member 0 of block
-          // j + 1 (the last pair re-reads itself)
-          const int32_t jn = s + 1 < G ? j : (j + 1 < b0 ? j + 1 : j);
-          double ln[4][4];
-          lload(s + 1 < G ? s + 1 : (j + 1 < b0 ? 0 : s), jn, ln);
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-              if (c < nc) {
-#pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2) acc[s][s2][c] += lc[s2][m] * y[m][c];
-              }
-#pragma unroll
-          for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) lc[s2][m] = ln[s2][m];
-        }
-      }
+        for (int m = 0; m < 4; ++m) lc[s2][m] = ln[s2][m];
     }
-    // the group's own blocks, in order
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      if (s < ns) {
-        const int64_t rs = r0 + SV_NB * s;
-        const int nr = n - rs < SV_NB ? (int)(n - rs) : SV_NB;
-        // L of the next member against this block, for the fold after the
-        // substitution (loaded now, used after it)
-        double lg[4][4];
-        if (s + 1 < ns) lload(s + 1, b0 + s, lg);
-        // butterfly over the 16 lanes of each row, then one lane writes the sum
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-          for (int c = 0; c < RC; ++c) {
-            if (c < nc) {
-              double v = acc[s][s2][c];
-#pragma unroll
-              for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 16);
-              if (q == 0) part[frow[s2]][c] = v;
-            }
-          }
-        __syncthreads();
-        if (w < nc) {
-          const int c = w;
-          double v = 0.0;
-          if (lane < nr) v = bown[s] - (b0 + s > 0 ? part[lane][c] : 0.0);
-          sv_chains_fwd<1>(&v, Lbb[s], rdiag[s], lane);
-          if (lane < nr) B[(rs + lane) * ldb + c0 + c] = v;
-          ys[lane][c] = v;  // zero past nr
-        }
-        __syncthreads();
-        // fold this block into the later members: the next one from lg, the
-        // rest with loads of their own
-#pragma unroll
-        for (int s3 = s + 1; s3 < G; ++s3) {
-          if (s3 < ns) {
-            double lf[4][4];
-            if (s3 == s + 1) {
-#pragma unroll
-              for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) lf[s2][m] = lg[s2][m];
-            } else {
-              lload(s3, b0 + s, lf);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-              for (int c = 0; c < RC; ++c)
-                if (c < nc) {
-                  const double yv = ys[q + 16 * m][c];
-#pragma unroll
-                  for (int s2 = 0; s2 < 4; ++s2) acc[s3][s2][c] += lf[s2][m] * yv;
-                }
-          }
-        }
-        __syncthreads();  // part and ys are rewritten by the next member
-      }
-    }
+      for (int c = 0; c < RC; ++c) ya[m][c] = yn[m][c];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  sv_publish(&ws->done_f, b0, ns, ok);
+  // butterfly over the 16 lanes of each row, then one lane writes the sum
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      double v = acc[s2][c];
+#pragma unroll
+      for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 16);
+      if (q == 0) part[frow[s2]][c] = v;
+    }
+  const bool all_ok = __syncthreads_and(ok);
+  if (w < nc) {
+    // the chain wave goes first in issue on its SIMD (the other workgroup on
+    // the CU streams its fold meanwhile)
+    __builtin_amdgcn_s_setprio(3);
+    const int c = w;
+    double v = bown - (lane < nr ? part[lane][c] : 0.0);
+    // row `lane` of L_{b,b-1} into registers before the wait
+    double lrow[SV_NB];
+#pragma unroll
+    for (int k = 0; k < SV_NB; ++k) lrow[k] = LsubT[k][lane];
+    // keep them in registers here (an empty statement that uses them), so the
+    // compiler does not move the LDS reads behind the wait
+#pragma unroll
+    for (int k = 0; k < SV_NB; ++k) asm volatile("" : "+v"(lrow[k]));
+    bool got = all_ok;
+    if (got && b > 0) {
+      // y_{b-1}, column c: lane k holds entry k
+      double yp = sv_pay_ld(Ypay + ((int64_t)(b - 1) * SV_NB + lane) * RC + c);
+      got = sv_wave_wait_full([&] { yp = sv_pay_ld(Ypay + ((int64_t)(b - 1) * SV_NB + lane) * RC + c); },
+                              [&] { return sv_pending(yp); }, ws, wait_ticks);
+      if (got) {
+        // L_{b,b-1} y_{b-1}: y_{b-1} through LDS (the wave's LDS operations
+        // run in order), four partial sums over k = 4 i + r, then
+        // (d0 + d1) + (d2 + d3)
+        ylds[c][lane] = yp;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < SV_NB; ++k) d[k & 3] = __builtin_fma(lrow[k], ylds[c][k], d[k & 3]);
+        v = v - ((d[0] + d[1]) + (d[2] + d[3]));
+      }
+    }
+    if (lane >= nr) v = 0.0;
+    sv_chains_fwd<1>(&v, Lbb, rdiag, lane);
+    if (got) sv_pay_st(Ypay + ((int64_t)b * SV_NB + lane) * RC + c, lane < nr ? v : 0.0);
+    __builtin_amdgcn_s_setprio(0);
+  }
 }
 
 // --------------------------------------------------------------- backward
-// x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j).  Groups of G blocks in
-// descending order: ticket t takes blocks bh = nb - 1 - G t down to
-// bh - G + 1 (member s is block bh - s), folds every later group's blocks
-// into all of them as they finish, then solves its own blocks from the top,
-// folding each into the members below it, and publishes the group at once.
-template <int RC, int G>
-__global__ __launch_bounds__(SV_THREADS) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                          double* __restrict__ B, int64_t nrhs, int64_t ldb,
-                                                          SvWs* ws, int64_t wait_ticks) {
+// x_b = L_bb^{-T} (y_b - sum_{j>b} L_jb^T x_j), one block per workgroup:
+// the four waves fold the blocks j >= b + 2 as their payloads arrive, then
+// wave c takes right-hand side c alone: it waits for x_{b+1}, subtracts the
+// fold and L_{b+1,b}^T x_{b+1} (the tile staged in LDS at the start),
+// substitutes, writes B and publishes its column.
+// Fold layout: thread (r, p) covers output row r of the block (column r of
+// each L_jb) and rows 16 p .. 16 p + 15 of every folded block; consecutive
+// r are consecutive addresses, so each wave reads 64 contiguous doubles per
+// row.  Each quarter p accumulates in block order; the quarters are then
+// combined in order p = 0..3.  Then y_b minus it; minus L_{b+1,b}^T x_{b+1}
+// as four partial sums (rows k = 4 i + r, ascending) added as
+// (d0 + d1) + (d2 + d3); then the substitution (sv_chains_bwd).
+template <int RC>
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                          double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                          const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
+                                                          int64_t wait_ticks) {
   __shared__ double part[4][SV_NB][RC + 1];
-  __shared__ double xs[SV_NB][RC + 1];
-  __shared__ double Lbb[G][SV_NB][SV_NB + 1];
-  __shared__ double rdiag[G][SV_NB];
-  __shared__ int32_t s_t, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ double Lbb[SV_NB][SV_NB + 1];
+  __shared__ double Lsub[SV_NB][SV_NB + 1];  // L_{b+1,b}
+  __shared__ double xlds[RC][SV_NB];         // x_{b+1}, broadcast to the chain wave's lanes
+  __shared__ double rdiag[SV_NB];
+  __shared__ int32_t s_t;
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int32_t t = sv_uniform(s_t);
-  const int32_t bh = nb - 1 - G * t;  // member 0; member s is block bh - s
-  const int ns = bh + 1 < G ? (int)(bh + 1) : G;
-  // thread (r, p): output row r of a member block (column r of each L_jb),
-  // rows 16p .. 16p+15 of every later block; consecutive r are consecutive
-  // addresses, so each wave reads 64 contiguous doubles per k
-  const int r = tid & 63, p = tid >> 6;
-  // the diagonal blocks of the group, staged before any wait
-#pragma unroll
-  for (int s = 0; s < G; ++s)
-    if (s < ns) {
-      const int64_t rs = (int64_t)(bh - s) * SV_NB;
-      sv_stage_diag(L, lda, rs, n - rs < SV_NB ? (int)(n - rs) : SV_NB, Lbb[s], rdiag[s]);
+  const int32_t b = nb - 1 - t;
+  const int64_t r0 = (int64_t)b * SV_NB;
+  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
+  const int r = tid & 63, p = tid >> 6, w = p, lane = r;
+  if (w >= nc && w < RC) sv_pay_st(Xpay + ((int64_t)b * SV_NB + lane) * RC + w, 0.0);
+  // the chain wave's own entries of y (published by the forward sweep, an
+  // earlier launch)
+  const double yown = w < nc ? Ypay[((int64_t)b * SV_NB + lane) * RC + w] : 0.0;
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
+  {
+    const int64_t j0 = r0 + SV_NB;
+    for (int e = tid; e < SV_NB * SV_NB; e += SV_THREADS) {
+      const int k = e / SV_NB, i = e % SV_NB;
+      Lsub[k][i] = (b + 1 < nb && j0 + k < n && i < nr) ? L[(j0 + k) * lda + r0 + i] : 0.0;
     }
-  auto load_col = [&](int s, int32_t j, double* dst) {
+  }
+  auto load_col = [&](int32_t j, double* dst) {
     const int64_t j0 = (int64_t)j * SV_NB;
     const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-    const int64_t col = (int64_t)(bh - s) * SV_NB + r;
-    const bool lv = s < ns && col < n;
+    const int64_t col = r0 + r;
+    const bool lv = r < nr;
     const double* base = L + (lv ? col : 0);
+    // rows past n are clamped to the last row (in bounds) and selected away
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int kk = 16 * p + k;
-      dst[k] = (lv && kk < njr) ? base[(j0 + kk) * lda] : 0.0;
+      const double v = base[(j0 + (kk < njr ? kk : njr - 1)) * lda];
+      dst[k] = (lv && kk < njr) ? v : 0.0;
     }
   };
-  static_assert(RC <= 4, "one right-hand side per wave in the substitutions");
-  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
-    const int nc = nrhs - c0 < RC ? (int)(nrhs - c0) : RC;
-    // the group's own entries of y, read before any wait (only this
-    // workgroup writes them): wave tid / 64 substitutes right-hand side
-    // tid / 64
-    double bown[G];
+  // this quarter's payload rows of block j, one entry per lane: lane l holds
+  // row 16 p + (l & 15), column (l >> 4) % RC (lanes past 16 RC repeat)
+  const int xrow = lane & 15, xcol = (lane >> 4) % RC;
+  auto xload = [&](int32_t j) { return sv_pay_ld(Xpay + ((int64_t)j * SV_NB + 16 * p + xrow) * RC + xcol); };
+  const int32_t jlast = b + 2;  // blocks nb - 1 down to b + 2
+  double acc[RC];
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int64_t R = (int64_t)(bh - s) * SV_NB + r;
-      bown[s] = (s < ns && p < nc && R < n) ? B[R * ldb + c0 + p] : 0.0;
-    }
-    double acc[G][RC];
-#pragma unroll
-    for (int s = 0; s < G; ++s)
-#pragma unroll
-      for (int c = 0; c < RC; ++c) acc[s][c] = 0.0;
-    double lc[16];
-    if (bh < nb - 1) load_col(0, nb - 1, lc);
-    int32_t j = nb - 1;
-    while (j > bh) {
-      const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-      if (ready < 0) {
-        ok = false;
-        break;
-      }
-      const int32_t jlow = nb - ready > bh + 1 ? nb - ready : bh + 1;
-      for (; j >= jlow; --j) {
-        const int64_t j0 = (int64_t)j * SV_NB;
-        const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-        double xv[16][RC];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int kk = 16 * p + k;
-          const double* xk = B + (j0 + (kk < njr ? kk : 0)) * ldb + c0;
-#pragma unroll
-          for (int c = 0; c < RC; ++c) xv[k][c] = (kk < njr && c < nc) ? xk[c] : 0.0;
-        }
-#pragma unroll
-        for (int s = 0; s < G; ++s) {
-          const int32_t jn = s + 1 < G ? j : (j - 1 > bh ? j - 1 : j);
-          double ln[16];
-          load_col(s + 1 < G ? s + 1 : (j - 1 > bh ? 0 : s), jn, ln);
-#pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            const int kk = 16 * p + k;
-            if (kk < njr) {
-#pragma unroll
-              for (int c = 0; c < RC; ++c)
-                if (c < nc) acc[s][c] += lc[k] * xv[k][c];
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 16; ++k) lc[k] = ln[k];
-        }
-      }
-    }
-    const int w = tid >> 6, lane = tid & 63;
-#pragma unroll
-    for (int s = 0; s < G; ++s) {
-      if (s < ns) {
-        const int32_t b = bh - s;
-        const int64_t r0 = (int64_t)b * SV_NB;
-        const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-        double lg[16];
-        if (s + 1 < ns) load_col(s + 1, b, lg);
-#pragma unroll
-        for (int c = 0; c < RC; ++c) part[p][r][c] = acc[s][c];
-        __syncthreads();
-        if (w < nc) {
-          const int c = w;
-          double v = 0.0;
-          if (lane < nr) {
-            const double sm = part[0][lane][c] + part[1][lane][c] + part[2][lane][c] + part[3][lane][c];
-            v = bown[s] - sm;
-          }
-          sv_chains_bwd<1>(&v, Lbb[s], rdiag[s], lane);
-          if (lane < nr) B[(r0 + lane) * ldb + c0 + c] = v;
-          xs[lane][c] = v;  // zero past nr
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s3 = s + 1; s3 < G; ++s3) {
-          if (s3 < ns) {
-            double lf[16];
-            if (s3 == s + 1) {
-#pragma unroll
-              for (int k = 0; k < 16; ++k) lf[k] = lg[k];
-            } else {
-              load_col(s3, b, lf);
-            }
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-              const int kk = 16 * p + k;
-              if (kk < nr) {
-#pragma unroll
-                for (int c = 0; c < RC; ++c)
-                  if (c < nc) acc[s3][c] += lf[k] * xs[kk][c];
-              }
-            }
-          }
-        }
-        __syncthreads();  // part and xs are rewritten by the next member
-      }
-    }
+  for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+  // the last folded tile (block b + 2) is read before any wait
+  double lt[16], lc[16], xa = 0.0;
+  bool ok = true;
+  if (jlast < nb) {
+    load_col(jlast, lt);
+    xa = xload(nb - 1);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  sv_publish(&ws->done_b, nb - 1 - bh, ns, ok);
+  if (jlast < nb - 1) load_col(nb - 1, lc);
+  // the probe: the last of this quarter's rows, column 0
+  auto probe = [&](int32_t j) { return Xpay + ((int64_t)j * SV_NB + 16 * p + 15) * RC; };
+  auto fold = [&](const double* l) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) acc[c] += l[k] * sv_readlane(xa, k + 16 * c);
+  };
+  for (int32_t j = nb - 1; j >= jlast; --j) {
+    if (!sv_wave_wait(probe(j), [&] { xa = xload(j); }, [&] { return sv_pending(xa); }, ws, wait_ticks)) {
+      ok = false;
+      break;
+    }
+    if (j == jlast) {
+      fold(lt);
+      break;
+    }
+    // the next block, while this one is folded (its tile unless it is the last)
+    const bool more = j - 1 > jlast;
+    double ln[16];
+    if (more) load_col(j - 1, ln);
+    const double xn = xload(j - 1);
+    fold(lc);
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lc[k] = ln[k];
+    }
+    xa = xn;
+  }
+#pragma unroll
+  for (int c = 0; c < RC; ++c) part[p][r][c] = acc[c];
+  const bool all_ok = __syncthreads_and(ok);
+  if (w < nc) {
+    __builtin_amdgcn_s_setprio(3);  // the chain wave first in issue (as in the forward sweep)
+    const int c = w;
+    const double sm = ((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c];
+    double v = lane < nr ? yown - sm : 0.0;
+    // column `lane` of L_{b+1,b} into registers before the wait
+    double lcol[SV_NB];
+#pragma unroll
+    for (int k = 0; k < SV_NB; ++k) lcol[k] = Lsub[k][lane];
+#pragma unroll
+    for (int k = 0; k < SV_NB; ++k) asm volatile("" : "+v"(lcol[k]));  // in registers before the wait
+    bool got = all_ok;
+    if (got && b + 1 < nb) {
+      // x_{b+1}, column c: lane k holds entry k
+      double xp = sv_pay_ld(Xpay + ((int64_t)(b + 1) * SV_NB + lane) * RC + c);
+      got = sv_wave_wait_full([&] { xp = sv_pay_ld(Xpay + ((int64_t)(b + 1) * SV_NB + lane) * RC + c); },
+                              [&] { return sv_pending(xp); }, ws, wait_ticks);
+      if (got) {
+        // L_{b+1,b}^T x_{b+1}: x_{b+1} through LDS, four partial sums over
+        // k = 4 i + r, then (d0 + d1) + (d2 + d3)
+        xlds[c][lane] = xp;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < SV_NB; ++k) d[k & 3] = __builtin_fma(lcol[k], xlds[c][k], d[k & 3]);
+        v = v - ((d[0] + d[1]) + (d[2] + d[3]));
+      }
+    }
+    if (lane >= nr) v = 0.0;
+    sv_chains_bwd<1>(&v, Lbb, rdiag, lane);
+    if (lane < nr) B[(r0 + lane) * ldb + c] = v;
+    if (got) sv_pay_st(Xpay + ((int64_t)b * SV_NB + lane) * RC + c, lane < nr ? v : 0.0);
+    __builtin_amdgcn_s_setprio(0);
+  }
 }
 
 // ------------------------------------------------ matrix-core fold sweeps
@@ -1029,6 +1012,9 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_inv(const double* __rest
     part[row][r16] = (row < nr && bok) ? bown[q] - acc[q] : 0.0;
   }
   __syncthreads();
+  // from here on this workgroup's waves are the chain: first in issue on
+  // their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   // c_b = D_b v: rows 16 w .., right-hand side r16
   sv_v4d y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1220,6 +1206,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_inv(const double* __rest
     part[row][r16] = (row < nr && bok) ? yown[q] - f : 0.0;
   }
   __syncthreads();
+  __builtin_amdgcn_s_setprio(3);  // the chain, first in issue
   // d_b = D_b^T v
   sv_v4d x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1355,13 +1342,13 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
   (void)T;
   const int64_t nb = (n + SV_NB - 1) / SV_NB;
   SvWs* ws = (SvWs*)work;
-  if (nrhs <= 2) {  // measured faster for one or two right-hand sides
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
-    const int64_t ngf = (nb + SV_GROUP_F - 1) / SV_GROUP_F, ngb = (nb + SV_GROUP_B - 1) / SV_GROUP_B;
-    hipLaunchKernelGGL((sv_forward<SV_RC_SMALL, SV_GROUP_F>), dim3((unsigned)ngf), dim3(SV_THREADS), 0, st, L, lda, n,
-                       B, nrhs, ldb, ws, wait_ticks);
-    hipLaunchKernelGGL((sv_backward<SV_RC_SMALL, SV_GROUP_B>), dim3((unsigned)ngb), dim3(SV_THREADS), 0, st, L, lda,
-                       n, B, nrhs, ldb, ws, wait_ticks);
+  if (nrhs <= SV_RC_SMALL) {  // measured faster for one or two right-hand sides
+    const SvMap m = sv_map(work, n, SV_RC_SMALL);
+    sv_launch_fill(m, st);
+    hipLaunchKernelGGL(sv_forward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n,
+                       (const double*)B, nrhs, ldb, m.ypay, m.xpay, ws, wait_ticks);
+    hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
+                       ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
     return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
