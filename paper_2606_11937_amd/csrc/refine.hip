@@ -34,6 +34,7 @@
 
 #define RF_THREADS 256
 #define RF_RC 16  // right-hand sides per pass of a product kernel
+#define RF_CH 2   // 16-wide k chunks per step of the product kernel (and in flight)
 
 typedef double rf_v4d __attribute__((ext_vector_type(4)));
 
@@ -43,10 +44,14 @@ __device__ __forceinline__ rf_v4d rf_mfma(double a, double b, rf_v4d c) {
 
 // ------------------------------------------------------------ A times X
 // Y = B - A X (Y = -A X when B is null) for symmetric A stored as its lower
-// triangle.  One workgroup per 64 rows; wave w owns rows
+// triangle, and, when rowabs is not null, rowabs[i] = sum_k |A_ik| (the row
+// sums of |A|, from the same reads).  One workgroup per 64 rows; wave w owns rows
 // 64 blockIdx + 16 w .. +15 and walks k = 0 .. n - 1 in 16-wide chunks,
 // reading A_ik from row i for k <= i and as A_ki from column i for k > i (so
 // every stored entry is read twice in all, once for each of its rows).
+// The row sums of |A| add, per lane, the entries it brings to the products
+// (chunks in ascending k), then the lanes of a row in the fixed order
+// (g0 + g1) + (g2 + g3).
 // MFMA operand layout (measured on gfx950): A-operand lane l holds row
 // l % 16 at k group l / 16, B-operand lane l holds column l % 16 at k group
 // l / 16, output item q of lane l is row 4 q + l / 16, column l % 16.  In a
@@ -58,7 +63,8 @@ __device__ __forceinline__ rf_v4d rf_mfma(double a, double b, rf_v4d c) {
 __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restrict__ A, int64_t lda, int64_t n,
                                                          const double* __restrict__ X, int64_t ldx,
                                                          const double* __restrict__ B, int64_t ldb,
-                                                         double* __restrict__ Y, int64_t ldy, int64_t nrhs) {
+                                                         double* __restrict__ Y, int64_t ldy, int64_t nrhs,
+                                                         double* __restrict__ rowabs) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = (lane >> 4) * 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;  // first output row of this wave
@@ -86,24 +92,33 @@ __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restric
         x[m] = (colok && kin) ? xv : 0.0;
       }
     };
-    // chunks in pairs, the next pair in flight while this one is multiplied
-    // (a chunk index past the end re-reads the last chunk and is not used)
+    // chunks in groups of RF_CH, the next group in flight while this one is
+    // multiplied (a chunk index past the end re-reads the last chunk and is
+    // not used)
     rf_v4d acc = {0.0, 0.0, 0.0, 0.0};
-    double a[8], x[8];
-    load(0, a, x);
-    load(nch > 1 ? 1 : 0, a + 4, x + 4);
-    for (int64_t ch = 0; ch < nch; ch += 2) {
-      double an[8], xn[8];
-      load(ch + 2 < nch ? ch + 2 : nch - 1, an, xn);
-      load(ch + 3 < nch ? ch + 3 : nch - 1, an + 4, xn + 4);
+    // with rowabs, the first pass also sums |A_ik| over this lane's k
+    const bool absum_on = rowabs != nullptr && c0 == 0;
+    double absum = 0.0;
+    double a[4 * RF_CH], x[4 * RF_CH];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc = rf_mfma(a[m], x[m], acc);
-      if (ch + 1 < nch) {
+    for (int h = 0; h < RF_CH; ++h) load(h < nch ? h : nch - 1, a + 4 * h, x + 4 * h);
+    for (int64_t ch = 0; ch < nch; ch += RF_CH) {
+      double an[4 * RF_CH], xn[4 * RF_CH];
 #pragma unroll
-        for (int m = 4; m < 8; ++m) acc = rf_mfma(a[m], x[m], acc);
+      for (int h = 0; h < RF_CH; ++h) load(ch + RF_CH + h < nch ? ch + RF_CH + h : nch - 1, an + 4 * h, xn + 4 * h);
+#pragma unroll
+      for (int h = 0; h < RF_CH; ++h) {
+        if (ch + h < nch) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) acc = rf_mfma(a[4 * h + m], x[4 * h + m], acc);
+          if (absum_on) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) absum += fabs(a[4 * h + m]);
+          }
+        }
       }
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < 4 * RF_CH; ++m) {
         a[m] = an[m];
         x[m] = xn[m];
       }
@@ -114,83 +129,14 @@ __global__ __launch_bounds__(RF_THREADS, 2) void rf_symv(const double* __restric
       const int64_t c = c0 + (lane & 15);
       if (r < n && c < nrhs) Y[r * ldy + c] = (B != nullptr ? B[r * ldb + c] : 0.0) - acc[q];
     }
-  }
-}
-
-// ------------------------------------------------------- ||A||_inf
-// Row sums of |A| for symmetric A stored as its lower triangle:
-// s_i = sum_{k <= i} |A_ik| + sum_{k > i} |A_ki|.  Grid (64-row blocks I,
-// RF_SEG segments of the 64-wide k tiles); workgroup (I, g) adds the tiles
-// K of its segment: K <= I row-wise (entries k <= i of rows of block I,
-// lanes along k), K >= I column-wise (entries k > i of rows of block K,
-// lanes along i).  Each entry of the stored triangle is read once for each
-// row it belongs to.  Sums run in a fixed order: per lane over the tiles in
-// the workgroup's order, then the 64 lanes of a row by a butterfly (row side) or the
-// four waves in order (column side); the segments are added in order by
-// rf_rowabs_max.  Partial sums go to part[g * n + i].
-#define RF_SEG 8
-__global__ __launch_bounds__(RF_THREADS) void rf_rowabs(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                        double* __restrict__ part) {
-  __shared__ double colp[4][64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t nb = (n + 63) / 64;
-  const int64_t I = blockIdx.x, i0 = I * 64;
-  const int64_t per = (nb + RF_SEG - 1) / RF_SEG;
-  const int64_t K0 = blockIdx.y * per, K1 = K0 + per < nb ? K0 + per : nb;
-  double racc[16];
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) racc[rr] = 0.0;
-  double cacc = 0.0;
-  const int64_t ic = i0 + lane;  // column side: this lane's row i
-  // the segment's tiles from a start that depends on I, so that the
-  // workgroups running at one time read different column offsets
-  const int64_t len = K1 > K0 ? K1 - K0 : 0;
-  for (int64_t t = 0; t < len; ++t) {
-    const int64_t K = K0 + (t + I) % len;
-    const int64_t k0 = K * 64;
-    if (K <= I) {  // row side: rows i = i0 + 16 w + rr, k = k0 + lane
-      const int64_t k = k0 + lane;
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int64_t i = i0 + 16 * w + rr;
-        const bool in = i < n && k <= i;
-        const double v = A[(in ? i : 0) * lda + (in ? k : 0)];
-        racc[rr] += in ? fabs(v) : 0.0;
-      }
-    }
-    if (K >= I) {  // column side: rows k = k0 + 16 w + rr, column i = ic
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int64_t k = k0 + 16 * w + rr;
-        const bool in = k < n && ic < n && k > ic;
-        const double v = A[(in ? k : 0) * lda + (in ? ic : 0)];
-        cacc += in ? fabs(v) : 0.0;
-      }
+    if (absum_on) {
+      // the four k groups of row r16: (g0 + g1) + (g2 + g3)
+      absum += __shfl_xor(absum, 16, 64);
+      absum += __shfl_xor(absum, 32, 64);
+      if (lane < 16 && rowok) rowabs[myrow] = absum;
     }
   }
-  colp[w][lane] = cacc;
-  // row side: the 64 lanes of each row, butterfly
-  double mine = 0.0;
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    double v = racc[rr];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-    if (lane == rr) mine = v;  // row 16 w + rr
-  }
-  __syncthreads();
-  // thread (w, lane < 16) holds row 16 w + lane of the row side
-  if (lane < 16) {
-    const int r = 16 * w + lane;
-    const double c = ((colp[0][r] + colp[1][r]) + colp[2][r]) + colp[3][r];
-    if (i0 + r < n) part[blockIdx.y * n + i0 + r] = mine + c;
-  }
 }
-
-// anorm[0] = max_i sum_g part[g * n + i] (one workgroup; segments added in
-// order, then the fixed max tree)
-__global__ __launch_bounds__(RF_THREADS) void rf_rowabs_max(const double* __restrict__ part, int64_t n,
-                                                            double* anorm);
 
 // ------------------------------------------------------- column reductions
 // Fixed-order tree over the 256 threads of the workgroup.
@@ -208,18 +154,6 @@ __device__ __forceinline__ double rf_block_reduce(double v, bool take_max) {
   const double r = red[0];
   __syncthreads();
   return r;
-}
-
-__global__ __launch_bounds__(RF_THREADS) void rf_rowabs_max(const double* __restrict__ part, int64_t n,
-                                                            double* anorm) {
-  double m = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += RF_THREADS) {
-    double t = 0.0;
-    for (int g = 0; g < RF_SEG; ++g) t += part[g * n + i];
-    m = fmax(m, t);
-  }
-  m = rf_block_reduce(m, true);
-  if (threadIdx.x == 0) anorm[0] = m;
 }
 
 // out[c] = max_i |U[i][c]| (one workgroup per column c).
@@ -306,7 +240,7 @@ struct RfWs {
   void* solve_ws;
   double* dinv;                   // inverted 64 x 64 diagonal blocks of L
   double *R, *Z, *P, *Q;          // n x nrhs each, leading dimension nrhs
-  double* rowsum;                 // RF_SEG x n partial row sums of |A|
+  double* rowsum;                 // n: the row sums of |A|
   double *anorm, *rmax, *xmax, *bmax, *eta, *rz, *rzn, *pq, *alpha, *beta;  // nrhs each (anorm: 1)
   int32_t *done, *zero, *mask;    // nrhs each
 };
@@ -323,7 +257,7 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
   w.Z = (double*)p; p += mat;
   w.P = (double*)p; p += mat;
   w.Q = (double*)p; p += mat;
-  w.rowsum = (double*)p; p += rf_r256(8 * n * RF_SEG);
+  w.rowsum = (double*)p; p += rf_r256(8 * n);
   double** vecs[] = {&w.anorm, &w.rmax, &w.xmax, &w.bmax, &w.eta, &w.rz, &w.rzn, &w.pq, &w.alpha, &w.beta};
   for (double** v : vecs) {
     *v = (double*)p;
@@ -337,11 +271,11 @@ RfWs rf_map(void* work, int64_t n, int64_t nrhs) {
   return w;
 }
 
-// Y = B - A X  (B null: Y = -A X)
+// Y = B - A X  (B null: Y = -A X); rowabs (optional): the row sums of |A|
 void rf_residual(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, const double* B, int64_t ldb,
-                 double* Y, int64_t ldy, int64_t nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(rf_symv, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y,
-                     ldy, nrhs);
+                 double* Y, int64_t ldy, int64_t nrhs, hipStream_t st, double* rowabs = nullptr) {
+  hipLaunchKernelGGL(rf_symv, dim3(rf_blocks(n, 64)), dim3(RF_THREADS), 0, st, A, lda, n, X, ldx, B, ldb, Y, ldy, nrhs,
+                     rowabs);
 }
 
 // eta of every column of (R, X, B) into w.eta, copied to host `eta`
@@ -363,7 +297,7 @@ double rf_max(const std::vector<double>& v) {
 }  // namespace
 
 int64_t tc_refine_ws_bytes(int64_t n, int64_t nrhs) {
-  return rf_r256(tc_solve_ws_bytes(n, nrhs, true)) + rf_r256(tc_solve_inv_bytes(n)) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n * RF_SEG) + 10 * rf_r256(8 * nrhs) +
+  return rf_r256(tc_solve_ws_bytes(n, nrhs, true)) + rf_r256(tc_solve_inv_bytes(n)) + 4 * rf_r256(8 * n * nrhs) + rf_r256(8 * n) + 10 * rf_r256(8 * nrhs) +
          3 * rf_r256(4 * nrhs);
 }
 
@@ -385,14 +319,14 @@ int tc_refine(const double* A, int64_t lda, const double* L, int64_t ldl, int64_
   if (tc_launch_invert_diag(L, n, ldl, w.dinv, st) != 0) return fail();
   // one status word for every sweep of the call
   if (tc_solve_status_reset(w.solve_ws, st) != 0) return fail();
-  // ||A||_inf from the row sums of |A|, and ||b||_inf per column
-  hipLaunchKernelGGL(rf_rowabs, dim3(rf_blocks(n, 64), RF_SEG), dim3(RF_THREADS), 0, st, A, lda, n, w.rowsum);
-  hipLaunchKernelGGL(rf_rowabs_max, dim3(1), dim3(RF_THREADS), 0, st, (const double*)w.rowsum, n, w.anorm);
+  // ||b||_inf per column (||A||_inf comes with the first residual)
   hipLaunchKernelGGL(rf_colmax, dim3((unsigned)nrhs), dim3(RF_THREADS), 0, st, B, ldb, n, w.bmax);
   // x0 = (L L^T)^-1 b
   hipLaunchKernelGGL(rf_copy, dim3(eb), dim3(256), 0, st, X, ldx, B, ldb, (const int32_t*)nullptr, n, nrhs);
   if (solve(X, ldx) != 0) return fail();
-  rf_residual(A, lda, n, X, ldx, B, ldb, w.R, nrhs, nrhs, st);
+  // the first residual also gives the row sums of |A|: ||A||_inf is their maximum
+  rf_residual(A, lda, n, X, ldx, B, ldb, w.R, nrhs, nrhs, st, w.rowsum);
+  hipLaunchKernelGGL(rf_colmax, dim3(1), dim3(RF_THREADS), 0, st, (const double*)w.rowsum, (int64_t)1, n, w.anorm);
   if (rf_eta_host(w, w.R, X, ldx, n, nrhs, eta, st) != 0) return fail();
   int64_t it = 0;
   int status = 1;

@@ -1,29 +1,24 @@
 // solve.hip -- A X = B with the Cholesky factor (the paper's motivating use:
 // SPD linear systems through the decomposition): forward substitution
-// L Y = B, then backward substitution L^T X = Y, in place in B.
+// L Y = B, then backward substitution L^T X = Y.
 //
-// Both sweeps are single launches over 64-row blocks.  Each workgroup takes
-// a group of consecutive blocks from an atomic ticket (ascending for the
-// forward sweep, descending for the backward one), so a workgroup only ever
-// waits for blocks whose tickets are smaller, all held by running
-// workgroups.  A "done" counter in the workspace records how many blocks,
-// in sweep order, are finished; a workgroup folds in every finished block
-// it sees (no waiting), re-reads the counter, and waits only for the last
-// few blocks before its own.  It then solves its own blocks in order,
-// folding each into the later ones of its group, and publishes the group.
-// Blocks finish and publish in sweep order.  The sweep streams L once from
-// HBM while the chain of 64 x 64 triangular solves runs.
+// Both sweeps are single launches over 64-row blocks, one block per
+// workgroup.  Each workgroup takes its block from an atomic ticket
+// (ascending for the forward sweep, descending for the backward one), so it
+// only ever waits for blocks whose tickets are smaller, all held by running
+// workgroups.  A finished block's solution reaches the workgroups that need
+// it as a payload of device-scope atomic stores (see the hand-off section);
+// a workgroup folds every earlier block as its payload arrives, and the
+// step on the chain -- the neighbour block's product and the block's own
+// solve -- starts the moment the neighbour's payload is complete.  The
+// sweep streams L once from HBM while the chain of 64 x 64 triangular
+// solves runs.
 //
-// Rounding order, for bitwise reproducibility: for row i of block b and
-// right-hand side c, the forward sweep accumulates per lane over its four
-// columns of every earlier block, in block order, and sums the 16 lanes of
-// a row by a butterfly; the backward sweep accumulates each of four thread
-// quarters p over its 16 rows of every later block in block order and
-// combines the quarters in order p = 0..3.  The sum is subtracted from B.
-// The in-block substitution scales each row of the diagonal block and the
+// Every sum runs in a fixed order (stated at each kernel), so results are
+// reproducible bit for bit and independent of the timing of the sweep.  The
+// in-block substitution scales each row of the diagonal block and the
 // right-hand side by the reciprocal of the row's pivot, then runs
-// sequentially in the column index with one FMA per entry.  None of this
-// depends on the grouping of blocks into workgroups.
+// sequentially in the column index with one FMA per entry.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -38,12 +33,12 @@
 #define SV_RC_SMALL 2
 #define SV_THREADS 256
 
-// Per-call counters of the two sweeps, then the call's status word: `error`
-// is set when a dependency wait ran out, cleared only when a call (or a
-// caller that groups several solves under one status) starts, so that the
-// counter reset before each 16-column group of right-hand sides keeps it.
+// The call's block tickets, then its status word: `error` is set when a
+// dependency wait ran out, cleared only when a call (or a caller that groups
+// several solves under one status) starts, so that the ticket reset before
+// each 16-column group of right-hand sides keeps it.
 struct SvWs {
-  int32_t ticket_f, done_f, ticket_b, done_b;
+  int32_t ticket_f, ticket_b, reserved[2];
   int32_t error, pad[59];
 };
 #define SV_COUNTER_WORDS 4
@@ -52,48 +47,7 @@ __device__ __forceinline__ int32_t sv_ld(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until *cnt > need (or the error flag / time limit trips).  Returns the
-// value seen, or -1 on abort.  Called by every thread; the acquire fence
-// orders this thread's later loads of the published blocks.
-__device__ __forceinline__ int32_t sv_wait_above(const int32_t* cnt, int32_t need, SvWs* ws, int64_t wait_ticks) {
-  int32_t v = sv_ld(cnt);
-  if (v <= need) {
-    const uint64_t t0 = wall_clock64();
-    while ((v = sv_ld(cnt)) <= need) {
-      if (sv_ld(&ws->error)) return -1;
-      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
-        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return -1;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return v;
-}
-
 __device__ __forceinline__ int32_t sv_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Workgroup-wide wait: thread 0 alone polls (the other waves sleep in the
-// barrier), and the value it saw reaches every thread through LDS.  One
-// thread-0 branch per call, between barriers, with a wave-uniform result.
-__device__ __forceinline__ int32_t sv_wait_wg(const int32_t* cnt, int32_t need, SvWs* ws, int64_t wait_ticks,
-                                              int32_t* slot) {
-  if (threadIdx.x == 0) *slot = sv_wait_above(cnt, need, ws, wait_ticks);
-  __syncthreads();
-  const int32_t v = sv_uniform(*slot);
-  __syncthreads();  // the slot is rewritten by the next call
-  return v;
-}
-
-// Publish the completion of cnt blocks in sweep order by setting `done` to
-// pos + cnt.  The caller has seen done == pos: its wait loop ends only when
-// every earlier block is finished, and only the owner of position pos moves
-// the counter on from there.  All threads have fenced their stores before.
-// A workgroup whose wait was aborted publishes nothing.
-__device__ __forceinline__ void sv_publish(int32_t* done, int32_t pos, int32_t cnt, bool ok) {
-  if (threadIdx.x == 0 && ok) __hip_atomic_store(done, pos + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Broadcast lane l's value of v to the whole wave (l wave-uniform).
 __device__ __forceinline__ double sv_readlane(double v, int l) {
@@ -153,6 +107,26 @@ __device__ __forceinline__ bool sv_wave_wait(const double* probe, Load load, Pen
     }
     __builtin_amdgcn_s_sleep(1);
     if (sv_pending(sv_pay_ld(probe))) continue;
+    load();
+    if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  }
+}
+
+// Wave-level wait for a whole payload block by reloading it (one round trip
+// per check; used for the one block on the chain, which one workgroup at a
+// time waits for).  Same contract as sv_wave_wait.
+template <class Load, class Pending>
+__device__ __forceinline__ bool sv_wave_wait_full(Load load, Pending pending, SvWs* ws, int64_t wait_ticks) {
+  if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t it = 0;; ++it) {
+    if ((it & 15) == 0) {
+      if (sv_ld(&ws->error)) return false;
+      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
+        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
     load();
     if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
   }
@@ -541,24 +515,17 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
 }
 
 // ------------------------------------------------ matrix-core fold sweeps
-// The same sweeps with the fold of every finished block done as a 64 x 64
-// by 64 x 16 product on the FP64 matrix cores (v_mfma_f64_16x16x4_f64):
-// wave w owns rows 16 w .. 16 w + 15 of the block and up to 16 right-hand
-// sides.  Operand layout (measured on gfx950): A-operand lane l holds row
-// l % 16 at k group l / 16, B-operand lane l holds column l % 16 at k group
-// l / 16, output item q of lane l is row 4 q + l / 16, column l % 16.  In a
-// 16-wide k chunk ch of a block, lane (r, g) brings k = 16 ch + 4 g + m to
-// MFMA m for both operands.  The factor entries of the next block are
-// loaded while the current block is folded (and its right-hand-side rows
-// too, when that block is already known to be finished).
-//
-// The in-block substitution gives each wave up to four right-hand sides,
-// c = w, w + 4, w + 8, w + 12, whose chains run interleaved: lane k holds
-// row k for all four, and each step broadcasts the pivot data once.
-//
-// Rounding order per output entry: blocks in sweep order; within a block
-// the 16 MFMAs in (chunk, m) order, each adding its four products; then the
-// subtraction from B and the sequential substitution.
+// Three to sixteen right-hand sides (payload width 16): the folds run as
+// 64 x 64 by 64 x 16 products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64).  Operand layout (measured on gfx950): A-operand
+// lane l holds row l % 16 at k group l / 16, B-operand lane l holds column
+// l % 16 at k group l / 16, output item q of lane l is row 4 q + l / 16,
+// column l % 16.
+// The blocks up to the second neighbour are folded as their payloads arrive
+// (each wave on its own); the neighbour's payload is waited for by wave 0
+// and handed to the others through LDS; then every wave substitutes up to
+// four right-hand sides, c = w, w + 4, w + 8, w + 12, with interleaved chains
+// (lane k holds row k), and publishes them.
 typedef double sv_v4d __attribute__((ext_vector_type(4)));
 #define SV_MF_RC 16
 
@@ -566,31 +533,55 @@ __device__ __forceinline__ sv_v4d sv_mfma(double a, double b, sv_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Up to four interleaved chains of wave w over the columns w + 4 t (a
+// wave-uniform choice of the unrolled loop keeps the live chains together).
+template <bool FWD>
+__device__ __forceinline__ void sv_chains_cols(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
+                                               int lane, int w, int ncl) {
+  const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
+  if (FWD) {
+    if (nt >= 4) sv_chains_fwd<4>(v, Lbb, rdiag, lane);
+    else if (nt == 3) sv_chains_fwd<3>(v, Lbb, rdiag, lane);
+    else if (nt == 2) sv_chains_fwd<2>(v, Lbb, rdiag, lane);
+    else if (nt == 1) sv_chains_fwd<1>(v, Lbb, rdiag, lane);
+  } else {
+    if (nt >= 4) sv_chains_bwd<4>(v, Lbb, rdiag, lane);
+    else if (nt == 3) sv_chains_bwd<3>(v, Lbb, rdiag, lane);
+    else if (nt == 2) sv_chains_bwd<2>(v, Lbb, rdiag, lane);
+    else if (nt == 1) sv_chains_bwd<1>(v, Lbb, rdiag, lane);
+  }
+}
+
+// Forward: wave w owns rows 16 w .. 16 w + 15 of the block (whole 512-byte
+// row segments of L); in a 16-wide k chunk ch, lane (r, g) brings
+// k = 16 ch + 4 g + m to MFMA m for both operands.  Rounding order per
+// entry: the blocks in sweep order, each as 16 MFMAs in (chunk, m) order;
+// B minus the sum; then the substitution.  B is read, not written: the
+// backward sweep reads y_b from the payload.
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                        double* __restrict__ B, int64_t nc, int64_t ldb, SvWs* ws,
-                                                        int64_t wait_ticks) {
+                                                           const double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                           double* Ypay, double* __restrict__ Xpay, SvWs* ws,
+                                                           int64_t wait_ticks) {
   __shared__ double part[SV_NB][SV_MF_RC + 1];
+  __shared__ double yl[SV_NB][SV_MF_RC + 1];  // y_{b-1}, handed over by wave 0
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_b, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ int32_t s_b, s_ok;
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const int32_t b = sv_uniform(s_b);
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
   const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
   const int arow = 16 * w + r16;
   const bool alive = arow < nr;
   const bool bok = r16 < nc;
-  // row arow of the block, columns 4 g .. of every earlier block
   const double* lrow = L + (r0 + (alive ? arow : 0)) * lda + g4;
-  // right-hand side r16, rows 4 g .. of every earlier block
-  const double* ycol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
-  // the pointers above stay in bounds for idle lanes (row 0 / column 0), so
-  // every lane loads and idle lanes select zero: no branches in the fold
+  const double* ypay = Ypay + (int64_t)g4 * SV_MF_RC + r16;
+  for (int e = tid; e < SV_NB * SV_MF_RC; e += SV_THREADS)
+    Xpay[(int64_t)b * SV_NB * SV_MF_RC + e] = __builtin_bit_cast(double, SV_SENTINEL);
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
   auto load_l = [&](int32_t j, double* a) {
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
@@ -604,78 +595,119 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restr
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const double v = ycol[((int64_t)j * SV_NB + 16 * ch + m) * ldb];
-        y[4 * ch + m] = bok ? v : 0.0;
-      }
+      for (int m = 0; m < 4; ++m) y[4 * ch + m] = sv_pay_ld(ypay + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
   };
-  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  double la[16], ya[16];
-  bool have_y = false;
-  if (b > 0) load_l(0, la);
-  int32_t j = 0;
-  while (j < b) {
-    const int32_t ready = sv_wait_wg(&ws->done_f, j, ws, wait_ticks, &s_ready);
-    if (ready < 0) {  // aborted: finish the barrier sequence, publish nothing
-        ok = false;
-        break;
-      }
-    const int32_t jend = ready < b ? ready : b;
-    for (; j < jend; ++j) {
-      if (!have_y) load_y(j, ya);
-      const int32_t jn = j + 1 < b ? j + 1 : j;  // the last block re-reads itself
-      double ln[16], yn[16];
-      load_l(jn, ln);
-      have_y = j + 1 < jend;
-      if (have_y) load_y(j + 1, yn);
+  // read before any wait: the own rows of B, the neighbour tile L_{b,b-1}
+  // and the last folded tile L_{b,b-2}
+  double bown[4];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    bown[q] = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
+  }
+  double lnb[16];
+  if (b > 0) load_l(b - 1, lnb);
+  const int32_t nfold = b > 1 ? b - 1 : 0;  // blocks 0 .. b - 2
+  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  double lt[16], la[16], ya[16];
+  bool ok = true;
+  if (nfold > 0) {
+    load_l(nfold - 1, lt);
+    load_y(0, ya);
+  }
+  if (nfold > 1) load_l(0, la);
+  auto pending = [&] {
+    bool p = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) p = p || sv_pending(ya[k]);
+    return p;
+  };
+  auto probe = [&](int32_t j) { return Ypay + ((int64_t)j * SV_NB + SV_NB - 1) * SV_MF_RC + SV_MF_RC - 1; };
+  for (int32_t j = 0; j + 1 < nfold; ++j) {
+    if (!sv_wave_wait(probe(j), [&] { load_y(j, ya); }, pending, ws, wait_ticks)) {
+      ok = false;
+      break;
+    }
+    const bool more = j + 2 < nfold;
+    double ln[16], yn[16];
+    if (more) load_l(j + 1, ln);
+    load_y(j + 1, yn);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
+    if (more) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) la[k] = ln[k];
-      if (have_y) {
+    }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) ya[k] = yn[k];
+    for (int k = 0; k < 16; ++k) ya[k] = yn[k];
+  }
+  if (ok && nfold > 0) {
+    if (sv_wave_wait(probe(nfold - 1), [&] { load_y(nfold - 1, ya); }, pending, ws, wait_ticks)) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = sv_mfma(lt[k], ya[k], acc);
+    } else {
+      ok = false;
+    }
+  }
+  // the neighbour y_{b-1}: wave 0 waits and hands it over through LDS
+  __builtin_amdgcn_s_setprio(3);
+  if (b > 0) {
+    if (w == 0) {
+      if (ok) load_y(b - 1, ya);
+      const bool got = ok && sv_wave_wait_full([&] { load_y(b - 1, ya); }, pending, ws, wait_ticks);
+      if (got) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) yl[16 * ch + g4 + m][r16] = ya[4 * ch + m];
       }
+      if (lane == 0) s_ok = got;
+    }
+    __syncthreads();
+    ok = ok && s_ok;
+    if (ok) {
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc = sv_mfma(lnb[4 * ch + m], yl[16 * ch + g4 + m][r16], acc);
     }
   }
-  // item q: row 16 w + 4 q + g, right-hand side r16
 #pragma unroll
-  for (int q = 0; q < 4; ++q) part[16 * w + 4 * q + (lane >> 4)][r16] = acc[q];
-  __syncthreads();
-  {
-    const int ncl = (int)nc;
-    double v[4];
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4);
+    part[row][r16] = (row < nr && bok) ? bown[q] - acc[q] : 0.0;
+  }
+  const bool all_ok = __syncthreads_and(ok);
+  double v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = part[lane][w + 4 * t];
+  sv_chains_cols<true>(v, Lbb, rdiag, lane, w, (int)nc);
+  if (all_ok) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = w + 4 * t;
-      v[t] = (c < ncl && lane < nr) ? B[(r0 + lane) * ldb + c] - (b > 0 ? part[lane][c] : 0.0) : 0.0;
-    }
-    // chains with no right-hand side are left out (a wave-uniform choice of
-    // the unrolled loop, so the live chains stay interleaved)
-    const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
-    if (nt >= 4) sv_chains_fwd<4>(v, Lbb, rdiag, lane);
-    else if (nt == 3) sv_chains_fwd<3>(v, Lbb, rdiag, lane);
-    else if (nt == 2) sv_chains_fwd<2>(v, Lbb, rdiag, lane);
-    else if (nt == 1) sv_chains_fwd<1>(v, Lbb, rdiag, lane);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = w + 4 * t;
-      if (c < ncl && lane < nr) B[(r0 + lane) * ldb + c] = v[t];
+      sv_pay_st(Ypay + ((int64_t)b * SV_NB + lane) * SV_MF_RC + c, (lane < nr && c < nc) ? v[t] : 0.0);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  sv_publish(&ws->done_f, b, 1, ok);
 }
 
+// Backward: the fold splits k across the waves (wave w takes rows
+// 16 w .. 16 w + 15 of every later block, for all 64 output rows: whole
+// 512-byte row segments of L, and only those 16 payload rows).  MFMA
+// (o, kc): output rows 16 o .., k rows 16 w + 4 kc + g.  Rounding order per
+// entry: each wave sums its blocks in sweep order (the neighbour last), each
+// as 4 MFMAs in kc order; the waves' sums combine as (w0 + w2) + (w1 + w3);
+// y_b minus that; then the substitution.
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                        double* __restrict__ B, int64_t nc, int64_t ldb, SvWs* ws,
-                                                        int64_t wait_ticks) {
-  __shared__ double part[SV_NB][SV_MF_RC + 1];
+                                                           double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                           const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
+                                                           int64_t wait_ticks) {
+  __shared__ double red[2][SV_NB][SV_MF_RC + 1];  // partial sums; red[0] then holds v
+  __shared__ double xl[SV_NB][SV_MF_RC + 1];      // x_{b+1}, handed over by wave 0
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_t, s_ready;
-  bool ok = true;  // no dependency wait aborted
+  __shared__ int32_t s_t, s_ok;
+  double(*part)[SV_MF_RC + 1] = red[0];
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -684,96 +716,152 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restr
   const int32_t b = nb - 1 - t;
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
-  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
-  const int arow = 16 * w + r16;  // output row of the block = column r0 + arow of L
-  const bool alive = arow < nr;
+  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4, g = lane >> 4;
   const bool bok = r16 < nc;
-  // column r0 + arow of L, rows 4 g .. of every later block
-  const double* lcol = L + (int64_t)g4 * lda + r0 + (alive ? arow : 0);
-  const double* xcol = B + (int64_t)g4 * ldb + (bok ? r16 : 0);
-  // rows of block j past n read as zero (only the last block is ragged)
-  // rows past the last row are clamped to it (in bounds) and selected away
+  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
   auto load_l = [&](int32_t j, double* a) {
     const int64_t j0 = (int64_t)j * SV_NB;
     const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kr = 16 * w + 4 * kc + g;
+      const bool kin = kr < njr;
+      const double* rowp = L + (j0 + (kin ? kr : 0)) * lda + r0;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int kk = 16 * ch + g4 + m;
-        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
-        const double v = lcol[(j0 + ks) * lda];
-        a[4 * ch + m] = (alive && kk < njr) ? v : 0.0;
+      for (int o = 0; o < 4; ++o) {
+        const int col = 16 * o + r16;
+        const bool cin = col < nr;
+        const double v = rowp[cin ? col : 0];
+        a[4 * o + kc] = (kin && cin) ? v : 0.0;
       }
+    }
+  };
+  auto load_xk = [&](int32_t j, double* x) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+      x[kc] = sv_pay_ld(Xpay + ((int64_t)j * SV_NB + 16 * w + 4 * kc + g) * SV_MF_RC + r16);
   };
   auto load_x = [&](int32_t j, double* x) {
-    const int64_t j0 = (int64_t)j * SV_NB;
-    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
+    const double* xp = Xpay + (int64_t)g4 * SV_MF_RC + r16;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int kk = 16 * ch + g4 + m;
-        const int ks = kk < njr ? 16 * ch + m : njr - 1 - g4;
-        const double v = xcol[(j0 + ks) * ldb];
-        x[4 * ch + m] = (bok && kk < njr) ? v : 0.0;
-      }
+      for (int m = 0; m < 4; ++m) x[4 * ch + m] = sv_pay_ld(xp + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
   };
-  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  double la[16], xa[16];
-  bool have_x = false;
-  if (b < nb - 1) load_l(nb - 1, la);
-  int32_t j = nb - 1;
-  while (j > b) {
-    const int32_t ready = sv_wait_wg(&ws->done_b, nb - 1 - j, ws, wait_ticks, &s_ready);
-    if (ready < 0) {
-        ok = false;
-        break;
-      }
-    const int32_t jlow = nb - ready > b + 1 ? nb - ready : b + 1;
-    for (; j >= jlow; --j) {
-      if (!have_x) load_x(j, xa);
-      const int32_t jn = j - 1 > b ? j - 1 : j;  // the last block re-reads itself
-      double ln[16], xn[16];
-      load_l(jn, ln);
-      have_x = j - 1 >= jlow;
-      if (have_x) load_x(j - 1, xn);
+  // read before any wait: the own rows of y (an earlier launch's payload),
+  // the neighbour tile (block b + 1) and the last folded tile (block b + 2)
+  double yown[4];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], xa[k], acc);
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + g;
+    yown[q] = Ypay[((int64_t)b * SV_NB + row) * SV_MF_RC + r16];
+  }
+  double lnb[16];
+  if (b + 1 < nb) load_l(b + 1, lnb);
+  const int32_t jlast = b + 2;
+  sv_v4d acc[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) acc[o] = (sv_v4d){0.0, 0.0, 0.0, 0.0};
+  double lt[16], la[16], xa[4];
+  bool ok = true;
+  if (jlast < nb) {
+    load_l(jlast, lt);
+    load_xk(nb - 1, xa);
+  }
+  if (jlast < nb - 1) load_l(nb - 1, la);
+  auto pending = [&] { return sv_pending(xa[0]) || sv_pending(xa[1]) || sv_pending(xa[2]) || sv_pending(xa[3]); };
+  auto probe = [&](int32_t j) { return Xpay + ((int64_t)j * SV_NB + 16 * w + 15) * SV_MF_RC + SV_MF_RC - 1; };
+  auto fold = [&](const double* a, const double* x) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) acc[o] = sv_mfma(a[4 * o + kc], x[kc], acc[o]);
+  };
+  for (int32_t j = nb - 1; j > jlast; --j) {
+    if (!sv_wave_wait(probe(j), [&] { load_xk(j, xa); }, pending, ws, wait_ticks)) {
+      ok = false;
+      break;
+    }
+    const bool more = j - 1 > jlast;
+    double ln[16], xn[4];
+    if (more) load_l(j - 1, ln);
+    load_xk(j - 1, xn);
+    fold(la, xa);
+    if (more) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) la[k] = ln[k];
-      if (have_x) {
+    }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) xa[k] = xn[k];
+    for (int k = 0; k < 4; ++k) xa[k] = xn[k];
+  }
+  if (ok && jlast < nb) {
+    if (sv_wave_wait(probe(jlast), [&] { load_xk(jlast, xa); }, pending, ws, wait_ticks))
+      fold(lt, xa);
+    else
+      ok = false;
+  }
+  // the neighbour x_{b+1}: wave 0 waits and hands it over through LDS
+  __builtin_amdgcn_s_setprio(3);
+  if (b + 1 < nb) {
+    if (w == 0) {
+      double xc[16];
+      auto pend16 = [&] {
+        bool p = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p = p || sv_pending(xc[k]);
+        return p;
+      };
+      if (ok) load_x(b + 1, xc);
+      const bool got = ok && sv_wave_wait_full([&] { load_x(b + 1, xc); }, pend16, ws, wait_ticks);
+      if (got) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) xl[16 * ch + g4 + m][r16] = xc[4 * ch + m];
       }
+      if (lane == 0) s_ok = got;
+    }
+    __syncthreads();
+    ok = ok && s_ok;
+    if (ok) {
+      double xk[4];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) xk[kc] = xl[16 * w + 4 * kc + g][r16];
+      fold(lnb, xk);
     }
   }
+  // combine the waves' sums: red[0] = w0 + w2, red[1] = w1 + w3
+  if (w < 2) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) part[16 * w + 4 * q + (lane >> 4)][r16] = acc[q];
-  __syncthreads();
-  {
-    const int ncl = (int)nc;
-    double v[4];
+    for (int o = 0; o < 4; ++o)
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int c = w + 4 * tt;
-      v[tt] = (c < ncl && lane < nr) ? B[(r0 + lane) * ldb + c] - (b < nb - 1 ? part[lane][c] : 0.0) : 0.0;
-    }
-    const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
-    if (nt >= 4) sv_chains_bwd<4>(v, Lbb, rdiag, lane);
-    else if (nt == 3) sv_chains_bwd<3>(v, Lbb, rdiag, lane);
-    else if (nt == 2) sv_chains_bwd<2>(v, Lbb, rdiag, lane);
-    else if (nt == 1) sv_chains_bwd<1>(v, Lbb, rdiag, lane);
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int c = w + 4 * tt;
-      if (c < ncl && lane < nr) B[(r0 + lane) * ldb + c] = v[tt];
-    }
+      for (int q = 0; q < 4; ++q) red[w][16 * o + 4 * q + g][r16] = acc[o][q];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  sv_publish(&ws->done_b, t, 1, ok);
+  if (w >= 2) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[w - 2][16 * o + 4 * q + g][r16] += acc[o][q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + g;
+    const double f = red[0][row][r16] + red[1][row][r16];
+    part[row][r16] = (row < nr && bok) ? yown[q] - f : 0.0;
+  }
+  const bool all_ok = __syncthreads_and(ok);
+  double v[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) v[tt] = part[lane][w + 4 * tt];
+  sv_chains_cols<false>(v, Lbb, rdiag, lane, w, (int)nc);
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const int c = w + 4 * tt;
+    if (lane < nr && c < nc) B[(r0 + lane) * ldb + c] = v[tt];
+    if (all_ok) sv_pay_st(Xpay + ((int64_t)b * SV_NB + lane) * SV_MF_RC + c, (lane < nr && c < nc) ? v[tt] : 0.0);
+  }
 }
 
 // ------------------------------------------- sweeps with inverted diagonals
@@ -867,25 +955,6 @@ __device__ __forceinline__ void sv_stage_inv(const double* __restrict__ D, doubl
   for (int e = threadIdx.x; e < SV_NB * SV_NB; e += SV_THREADS) Ds[e / SV_NB][e % SV_NB] = D[e];
 }
 
-// Wave-level wait for a whole payload block by reloading it (one round trip
-// per check; used for the one block on the chain, which one workgroup at a
-// time waits for).  Same contract as sv_wave_wait.
-template <class Load, class Pending>
-__device__ __forceinline__ bool sv_wave_wait_full(Load load, Pending pending, SvWs* ws, int64_t wait_ticks) {
-  if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
-  const uint64_t t0 = wall_clock64();
-  for (uint32_t it = 0;; ++it) {
-    if ((it & 15) == 0) {
-      if (sv_ld(&ws->error)) return false;
-      if (wall_clock64() - t0 > (uint64_t)wait_ticks) {
-        __hip_atomic_store(&ws->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    load();
-    if (__builtin_amdgcn_ballot_w64(pending()) == 0) return true;
-  }
-}
 
 // The forward sweep reads its own rows of the right-hand side from B and
 // publishes y_b into the payload Ypay (it does not write B); the backward
@@ -1351,13 +1420,14 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
                        ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
     return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
   }
+  const SvMap m = sv_map(work, n, SV_MF_RC);
   for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
     const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
-    hipLaunchKernelGGL(sv_clear, dim3(1), dim3(64), 0, st, ws, SV_COUNTER_WORDS);
-    hipLaunchKernelGGL(sv_fwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,
-                       wait_ticks);
-    hipLaunchKernelGGL(sv_bwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb, ws,
-                       wait_ticks);
+    sv_launch_fill(m, st);
+    hipLaunchKernelGGL(sv_fwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, (const double*)(B + c0), nc,
+                       ldb, m.ypay, m.xpay, ws, wait_ticks);
+    hipLaunchKernelGGL(sv_bwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb,
+                       (const double*)m.ypay, m.xpay, ws, wait_ticks);
   }
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }
