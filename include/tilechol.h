@@ -171,14 +171,20 @@ int chol_factor_noalloc(double* A, int64_t n, int64_t lda, int64_t T, int sched,
  * CHOL_NOT_SPD or CHOL_ETIMEOUT. */
 int chol_factor_info(const void* work, void* stream, int64_t* info);
 
-/* Bytes of device workspace chol_solve needs (a few counters); < 0 on
- * invalid arguments. */
+/* Bytes of device workspace chol_solve needs: a 256-byte header (block
+ * tickets and the status word), then two payload areas of
+ * ceil(n / 64) * 64 rows of 2 (nrhs <= 2) or 16 (nrhs > 2) doubles each,
+ * every part rounded up to 256 bytes; < 0 on invalid arguments. */
 int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
 
 /* Solve A X = B with the factor from chol_factor (the paper's motivating
  * use, SPD linear systems via the Cholesky decomposition): forward
  * substitution L Y = B, then backward substitution L^T X = Y, each one
- * launch over 64-row blocks that wait on per-sweep completion counters.
+ * launch over 64-row blocks (one per workgroup).  A solved block reaches
+ * the workgroups of later blocks through the workspace's payload areas
+ * (device-scope atomic stores read until no sentinel remains), so no
+ * counter or cache flush sits between two blocks of the chain; sixteen
+ * right-hand sides at most per pass, more in passes of 16.
  *   L      device pointer to the factor (lower triangle read only).
  *   B      device pointer, n x nrhs row-major, leading dimension
  *          ldb >= max(1, nrhs); overwritten by X.
@@ -248,15 +254,21 @@ enum {
 /* Status of chol_solve_refine when max_iter is reached first. */
 #define CHOL_NOT_CONVERGED 2
 
-/* Bytes of device workspace chol_solve_refine needs: four n x nrhs FP64
- * blocks, n doubles and a few per-column scalars.  < 0 on invalid
- * arguments. */
+/* Bytes of device workspace chol_solve_refine needs: the solve's header and
+ * 16-column payloads, three arrays of ceil(n / 64) 64 x 64 blocks (the
+ * inverted diagonal blocks of L and the coupling blocks of neighbouring
+ * block rows), four n x nrhs FP64 blocks, n doubles and a few per-column
+ * scalars.  < 0 on invalid arguments. */
 int64_t chol_refine_workspace_size(int64_t n, int64_t T, int64_t nrhs);
 
 /* Solve A X = B in FP64 to backward error <= tol per column, with a factor
  * L L^T of A (or of a shifted A) from chol_factor_mixed or chol_factor.
  * The backward error of column c is ||b - A x||_inf / (||A||_inf ||x||_inf
- * + ||b||_inf).
+ * + ||b||_inf).  The solves with L L^T use the 64 x 64 diagonal blocks of L
+ * inverted once per call and the products D_b L_{b,b-1} of neighbouring
+ * block rows, so one matrix-core product per block sits on the sweeps'
+ * chain; their rounding (about kappa(L_bb) u) is corrected by the
+ * refinement like the factor's own error.
  *   A       device, the original SPD matrix (lower triangle read; lda).
  *   L       device, the factor (lower triangle read; ldl).
  *   B       device, n x nrhs row-major (ldb >= nrhs), read only.
