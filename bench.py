@@ -70,10 +70,13 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense matrix
 # code (KERNEL_SOURCES) the counters were taken with: if it differs, the
 # figure no longer describes this kernel and the line reports traffic as null.
 TRAFFIC = {
-    # (schedule, n, T): (bytes per update launch, sha256 of the kernel sources);
-    # profiles/forkjoin_n32768_T1024_kernels.md holds the counter readings
-    ("fork_join", 32768, 1024): (14840737564,
-                                 "edf0e223697f76ccb4261f59af1a4a02bcd3280bb5e66fa497472d8eb731c980"),
+    # (schedule, n, T): (bytes per launch of the roofline kernel, sha256 of the
+    # kernel sources); the profiles under profiles/ hold the counter readings
+    # (forkjoin_n32768_T1024_kernels.md, lookahead_n32768_T1024_kernels.md)
+    ("fork_join", 32768, 1024): (14837566782,
+                                 "8f41d5310a11b1bc350fb5089075acda6493f7db3d6bccb957c0c31504411cc7"),
+    ("fork_join_lookahead", 32768, 1024): (13935044036,
+                                           "9b97f7195ca964e4ad1168d8e82b42e7a4a2fbc78055e27b5b91d1b8c1878bcc"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,
