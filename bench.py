@@ -75,8 +75,9 @@ TRAFFIC = {
     # (forkjoin_n32768_T1024_kernels.md, lookahead_n32768_T1024_kernels.md)
     ("fork_join", 32768, 1024): (14837566782,
                                  "8f41d5310a11b1bc350fb5089075acda6493f7db3d6bccb957c0c31504411cc7"),
-    ("fork_join_lookahead", 32768, 1024): (13935044036,
-                                           "9b97f7195ca964e4ad1168d8e82b42e7a4a2fbc78055e27b5b91d1b8c1878bcc"),
+    # lookahead: the bulk of one step (its pool launch and tail summed)
+    ("fork_join_lookahead", 32768, 1024): (12539996553,
+                                           "be30c70d6398a5b88dd8dc16be9a258de3b2216310a1e280b3d7d4fcad81b00e"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,
@@ -709,10 +710,14 @@ def main():
     value = flops / (ms_step * 1e-3) / 1e12
 
     if sched == "fork_join_lookahead":
-        # the bulk of each step's update runs on the second stream, one launch
-        # at a time: its summed launch time fits inside the step
-        kernel = ("tc_fj_update_rest (SYRK+GEMM trailing update of the tile columns beyond J+1, one launch per "
-                  "step on the second stream, concurrent with the next panel chain)")
+        # the bulk of each step's update: one interval per step (its pool
+        # launch on the second stream and that launch's tail on the caller's
+        # stream share one unit counter), one step at a time, so the summed
+        # intervals fit inside the step
+        kernel = ("tc_fj_update_pool (SYRK+GEMM trailing update of the tile columns beyond J+1: per step a launch on "
+                  "the second stream leaving workgroup slots to the next panel chain, and a tail launch on the "
+                  "caller's stream behind that chain, on one unit counter; timed from the first's start to the "
+                  "later end)")
         kms, kcount = launches["update_rest"]
         kflops = update_flops(n, T, beyond_next=True) * K
     elif sched.startswith("fork_join"):

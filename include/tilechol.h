@@ -504,9 +504,11 @@ int64_t chol_async_grid(void);
  * Per-launch device time of chol_factor.  `kinds` is a bit mask: bit k
  * (k = CHOL_UNIT_POTRF, CHOL_UNIT_TRSM, CHOL_UNIT_UPDATE, CHOL_UNIT_PANEL)
  * times the fork-join launches of that unit kind, bit 4 the persistent
- * launch of the asynchronous schedule, bit 5 the trailing-update launches
- * that CHOL_SCHED_FORK_JOIN_LOOKAHEAD runs on its second stream (the
- * columns beyond J+1; its column-(J+1) launches count under bit
+ * launch of the asynchronous schedule, bit 5 the bulk trailing update of
+ * each step of CHOL_SCHED_FORK_JOIN_LOOKAHEAD (the columns beyond J+1: one
+ * interval per step, from its launch on the second stream to the later of
+ * that launch's end and the end of its tail launch on the call's stream,
+ * which shares its unit counter; its column-(J+1) launches count under bit
  * CHOL_UNIT_UPDATE); 0 turns timing off.  While enabled on
  * the calling thread, each selected launch chol_factor enqueues is
  * bracketed by a pair of HIP events on the call's stream (events are

@@ -244,16 +244,28 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_range(double* A, i
   }
 }
 
-// The rest of step J's update (columns beyond J+1) on the second stream:
-// the same units and bodies as the range kernel, under a name of its own so
-// that traces and counters report the bulk launches apart from the small
-// column-(J+1) launches that overlap them.
-__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_rest(double* A, int64_t lda, TcGeom g, int32_t J,
-                                                                   TcWs ws, int64_t first) {
+// The bulk of step J's update (units [first, first + count) of the launch
+// order above) by workgroups that take units from a counter until none is
+// left.  The lookahead schedule launches it twice per step on one counter:
+// first with fewer workgroups than fit on the chip, so that the panel chain
+// of step J+1 finds free workgroup slots at once instead of queueing behind
+// the bulk, then, behind that chain, into the slots the chain frees.  Each
+// unit's body, and the order of the updates each block receives, are those
+// of the one-unit-per-workgroup launch.
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_pool(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                   TcWs ws, int64_t first, int64_t count,
+                                                                   unsigned long long* ctr) {
   __shared__ TcUpdSmem sm;
+  __shared__ int64_t s_u;
   if (tc_err_set(ws.hdr) || ws.noop) return;
-  const TcUnit u = tc_decode_trailing(g, J, J, first + blockIdx.x);
-  tc_run_update(A, lda, g, u, sm);
+  for (;;) {
+    if (threadIdx.x == 0) s_u = (int64_t)atomicAdd(ctr, 1ull);
+    __syncthreads();  // also: every thread is done with the previous unit's LDS
+    const int64_t u = s_u;
+    if (u >= count) break;
+    tc_run_update(A, lda, g, tc_decode_trailing(g, J, J, first + u), sm);
+    __syncthreads();  // s_u is rewritten next
+  }
 }
 
 // ----------------------------------------------- low-precision trailing update
@@ -874,6 +886,7 @@ struct TcTimer {
   struct Rec {
     int kind;
     hipEvent_t a, b;
+    hipEvent_t b2;  // a second end event on another stream (or null): the interval ends at the later one
   };
   std::vector<Rec> recs;
   hipEvent_t next() {
@@ -902,9 +915,19 @@ void tc_timed(int kind, hipStream_t st, F fn) {
   (void)hipEventRecord(a, st);
   fn();
   (void)hipEventRecord(b, st);
-  g_timer.recs.push_back({kind, a, b});
+  g_timer.recs.push_back({kind, a, b, nullptr});
 }
 }  // namespace
+
+// Index of the last timed record (or -1 when `kind` is not timed), and
+// ending that record also at an event recorded now on `st`.
+static int tc_timed_last(int kind) { return (g_timer.mask >> kind & 1) ? (int)g_timer.recs.size() - 1 : -1; }
+static void tc_timed_extend(int rec, hipStream_t st) {
+  if (rec < 0 || rec >= (int)g_timer.recs.size()) return;
+  hipEvent_t e = g_timer.next();
+  if (e == nullptr || hipEventRecord(e, st) != hipSuccess) return;
+  g_timer.recs[rec].b2 = e;
+}
 
 int tc_timing_enable(int mask) {
   const int prev = g_timer.mask;
@@ -920,9 +943,10 @@ int tc_timing_read(hipStream_t st, double ms[TC_TIMING_KINDS], int64_t cnt[TC_TI
   int rc = 0;
   if (hipStreamSynchronize(st) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
   for (const TcTimer::Rec& r : g_timer.recs) {
-    float t = 0.0f;
+    float t = 0.0f, t2 = 0.0f;
     if (rc == 0 && hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
-    ms[r.kind] += t;
+    if (rc == 0 && r.b2 != nullptr && hipEventElapsedTime(&t2, r.a, r.b2) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
+    ms[r.kind] += t2 > t ? t2 : t;
     cnt[r.kind] += 1;
   }
   g_timer.recs.clear();
@@ -1081,6 +1105,8 @@ static int tc_launch_factor_graph(double* A, int64_t n, int64_t lda, int64_t T, 
   return tc_chk(hipGetLastError());
 }
 
+static int64_t tc_pool_grid_size();
+
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks, int64_t chunk) {
   const int sched = sched_flags & 0xff;
@@ -1129,16 +1155,40 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
     // caller's) runs the panel chain and, for step J, the update of column
     // J+1 only; stream B runs the update of the columns beyond J+1, which
     // overlaps the panel chain of step J+1.  Each block still receives its
-    // updates in step order: the column-(J+1) update of step J waits for B's
-    // update of step J-1, and B's update of step J waits for A's panel J.
+    // updates in step order: the column-(J+1) update of step J waits for the
+    // bulk of step J-1, and the bulk of step J for A's panel J and column
+    // J+1 (which ran after the bulk of step J-1).
+    // The bulk runs as a pool (tc_fj_update_pool) on a per-step unit counter:
+    // on B with `reserve` workgroup slots left free for A's panel chain, then
+    // on A behind the next step's chain, into the slots the chain frees.
+    // Unit bodies and per-block update order are the fork-join ones, so the
+    // factor is bit-identical to every other schedule.
     hipStream_t sb = tc_side_stream();
     hipEvent_t ea = tc_side_event(0), eb = tc_side_event(1);
     if (sb == nullptr || ea == nullptr || eb == nullptr) return TC_LAUNCH_EDEVICE;
+    const int64_t cap = tc_pool_grid_size();
+    if (cap <= 0) return TC_LAUNCH_EDEVICE;
+    // slots left to the chain: 3/16 of the chip, measured best among 1/16 ..
+    // 6/16 at n=32768, T=1024 (205.6 .. 204.4 .. 206.4 ms)
+    const int64_t reserve = cap * 3 / 16 > 0 ? cap * 3 / 16 : 1;
+    // the per-step unit counters live in the phase-offset words (used by the
+    // persistent schedule only)
+    unsigned long long* cnt = (unsigned long long*)ws.offs;
+    hipLaunchKernelGGL(tc_fill_zero, dim3(1), dim3(256), 0, st, (int32_t*)ws.offs, (int64_t)(2 * (g.M + 1)));
     tc_timed(TC_UNIT_POTRF, st, [&] {
       hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
     });
-    if (hipEventRecord(ea, st) != hipSuccess || hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
     bool b_used = false;
+    int32_t tail = -1;  // the step whose bulk still needs its second launch on A
+    int64_t tail_first = 0, tail_count = 0;
+    int tail_rec = -1;  // its timing record, ended by the tail too
+    auto launch_tail = [&]() {
+      if (tail < 0) return;
+      hipLaunchKernelGGL(tc_fj_update_pool, dim3((unsigned)reserve), dim3(TC_THREADS), 0, st, A, lda, g, tail, ws,
+                         tail_first, tail_count, cnt + tail);
+      tc_timed_extend(tail_rec, st);
+      tail = -1;
+    };
     for (int32_t J = 0; J < g.M; ++J) {
       for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
         const int64_t nt = tc_trsm_count(g, J, sc);
@@ -1152,25 +1202,33 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
             hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
           });
       }
+      launch_tail();  // step J-1's bulk, into the slots panel J leaves
       const int64_t nu = tc_trailing_units(g, J);
       if (nu <= 0) continue;
       const int64_t ncol = tc_colsize(g, J + 1);  // units of tile column J+1 at step J
-      if (hipEventRecord(ea, st) != hipSuccess) return TC_LAUNCH_EDEVICE;  // panel J done
-      if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;  // B's step J-1
+      if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;  // B's bulk J-1
+      // column J+1 first, on the whole chip: the chain of step J+1 waits
+      // for it, while the bulk waits only for its own inputs
       tc_timed(TC_UNIT_UPDATE, st, [&] {
         hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)ncol), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
                            (int64_t)0);
       });
+      if (hipEventRecord(ea, st) != hipSuccess) return TC_LAUNCH_EDEVICE;  // panel J, bulk J-1, column J+1
       if (nu > ncol) {
         if (hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
         tc_timed(TC_TIMING_REST, sb, [&] {
-          hipLaunchKernelGGL(tc_fj_update_rest, dim3((unsigned)(nu - ncol)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
-                             ws, ncol);
+          hipLaunchKernelGGL(tc_fj_update_pool, dim3((unsigned)(cap - reserve)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
+                             ws, ncol, nu - ncol, cnt + J);
         });
+        tail_rec = tc_timed_last(TC_TIMING_REST);
         if (hipEventRecord(eb, sb) != hipSuccess) return TC_LAUNCH_EDEVICE;
         b_used = true;
+        tail = J;
+        tail_first = ncol;
+        tail_count = nu - ncol;
       }
     }
+    launch_tail();
     // the caller's stream covers all of it
     if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
     return tc_chk(hipGetLastError());
@@ -1503,6 +1561,12 @@ int64_t tc_batched_grid_size() {
 int64_t tc_sync_grid_size() {
   static int64_t cached[64] = {0};
   return tc_persistent_grid(tc_sync, cached);
+}
+
+// Co-resident workgroups of the bulk-update pool kernel.
+static int64_t tc_pool_grid_size() {
+  static int64_t cached[64] = {0};
+  return tc_persistent_grid(tc_fj_update_pool, cached);
 }
 
 // ------------------------------------------ factorization without allocation
