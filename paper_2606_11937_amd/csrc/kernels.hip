@@ -29,6 +29,7 @@
 
 #include "batch_plan.h"
 #include "dag.h"
+#include "gptr.h"
 #include "launch.h"
 #include "tile_ops.h"
 #include "tile_ops_lp.h"
@@ -503,49 +504,125 @@ __global__ __launch_bounds__(TC_THREADS) void tc_batch_units(const TcBatchMat* _
 }
 
 // ---- one-workgroup solve with one right-hand side, in place in b
-// (forward then backward substitution over 64-row blocks; the finished part
-// is folded in by 4 threads per row with a fixed combination order, and
-// the diagonal block is solved by wave 0 in registers, one row per lane).
+// (forward then backward substitution over 64-row blocks).  The finished
+// part of x is folded into a block with reads along the stored rows of L, a
+// whole 512-byte row segment per wave instruction and up to 32 of them in
+// flight: forward, wave w takes the block's rows 16w..16w+15 and lane l the
+// columns l (mod 64), its 16 per-row partial sums then reduced across the
+// wave by a halving exchange; backward, wave w takes the 64-row chunks w,
+// w + 4, ... below the block and lane l column l of the block, the four
+// wave partials then added in wave order.  The diagonal block, loaded into
+// registers before the fold and parked in LDS after it, is solved by wave 0
+// in registers, one row per lane.  Every sum has a fixed order.
 struct TcSolveSmem {
   double Lbb[64][65];
-  double rdiag[64];
-  double part[64];
+  double part[4][64];
 };
 
-__device__ __forceinline__ void tc_wg_stage_diag(const double* L, int64_t lda, int64_t r0, int nr, TcSolveSmem& sm) {
-  for (int e = tc_tid(); e < 64 * 64; e += TC_THREADS) {
-    const int i = e >> 6, k = e & 63;
-    sm.Lbb[i][k] = (i < nr && k <= i) ? L[(r0 + i) * lda + r0 + k] : (i == k ? 1.0 : 0.0);
+// Sums of 16 per-lane partials (acc[q] for row q) over the 64 lanes of a
+// wave: halving exchanges over lane bits 5, 4, 3, 2 leave lane l holding a
+// partial of row (l >> 2), the exchanges over bits 0, 1 complete it.
+__device__ __forceinline__ double tc_wave_rowsum16(double acc[16], int lane) {
+#pragma unroll
+  for (int h = 8, bit = 32; h >= 1; h >>= 1, bit >>= 1) {
+    const bool hi = (lane & bit) != 0;
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+      const double send = hi ? acc[q] : acc[q + h];
+      const double keep = hi ? acc[q + h] : acc[q];
+      acc[q] = keep + __shfl_xor(send, bit);
+    }
   }
-  __syncthreads();
-  if (tc_tid() < 64) sm.rdiag[tc_tid()] = 1.0 / sm.Lbb[tc_tid()][tc_tid()];
-  __syncthreads();
+  double s = acc[0];
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  return s;
 }
 
 // One column of the right-hand sides: entries b[k * ldb].
 __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_t lda, int64_t n,
                                             double* __restrict__ b, int64_t ldb, TcSolveSmem& sm) {
   const int tid = tc_tid(), lane = tid & 63, w = tid >> 6;
-  const int r = tid >> 2, p = tid & 3;
+  const int wu = tc_uniform((int32_t)w);
   const int64_t nb = (n + 63) / 64;
+  double dv[16];
+  // the diagonal block, rows w + 4q, column lane, staged in LDS while the
+  // first loads of the fold are in flight.  A full block is read whole (the
+  // entries above its diagonal are never used); the last block reads zeros
+  // past its end, and its padding rows take a unit pivot in the substitution.
+  // (The thread index is re-read so that nothing lane-dependent is hoisted
+  // out of the block loop and kept live across it.)
+  auto load_diag = [&](int64_t r0, int nr) {
+    const int t = tc_tid(), wl = t >> 6, ll = t & 63;
+    const int32_t wo = (int32_t)(wl * lda) + ll;
+    if (nr == 64) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double* Bq = L + (r0 + 4 * q) * lda + r0;
+        dv[q] = Bq[wo];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double* Bq = L + (r0 + 4 * q) * lda + r0;
+        dv[q] = (wl + 4 * q < nr && ll < nr) ? Bq[wo] : 0.0;
+      }
+    }
+  };
+  auto put_diag = [&]() {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sm.Lbb[w + 4 * q][lane] = dv[q];
+  };
   for (int64_t blk = 0; blk < nb; ++blk) {
     const int64_t r0 = blk * 64;
     const int nr = n - r0 < 64 ? (int)(n - r0) : 64;
-    double s = 0.0;
-    if (r < nr) {
-      const double* Lr = L + (r0 + r) * lda;
-      for (int64_t k = p; k < r0; k += 4) s += Lr[k] * b[k * ldb];
+    // part_i = sum_{k < r0} L_ik x_k; rows past the block's end read its
+    // last row (their sums are never used).  The row addresses are uniform:
+    // lane l reads element l of each 64-column segment.
+    double acc[16];
+    int32_t rq[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      acc[q] = 0.0;
+      rq[q] = 16 * wu + q < nr ? 16 * wu + q : nr - 1;
     }
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    if (p == 0) sm.part[r] = s;
-    tc_wg_stage_diag(L, lda, r0, nr, sm);
+    // two register sets: the loads of the next 64 columns are issued before
+    // the current ones are folded in (the scheduling barriers keep the
+    // compiler from interleaving each load with its use)
+    double va[16], vb[16], xa = 0.0, xb = 0.0;
+    auto fetch = [&](double(&v)[16], double& x, int64_t c0) {
+      x = b[(c0 + lane) * ldb];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double* Lr = L + (r0 + rq[q]) * lda + c0;
+        v[q] = Lr[lane];
+      }
+    };
+    auto fold = [&](const double(&v)[16], double x) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(v[q], x, acc[q]);
+    };
+    if (r0 > 0) fetch(va, xa, 0);
+    load_diag(r0, nr);  // its wait overlaps the first fetch
+    put_diag();
+    for (int64_t c0 = 0; c0 < r0; c0 += 128) {
+      if (c0 + 64 < r0) fetch(vb, xb, c0 + 64);
+      __builtin_amdgcn_sched_barrier(0);
+      fold(va, xa);
+      if (c0 + 64 >= r0) break;
+      if (c0 + 128 < r0) fetch(va, xa, c0 + 128);
+      __builtin_amdgcn_sched_barrier(0);
+      fold(vb, xb);
+    }
+    const double s = tc_wave_rowsum16(acc, lane);
+    if ((lane & 3) == 0) sm.part[0][16 * w + (lane >> 2)] = s;
+    __syncthreads();
     if (w == 0) {
-      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[lane] : 0.0;
+      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[0][lane] : 0.0;
       double lr[64];
 #pragma unroll
       for (int i = 0; i < 64; ++i) lr[i] = sm.Lbb[lane][i];
-      const double dl = sm.Lbb[lane][lane], rl = sm.rdiag[lane];
+      const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
 #pragma unroll
       for (int i = 0; i < 64; ++i) {
         const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
@@ -559,19 +636,50 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
   for (int64_t blk = nb - 1; blk >= 0; --blk) {
     const int64_t r0 = blk * 64;
     const int nr = n - r0 < 64 ? (int)(n - r0) : 64;
-    double s = 0.0;
-    if (r < nr)
-      for (int64_t k = r0 + 64 + p; k < n; k += 4) s += L[k * lda + r0 + r] * b[k * ldb];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    if (p == 0) sm.part[r] = s;
-    tc_wg_stage_diag(L, lda, r0, nr, sm);
+    // part_j = sum_{k >= r0 + 64} L_kj x_k for column j = r0 + lane (every
+    // block but the last, whose loop is empty, has 64 columns).  Wave w takes
+    // the 64-row chunks w, w + 4, ... below the block, 16 rows at a time,
+    // with the next 16 rows' loads in flight; rows past n read row n - 1
+    // against a zero x.
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    double va[16], vb[16], xa = 0.0, xb = 0.0;
+    auto fetch = [&](double(&v)[16], double& x, int64_t k) {
+      const int64_t kx = k + (lane & 15);
+      x = kx < n ? b[kx * ldb] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t kr = k + q < n ? k + q : n - 1;
+        const double* Lr = L + kr * lda + r0;
+        v[q] = Lr[lane];
+      }
+    };
+    auto fold = [&](const double(&v)[16], double x) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a4[q & 3] = __builtin_fma(v[q], tc_readlane(x, q), a4[q & 3]);
+    };
+    const int64_t kb = r0 + 64;
+    auto gk = [&](int64_t j) { return kb + 64 * (wu + 4 * (j >> 2)) + 16 * (j & 3); };
+    if (gk(0) < n) fetch(va, xa, gk(0));
+    load_diag(r0, nr);
+    put_diag();
+    for (int64_t j = 0; gk(j) < n; j += 2) {
+      if (gk(j + 1) < n) fetch(vb, xb, gk(j + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      fold(va, xa);
+      if (gk(j + 1) >= n) break;
+      if (gk(j + 2) < n) fetch(va, xa, gk(j + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      fold(vb, xb);
+    }
+    sm.part[w][lane] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    __syncthreads();
     if (w == 0) {
-      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[lane] : 0.0;
+      const double s = (sm.part[0][lane] + sm.part[1][lane]) + (sm.part[2][lane] + sm.part[3][lane]);
+      double v = lane < nr ? b[(r0 + lane) * ldb] - s : 0.0;
       double lc[64];
 #pragma unroll
       for (int i = 0; i < 64; ++i) lc[i] = sm.Lbb[i][lane];
-      const double dl = sm.Lbb[lane][lane], rl = sm.rdiag[lane];
+      const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
 #pragma unroll
       for (int i = 63; i >= 0; --i) {
         const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
@@ -584,11 +692,13 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
   }
 }
 
-// A pointer read from LDS is generic; casting it through the global address
-// space lets the compiler use global (not flat) instructions for it.
-template <typename T>
-__device__ __forceinline__ T* tc_global(T* p) {
-  return (T*)(__attribute__((address_space(1))) T*)p;
+__device__ __forceinline__ TcWs tc_global_ws(const TcWs& w) {
+  TcWs g = w;
+  g.hdr = tc_global(w.hdr);
+  g.offs = tc_global(w.offs);
+  g.pdone = tc_global(w.pdone);
+  g.ver = tc_global(w.ver);
+  return g;
 }
 
 // ---- one-workgroup residual r = b0 - A0 x of one matrix (A0 symmetric, its
@@ -727,9 +837,12 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // thread 0: publish the previous unit, take a ticket, wait for its inputs
     // (one thread-0 region per pass, as in the single-matrix kernel)
     if (threadIdx.x == 0) {
-      if (s_unit.kind >= 0 && s_unit.kind != TC_UNIT_SOLVE && s_run && !tc_err_set(s_mat.ws.hdr)) {
-        tc_unit_publish(s_mat.g, s_mat.ws, s_unit);
-        __hip_atomic_fetch_add(s_mat.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (s_unit.kind >= 0 && s_unit.kind != TC_UNIT_SOLVE && s_run) {
+        const TcWs pws = tc_global_ws(s_mat.ws);
+        if (!tc_err_set(pws.hdr)) {
+          tc_unit_publish(s_mat.g, pws, s_unit);
+          __hip_atomic_fetch_add(tc_global(s_mat.done), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       const int64_t t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int32_t go = 0, run = 0;
@@ -739,15 +852,17 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const TcUnit u = {e.kind, e.J, e.I, e.a, e.K, e.b};
         go = 1;
         run = 1;
+        const TcWs mws = tc_global_ws(s_mat.ws);
+        const int32_t* mdone = tc_global(s_mat.done);
         const uint64_t t0 = wall_clock64();
         for (;;) {
-          if (tc_err_set(s_mat.ws.hdr)) { run = 0; break; }
+          if (tc_err_set(mws.hdr)) { run = 0; break; }
           const bool ready = u.kind == TC_UNIT_SOLVE
-                                 ? __hip_atomic_load(s_mat.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                 ? __hip_atomic_load(mdone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
                                        s_mat.nunits
-                                 : tc_unit_ready(s_mat.g, s_mat.ws, u);
+                                 : tc_unit_ready(s_mat.g, mws, u);
           if (ready) break;
-          if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(s_mat.ws.hdr, 2, t + 1); run = 0; break; }
+          if (wall_clock64() - t0 > (uint64_t)wait_ticks) { tc_report_fail(mws.hdr, 2, t + 1); run = 0; break; }
           __builtin_amdgcn_s_sleep(1);
         }
         if (run) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1394,10 +1509,15 @@ __global__ __launch_bounds__(TC_THREADS) void tc_batch_copy(const TcBatchMat* __
   const TcBatchMat& d = mats[blockIdx.x];
   const int64_t n = d.g.n;
   if (d.A0 == nullptr || n <= 0) return;
+  double* A = tc_global(d.A);
+  const double* A0 = tc_global(d.A0);
+  double* b = tc_global(d.b);
+  const double* b0 = tc_global(d.b0);
+  const int64_t lda = d.lda, lda0 = d.lda0;
   for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
-    if (d.A != d.A0)
-      for (int64_t j = threadIdx.x; j <= i; j += TC_THREADS) d.A[i * d.lda + j] = d.A0[i * d.lda0 + j];
-    if (threadIdx.x == 0) d.b[i] = d.b0[i];
+    if (A != A0)
+      for (int64_t j = threadIdx.x; j <= i; j += TC_THREADS) A[i * lda + j] = A0[i * lda0 + j];
+    if (threadIdx.x == 0) b[i] = b0[i];
   }
 }
 

@@ -39,6 +39,7 @@
 #include <thread>
 #include <vector>
 
+#include "gptr.h"
 #include "launch.h"
 #include "serve_core.h"
 #include "tuned_tiles.h"
@@ -61,6 +62,19 @@ struct SrvDesc {
   int32_t fresh;      // FACTOR or SOLVE item: X starts from B
 };
 
+// The descriptor of a workgroup's item with its addresses in the global
+// address space (every lane reads the same descriptor).
+__device__ __forceinline__ SrvDesc srv_global(SrvDesc d) {
+  d.L = tc_global(d.L);
+  d.pts = tc_global(d.pts);
+  d.B = tc_global(d.B);
+  d.X = tc_global(d.X);
+  d.R = tc_global(d.R);
+  d.stats = tc_global(d.stats);
+  d.serr = tc_global(d.serr);
+  return d;
+}
+
 __device__ __forceinline__ double srv_k(const double* p, int64_t i, int64_t j, double inv2l2, double nugget) {
   const double d0 = p[2 * i] - p[2 * j], d1 = p[2 * i + 1] - p[2 * j + 1];
   return exp(-(d0 * d0 + d1 * d1) * inv2l2) + (i == j ? nugget : 0.0);
@@ -68,7 +82,7 @@ __device__ __forceinline__ double srv_k(const double* p, int64_t i, int64_t j, d
 
 // A_ij for j <= i of the FACTOR items; grid (row blocks of 8, items).
 __global__ __launch_bounds__(SRV_THREADS) void srv_assemble(const SrvDesc* __restrict__ items) {
-  const SrvDesc d = items[blockIdx.y];
+  const SrvDesc d = srv_global(items[blockIdx.y]);
   if (d.item != tcs::ITEM_FACTOR) return;
   const int64_t i0 = (int64_t)blockIdx.x * 8;
   for (int64_t i = i0; i < i0 + 8 && i < d.n; ++i)
@@ -78,7 +92,7 @@ __global__ __launch_bounds__(SRV_THREADS) void srv_assemble(const SrvDesc* __res
 // Before the solves: X = B for items that start a solution; zero the
 // statistics of every item.  Grid (row blocks of 256, items).
 __global__ __launch_bounds__(SRV_THREADS) void srv_prepare(const SrvDesc* __restrict__ items) {
-  const SrvDesc d = items[blockIdx.y];
+  const SrvDesc d = srv_global(items[blockIdx.y]);
   const int64_t e = (int64_t)blockIdx.x * SRV_THREADS + threadIdx.x;
   if (d.fresh && e < d.n * d.nrhs) d.X[e] = d.B[e];
   if (blockIdx.x == 0 && threadIdx.x < 3 * d.nrhs + 3) d.stats[threadIdx.x] = 0.0;  // tcs::stats_doubles
@@ -86,7 +100,7 @@ __global__ __launch_bounds__(SRV_THREADS) void srv_prepare(const SrvDesc* __rest
 
 // After a correction's solve: X += R.  Grid (row blocks of 256, items).
 __global__ __launch_bounds__(SRV_THREADS) void srv_apply(const SrvDesc* __restrict__ items) {
-  const SrvDesc d = items[blockIdx.y];
+  const SrvDesc d = srv_global(items[blockIdx.y]);
   const int64_t e = (int64_t)blockIdx.x * SRV_THREADS + threadIdx.x;
   if (d.item == tcs::ITEM_CORRECT && e < d.n * d.nrhs) d.X[e] = d.X[e] + d.R[e];
 }
@@ -100,7 +114,7 @@ __device__ __forceinline__ void srv_atomic_max(double* p, double v) {
 // 64, items).  Thread (row r, part p) sums columns j = p, p + 4, ... of row
 // i = 64 block + r; the four parts are combined in a fixed order.
 __global__ __launch_bounds__(SRV_THREADS) void srv_residual(const SrvDesc* __restrict__ items) {
-  const SrvDesc d = items[blockIdx.y];
+  const SrvDesc d = srv_global(items[blockIdx.y]);
   const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
   const bool row = i < d.n;

@@ -235,24 +235,61 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
   }
   if (!active) return;
 
-  // epilogue: C -= acc on the stored part, one 16-row group at a time (the
-  // scheduling barriers keep the compiler from hoisting all 64 loads of C
-  // ahead of the first subtraction, which would need 128 more registers)
+  // epilogue: C -= acc on the stored part, one 16-row group at a time.  A
+  // full block reads its C values unconditionally (for a diagonal block the
+  // entries above the diagonal are read and left alone), the loads of the
+  // next group issued before the current one is stored, so each wave has at
+  // most one memory round trip outstanding per group instead of one per
+  // element; the scheduling barriers keep the compiler from hoisting more
+  // loads (each group takes 32 registers).  A ragged block guards every
+  // access.
   const int orow = lane >> 4, ocol = lane & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
+  if (mr == 128 && mc == 128) {
+    double* cb = C + (int64_t)(wm * 64 + orow) * lda + wn * 64 + ocol;
+    double cv[2][16];
+    auto cload = [&](double(&v)[16], int i) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        const double* rp = cb + (int64_t)(i * 16 + 4 * q) * lda;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = rp[16 * j];
+      }
+    };
+    auto cstore = [&](const double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double* rp = cb + (int64_t)(i * 16 + 4 * q) * lda;
         const int r = wm * 64 + i * 16 + 4 * q + orow;
-        const int c = wn * 64 + j * 16 + ocol;
-        if (r < mr && c < mc && (!diag || r >= c)) {
-          double* p = C + (int64_t)r * lda + c;
-          *p = *p - acc[i][j][q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          if (!diag || r >= c) rp[16 * j] = v[4 * q + j] - acc[i][j][q];
         }
       }
-    __builtin_amdgcn_sched_barrier(0);
+    };
+    cload(cv[0], 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i + 1 < 4) cload(cv[(i + 1) & 1], i + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      cstore(cv[i & 1], i);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = wm * 64 + i * 16 + 4 * q + orow;
+          const int c = wn * 64 + j * 16 + ocol;
+          if (r < mr && c < mc && (!diag || r >= c)) {
+            double* p = C + (int64_t)r * lda + c;
+            *p = *p - acc[i][j][q];
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
