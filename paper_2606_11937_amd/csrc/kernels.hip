@@ -145,6 +145,20 @@ __device__ __forceinline__ void tc_run_panel(double* A, int64_t lda, const TcGeo
                   tc_rows(g, u.J, u.b), tc_rows(g, u.J, u.K), ri == rt, sm);
 }
 
+// UPDATE and PANEL units through one call of the block product, so that the
+// persistent kernels, which run both kinds, hold one copy of its code.
+__device__ __forceinline__ void tc_run_product(double* A, int64_t lda, const TcGeom& g, const TcUnit& u,
+                                               TcUpdSmem& sm) {
+  const bool up = u.kind == TC_UNIT_UPDATE;
+  const int64_t ri = tc_row0(g, u.I, u.a);
+  const int64_t rk = up ? tc_row0(g, u.K, u.b) : tc_row0(g, u.J, u.b);
+  const int64_t ck = up ? (int64_t)u.J * g.T : tc_row0(g, u.J, u.K);
+  const int mc = up ? tc_rows(g, u.K, u.b) : tc_rows(g, u.J, u.b);
+  const int kd = up ? (int)tc_tdim(g, u.J) : tc_rows(g, u.J, u.K);
+  tc_update_block(A + ri * lda + rk, A + ri * lda + ck, A + rk * lda + ck, lda, tc_rows(g, u.I, u.a), mc, kd,
+                  ri == rk, sm);
+}
+
 // ---------------------------------------------------------- fork-join kernels
 // The fork-join kernels declare only the shared memory their body uses (the
 // persistent kernel needs the union of all of them).
@@ -464,10 +478,8 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     const TcGeom cg = tc_ctx_geom(s_ctx.g);
     if (ws.noop) {
       // measurement mode: the schedule's own cost only
-    } else if (u.kind == TC_UNIT_UPDATE) {
-      tc_run_update(A, lda, cg, u, sm.upd);
-    } else if (u.kind == TC_UNIT_PANEL) {
-      tc_run_panel(A, lda, cg, u, sm.upd);
+    } else if (u.kind == TC_UNIT_UPDATE || u.kind == TC_UNIT_PANEL) {
+      tc_run_product(A, lda, cg, u, sm.upd);
     } else if (u.kind == TC_UNIT_TRSM) {
       tc_run_trsm(A, lda, cg, u.J, u.K, u.I, u.a, sm.trsm);
     } else {
@@ -619,15 +631,20 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     __syncthreads();
     if (w == 0) {
       double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[0][lane] : 0.0;
-      double lr[64];
-#pragma unroll
-      for (int i = 0; i < 64; ++i) lr[i] = sm.Lbb[lane][i];
       const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
+      // eight pivots per pass (a rolled loop keeps the kernel's code small)
+#pragma unroll 1
+      for (int i0 = 0; i0 < nr; i0 += 8) {
+        double l8[8];
 #pragma unroll
-      for (int i = 0; i < 64; ++i) {
-        const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
-        if (lane == i) v = xi;
-        else if (lane > i) v = v - lr[i] * xi;
+        for (int k = 0; k < 8; ++k) l8[k] = sm.Lbb[lane][i0 + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k;
+          const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
+          if (lane == i) v = xi;
+          else if (lane > i) v = v - l8[k] * xi;
+        }
       }
       if (lane < nr) b[(r0 + lane) * ldb] = v;
     }
@@ -676,15 +693,20 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     if (w == 0) {
       const double s = (sm.part[0][lane] + sm.part[1][lane]) + (sm.part[2][lane] + sm.part[3][lane]);
       double v = lane < nr ? b[(r0 + lane) * ldb] - s : 0.0;
-      double lc[64];
-#pragma unroll
-      for (int i = 0; i < 64; ++i) lc[i] = sm.Lbb[i][lane];
       const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
+      // pivots from the last one down, eight per pass (padding rows give 0)
+#pragma unroll 1
+      for (int i0 = ((nr - 1) >> 3) << 3; i0 >= 0; i0 -= 8) {
+        double l8[8];
 #pragma unroll
-      for (int i = 63; i >= 0; --i) {
-        const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
-        if (lane == i) v = xi;
-        else if (lane < i) v = v - lc[i] * xi;
+        for (int k = 0; k < 8; ++k) l8[k] = sm.Lbb[i0 + k][lane];
+#pragma unroll
+        for (int k = 7; k >= 0; --k) {
+          const int i = i0 + k;
+          const double xi = tc_div_rcp(tc_readlane(v, i), tc_readlane(dl, i), tc_readlane(rl, i));
+          if (lane == i) v = xi;
+          else if (lane < i) v = v - l8[k] * xi;
+        }
       }
       if (lane < nr) b[(r0 + lane) * ldb] = v;
     }
@@ -778,31 +800,40 @@ union alignas(512) TcBatchSmem {
   TcResSmem r;
 };
 
-// Solve with refinement of one matrix (one right-hand side, in place in x,
-// which holds b0 on entry): x = (L L^T)^-1 b0, then while the backward error
-// ||b0 - A0 x||_inf / (||A0||_inf ||x||_inf + ||b0||_inf) exceeds tol and
-// fewer than max_iter corrections were applied, x += (L L^T)^-1 (b0 - A0 x).
-// Writes {eta, corrections} to stat.
-__device__ __forceinline__ void tc_wg_solve_refine(const double* __restrict__ L, int64_t lda, int64_t n, double* x,
-                                                   const double* A0, int64_t lda0, const double* b0, double* R,
-                                                   double tol, int64_t max_iter, double* stat, TcBatchSmem& sm) {
-  tc_wg_solve(L, lda, n, x, 1, sm.s);
-  int64_t it = 0;
+// The solve unit of one matrix.  Plain: each of the nrhs columns of B
+// (leading dimension ldb) in turn, in place.  With refinement (one
+// right-hand side, in place in x = B, which holds b0 on entry): x = (L L^T)^-1
+// b0, then while the backward error ||b0 - A0 x||_inf / (||A0||_inf ||x||_inf
+// + ||b0||_inf) exceeds tol and fewer than max_iter corrections were applied,
+// x += (L L^T)^-1 (b0 - A0 x); {eta, corrections} go to stat.  Every pass
+// goes through one call of the solve, which keeps the kernel's code small.
+__device__ __forceinline__ void tc_wg_solve_unit(const double* __restrict__ L, int64_t lda, int64_t n, double* B,
+                                                 int64_t nrhs, int64_t ldb, bool refine, const double* A0,
+                                                 int64_t lda0, const double* b0, double* R, double tol,
+                                                 int64_t max_iter, double* stat, TcBatchSmem& sm) {
+  if (!refine && nrhs <= 0) return;
   double eta = 0.0;
-  for (;;) {
-    tc_wg_residual(A0, lda0, n, x, b0, R, sm.r);
+  int64_t p = 0;
+  for (;; ++p) {
+    // refinement: the first pass solves in x, the later ones for the correction in R
+    tc_wg_solve(L, lda, n, refine ? (p == 0 ? B : R) : B + p, refine ? 1 : ldb, sm.s);
+    if (!refine) {
+      if (p + 1 >= nrhs) break;
+      continue;
+    }
+    if (p > 0) {
+      for (int64_t i = tc_tid(); i < n; i += TC_THREADS) B[i] = B[i] + R[i];
+      __syncthreads();
+    }
+    tc_wg_residual(A0, lda0, n, B, b0, R, sm.r);
     const double den = sm.r.red[3][0] * sm.r.red[1][0] + sm.r.red[2][0];
     eta = tc_uniform(den > 0.0 ? sm.r.red[0][0] / den : 0.0);
     __syncthreads();
-    if (!(eta > tol) || it >= max_iter) break;
-    tc_wg_solve(L, lda, n, R, 1, sm.s);
-    for (int64_t i = tc_tid(); i < n; i += TC_THREADS) x[i] = x[i] + R[i];
-    __syncthreads();
-    ++it;
+    if (!(eta > tol) || p >= max_iter) break;
   }
-  if (tc_tid() == 0) {
+  if (refine && tc_tid() == 0) {
     stat[0] = eta;
-    stat[1] = (double)it;
+    stat[1] = (double)p;
   }
 }
 
@@ -880,19 +911,15 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
       double* A = tc_global(s_mat.A);
       const int64_t lda = tc_ctx64(s_mat.lda);
       const int32_t prec = tc_ctx32(s_mat.prec);
-      if (u.kind == TC_UNIT_UPDATE) {
-        if (prec == TC_PREC_FP32) {
-          const float* P = tc_global(s_mat.P);
-          const int64_t ldp = tc_ctx64(s_mat.ldp);
-          const int64_t ri = tc_row0(cg, u.I, u.a), rk = tc_row0(cg, u.K, u.b), cj = (int64_t)u.J * cg.T;
-          tc_update_block_lp<TC_PREC_FP32>(A + ri * lda + rk, P + ri * ldp + cj, P + rk * ldp + cj, lda, ldp,
-                                           tc_rows(cg, u.I, u.a), tc_rows(cg, u.K, u.b), (int)tc_tdim(cg, u.J),
-                                           ri == rk, sm.f.upd);
-        } else {
-          tc_run_update(A, lda, cg, u, sm.f.upd);
-        }
-      } else if (u.kind == TC_UNIT_PANEL) {
-        tc_run_panel(A, lda, cg, u, sm.f.upd);
+      if (u.kind == TC_UNIT_UPDATE && prec == TC_PREC_FP32) {
+        const float* P = tc_global(s_mat.P);
+        const int64_t ldp = tc_ctx64(s_mat.ldp);
+        const int64_t ri = tc_row0(cg, u.I, u.a), rk = tc_row0(cg, u.K, u.b), cj = (int64_t)u.J * cg.T;
+        tc_update_block_lp<TC_PREC_FP32>(A + ri * lda + rk, P + ri * ldp + cj, P + rk * ldp + cj, lda, ldp,
+                                         tc_rows(cg, u.I, u.a), tc_rows(cg, u.K, u.b), (int)tc_tdim(cg, u.J),
+                                         ri == rk, sm.f.upd);
+      } else if (u.kind == TC_UNIT_UPDATE || u.kind == TC_UNIT_PANEL) {
+        tc_run_product(A, lda, cg, u, sm.f.upd);
       } else if (u.kind == TC_UNIT_TRSM) {
         tc_run_trsm(A, lda, cg, u.J, u.K, u.I, u.a, sm.f.trsm);
         if (prec == TC_PREC_FP32 && u.K == tc_sb(cg, u.J) - 1 && u.I > u.J) {
@@ -901,14 +928,11 @@ __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         }
       } else if (u.kind == TC_UNIT_POTRF) {
         tc_run_potrf(A, lda, cg, u.J, u.a, tc_global(s_mat.ws.hdr), sm.f.potrf);
-      } else if (tc_ctx32(s_mat.refine)) {
-        tc_wg_solve_refine(A, lda, cg.n, tc_global(s_mat.b), tc_global(s_mat.A0), tc_ctx64(s_mat.lda0),
-                           tc_global(s_mat.b0), tc_global(s_mat.R), tc_uniform(s_mat.tol), tc_ctx64(s_mat.max_iter),
-                           tc_global(s_mat.stat), sm);
       } else {
-        const int64_t nrhs = tc_ctx64(s_mat.nrhs), ldb = tc_ctx64(s_mat.ldb);
-        double* B = tc_global(s_mat.b);
-        for (int64_t c = 0; c < nrhs; ++c) tc_wg_solve(A, lda, cg.n, B + c, ldb, sm.s);
+        tc_wg_solve_unit(A, lda, cg.n, tc_global(s_mat.b), tc_ctx64(s_mat.nrhs), tc_ctx64(s_mat.ldb),
+                         tc_ctx32(s_mat.refine) != 0, tc_global(s_mat.A0), tc_ctx64(s_mat.lda0), tc_global(s_mat.b0),
+                         tc_global(s_mat.R), tc_uniform(s_mat.tol), tc_ctx64(s_mat.max_iter), tc_global(s_mat.stat),
+                         sm);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

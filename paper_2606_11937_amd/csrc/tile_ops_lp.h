@@ -218,20 +218,54 @@ __device__ __forceinline__ void tc_update_block_lp(double* __restrict__ C, const
   }
   if (!active) return;
 
+  // epilogue as in tc_update_block: a full block loads each 16-row group of
+  // C ahead of the previous group's stores; a ragged block guards every access
   const int orow = (lane >> 4) * 4, ocol = lane & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
+  if (mr == 128 && mc == 128) {
+    double* cb = C + (int64_t)(wm * 64 + orow) * lda + wn * 64 + ocol;
+    double cv[2][16];
+    auto cload = [&](double(&v)[16], int i) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        const double* rp = cb + (int64_t)(i * 16 + q) * lda;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = rp[16 * j];
+      }
+    };
+    auto cstore = [&](const double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double* rp = cb + (int64_t)(i * 16 + q) * lda;
         const int r = wm * 64 + i * 16 + orow + q;
-        const int c = wn * 64 + j * 16 + ocol;
-        if (r < mr && c < mc && (!diag || r >= c)) {
-          double* p = C + (int64_t)r * lda + c;
-          *p = *p - (double)acc[i][j][q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          if (!diag || r >= c) rp[16 * j] = v[4 * q + j] - (double)acc[i][j][q];
         }
       }
-    __builtin_amdgcn_sched_barrier(0);
+    };
+    cload(cv[0], 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i + 1 < 4) cload(cv[(i + 1) & 1], i + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      cstore(cv[i & 1], i);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = wm * 64 + i * 16 + orow + q;
+          const int c = wn * 64 + j * 16 + ocol;
+          if (r < mr && c < mc && (!diag || r >= c)) {
+            double* p = C + (int64_t)r * lda + c;
+            *p = *p - (double)acc[i][j][q];
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
