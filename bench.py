@@ -73,11 +73,11 @@ TRAFFIC = {
     # (schedule, n, T): (bytes per launch of the roofline kernel, sha256 of the
     # kernel sources); the profiles under profiles/ hold the counter readings
     # (forkjoin_n32768_T1024_kernels.md, lookahead_n32768_T1024_kernels.md)
-    ("fork_join", 32768, 1024): (14691996517,
-                                 "b89844aceb633ab25881631fa45e6e0f1be7a2955833019ba6c59130b99f4bbc"),
+    ("fork_join", 32768, 1024): (14691539678,
+                                 "d285ac6b36ad61e52db4c46962ddea1ee97ebb3f000c665c0fc2dbd841f6e989"),
     # lookahead: the bulk of one step (its pool launch and tail summed)
-    ("fork_join_lookahead", 32768, 1024): (13005281124,
-                                           "954f36aa5629c4176c2b9480a78785473d10a97d363f5689f720b6ac0b1fdd28"),
+    ("fork_join_lookahead", 32768, 1024): (12910698553,
+                                           "fced0e1f0915ab1cf65b20f775ecc1d5b85f7826684ae574dff6cbfa456fb38d"),
 }
 # the device code the counters describe: the tile bodies, the DAG decode, the
 # fork-join kernels (unit runners up to the naive variant) of kernels.hip,

@@ -241,8 +241,8 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
   // next group issued before the current one is stored, so each wave has at
   // most one memory round trip outstanding per group instead of one per
   // element; the scheduling barriers keep the compiler from hoisting more
-  // loads (each group takes 32 registers).  A ragged block guards every
-  // access.
+  // loads (each group takes 32 registers).  A ragged block reads from
+  // clamped positions and guards its stores.
   const int orow = lane >> 4, ocol = lane & 15;
   if (mr == 128 && mc == 128) {
     double* cb = C + (int64_t)(wm * 64 + orow) * lda + wn * 64 + ocol;
@@ -275,20 +275,38 @@ __device__ __forceinline__ void tc_update_block(double* __restrict__ C, const do
       cstore(cv[i & 1], i);
     }
   } else {
+    // ragged: the same pipeline, loads from clamped (in-block) positions,
+    // stores guarded
+    double cv[2][16];
+    auto cload = [&](double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 16 + 4 * q + orow;
+        const double* rp = C + (int64_t)(r < mr ? r : mr - 1) * lda;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          v[4 * q + j] = rp[c < mc ? c : mc - 1];
+        }
+      }
+    };
+    auto cstore = [&](const double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 16 + 4 * q + orow;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          if (r < mr && c < mc && (!diag || r >= c)) C[(int64_t)r * lda + c] = v[4 * q + j] - acc[i][j][q];
+        }
+      }
+    };
+    cload(cv[0], 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = wm * 64 + i * 16 + 4 * q + orow;
-          const int c = wn * 64 + j * 16 + ocol;
-          if (r < mr && c < mc && (!diag || r >= c)) {
-            double* p = C + (int64_t)r * lda + c;
-            *p = *p - acc[i][j][q];
-          }
-        }
+      if (i + 1 < 4) cload(cv[(i + 1) & 1], i + 1);
       __builtin_amdgcn_sched_barrier(0);
+      cstore(cv[i & 1], i);
     }
   }
 }

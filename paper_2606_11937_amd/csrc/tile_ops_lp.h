@@ -218,8 +218,9 @@ __device__ __forceinline__ void tc_update_block_lp(double* __restrict__ C, const
   }
   if (!active) return;
 
-  // epilogue as in tc_update_block: a full block loads each 16-row group of
-  // C ahead of the previous group's stores; a ragged block guards every access
+  // epilogue as in tc_update_block: each 16-row group of C is loaded ahead of
+  // the previous group's stores (a ragged block from clamped positions, with
+  // its stores guarded)
   const int orow = (lane >> 4) * 4, ocol = lane & 15;
   if (mr == 128 && mc == 128) {
     double* cb = C + (int64_t)(wm * 64 + orow) * lda + wn * 64 + ocol;
@@ -252,20 +253,38 @@ __device__ __forceinline__ void tc_update_block_lp(double* __restrict__ C, const
       cstore(cv[i & 1], i);
     }
   } else {
+    // ragged: loads from clamped (in-block) positions, stores guarded
+    double cv[2][16];
+    auto cload = [&](double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 16 + orow + q;
+        const double* rp = C + (int64_t)(r < mr ? r : mr - 1) * lda;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          v[4 * q + j] = rp[c < mc ? c : mc - 1];
+        }
+      }
+    };
+    auto cstore = [&](const double(&v)[16], int i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 16 + orow + q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = wn * 64 + j * 16 + ocol;
+          if (r < mr && c < mc && (!diag || r >= c))
+            C[(int64_t)r * lda + c] = v[4 * q + j] - (double)acc[i][j][q];
+        }
+      }
+    };
+    cload(cv[0], 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = wm * 64 + i * 16 + orow + q;
-          const int c = wn * 64 + j * 16 + ocol;
-          if (r < mr && c < mc && (!diag || r >= c)) {
-            double* p = C + (int64_t)r * lda + c;
-            *p = *p - (double)acc[i][j][q];
-          }
-        }
+      if (i + 1 < 4) cload(cv[(i + 1) & 1], i + 1);
       __builtin_amdgcn_sched_barrier(0);
+      cstore(cv[i & 1], i);
     }
   }
 }
