@@ -85,14 +85,20 @@ def main():
         del As, Bs, Ls, Xs
         torch.cuda.empty_cache()
     rows.append({"n_max": 1048576, "T": 1024})
-    out = {
+    # the other tables of the file (the FP32 tile table, the serving plan)
+    # are kept as they are
+    out = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            out = json.load(f)
+    out.update({
         "about": ("Tile side T of each matrix of a batched factorization, chosen from (n, precision) only. Rows "
                   "are n-buckets: a matrix of order n takes the first row with n <= n_max; T = 0 means one tile "
                   "(T = n). Written by paper_2606_11937_amd/tune_batched.py from a sweep on MI355X."),
         "source": "measured: median of 3 batched factor+solve runs per (bucket, T) on one MI355X",
         "fp64": rows,
         "sweep": log,
-    }
+    })
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({"table": rows}), flush=True)
