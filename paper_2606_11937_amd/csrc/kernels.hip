@@ -748,13 +748,22 @@ __device__ __forceinline__ void tc_wg_residual(const double* __restrict__ A0, in
     double acc = 0.0, asum = 0.0;
     for (int64_t C0 = 0; C0 < n; C0 += 64) {
       if (tid < 64) sm.xs[tid] = C0 + tid < n ? x[C0 + tid] : 0.0;
-      for (int e = tid; e < 64 * 64; e += TC_THREADS) {
-        // coalesced: along the stored row of the lower triangle
+      // coalesced: along the stored row of the lower triangle.  All 16 loads
+      // of a thread are issued before the first is stored (from clamped,
+      // in-range positions; entries past n are then replaced by zero).
+      double tv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * TC_THREADS;
         const int i = C0 > R0 ? (e & 63) : (e >> 6), k = C0 > R0 ? (e >> 6) : (e & 63);
-        const int64_t gi = R0 + i, gj = C0 + k;
-        double v = 0.0;
-        if (gi < n && gj < n) v = gj <= gi ? A0[gi * lda0 + gj] : A0[gj * lda0 + gi];
-        sm.t[i][k] = v;
+        const int64_t gi = R0 + i < n ? R0 + i : n - 1, gj = C0 + k < n ? C0 + k : n - 1;
+        tv[q] = gj <= gi ? A0[gi * lda0 + gj] : A0[gj * lda0 + gi];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * TC_THREADS;
+        const int i = C0 > R0 ? (e & 63) : (e >> 6), k = C0 > R0 ? (e >> 6) : (e & 63);
+        sm.t[i][k] = (R0 + i < n && C0 + k < n) ? tv[q] : 0.0;
       }
       __syncthreads();
 #pragma unroll
@@ -845,10 +854,20 @@ __device__ __forceinline__ void tc_round_strip(const double* __restrict__ A, int
   const int64_t r0 = tc_row0(g, I, a), c0 = (int64_t)J * g.T;
   const int mr = tc_rows(g, I, a);
   const int64_t kd = tc_tdim(g, J);
-  for (int64_t e = tc_tid(); e < (int64_t)mr * kd; e += TC_THREADS) {
-    const int64_t rr = e / kd, k = e - rr * kd;
-    P[(r0 + rr) * ldp + c0 + k] = tc_round_lp<TC_PREC_FP32>(A[(r0 + rr) * lda + c0 + k]);
-  }
+  // eight rows at a time, their loads issued before the first store (rows
+  // past the block's end re-read its last row and are not stored)
+  for (int rb = 0; rb < mr; rb += 8)
+    for (int64_t k = tc_tid(); k < kd; k += TC_THREADS) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rr = rb + q < mr ? rb + q : mr - 1;
+        v[q] = A[(r0 + rr) * lda + c0 + k];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (rb + q < mr) P[(r0 + rb + q) * ldp + c0 + k] = tc_round_lp<TC_PREC_FP32>(v[q]);
+    }
 }
 
 __global__ __launch_bounds__(TC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void tc_batched(
