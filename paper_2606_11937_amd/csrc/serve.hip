@@ -46,7 +46,6 @@
 
 #define SRV_THREADS 256
 #define SRV_MAX_RHS 8
-#define SRV_SIDE 4  // side streams per tick stream for the items' solves
 
 // One work item of a tick (see serve_core.h).
 struct SrvDesc {
@@ -188,11 +187,6 @@ struct TcServer {
   int64_t wait_ticks = 0;
   std::unique_ptr<tcs::Core> core;
   hipStream_t st[2] = {nullptr, nullptr};
-  // the items' solves of a tick on stream k are spread over side[k] (forked
-  // after the tick's factorization, joined before its corrections)
-  hipStream_t side[2][SRV_SIDE] = {};
-  hipEvent_t fork[2] = {nullptr, nullptr};
-  hipEvent_t join[2][SRV_SIDE] = {};
   std::mutex mu;
   std::condition_variable cv;
   std::vector<Flight> inflight;
@@ -280,27 +274,13 @@ bool launch_tick(TcServer& S, Flight& f) {
   hipLaunchKernelGGL(srv_prepare, dim3((unsigned)((emax + SRV_THREADS - 1) / SRV_THREADS), (unsigned)m),
                      dim3(SRV_THREADS), 0, st, meta_d);
   // each item's solve, with a solve workspace (and status word) of its own:
-  // of B (in X) for a new solution, of the residual R for a correction.  The
-  // solves are independent and each fills only part of the chip, so with
-  // several items they run side by side on the tick stream's side streams
-  // (every wait below is enqueued after the record it waits for)
-  const int nside = m > 1 ? (int)std::min<int64_t>(m, SRV_SIDE) : 0;
-  if (nside > 0) {
-    if (hipEventRecord(S.fork[t.stream], st) != hipSuccess) return false;
-    for (int j = 0; j < nside; ++j)
-      if (hipStreamWaitEvent(S.side[t.stream][j], S.fork[t.stream], 0) != hipSuccess) return false;
-  }
+  // of B (in X) for a new solution, of the residual R for a correction
   for (int64_t q = 0; q < m; ++q) {
     const tcs::Request& R = *f.rq[q];
     double* rhs = desc[q].fresh ? desc[q].X : desc[q].R;
     char* sws = ws + t.solve_off[q];
-    hipStream_t ss = nside > 0 ? S.side[t.stream][q % nside] : st;
-    if (tc_solve_status_reset(sws, ss) != 0) return false;
-    if (tc_launch_solve(desc[q].L, R.n, R.n, 128, rhs, R.nrhs, R.nrhs, sws, ss, S.wait_ticks) != 0) return false;
-  }
-  for (int j = 0; j < nside; ++j) {
-    if (hipEventRecord(S.join[t.stream][j], S.side[t.stream][j]) != hipSuccess) return false;
-    if (hipStreamWaitEvent(st, S.join[t.stream][j], 0) != hipSuccess) return false;
+    if (tc_solve_status_reset(sws, st) != 0) return false;
+    if (tc_launch_solve(desc[q].L, R.n, R.n, 128, rhs, R.nrhs, R.nrhs, sws, st, S.wait_ticks) != 0) return false;
   }
   hipLaunchKernelGGL(srv_apply, dim3((unsigned)((emax + SRV_THREADS - 1) / SRV_THREADS), (unsigned)m),
                      dim3(SRV_THREADS), 0, st, (const SrvDesc*)meta_d);
@@ -442,14 +422,8 @@ int tc_server_create(void* arena, int64_t arena_bytes, int64_t pinned_bytes, int
   S->wait_ticks = wait_ticks;
   S->core = std::make_unique<tcs::Core>(arena_bytes, r256(pinned_bytes), mode, max_per_tick, make_sizer(),
                                         tc_serve_plan_table());
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 2; ++k)
     if (hipStreamCreateWithFlags(&S->st[k], hipStreamNonBlocking) != hipSuccess) return TC_LAUNCH_EDEVICE;
-    if (hipEventCreateWithFlags(&S->fork[k], hipEventDisableTiming) != hipSuccess) return TC_LAUNCH_EDEVICE;
-    for (int j = 0; j < SRV_SIDE; ++j) {
-      if (hipStreamCreateWithFlags(&S->side[k][j], hipStreamNonBlocking) != hipSuccess) return TC_LAUNCH_EDEVICE;
-      if (hipEventCreateWithFlags(&S->join[k][j], hipEventDisableTiming) != hipSuccess) return TC_LAUNCH_EDEVICE;
-    }
-  }
   S->worker = std::thread(worker_main, S.get());
   *out = S.release();
   return 0;
@@ -545,21 +519,12 @@ int tc_server_destroy(TcServer* S) {
   int rc = S->error ? TC_LAUNCH_EDEVICE : 0;
   // after an error ticks may still be on the device: let them finish before
   // the pinned staging they copy into is freed
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 2; ++k)
     if (S->st[k] && hipStreamSynchronize(S->st[k]) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
-    for (int j = 0; j < SRV_SIDE; ++j)
-      if (S->side[k][j] && hipStreamSynchronize(S->side[k][j]) != hipSuccess) rc = TC_LAUNCH_EDEVICE;
-  }
   for (Flight& f : S->inflight)
     if (f.done) (void)hipEventDestroy(f.done);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 2; ++k)
     if (S->st[k]) (void)hipStreamDestroy(S->st[k]);
-    if (S->fork[k]) (void)hipEventDestroy(S->fork[k]);
-    for (int j = 0; j < SRV_SIDE; ++j) {
-      if (S->side[k][j]) (void)hipStreamDestroy(S->side[k][j]);
-      if (S->join[k][j]) (void)hipEventDestroy(S->join[k][j]);
-    }
-  }
   if (S->pinned) (void)hipHostFree(S->pinned);
   delete S;
   return rc;
