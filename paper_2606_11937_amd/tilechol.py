@@ -329,12 +329,29 @@ def chol_batched_tile(n: int, prec="fp64") -> int:
 
 
 def _batch_args(As):
+    """Checks every matrix as _check_matrix does and returns the batch's
+    count, orders, device pointers, orders and leading dimensions; one pass,
+    with as few tensor attribute reads per matrix as the checks allow (a
+    batch has thousands of them)."""
+    import torch
+    f64, Tensor = torch.float64, torch.Tensor
+    ns, ldas, ps = [], [], []
     for A in As:
-        _check_matrix(A)
+        if not isinstance(A, Tensor):
+            raise TypeError("A must be a 2-D float64 torch tensor")
+        sh, st = A.shape, A.stride()
+        if A.dtype is not f64 or len(sh) != 2:
+            raise TypeError("A must be a 2-D float64 torch tensor")
+        if not A.is_cuda:
+            raise TypeError("A must live on the GPU")
+        if sh[1] > 0 and st[1] != 1:
+            raise TypeError("A must be row-major (stride(1) == 1)")
+        n = sh[0]
+        ns.append(n)
+        ldas.append(st[0] if n > 1 else max(1, sh[1]))
+        ps.append(A.data_ptr())
     b = len(As)
-    ns = [A.shape[0] for A in As]
-    ldas = [A.stride(0) if A.shape[0] > 1 else max(1, A.shape[1]) for A in As]
-    ptrs = (ctypes.c_void_p * max(b, 1))(*[A.data_ptr() for A in As])
+    ptrs = (ctypes.c_void_p * max(b, 1))(*ps)
     return b, ns, ptrs, (ctypes.c_int64 * max(b, 1))(*ns), (ctypes.c_int64 * max(b, 1))(*ldas)
 
 
@@ -365,8 +382,9 @@ def chol_factor_solve_batched(As, Bs, Ts=None, work=None, stream=None, sync: boo
     b, ns, ptrs, n_arr, l_arr = _batch_args(As)
     if len(Bs) != b:
         raise ValueError("one right-hand side per matrix")
-    for A, B in zip(As, Bs):
-        if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous() and B.numel() == A.shape[0]):
+    f64 = torch.float64
+    for B, n in zip(Bs, ns):
+        if B.dtype is not f64 or not B.is_cuda or B.numel() != n or not B.is_contiguous():
             raise TypeError("each right-hand side must be a contiguous float64 GPU vector of n entries")
     if work is None:
         nb = chol_factor_solve_batched_workspace_size(ns, Ts)
