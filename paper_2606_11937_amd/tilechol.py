@@ -416,16 +416,16 @@ def chol_factor_solve_batched_mixed(As, Ls, Bs, Xs, Ts=None, precs=None, tol: fl
     A_i x_i = b_i into X_i with FP64 refinement to tol, all in one persistent
     launch.  Returns (infos, corrections, etas) when sync."""
     import torch
-    b = len(As)
-    for A in As:
-        _check_matrix(A)
-    for L in Ls:
-        _check_matrix(L, "L")
-    ns = [A.shape[0] for A in As]
-    ld = lambda t: t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
+    b, ns, a_ptrs, n_arr, la_arr = _batch_args(As)
+    bl, nls, l_ptrs, _, ll_arr = _batch_args(Ls)
+    if bl != b or len(Bs) != b or len(Xs) != b:
+        raise ValueError("As, Ls, Bs and Xs must have one entry per matrix")
+    if nls != ns:
+        raise ValueError("each L must have the order of its A")
+    f64 = torch.float64
     for n, B, X in zip(ns, Bs, Xs):
         for v in (B, X):
-            if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous() and v.numel() == n):
+            if v.dtype is not f64 or not v.is_cuda or v.numel() != n or not v.is_contiguous():
                 raise TypeError("right-hand sides and solutions must be contiguous float64 GPU vectors of n entries")
     if work is None:
         nb = chol_factor_solve_batched_mixed_workspace_size(ns, Ts, precs)
@@ -433,13 +433,12 @@ def chol_factor_solve_batched_mixed(As, Ls, Bs, Xs, Ts=None, precs=None, tol: fl
             raise TileCholError(nb, "chol_factor_solve_batched_mixed_workspace_size", last_bad_arg())
         work = torch.empty(max(nb, 8), dtype=torch.uint8, device=As[0].device if b else "cuda")
     vp = lambda ts: (ctypes.c_void_p * max(b, 1))(*[t.data_ptr() for t in ts])
-    i64 = lambda v: (ctypes.c_int64 * max(b, 1))(*v)
     t_arr = (ctypes.c_int64 * b)(*Ts) if Ts is not None else None
     p_arr = (ctypes.c_int32 * b)(*[_prec(p) for p in precs]) if precs is not None else None
     infos, its = (ctypes.c_int64 * max(b, 1))(), (ctypes.c_int64 * max(b, 1))()
     etas = (ctypes.c_double * max(b, 1))()
-    st = lib.chol_factor_solve_batched_mixed(vp(As), vp(Ls), vp(Bs), vp(Xs), i64(ns), i64([ld(A) for A in As]),
-                                             i64([ld(L) for L in Ls]), b, t_arr, p_arr, float(tol), int(max_iter),
+    st = lib.chol_factor_solve_batched_mixed(a_ptrs, l_ptrs, vp(Bs), vp(Xs), n_arr, la_arr, ll_arr, b, t_arr, p_arr,
+                                             float(tol), int(max_iter),
                                              ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream),
                                              infos if sync else None, its if sync else None,
                                              etas if sync else None)
