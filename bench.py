@@ -487,7 +487,7 @@ def batched_compare(tc, count: int = 4096, seed: int = 3, reps: int = 3):
 
 
 def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: float = 96.0,
-                  resident: float = 0.0, plan=None):
+                  resident: float = 0.0, plan=None, wait_limit_s: float = 2.0):
     """Submit `count` requests with exponential inter-arrival times (rate per
     second) to a fresh server, from this thread at their scheduled times,
     then collect every result.  Latency is the server's own: submission to
@@ -499,6 +499,8 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
     with probability `resident`, a solve (new right-hand sides, same
     tolerance class) against the factor of a random earlier request whose
     result is already in (factors the server evicted are refused and counted).
+    The server runs with a dependency-wait limit of wait_limit_s: a wait that
+    runs out restarts its request once (see chol_server_wait).
     """
     import numpy as np
     import torch
@@ -513,7 +515,11 @@ def serve_compare(tc, rate: float, count: int, seed: int, mode: str, arena_gb: f
                      1e-6 if rng.random() < 0.5 else 1e-12))
     solve_draw = rng.random(count)
     arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
-    srv = tc.Server(arena, 8 << 30, mode)
+    prev = tc.chol_set_wait_limit(wait_limit_s)  # the server keeps the limit it was created with
+    try:
+        srv = tc.Server(arena, 8 << 30, mode)
+    finally:
+        tc.chol_set_wait_limit(prev)
     if plan is not None:
         srv.set_plan(*plan)
     ids, lag, kinds = [], 0.0, []

@@ -421,7 +421,8 @@ int chol_server_submit_solve(chol_server* server, int64_t factor, const double* 
  * error, *latency_s the time from submission to the result being in host
  * memory.  Returns CHOL_OK (eta <= tol), CHOL_NOT_CONVERGED (done, eta >
  * tol), CHOL_NOT_SPD (*info as for chol_factor), CHOL_ESTALLED (a dependency
- * wait exceeded chol_set_wait_limit and X is unspecified: *info = 1 + the
+ * wait exceeded chol_set_wait_limit, in the request's first run and again
+ * in the one restart it is given, and X is unspecified: *info = 1 + the
  * ticket, within its tick's launch, of the factorization unit that waited,
  * or -1 when a solve sweep's wait ran out), CHOL_EWORKSPACE (the request can
  * never fit in the arena), CHOL_ETIMEOUT (not done yet), or a negative error

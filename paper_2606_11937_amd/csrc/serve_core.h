@@ -137,6 +137,7 @@ struct Request {
   Plan plan;
   int prec = PREC_FP64;     // precision of the factor in use
   int corrections = 0, refactors = 0, items = 0;
+  int stall_retries = 0;  // runs restarted after a dependency wait ran out
   int next_item = ITEM_FACTOR;
   // regions: the factor (L + points; for SOLVE requests the resident
   // factor's) and the request's own work region; pinned staging
@@ -335,10 +336,20 @@ class Core {
       R.eta = r.eta;
       if (t.items[q].item == ITEM_FACTOR && r.factor_err == 1) {
         complete(R, id, ST_NOT_SPD, r.factor_info, now);
-      } else if (t.items[q].item == ITEM_FACTOR && r.factor_err) {
-        complete(R, id, ST_STALLED, r.factor_info > 0 ? r.factor_info : 1, now);
-      } else if (r.solve_err) {
-        complete(R, id, ST_STALLED, -1, now);
+      } else if ((t.items[q].item == ITEM_FACTOR && r.factor_err) || r.solve_err) {
+        // a dependency wait ran out (the result is unspecified): the request
+        // starts over once (a fresh solve, after a new factorization unless it
+        // solves with a resident factor), then is reported as stalled
+        if (R.stall_retries == 0) {
+          R.stall_retries = 1;
+          R.corrections = 0;
+          R.next_item = R.kind == REQ_SOLVE ? ITEM_SOLVE : ITEM_FACTOR;
+          ready_.push_back(id);
+        } else if (t.items[q].item == ITEM_FACTOR && r.factor_err) {
+          complete(R, id, ST_STALLED, r.factor_info > 0 ? r.factor_info : 1, now);
+        } else {
+          complete(R, id, ST_STALLED, -1, now);
+        }
       } else if (!(r.eta > R.tol)) {
         complete(R, id, ST_DONE, 0, now);
       } else if (R.corrections < R.plan.max_corr) {

@@ -250,3 +250,31 @@ def test_server_evicts_least_recently_used_factors(tc):
             _check_against_oracle(*r[:4], X, 1e-12)
         say(f"evicted {srv.evictions()} factors: {gone} of {[f for f, _ in fs]}")
         assert gone and gone == sorted(gone) and gone[0] == fs[0][0]  # oldest first
+
+
+def test_server_stalled_request_restarts_once(tc):
+    """A dependency wait that runs out restarts its request once; when the
+    restart runs out too, the request is reported as stalled (X unspecified).
+    The condition is forced from the host: the server is created with a
+    wait limit of one microsecond, so every wait that is not satisfied at
+    once ends (no kernel can hang).  A server with the normal limit then
+    serves the same request to its tolerance."""
+    rng = np.random.default_rng(81)
+    n = 3000
+    p, B, ell, nug = rng.random((n, 2)), rng.standard_normal((n, 2)), 0.2, 1e-2
+    prev = tc.chol_set_wait_limit(1e-6)
+    try:
+        srv = tc.Server(arena(4 << 30), 256 << 20, "continuous")
+    finally:
+        tc.chol_set_wait_limit(prev)
+    with srv:
+        rid = srv.submit(p, B, ell, nug, 1e-12)
+        st, X, eta, lat, info = srv.wait(rid, timeout=120)
+        say(f"server with a 1 us wait limit: status {st} info {info} ticks {srv.ticks()}")
+        assert st == tc.CHOL_ESTALLED
+        assert srv.ticks() >= 2  # the first run and its restart
+    with tc.Server(arena(4 << 30), 256 << 20, "continuous") as srv:
+        rid = srv.submit(p, B, ell, nug, 1e-12)
+        st, X, eta, lat, info = srv.wait(rid, timeout=120)
+        assert st == tc.CHOL_OK
+        _check_against_oracle(p, B, ell, nug, X, 1e-12)
