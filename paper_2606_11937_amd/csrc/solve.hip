@@ -245,14 +245,24 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __rest
   int frow[4];
 #pragma unroll
   for (int s2 = 0; s2 < 4; ++s2) frow[s2] = 16 * s2 + 4 * w + rr;
+  // A full block reads its rows with plain loads, all in flight together;
+  // the ragged last block clamps rows past n to row n - 1 (in bounds) and
+  // selects them away after the loads (a block-uniform choice between the
+  // two, so no load sits in a branch of its own).
+  const bool full = r0 + SV_NB <= n;
   auto lload = [&](int32_t j, double (*dst)[4]) {
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int64_t R = r0 + frow[s2];
-      const bool lv = R < n;
-      const double* p = L + (lv ? R : 0) * lda + q + (int64_t)j * SV_NB;
+      const double* p = L + (full || R < n ? R : n - 1) * lda + q + (int64_t)j * SV_NB;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) dst[s2][m] = lv ? p[16 * m] : 0.0;
+      for (int m = 0; m < 4; ++m) dst[s2][m] = p[16 * m];
+    }
+    if (!full) {
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) dst[s2][m] = r0 + frow[s2] < n ? dst[s2][m] : 0.0;
     }
   };
   auto yload = [&](int32_t j, double (*y)[RC]) {
@@ -416,18 +426,27 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
       Lsub[k][i] = (b + 1 < nb && j0 + k < n && i < nr) ? L[(j0 + k) * lda + r0 + i] : 0.0;
     }
   }
+  // Only the blocks b <= nb - 3 fold, and they are full, so the column
+  // r0 + r is inside the matrix.  A full block j is read with 16 plain
+  // loads in flight together; the ragged last one clamps rows past n to
+  // its last row (in bounds) and selects them away (a wave-uniform choice
+  // between the two, so no load sits in a branch of its own).
   auto load_col = [&](int32_t j, double* dst) {
     const int64_t j0 = (int64_t)j * SV_NB;
-    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-    const int64_t col = r0 + r;
-    const bool lv = r < nr;
-    const double* base = L + (lv ? col : 0);
-    // rows past n are clamped to the last row (in bounds) and selected away
+    const double* base = L + r0 + r;
+    if (n - j0 >= SV_NB) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int kk = 16 * p + k;
-      const double v = base[(j0 + (kk < njr ? kk : njr - 1)) * lda];
-      dst[k] = (lv && kk < njr) ? v : 0.0;
+      for (int k = 0; k < 16; ++k) dst[k] = base[(j0 + 16 * p + k) * lda];
+    } else {
+      const int njr = (int)(n - j0);
+      double v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int kk = 16 * p + k;
+        v[k] = base[(j0 + (kk < njr ? kk : njr - 1)) * lda];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) dst[k] = 16 * p + k < njr ? v[k] : 0.0;
     }
   };
   // this quarter's payload rows of block j, one entry per lane: lane l holds
