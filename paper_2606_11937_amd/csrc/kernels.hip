@@ -614,6 +614,9 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[q] = __builtin_fma(v[q], x, acc[q]);
     };
+    // the block's own entries of b (wave 0 uses them after the fold), read
+    // now so that their round trip overlaps the fold
+    const double bo = b[(r0 + (lane < nr ? lane : nr - 1)) * ldb];
     if (r0 > 0) fetch(va, xa, 0);
     load_diag(r0, nr);  // its wait overlaps the first fetch
     put_diag();
@@ -630,7 +633,7 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     if ((lane & 3) == 0) sm.part[0][16 * w + (lane >> 2)] = s;
     __syncthreads();
     if (w == 0) {
-      double v = lane < nr ? b[(r0 + lane) * ldb] - sm.part[0][lane] : 0.0;
+      double v = lane < nr ? bo - sm.part[0][lane] : 0.0;
       const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
       // eight pivots per pass (a rolled loop keeps the kernel's code small)
 #pragma unroll 1
@@ -676,6 +679,7 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     };
     const int64_t kb = r0 + 64;
     auto gk = [&](int64_t j) { return kb + 64 * (wu + 4 * (j >> 2)) + 16 * (j & 3); };
+    const double bo = b[(r0 + (lane < nr ? lane : nr - 1)) * ldb];  // as in the forward sweep
     if (gk(0) < n) fetch(va, xa, gk(0));
     load_diag(r0, nr);
     put_diag();
@@ -692,7 +696,7 @@ __device__ __forceinline__ void tc_wg_solve(const double* __restrict__ L, int64_
     __syncthreads();
     if (w == 0) {
       const double s = (sm.part[0][lane] + sm.part[1][lane]) + (sm.part[2][lane] + sm.part[3][lane]);
-      double v = lane < nr ? b[(r0 + lane) * ldb] - s : 0.0;
+      double v = lane < nr ? bo - s : 0.0;
       const double dl = lane < nr ? sm.Lbb[lane][lane] : 1.0, rl = 1.0 / dl;
       // pivots from the last one down, eight per pass (padding rows give 0)
 #pragma unroll 1
