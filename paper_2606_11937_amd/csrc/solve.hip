@@ -26,11 +26,16 @@
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
-// One or two right-hand sides go through the kernels with lane-level folds
-// (sv_forward / sv_backward); more are taken in groups of 16 by the kernels
-// whose folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel
-// pair per group.
+// Up to eight right-hand sides go through the kernels with lane-level folds
+// (sv_forward / sv_backward), one substitution chain per wave: one or two
+// in a single pass of payload width 2, three to eight in passes of four
+// (payload width 4).  More are taken in groups of 16 by the kernels whose
+// folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel pair
+// per group.  A column's arithmetic in the lane-level kernels does not depend
+// on the pass width, so its result is the same bit for bit in either.
 #define SV_RC_SMALL 2
+#define SV_RC_MID 4
+#define SV_MID_MAX 8
 #define SV_THREADS 256
 
 // The call's block tickets, then its status word: `error` is set when a
@@ -216,6 +221,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __rest
                                                          const double* __restrict__ B, int64_t nc, int64_t ldb,
                                                          double* Ypay, double* __restrict__ Xpay, SvWs* ws,
                                                          int64_t wait_ticks) {
+  static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double LsubT[SV_NB][SV_NB + 1];  // L_{b,b-1}, transposed
@@ -399,6 +405,7 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
                                                           double* __restrict__ B, int64_t nc, int64_t ldb,
                                                           const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
                                                           int64_t wait_ticks) {
+  static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[4][SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double Lsub[SV_NB][SV_NB + 1];  // L_{b+1,b}
@@ -1353,8 +1360,12 @@ __global__ void sv_clear(SvWs* ws, int words) {
 
 namespace {
 inline int64_t sv_r256(int64_t x) { return (x + 255) & ~(int64_t)255; }
-// payload columns: 2 for the one- and two-column sweeps, 16 otherwise
-inline int64_t sv_pay_width(int64_t nrhs, bool inv) { return (!inv && nrhs <= SV_RC_SMALL) ? SV_RC_SMALL : SV_MF_RC; }
+// payload columns: 2 for one or two right-hand sides, 4 for three to eight
+// (passes of four), 16 otherwise and for the refinement sweeps
+inline int64_t sv_pay_width(int64_t nrhs, bool inv) {
+  if (inv || nrhs > SV_MID_MAX) return SV_MF_RC;
+  return nrhs <= SV_RC_SMALL ? SV_RC_SMALL : SV_RC_MID;
+}
 inline int64_t sv_pay_entries(int64_t n, int64_t pw) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * pw; }
 // header, then the forward and the backward payloads
 struct SvMap {
@@ -1437,6 +1448,18 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
                        (const double*)B, nrhs, ldb, m.ypay, m.xpay, ws, wait_ticks);
     hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
                        ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
+    return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+  }
+  if (nrhs <= SV_MID_MAX) {  // one chain per wave: measured faster than a 16-column pass up to eight
+    const SvMap m = sv_map(work, n, SV_RC_MID);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC_MID) {
+      const int64_t nc = nrhs - c0 < SV_RC_MID ? nrhs - c0 : SV_RC_MID;
+      sv_launch_fill(m, st);
+      hipLaunchKernelGGL(sv_forward<SV_RC_MID>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n,
+                         (const double*)(B + c0), nc, ldb, m.ypay, m.xpay, ws, wait_ticks);
+      hipLaunchKernelGGL(sv_backward<SV_RC_MID>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc,
+                         ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
+    }
     return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
   }
   const SvMap m = sv_map(work, n, SV_MF_RC);

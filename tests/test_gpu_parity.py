@@ -277,12 +277,13 @@ def test_solve_backward_error(tc, n, nrhs, T):
 
 
 @pytest.mark.parametrize("n", [63, 64, 65, 128, 191, 192, 193, 320, 449, 1000])
-@pytest.mark.parametrize("nrhs", [1, 2])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5, 8])
 def test_solve_small_rhs_groups(tc, n, nrhs):
-    """The sweeps for one or two right-hand sides take consecutive 64-row
-    blocks in groups per workgroup: block counts that leave a one-block
-    last group, ragged last blocks, and a strided B (ldb > nrhs), against
-    the oracle's factor and solve."""
+    """The lane-level sweeps (one chain wave per right-hand side; up to
+    eight right-hand sides, in passes of four past two): block counts that
+    leave a one-block last group, ragged last blocks, a partly filled last
+    pass, and a strided B (ldb > nrhs), against the oracle's factor and
+    solve."""
     import torch
     A = inputs.gg_plus_identity(n, seed=61 + n)
     Lref, info = oracle.potrf(A)
@@ -302,13 +303,37 @@ def test_solve_small_rhs_groups(tc, n, nrhs):
     assert np.abs(X - Xref).max() <= 1e-10 * max(1.0, np.abs(Xref).max())
 
 
-@pytest.mark.parametrize("nrhs", [1, 20])
+@pytest.mark.parametrize("n", [200, 1000])
+def test_solve_columns_independent_of_pass_width(tc, n):
+    """A column's result from the lane-level sweeps does not depend on how
+    many right-hand sides share its pass: each column of 1-, 2-, 3-, 4-, 6-
+    and 8-column solves equals, bit for bit, the 1-column solve of that
+    column alone."""
+    import torch
+    A = inputs.gg_plus_identity(n, seed=81 + n)
+    Lref, _ = oracle.potrf(A)
+    Lg = torch.from_numpy(np.ascontiguousarray(np.tril(Lref))).cuda()
+    B = np.random.default_rng(82).standard_normal((n, 8))
+    alone = []
+    for c in range(8):
+        Bc = torch.from_numpy(np.ascontiguousarray(B[:, c:c + 1])).cuda()
+        tc.chol_solve(Lg, Bc, 128)
+        alone.append(Bc.cpu().numpy()[:, 0])
+    for k in (2, 3, 4, 6, 8):
+        Bg = torch.from_numpy(np.ascontiguousarray(B[:, :k])).cuda()
+        tc.chol_solve(Lg, Bg, 128)
+        X = Bg.cpu().numpy()
+        for c in range(k):
+            assert np.array_equal(X[:, c], alone[c]), (k, c)
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 20])
 def test_solve_wait_limit_never_hangs(tc, nrhs):
     """With a zero dependency-wait limit the sweeps give up their waits: the
     call must return, the stream drain, and chol_solve_info must report
     CHOL_ETIMEOUT (B is then unspecified) -- or CHOL_OK with a correct B if
-    no block ever had to wait.  The status survives the per-group counter
-    resets of the 20-column case.  With the limit restored, the same
+    no block ever had to wait.  The status survives the per-pass counter
+    resets of the 5- and 20-column cases.  With the limit restored, the same
     workspace must give a correct solve and report CHOL_OK."""
     import torch
     n = 1000
