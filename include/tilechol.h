@@ -173,8 +173,8 @@ int chol_factor_info(const void* work, void* stream, int64_t* info);
 
 /* Bytes of device workspace chol_solve needs: a 256-byte header (block
  * tickets and the status word), then two payload areas of
- * ceil(n / 64) * 64 rows of 2 (nrhs <= 2), 4 (3 <= nrhs <= 8) or 16
- * (nrhs > 8) doubles each,
+ * ceil(n / 64) * 64 rows of 2 (nrhs <= 2) or 4 x min(16, ceil(nrhs / 4))
+ * (nrhs > 2) doubles each,
  * every part rounded up to 256 bytes; < 0 on invalid arguments. */
 int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
 
@@ -185,9 +185,10 @@ int64_t chol_solve_workspace_size(int64_t n, int64_t T, int64_t nrhs);
  * the workgroups of later blocks through the workspace's payload areas
  * (device-scope atomic stores read until no sentinel remains), so no
  * counter or cache flush sits between two blocks of the chain.  One or two
- * right-hand sides take one pass, three to eight passes of four, more
- * passes of sixteen (a column's result is the same whether it is solved
- * alone or with up to seven others).
+ * right-hand sides take one pass; more take passes of four, up to 16 passes
+ * (64 columns) sharing one launch pair, further columns further launch
+ * pairs.  A column's result is the same bit for bit however many others
+ * share its call.
  *   L      device pointer to the factor (lower triangle read only).
  *   B      device pointer, n x nrhs row-major, leading dimension
  *          ldb >= max(1, nrhs); overwritten by X.

@@ -26,22 +26,21 @@
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
-// Up to eight right-hand sides go through the kernels with lane-level folds
-// (sv_forward / sv_backward), one substitution chain per wave: one or two
-// in a single pass of payload width 2, three to eight in passes of four
-// (payload width 4).  More are taken in groups of 16 by the kernels whose
-// folds run on the matrix cores (sv_fwd_mf / sv_bwd_mf), one kernel pair
-// per group.  A column's arithmetic in the lane-level kernels does not depend
-// on the pass width, so its result is the same bit for bit in either.
+// The right-hand sides go through the kernels with lane-level folds
+// (sv_forward / sv_backward), one substitution chain per wave: one or two in
+// a single pass of payload width 2, three or more in passes of four (payload
+// width 4), up to SV_PASSES of them sharing one launch pair with their
+// blocks interleaved.  A column's arithmetic does not depend on the pass
+// width, so its result is the same bit for bit in either.
 #define SV_RC_SMALL 2
 #define SV_RC_MID 4
-#define SV_MID_MAX 8
+#define SV_PASSES 16
 #define SV_THREADS 256
 
 // The call's block tickets, then its status word: `error` is set when a
 // dependency wait ran out, cleared only when a call (or a caller that groups
 // several solves under one status) starts, so that the ticket reset before
-// each 16-column group of right-hand sides keeps it.
+// each launch pair of a many-column solve keeps it.
 struct SvWs {
   int32_t ticket_f, ticket_b, reserved[2];
   int32_t error, pad[59];
@@ -220,7 +219,7 @@ template <int RC>
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                          const double* __restrict__ B, int64_t nc, int64_t ldb,
                                                          double* Ypay, double* __restrict__ Xpay, SvWs* ws,
-                                                         int64_t wait_ticks) {
+                                                         int64_t wait_ticks, int32_t npass, int64_t pstride) {
   static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
@@ -231,7 +230,15 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __rest
   const int tid = threadIdx.x;
   if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int32_t b = sv_uniform(s_b);
+  // npass passes of RC columns share the launch, their blocks interleaved in
+  // ticket order: ticket g is block g / npass of pass g % npass, and waits
+  // only for smaller tickets of its own pass
+  const int32_t g = sv_uniform(s_b);
+  const int32_t b = g / npass, pass = g - b * npass;
+  B += pass * RC;
+  nc = nc - pass * RC < RC ? nc - pass * RC : RC;
+  Ypay += pass * pstride;
+  Xpay += pass * pstride;
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
   const int w = tid >> 6, lane = tid & 63, rr = lane >> 4, q = lane & 15;
@@ -404,7 +411,7 @@ template <int RC>
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
                                                           double* __restrict__ B, int64_t nc, int64_t ldb,
                                                           const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
-                                                          int64_t wait_ticks) {
+                                                          int64_t wait_ticks, int32_t npass, int64_t pstride) {
   static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[4][SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
@@ -416,7 +423,13 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
   if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int32_t t = sv_uniform(s_t);
+  // passes interleaved in ticket order, as in the forward sweep
+  const int32_t g = sv_uniform(s_t);
+  const int32_t t = g / npass, pass = g - t * npass;
+  B += pass * RC;
+  nc = nc - pass * RC < RC ? nc - pass * RC : RC;
+  Ypay += pass * pstride;
+  Xpay += pass * pstride;
   const int32_t b = nb - 1 - t;
   const int64_t r0 = (int64_t)b * SV_NB;
   const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
@@ -540,354 +553,17 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
   }
 }
 
-// ------------------------------------------------ matrix-core fold sweeps
-// Three to sixteen right-hand sides (payload width 16): the folds run as
-// 64 x 64 by 64 x 16 products on the FP64 matrix cores
-// (v_mfma_f64_16x16x4_f64).  Operand layout (measured on gfx950): A-operand
-// lane l holds row l % 16 at k group l / 16, B-operand lane l holds column
-// l % 16 at k group l / 16, output item q of lane l is row 4 q + l / 16,
-// column l % 16.
-// The blocks up to the second neighbour are folded as their payloads arrive
-// (each wave on its own); the neighbour's payload is waited for by wave 0
-// and handed to the others through LDS; then every wave substitutes up to
-// four right-hand sides, c = w, w + 4, w + 8, w + 12, with interleaved chains
-// (lane k holds row k), and publishes them.
+// ------------------------------------------------ matrix-core operands
+// The refinement sweeps below run their products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64), 16 right-hand sides per pass (payload width 16).
+// Operand layout (measured on gfx950): A-operand lane l holds row l % 16 at
+// k group l / 16, B-operand lane l holds column l % 16 at k group l / 16,
+// output item q of lane l is row 4 q + l / 16, column l % 16.
 typedef double sv_v4d __attribute__((ext_vector_type(4)));
 #define SV_MF_RC 16
 
 __device__ __forceinline__ sv_v4d sv_mfma(double a, double b, sv_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// Up to four interleaved chains of wave w over the columns w + 4 t (a
-// wave-uniform choice of the unrolled loop keeps the live chains together).
-template <bool FWD>
-__device__ __forceinline__ void sv_chains_cols(double* v, const double (*Lbb)[SV_NB + 1], const double* rdiag,
-                                               int lane, int w, int ncl) {
-  const int nt = ncl > w ? (ncl - w + 3) / 4 : 0;
-  if (FWD) {
-    if (nt >= 4) sv_chains_fwd<4>(v, Lbb, rdiag, lane);
-    else if (nt == 3) sv_chains_fwd<3>(v, Lbb, rdiag, lane);
-    else if (nt == 2) sv_chains_fwd<2>(v, Lbb, rdiag, lane);
-    else if (nt == 1) sv_chains_fwd<1>(v, Lbb, rdiag, lane);
-  } else {
-    if (nt >= 4) sv_chains_bwd<4>(v, Lbb, rdiag, lane);
-    else if (nt == 3) sv_chains_bwd<3>(v, Lbb, rdiag, lane);
-    else if (nt == 2) sv_chains_bwd<2>(v, Lbb, rdiag, lane);
-    else if (nt == 1) sv_chains_bwd<1>(v, Lbb, rdiag, lane);
-  }
-}
-
-// Forward: wave w owns rows 16 w .. 16 w + 15 of the block (whole 512-byte
-// row segments of L); in a 16-wide k chunk ch, lane (r, g) brings
-// k = 16 ch + 4 g + m to MFMA m for both operands.  Rounding order per
-// entry: the blocks in sweep order, each as 16 MFMAs in (chunk, m) order;
-// B minus the sum; then the substitution.  B is read, not written: the
-// backward sweep reads y_b from the payload.
-__global__ __launch_bounds__(SV_THREADS, 2) void sv_fwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                           const double* __restrict__ B, int64_t nc, int64_t ldb,
-                                                           double* Ypay, double* __restrict__ Xpay, SvWs* ws,
-                                                           int64_t wait_ticks) {
-  __shared__ double part[SV_NB][SV_MF_RC + 1];
-  __shared__ double yl[SV_NB][SV_MF_RC + 1];  // y_{b-1}, handed over by wave 0
-  __shared__ double Lbb[SV_NB][SV_NB + 1];
-  __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_b, s_ok;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const int32_t b = sv_uniform(s_b);
-  const int64_t r0 = (int64_t)b * SV_NB;
-  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4;
-  const int arow = 16 * w + r16;
-  const bool alive = arow < nr;
-  const bool bok = r16 < nc;
-  const double* lrow = L + (r0 + (alive ? arow : 0)) * lda + g4;
-  const double* ypay = Ypay + (int64_t)g4 * SV_MF_RC + r16;
-  for (int e = tid; e < SV_NB * SV_MF_RC; e += SV_THREADS)
-    Xpay[(int64_t)b * SV_NB * SV_MF_RC + e] = __builtin_bit_cast(double, SV_SENTINEL);
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
-  auto load_l = [&](int32_t j, double* a) {
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const double v = lrow[(int64_t)j * SV_NB + 16 * ch + m];
-        a[4 * ch + m] = alive ? v : 0.0;
-      }
-  };
-  auto load_y = [&](int32_t j, double* y) {
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) y[4 * ch + m] = sv_pay_ld(ypay + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
-  };
-  // read before any wait: the own rows of B, the neighbour tile L_{b,b-1}
-  // and the last folded tile L_{b,b-2}
-  double bown[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4);
-    bown[q] = (row < nr && bok) ? B[(r0 + row) * ldb + r16] : 0.0;
-  }
-  double lnb[16];
-  if (b > 0) load_l(b - 1, lnb);
-  const int32_t nfold = b > 1 ? b - 1 : 0;  // blocks 0 .. b - 2
-  sv_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  double lt[16], la[16], ya[16];
-  bool ok = true;
-  if (nfold > 0) {
-    load_l(nfold - 1, lt);
-    load_y(0, ya);
-  }
-  if (nfold > 1) load_l(0, la);
-  auto pending = [&] {
-    bool p = false;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) p = p || sv_pending(ya[k]);
-    return p;
-  };
-  auto probe = [&](int32_t j) { return Ypay + ((int64_t)j * SV_NB + SV_NB - 1) * SV_MF_RC + SV_MF_RC - 1; };
-  for (int32_t j = 0; j + 1 < nfold; ++j) {
-    if (!sv_wave_wait(probe(j), [&] { load_y(j, ya); }, pending, ws, wait_ticks)) {
-      ok = false;
-      break;
-    }
-    const bool more = j + 2 < nfold;
-    double ln[16], yn[16];
-    if (more) load_l(j + 1, ln);
-    load_y(j + 1, yn);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) acc = sv_mfma(la[k], ya[k], acc);
-    if (more) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) la[k] = ln[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ya[k] = yn[k];
-  }
-  if (ok && nfold > 0) {
-    if (sv_wave_wait(probe(nfold - 1), [&] { load_y(nfold - 1, ya); }, pending, ws, wait_ticks)) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) acc = sv_mfma(lt[k], ya[k], acc);
-    } else {
-      ok = false;
-    }
-  }
-  // the neighbour y_{b-1}: wave 0 waits and hands it over through LDS
-  __builtin_amdgcn_s_setprio(3);
-  if (b > 0) {
-    if (w == 0) {
-      if (ok) load_y(b - 1, ya);
-      const bool got = ok && sv_wave_wait_full([&] { load_y(b - 1, ya); }, pending, ws, wait_ticks);
-      if (got) {
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) yl[16 * ch + g4 + m][r16] = ya[4 * ch + m];
-      }
-      if (lane == 0) s_ok = got;
-    }
-    __syncthreads();
-    ok = ok && s_ok;
-    if (ok) {
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc = sv_mfma(lnb[4 * ch + m], yl[16 * ch + g4 + m][r16], acc);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4);
-    part[row][r16] = (row < nr && bok) ? bown[q] - acc[q] : 0.0;
-  }
-  const bool all_ok = __syncthreads_and(ok);
-  double v[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) v[t] = part[lane][w + 4 * t];
-  sv_chains_cols<true>(v, Lbb, rdiag, lane, w, (int)nc);
-  if (all_ok) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = w + 4 * t;
-      sv_pay_st(Ypay + ((int64_t)b * SV_NB + lane) * SV_MF_RC + c, (lane < nr && c < nc) ? v[t] : 0.0);
-    }
-  }
-}
-
-// Backward: the fold splits k across the waves (wave w takes rows
-// 16 w .. 16 w + 15 of every later block, for all 64 output rows: whole
-// 512-byte row segments of L, and only those 16 payload rows).  MFMA
-// (o, kc): output rows 16 o .., k rows 16 w + 4 kc + g.  Rounding order per
-// entry: each wave sums its blocks in sweep order (the neighbour last), each
-// as 4 MFMAs in kc order; the waves' sums combine as (w0 + w2) + (w1 + w3);
-// y_b minus that; then the substitution.
-__global__ __launch_bounds__(SV_THREADS, 2) void sv_bwd_mf(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                           double* __restrict__ B, int64_t nc, int64_t ldb,
-                                                           const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
-                                                           int64_t wait_ticks) {
-  __shared__ double red[2][SV_NB][SV_MF_RC + 1];  // partial sums; red[0] then holds v
-  __shared__ double xl[SV_NB][SV_MF_RC + 1];      // x_{b+1}, handed over by wave 0
-  __shared__ double Lbb[SV_NB][SV_NB + 1];
-  __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_t, s_ok;
-  double(*part)[SV_MF_RC + 1] = red[0];
-  const int tid = threadIdx.x;
-  const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
-  if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const int32_t t = sv_uniform(s_t);
-  const int32_t b = nb - 1 - t;
-  const int64_t r0 = (int64_t)b * SV_NB;
-  const int nr = n - r0 < SV_NB ? (int)(n - r0) : SV_NB;
-  const int w = tid >> 6, lane = tid & 63, r16 = lane & 15, g4 = (lane >> 4) * 4, g = lane >> 4;
-  const bool bok = r16 < nc;
-  sv_stage_diag(L, lda, r0, nr, Lbb, rdiag);
-  auto load_l = [&](int32_t j, double* a) {
-    const int64_t j0 = (int64_t)j * SV_NB;
-    const int njr = n - j0 < SV_NB ? (int)(n - j0) : SV_NB;
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-      const int kr = 16 * w + 4 * kc + g;
-      const bool kin = kr < njr;
-      const double* rowp = L + (j0 + (kin ? kr : 0)) * lda + r0;
-#pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        const int col = 16 * o + r16;
-        const bool cin = col < nr;
-        const double v = rowp[cin ? col : 0];
-        a[4 * o + kc] = (kin && cin) ? v : 0.0;
-      }
-    }
-  };
-  auto load_xk = [&](int32_t j, double* x) {
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc)
-      x[kc] = sv_pay_ld(Xpay + ((int64_t)j * SV_NB + 16 * w + 4 * kc + g) * SV_MF_RC + r16);
-  };
-  auto load_x = [&](int32_t j, double* x) {
-    const double* xp = Xpay + (int64_t)g4 * SV_MF_RC + r16;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) x[4 * ch + m] = sv_pay_ld(xp + ((int64_t)j * SV_NB + 16 * ch + m) * SV_MF_RC);
-  };
-  // read before any wait: the own rows of y (an earlier launch's payload),
-  // the neighbour tile (block b + 1) and the last folded tile (block b + 2)
-  double yown[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + g;
-    yown[q] = Ypay[((int64_t)b * SV_NB + row) * SV_MF_RC + r16];
-  }
-  double lnb[16];
-  if (b + 1 < nb) load_l(b + 1, lnb);
-  const int32_t jlast = b + 2;
-  sv_v4d acc[4];
-#pragma unroll
-  for (int o = 0; o < 4; ++o) acc[o] = (sv_v4d){0.0, 0.0, 0.0, 0.0};
-  double lt[16], la[16], xa[4];
-  bool ok = true;
-  if (jlast < nb) {
-    load_l(jlast, lt);
-    load_xk(nb - 1, xa);
-  }
-  if (jlast < nb - 1) load_l(nb - 1, la);
-  auto pending = [&] { return sv_pending(xa[0]) || sv_pending(xa[1]) || sv_pending(xa[2]) || sv_pending(xa[3]); };
-  auto probe = [&](int32_t j) { return Xpay + ((int64_t)j * SV_NB + 16 * w + 15) * SV_MF_RC + SV_MF_RC - 1; };
-  auto fold = [&](const double* a, const double* x) {
-#pragma unroll
-    for (int o = 0; o < 4; ++o)
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) acc[o] = sv_mfma(a[4 * o + kc], x[kc], acc[o]);
-  };
-  for (int32_t j = nb - 1; j > jlast; --j) {
-    if (!sv_wave_wait(probe(j), [&] { load_xk(j, xa); }, pending, ws, wait_ticks)) {
-      ok = false;
-      break;
-    }
-    const bool more = j - 1 > jlast;
-    double ln[16], xn[4];
-    if (more) load_l(j - 1, ln);
-    load_xk(j - 1, xn);
-    fold(la, xa);
-    if (more) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) la[k] = ln[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) xa[k] = xn[k];
-  }
-  if (ok && jlast < nb) {
-    if (sv_wave_wait(probe(jlast), [&] { load_xk(jlast, xa); }, pending, ws, wait_ticks))
-      fold(lt, xa);
-    else
-      ok = false;
-  }
-  // the neighbour x_{b+1}: wave 0 waits and hands it over through LDS
-  __builtin_amdgcn_s_setprio(3);
-  if (b + 1 < nb) {
-    if (w == 0) {
-      double xc[16];
-      auto pend16 = [&] {
-        bool p = false;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) p = p || sv_pending(xc[k]);
-        return p;
-      };
-      if (ok) load_x(b + 1, xc);
-      const bool got = ok && sv_wave_wait_full([&] { load_x(b + 1, xc); }, pend16, ws, wait_ticks);
-      if (got) {
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) xl[16 * ch + g4 + m][r16] = xc[4 * ch + m];
-      }
-      if (lane == 0) s_ok = got;
-    }
-    __syncthreads();
-    ok = ok && s_ok;
-    if (ok) {
-      double xk[4];
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) xk[kc] = xl[16 * w + 4 * kc + g][r16];
-      fold(lnb, xk);
-    }
-  }
-  // combine the waves' sums: red[0] = w0 + w2, red[1] = w1 + w3
-  if (w < 2) {
-#pragma unroll
-    for (int o = 0; o < 4; ++o)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[w][16 * o + 4 * q + g][r16] = acc[o][q];
-  }
-  __syncthreads();
-  if (w >= 2) {
-#pragma unroll
-    for (int o = 0; o < 4; ++o)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[w - 2][16 * o + 4 * q + g][r16] += acc[o][q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + g;
-    const double f = red[0][row][r16] + red[1][row][r16];
-    part[row][r16] = (row < nr && bok) ? yown[q] - f : 0.0;
-  }
-  const bool all_ok = __syncthreads_and(ok);
-  double v[4];
-#pragma unroll
-  for (int tt = 0; tt < 4; ++tt) v[tt] = part[lane][w + 4 * tt];
-  sv_chains_cols<false>(v, Lbb, rdiag, lane, w, (int)nc);
-#pragma unroll
-  for (int tt = 0; tt < 4; ++tt) {
-    const int c = w + 4 * tt;
-    if (lane < nr && c < nc) B[(r0 + lane) * ldb + c] = v[tt];
-    if (all_ok) sv_pay_st(Xpay + ((int64_t)b * SV_NB + lane) * SV_MF_RC + c, (lane < nr && c < nc) ? v[tt] : 0.0);
-  }
 }
 
 // ------------------------------------------- sweeps with inverted diagonals
@@ -1360,23 +1036,33 @@ __global__ void sv_clear(SvWs* ws, int words) {
 
 namespace {
 inline int64_t sv_r256(int64_t x) { return (x + 255) & ~(int64_t)255; }
-// payload columns: 2 for one or two right-hand sides, 4 for three to eight
-// (passes of four), 16 otherwise and for the refinement sweeps
+// payload columns: 2 for one or two right-hand sides, 4 for more (passes of
+// four), 16 for the refinement sweeps
 inline int64_t sv_pay_width(int64_t nrhs, bool inv) {
-  if (inv || nrhs > SV_MID_MAX) return SV_MF_RC;
+  if (inv) return SV_MF_RC;
   return nrhs <= SV_RC_SMALL ? SV_RC_SMALL : SV_RC_MID;
 }
 inline int64_t sv_pay_entries(int64_t n, int64_t pw) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * pw; }
-// header, then the forward and the backward payloads
+// passes of four columns that share one launch pair (at most SV_PASSES;
+// more columns take further launch pairs over the same payload areas), else
+// one
+inline int64_t sv_npass(int64_t nrhs, bool inv) {
+  if (sv_pay_width(nrhs, inv) != SV_RC_MID) return 1;
+  const int64_t p = (nrhs + SV_RC_MID - 1) / SV_RC_MID;
+  return p < SV_PASSES ? p : SV_PASSES;
+}
+// header, then the forward and the backward payloads, each npass areas of
+// `stride` entries
 struct SvMap {
   SvWs* ws;
   double *ypay, *xpay;
-  int64_t entries;
+  int64_t stride, entries;
 };
-SvMap sv_map(void* work, int64_t n, int64_t pw) {
+SvMap sv_map(void* work, int64_t n, int64_t pw, int64_t npass = 1) {
   SvMap m;
   m.ws = (SvWs*)work;
-  m.entries = sv_pay_entries(n, pw);
+  m.stride = sv_pay_entries(n, pw);
+  m.entries = m.stride * npass;
   m.ypay = (double*)((char*)work + sv_r256(sizeof(SvWs)));
   m.xpay = (double*)((char*)m.ypay + sv_r256(8 * m.entries));
   return m;
@@ -1389,7 +1075,7 @@ void sv_launch_fill(const SvMap& m, hipStream_t st) {
 }  // namespace
 
 int64_t tc_solve_ws_bytes(int64_t n, int64_t nrhs, bool inv) {
-  return sv_r256(sizeof(SvWs)) + 2 * sv_r256(8 * sv_pay_entries(n, sv_pay_width(nrhs, inv)));
+  return sv_r256(sizeof(SvWs)) + 2 * sv_r256(8 * sv_pay_entries(n, sv_pay_width(nrhs, inv)) * sv_npass(nrhs, inv));
 }
 
 int tc_solve_status_reset(void* work, hipStream_t st) {
@@ -1445,31 +1131,25 @@ int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* 
     const SvMap m = sv_map(work, n, SV_RC_SMALL);
     sv_launch_fill(m, st);
     hipLaunchKernelGGL(sv_forward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n,
-                       (const double*)B, nrhs, ldb, m.ypay, m.xpay, ws, wait_ticks);
+                       (const double*)B, nrhs, ldb, m.ypay, m.xpay, ws, wait_ticks, 1, m.stride);
     hipLaunchKernelGGL(sv_backward<SV_RC_SMALL>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B, nrhs,
-                       ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
+                       ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks, 1, m.stride);
     return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
   }
-  if (nrhs <= SV_MID_MAX) {  // one chain per wave: measured faster than a 16-column pass up to eight
-    const SvMap m = sv_map(work, n, SV_RC_MID);
-    for (int64_t c0 = 0; c0 < nrhs; c0 += SV_RC_MID) {
-      const int64_t nc = nrhs - c0 < SV_RC_MID ? nrhs - c0 : SV_RC_MID;
-      sv_launch_fill(m, st);
-      hipLaunchKernelGGL(sv_forward<SV_RC_MID>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n,
-                         (const double*)(B + c0), nc, ldb, m.ypay, m.xpay, ws, wait_ticks);
-      hipLaunchKernelGGL(sv_backward<SV_RC_MID>, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc,
-                         ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks);
-    }
-    return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
-  }
-  const SvMap m = sv_map(work, n, SV_MF_RC);
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SV_MF_RC) {
-    const int64_t nc = nrhs - c0 < SV_MF_RC ? nrhs - c0 : SV_MF_RC;
+  // one chain per wave, up to SV_PASSES passes of four in one launch pair
+  // (measured faster at every size than 16-column passes whose folds ran on
+  // the matrix cores, four chains per wave)
+  const int64_t npass = sv_npass(nrhs, false);
+  const SvMap m = sv_map(work, n, SV_RC_MID, npass);
+  const int64_t cols = npass * SV_RC_MID;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += cols) {
+    const int64_t nc = nrhs - c0 < cols ? nrhs - c0 : cols;
+    const int64_t np = (nc + SV_RC_MID - 1) / SV_RC_MID;
     sv_launch_fill(m, st);
-    hipLaunchKernelGGL(sv_fwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, (const double*)(B + c0), nc,
-                       ldb, m.ypay, m.xpay, ws, wait_ticks);
-    hipLaunchKernelGGL(sv_bwd_mf, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, B + c0, nc, ldb,
-                       (const double*)m.ypay, m.xpay, ws, wait_ticks);
+    hipLaunchKernelGGL(sv_forward<SV_RC_MID>, dim3((unsigned)(nb * np)), dim3(SV_THREADS), 0, st, L, lda, n,
+                       (const double*)(B + c0), nc, ldb, m.ypay, m.xpay, ws, wait_ticks, (int32_t)np, m.stride);
+    hipLaunchKernelGGL(sv_backward<SV_RC_MID>, dim3((unsigned)(nb * np)), dim3(SV_THREADS), 0, st, L, lda, n,
+                       B + c0, nc, ldb, (const double*)m.ypay, m.xpay, ws, wait_ticks, (int32_t)np, m.stride);
   }
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }

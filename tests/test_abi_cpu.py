@@ -103,12 +103,14 @@ def test_workspace_sizes(tc):
     # counters grow with the number of row blocks
     assert tc.chol_factor_workspace_size(32768, 128, 1) > tc.chol_factor_workspace_size(8192, 128, 1)
     # a 256-byte header, then the forward and backward payloads: 64-row
-    # blocks of 2 columns (one or two right-hand sides), 4 columns (three to
-    # eight, in passes of four) or 16 columns
+    # blocks of 2 columns (one or two right-hand sides) or 4 columns per
+    # pass of four (up to 16 passes share a launch pair and its payloads)
     r256 = lambda x: (x + 255) // 256 * 256
-    for n, nrhs in ((100, 3), (100, 1), (100, 2), (100, 8), (100, 9), (64, 16), (65, 40), (32768, 1)):
-        pw = 2 if nrhs <= 2 else (4 if nrhs <= 8 else 16)
-        want = 256 + 2 * r256(8 * ((n + 63) // 64) * 64 * pw)
+    for n, nrhs in ((100, 3), (100, 1), (100, 2), (100, 8), (100, 9), (64, 16), (65, 40), (65, 64),
+                    (65, 65), (65, 200), (32768, 1)):
+        pw = 2 if nrhs <= 2 else 4
+        npass = min(16, (nrhs + 3) // 4) if pw == 4 else 1
+        want = 256 + 2 * r256(8 * ((n + 63) // 64) * 64 * pw * npass)
         assert tc.chol_solve_workspace_size(n, 16, nrhs) == want
     assert tc.chol_solve_workspace_size(100, 0, 3) == tc.CHOL_EINVAL
 

@@ -258,7 +258,8 @@ def test_solve_integer_exact(tc):
         assert np.array_equal(Bg.cpu().numpy(), X), T
 
 
-@pytest.mark.parametrize("n,nrhs,T", [(1, 1, 8), (130, 1, 128), (1024, 16, 128), (999, 5, 256), (512, 20, 64)])
+@pytest.mark.parametrize("n,nrhs,T", [(1, 1, 8), (130, 1, 128), (1024, 16, 128), (999, 5, 256), (512, 20, 64),
+                                      (300, 70, 128), (65, 130, 64)])
 def test_solve_backward_error(tc, n, nrhs, T):
     import torch
     A = inputs.gg_plus_identity(n, seed=43 + n)
@@ -305,21 +306,21 @@ def test_solve_small_rhs_groups(tc, n, nrhs):
 
 @pytest.mark.parametrize("n", [200, 1000])
 def test_solve_columns_independent_of_pass_width(tc, n):
-    """A column's result from the lane-level sweeps does not depend on how
-    many right-hand sides share its pass: each column of 1-, 2-, 3-, 4-, 6-
-    and 8-column solves equals, bit for bit, the 1-column solve of that
-    column alone."""
+    """A column's result does not depend on how many right-hand sides share
+    its call: each column of 2- to 70-column solves (one pass; passes of
+    four in one launch pair; more than one launch pair past 64 columns)
+    equals, bit for bit, the 1-column solve of that column alone."""
     import torch
     A = inputs.gg_plus_identity(n, seed=81 + n)
     Lref, _ = oracle.potrf(A)
     Lg = torch.from_numpy(np.ascontiguousarray(np.tril(Lref))).cuda()
-    B = np.random.default_rng(82).standard_normal((n, 8))
+    B = np.random.default_rng(82).standard_normal((n, 70))
     alone = []
-    for c in range(8):
+    for c in range(70):
         Bc = torch.from_numpy(np.ascontiguousarray(B[:, c:c + 1])).cuda()
         tc.chol_solve(Lg, Bc, 128)
         alone.append(Bc.cpu().numpy()[:, 0])
-    for k in (2, 3, 4, 6, 8):
+    for k in (2, 3, 4, 6, 8, 16, 37, 70):
         Bg = torch.from_numpy(np.ascontiguousarray(B[:, :k])).cuda()
         tc.chol_solve(Lg, Bg, 128)
         X = Bg.cpu().numpy()
