@@ -7,7 +7,11 @@ For every n-bucket a batch of orders drawn log-uniformly inside the bucket
 chol_factor_solve_batched with each candidate tile side given explicitly;
 the fastest side (median of 3 runs) becomes the bucket's row of the table.
 The table is chosen from (n, precision) only, and the library compiles it in
-(build.py turns the JSON into tc_tuned_batched_tile).  Only FP64 is swept.
+(build.py turns the JSON into tc_tuned_batched_tile and
+tc_tuned_batched_tile_fp32).  --prec fp64 (the default) sweeps
+chol_factor_solve_batched and writes the "fp64" table; --prec fp32 sweeps
+chol_factor_solve_batched_mixed with every matrix in FP32 (refined to 1e-12)
+and writes the "fp32" table.
 """
 from __future__ import annotations
 
@@ -30,7 +34,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "tuning", "batched_tiles.json"))
     ap.add_argument("--flops", type=float, default=3e11, help="work per bucket batch (n^3/3 summed)")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
     args = ap.parse_args()
+    fp32 = args.prec == "fp32"
     rows = []
     log = []
     for lo, hi in BUCKETS:
@@ -57,25 +63,33 @@ def main():
             if T != 0 and T >= hi:
                 continue
             Ts = [n if T == 0 else T for n in sizes]
-            work = torch.empty(tc.chol_factor_solve_batched_workspace_size(sizes, Ts), dtype=torch.uint8,
-                               device="cuda")
+            if fp32:
+                precs = ["fp32"] * count
+                wbytes = tc.chol_factor_solve_batched_mixed_workspace_size(sizes, Ts, precs)
+            else:
+                wbytes = tc.chol_factor_solve_batched_workspace_size(sizes, Ts)
+            work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
             times = []
             for r in range(4):
-                for L, A in zip(Ls, As):
-                    L.copy_(A)
-                for X, b in zip(Xs, Bs):
-                    X.copy_(b)
+                if not fp32:  # the FP32 path reads the originals and writes L and x itself
+                    for L, A in zip(Ls, As):
+                        L.copy_(A)
+                    for X, b in zip(Xs, Bs):
+                        X.copy_(b)
                 torch.cuda.synchronize()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                tc.chol_factor_solve_batched(Ls, Xs, Ts, work=work, sync=False)
+                if fp32:
+                    tc.chol_factor_solve_batched_mixed(As, Ls, Bs, Xs, Ts=Ts, precs=precs, work=work, sync=False)
+                else:
+                    tc.chol_factor_solve_batched(Ls, Xs, Ts, work=work, sync=False)
                 e1.record()
                 torch.cuda.synchronize()
                 if r:
                     times.append(e0.elapsed_time(e1))
             ms = statistics.median(times)
             flops = sum(n ** 3 / 3 for n in sizes)
-            rec = {"bucket": [lo, hi], "count": count, "T": T, "ms": round(ms, 3),
+            rec = {"prec": args.prec, "bucket": [lo, hi], "count": count, "T": T, "ms": round(ms, 3),
                    "tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
             print(json.dumps(rec), flush=True)
             log.append(rec)
@@ -85,8 +99,8 @@ def main():
         del As, Bs, Ls, Xs
         torch.cuda.empty_cache()
     rows.append({"n_max": 1048576, "T": 1024})
-    # the other tables of the file (the FP32 tile table, the serving plan)
-    # are kept as they are
+    # the file's other tables (the other precision's tile table, the serving
+    # plan) are kept as they are
     out = {}
     if os.path.exists(args.out):
         with open(args.out) as f:
@@ -96,8 +110,8 @@ def main():
                   "are n-buckets: a matrix of order n takes the first row with n <= n_max; T = 0 means one tile "
                   "(T = n). Written by paper_2606_11937_amd/tune_batched.py from a sweep on MI355X."),
         "source": "measured: median of 3 batched factor+solve runs per (bucket, T) on one MI355X",
-        "fp64": rows,
-        "sweep": log,
+        args.prec: rows,
+        "sweep" if not fp32 else "sweep_fp32": log,
     })
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
