@@ -204,6 +204,8 @@ bool launch_tick(TcServer& S, Flight& f) {
   hipStream_t st = S.st[t.stream];
   const int64_t m = (int64_t)t.items.size();
   std::vector<SrvDesc> desc(m);
+  std::vector<TcSolveJob> jobs(m);
+  int64_t tickets = 0, max_entries = 0;
   std::vector<double*> A;
   std::vector<int64_t> n, T;
   std::vector<int32_t> prec;
@@ -229,6 +231,17 @@ bool launch_tick(TcServer& S, Flight& f) {
     D.item = it.item;
     D.fresh = it.item != tcs::ITEM_CORRECT;
     D.serr = (const int32_t*)(S.arena + t.ws_off + t.solve_off[q] + tc_solve_status_offset());
+    // the item's solve, in the tick's one solve launch: of B (in X) for a
+    // new solution, of the residual R for a correction
+    TcSolveJob& J = jobs[q];
+    J.L = D.L;
+    J.B = D.fresh ? D.X : D.R;
+    J.work = S.arena + t.ws_off + t.solve_off[q];
+    J.n = J.lda = R.n;
+    J.nrhs = J.ldb = R.nrhs;
+    J.first = tickets;
+    tickets += tc_solve_many_tickets(R.n, R.nrhs);
+    max_entries = std::max(max_entries, ((R.n + 63) / 64) * 64 * 4 * ((R.nrhs + 3) / 4));
     nmax = std::max(nmax, R.n);
     emax = std::max(emax, R.n * R.nrhs);
     // inputs of a request's first item through its pinned staging
@@ -250,11 +263,17 @@ bool launch_tick(TcServer& S, Flight& f) {
       prec.push_back(R.prec);
     }
   }
-  // descriptors: pinned -> device
+  // descriptors, then the solve jobs: pinned -> device; the solve launch's
+  // two counters follow them
   SrvDesc* meta_h = (SrvDesc*)(S.pinned + t.meta_pin);
   memcpy(meta_h, desc.data(), sizeof(SrvDesc) * m);
+  memcpy((char*)meta_h + sizeof(SrvDesc) * m, jobs.data(), sizeof(TcSolveJob) * m);
   SrvDesc* meta_d = (SrvDesc*)(S.arena + t.meta_dev);
-  if (hipMemcpyAsync(meta_d, meta_h, sizeof(SrvDesc) * m, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+  const TcSolveJob* jobs_d = (const TcSolveJob*)((char*)meta_d + sizeof(SrvDesc) * m);
+  int32_t* solve_ctr = (int32_t*)((char*)meta_d + (sizeof(SrvDesc) + sizeof(TcSolveJob)) * m);
+  if (hipMemcpyAsync(meta_d, meta_h, (sizeof(SrvDesc) + sizeof(TcSolveJob)) * m, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return false;
   char* ws = S.arena + t.ws_off;
   if (!A.empty()) {
     hipLaunchKernelGGL(srv_assemble, dim3((unsigned)((nmax + 7) / 8), (unsigned)m), dim3(SRV_THREADS), 0, st, meta_d);
@@ -273,15 +292,9 @@ bool launch_tick(TcServer& S, Flight& f) {
   }
   hipLaunchKernelGGL(srv_prepare, dim3((unsigned)((emax + SRV_THREADS - 1) / SRV_THREADS), (unsigned)m),
                      dim3(SRV_THREADS), 0, st, meta_d);
-  // each item's solve, with a solve workspace (and status word) of its own:
-  // of B (in X) for a new solution, of the residual R for a correction
-  for (int64_t q = 0; q < m; ++q) {
-    const tcs::Request& R = *f.rq[q];
-    double* rhs = desc[q].fresh ? desc[q].X : desc[q].R;
-    char* sws = ws + t.solve_off[q];
-    if (tc_solve_status_reset(sws, st) != 0) return false;
-    if (tc_launch_solve(desc[q].L, R.n, R.n, 128, rhs, R.nrhs, R.nrhs, sws, st, S.wait_ticks) != 0) return false;
-  }
+  // every item's solve in one launch pair, each with a solve workspace (and
+  // status word) of its own
+  if (tc_launch_solve_many(jobs_d, m, tickets, max_entries, solve_ctr, st, S.wait_ticks) != 0) return false;
   hipLaunchKernelGGL(srv_apply, dim3((unsigned)((emax + SRV_THREADS - 1) / SRV_THREADS), (unsigned)m),
                      dim3(SRV_THREADS), 0, st, (const SrvDesc*)meta_d);
   hipLaunchKernelGGL(srv_residual, dim3((unsigned)((nmax + 63) / 64), (unsigned)m), dim3(SRV_THREADS), 0, st,
@@ -342,9 +355,11 @@ tcs::WsSizer make_sizer() {
   };
   z.fifo = [](int64_t n) { return tc_ws_bytes(n, tc_default_tile(n)); };
   z.tile = [](int64_t n, int prec) { return tc_tuned_batched_tile_prec(n, prec); };
-  z.solve_ws = [](int64_t n, int64_t nrhs) { return tc_solve_ws_bytes(n, nrhs, false); };
+  z.solve_ws = [](int64_t n, int64_t nrhs) { return tc_solve_many_ws_bytes(n, nrhs); };
   z.header = tc_ws_header_bytes();
-  z.desc = (int64_t)sizeof(SrvDesc);
+  // an item's descriptor and solve job, and room for the solve launch's two
+  // counters after the last job
+  z.desc = (int64_t)(sizeof(SrvDesc) + sizeof(TcSolveJob) + 16);
   return z;
 }
 

@@ -215,25 +215,22 @@ __device__ __forceinline__ void sv_chains_bwd(double* v, const double (*Lbb)[SV_
 // k = 4 i + r, ascending) added as (d0 + d1) + (d2 + d3); then the
 // substitution (sv_chains_fwd).  The forward sweep does not write
 // B: the backward sweep reads y_b from the payload.
+// The workgroup with ticket g (counted from the solve's first) of the
+// forward sweep; npass passes of RC columns share the launch, their blocks
+// interleaved in ticket order: ticket g is block g / npass of pass
+// g % npass, and waits only for smaller tickets of its own pass.
 template <int RC>
-__global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                         const double* __restrict__ B, int64_t nc, int64_t ldb,
-                                                         double* Ypay, double* __restrict__ Xpay, SvWs* ws,
-                                                         int64_t wait_ticks, int32_t npass, int64_t pstride) {
+__device__ __forceinline__ void sv_forward_run(const double* __restrict__ L, int64_t lda, int64_t n,
+                                               const double* __restrict__ B, int64_t nc, int64_t ldb, double* Ypay,
+                                               double* __restrict__ Xpay, SvWs* ws, int64_t wait_ticks, int32_t npass,
+                                               int64_t pstride, int32_t g) {
   static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double LsubT[SV_NB][SV_NB + 1];  // L_{b,b-1}, transposed
   __shared__ double ylds[RC][SV_NB];          // y_{b-1}, broadcast to the chain wave's lanes
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_b;
   const int tid = threadIdx.x;
-  if (tid == 0) s_b = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  // npass passes of RC columns share the launch, their blocks interleaved in
-  // ticket order: ticket g is block g / npass of pass g % npass, and waits
-  // only for smaller tickets of its own pass
-  const int32_t g = sv_uniform(s_b);
   const int32_t b = g / npass, pass = g - b * npass;
   B += pass * RC;
   nc = nc - pass * RC < RC ? nc - pass * RC : RC;
@@ -407,24 +404,21 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __rest
 // combined in order p = 0..3.  Then y_b minus it; minus L_{b+1,b}^T x_{b+1}
 // as four partial sums (rows k = 4 i + r, ascending) added as
 // (d0 + d1) + (d2 + d3); then the substitution (sv_chains_bwd).
+// The workgroup with ticket g of the backward sweep (passes interleaved in
+// ticket order, as in the forward sweep).
 template <int RC>
-__global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
-                                                          double* __restrict__ B, int64_t nc, int64_t ldb,
-                                                          const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
-                                                          int64_t wait_ticks, int32_t npass, int64_t pstride) {
+__device__ __forceinline__ void sv_backward_run(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
+                                                int64_t wait_ticks, int32_t npass, int64_t pstride, int32_t g) {
   static_assert(RC >= 1 && RC <= SV_THREADS / 64, "one chain wave per right-hand side");
   __shared__ double part[4][SV_NB][RC + 1];
   __shared__ double Lbb[SV_NB][SV_NB + 1];
   __shared__ double Lsub[SV_NB][SV_NB + 1];  // L_{b+1,b}
   __shared__ double xlds[RC][SV_NB];         // x_{b+1}, broadcast to the chain wave's lanes
   __shared__ double rdiag[SV_NB];
-  __shared__ int32_t s_t;
   const int tid = threadIdx.x;
   const int32_t nb = (int32_t)((n + SV_NB - 1) / SV_NB);
-  if (tid == 0) s_t = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  // passes interleaved in ticket order, as in the forward sweep
-  const int32_t g = sv_uniform(s_t);
   const int32_t t = g / npass, pass = g - t * npass;
   B += pass * RC;
   nc = nc - pass * RC < RC ? nc - pass * RC : RC;
@@ -551,6 +545,97 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __res
     if (got) sv_pay_st(Xpay + ((int64_t)b * SV_NB + lane) * RC + c, lane < nr ? v : 0.0);
     __builtin_amdgcn_s_setprio(0);
   }
+}
+
+// One solve per launch pair: the ticket from the solve's own counters.
+template <int RC>
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_forward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                         const double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                         double* Ypay, double* __restrict__ Xpay, SvWs* ws,
+                                                         int64_t wait_ticks, int32_t npass, int64_t pstride) {
+  __shared__ int32_t s_g;
+  if (threadIdx.x == 0) s_g = __hip_atomic_fetch_add(&ws->ticket_f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  sv_forward_run<RC>(L, lda, n, B, nc, ldb, Ypay, Xpay, ws, wait_ticks, npass, pstride, sv_uniform(s_g));
+}
+
+template <int RC>
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_backward(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                          double* __restrict__ B, int64_t nc, int64_t ldb,
+                                                          const double* __restrict__ Ypay, double* Xpay, SvWs* ws,
+                                                          int64_t wait_ticks, int32_t npass, int64_t pstride) {
+  __shared__ int32_t s_g;
+  if (threadIdx.x == 0) s_g = __hip_atomic_fetch_add(&ws->ticket_b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  sv_backward_run<RC>(L, lda, n, B, nc, ldb, Ypay, Xpay, ws, wait_ticks, npass, pstride, sv_uniform(s_g));
+}
+
+// ------------------------------------------------- several solves per launch
+// The sweeps of several independent solves (a serving tick's items) in one
+// launch pair, all in passes of four: job j owns the tickets [first_j,
+// first_{j+1}) of a launch-wide counter, its blocks and passes in the order
+// of a launch of its own, so every wait is still on a smaller ticket of the
+// same job (taken by a workgroup that has started).  Each job's workspace
+// has the single-solve layout: its status word, then its payloads.
+__host__ __device__ inline int64_t sv_jr256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+__host__ __device__ inline int64_t sv_job_passes(int64_t nrhs) {
+  return nrhs > SV_RC_MID ? (nrhs + SV_RC_MID - 1) / SV_RC_MID : 1;
+}
+__host__ __device__ inline int64_t sv_job_stride(int64_t n) { return ((n + SV_NB - 1) / SV_NB) * SV_NB * SV_RC_MID; }
+
+// This workgroup's job and its ticket within the job (every thread of the
+// workgroup takes part; uniform results).
+__device__ __forceinline__ void sv_take_job(const TcSolveJob* jobs, int64_t count, int32_t* ctr, int32_t& job,
+                                            int32_t& g) {
+  __shared__ int32_t s_g, s_j;
+  if (threadIdx.x == 0) s_g = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int64_t t = s_g;
+  for (int64_t c0 = 0; c0 < count; c0 += SV_THREADS) {
+    const int64_t j = c0 + threadIdx.x;
+    if (j < count && jobs[j].first <= t && (j + 1 == count || t < jobs[j + 1].first)) s_j = (int32_t)j;
+  }
+  __syncthreads();
+  job = sv_uniform(s_j);
+  g = sv_uniform((int32_t)(t - jobs[job].first));
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_forward_many(const TcSolveJob* jobs, int64_t count, int32_t* ctr,
+                                                              int64_t wait_ticks) {
+  int32_t j, g;
+  sv_take_job(jobs, count, ctr, j, g);
+  const TcSolveJob J = jobs[j];
+  const int64_t np = sv_job_passes(J.nrhs), stride = sv_job_stride(J.n);
+  SvWs* ws = (SvWs*)J.work;
+  double* ypay = (double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
+  double* xpay = (double*)((char*)ypay + sv_jr256(8 * stride * np));
+  sv_forward_run<SV_RC_MID>(J.L, J.lda, J.n, J.B, J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks, (int32_t)np, stride, g);
+}
+
+__global__ __launch_bounds__(SV_THREADS, 2) void sv_backward_many(const TcSolveJob* jobs, int64_t count, int32_t* ctr,
+                                                               int64_t wait_ticks) {
+  int32_t j, g;
+  sv_take_job(jobs, count, ctr + 1, j, g);
+  const TcSolveJob J = jobs[j];
+  const int64_t np = sv_job_passes(J.nrhs), stride = sv_job_stride(J.n);
+  SvWs* ws = (SvWs*)J.work;
+  const double* ypay = (const double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
+  double* xpay = (double*)((char*)ypay + sv_jr256(8 * stride * np));
+  sv_backward_run<SV_RC_MID>(J.L, J.lda, J.n, J.B, J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks, (int32_t)np, stride, g);
+}
+
+// Job blockIdx.y: its status struct cleared (tickets and status word) and
+// its forward payloads set to the sentinel; the launch's two counters
+// cleared by the first workgroup.
+__global__ void sv_fill_many(const TcSolveJob* jobs, int32_t* ctr) {
+  const TcSolveJob J = jobs[blockIdx.y];
+  const int64_t count = sv_job_stride(J.n) * sv_job_passes(J.nrhs);
+  double* ypay = (double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
+  if (blockIdx.x == 0 && threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)J.work)[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0;
+  const double s = __builtin_bit_cast(double, SV_SENTINEL);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    ypay[i] = s;
 }
 
 // ------------------------------------------------ matrix-core operands
@@ -1119,6 +1204,23 @@ int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* D
     hipLaunchKernelGGL(sv_bwd_inv, dim3((unsigned)nb), dim3(SV_THREADS), 0, st, L, lda, n, Dinv, Q, B + c0, nc, ldb,
                        (const double*)m.ypay, m.xpay, m.ws, wait_ticks);
   }
+  return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
+}
+
+int64_t tc_solve_many_ws_bytes(int64_t n, int64_t nrhs) {
+  return sv_jr256(sizeof(SvWs)) + 2 * sv_jr256(8 * sv_job_stride(n) * sv_job_passes(nrhs));
+}
+
+int64_t tc_solve_many_tickets(int64_t n, int64_t nrhs) { return ((n + SV_NB - 1) / SV_NB) * sv_job_passes(nrhs); }
+
+int tc_launch_solve_many(const TcSolveJob* jobs, int64_t count, int64_t tickets, int64_t max_entries, int32_t* ctr,
+                         hipStream_t st, int64_t wait_ticks) {
+  if (count <= 0 || tickets <= 0) return 0;
+  int64_t bx = (max_entries + 255) / 256;
+  bx = bx < 1 ? 1 : (bx > 64 ? 64 : bx);
+  hipLaunchKernelGGL(sv_fill_many, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, st, jobs, ctr);
+  hipLaunchKernelGGL(sv_forward_many, dim3((unsigned)tickets), dim3(SV_THREADS), 0, st, jobs, count, ctr, wait_ticks);
+  hipLaunchKernelGGL(sv_backward_many, dim3((unsigned)tickets), dim3(SV_THREADS), 0, st, jobs, count, ctr, wait_ticks);
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
 }
 

@@ -373,10 +373,11 @@ int run_serve(uint64_t seed, int steps) {
     };
     z.fifo = [](int64_t n) { return (int64_t)(1 << 20) + 4 * (n / 128 + 1) * (n / 128 + 1); };
     z.tile = [](int64_t n, int prec) { return tc_tuned_batched_tile_prec(n, prec); };
-    // a solve workspace of the real shape: a header, then two payloads of
-    // 64-row blocks with 2 or 16 columns
+    // a solve workspace of the real shape (the server's solves share one
+    // launch, in passes of four): a header, then two payloads of 64-row
+    // blocks with 4 columns per pass
     z.solve_ws = [](int64_t n, int64_t nrhs) {
-      return (int64_t)256 + 2 * tcs::r256(8 * ((n + 63) / 64) * 64 * (nrhs <= 2 ? 2 : 16));
+      return (int64_t)256 + 2 * tcs::r256(8 * ((n + 63) / 64) * 64 * 4 * ((nrhs + 3) / 4));
     };
     tcs::PlanTable pt;
     pt.fp32_min_n_loose = 700;
