@@ -227,12 +227,16 @@ enum {
 #define CHOL_MIXED_SCALE 1 /* factor D^-1 A D^-1 with D = diag(A)^(1/2), return D L^ */
 
 /* Bytes of device workspace chol_factor_mixed needs: the fork-join
- * workspace plus n doubles (D) plus the rounded panel copy (n rows of
- * ceil(T / 64) * 64 elements of the chosen precision).  < 0 on invalid
+ * workspace plus n doubles (D) plus two rounded panel copies (each n rows
+ * of ceil(T / 64) * 64 elements of the chosen precision).  < 0 on invalid
  * arguments. */
 int64_t chol_factor_mixed_workspace_size(int64_t n, int64_t T, int prec);
 
-/* Factor in place with low-precision trailing products (fork-join schedule).
+/* Factor in place with low-precision trailing products.  CHOL_PREC_FP32 and
+ * CHOL_PREC_BF16 run the fork-join schedule with a one-step lookahead on a
+ * second stream (panel J+1 is factored, and rounded into the second panel
+ * copy, while the bulk of step J's update runs; the factor is the same bit
+ * for bit as with plain fork-join); CHOL_PREC_FP64 runs plain fork-join.
  *   A, n, lda, T, work, stream, info   as for chol_factor.
  *   prec    one of CHOL_PREC_*.
  *   flags   0 or CHOL_MIXED_SCALE.

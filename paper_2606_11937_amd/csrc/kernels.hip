@@ -305,19 +305,60 @@ __global__ __launch_bounds__(TC_THREADS) void tc_round_panel(const double* A, in
   }
 }
 
+// Trailing-update unit u of step J from the rounded panel copy P.
+template <int PREC>
+__device__ __forceinline__ void tc_run_update_lp(double* A, int64_t lda, const TcGeom& g, int32_t J, const TcUnit& u,
+                                                 const typename TcLp<PREC>::elem* P, int64_t ldp, TcUpdSmem& sm) {
+  const int64_t ri = tc_row0(g, u.I, u.a);
+  const int64_t rk = tc_row0(g, u.K, u.b);
+  tc_update_block_lp<PREC>(A + ri * lda + rk, P + ri * ldp, P + rk * ldp, lda, ldp, tc_rows(g, u.I, u.a),
+                           tc_rows(g, u.K, u.b), (int)tc_tdim(g, J), ri == rk, sm);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws,
                                                                  const typename TcLp<PREC>::elem* P, int64_t ldp) {
   __shared__ TcUpdPotrfSmem sm;
   if (tc_err_set(ws.hdr) || ws.noop) return;
-  const TcUnit u = tc_decode_trailing(g, J, J, blockIdx.x);
-  const int64_t ri = tc_row0(g, u.I, u.a);
-  const int64_t rk = tc_row0(g, u.K, u.b);
-  tc_update_block_lp<PREC>(A + ri * lda + rk, P + ri * ldp, P + rk * ldp, lda, ldp, tc_rows(g, u.I, u.a),
-                           tc_rows(g, u.K, u.b), (int)tc_tdim(g, J), ri == rk, sm.upd);
+  tc_run_update_lp<PREC>(A, lda, g, J, tc_decode_trailing(g, J, J, blockIdx.x), P, ldp, sm.upd);
   if (blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
     __syncthreads();
     tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
+  }
+}
+
+// The lookahead schedule's kernels for the low-precision update, as for FP64
+// (tc_fj_update_range, tc_fj_update_pool): units [first, first + gridDim.x)
+// with the fused POTRF(J+1, 0) when first == 0, and the pool on a unit
+// counter.  Same unit bodies, so the factor equals the fork-join one.
+template <int PREC>
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp_range(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                       TcWs ws, const typename TcLp<PREC>::elem* P,
+                                                                       int64_t ldp, int64_t first) {
+  __shared__ TcUpdPotrfSmem sm;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  tc_run_update_lp<PREC>(A, lda, g, J, tc_decode_trailing(g, J, J, first + blockIdx.x), P, ldp, sm.upd);
+  if (first == 0 && blockIdx.x == 0) {
+    __syncthreads();
+    tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp_pool(double* A, int64_t lda, TcGeom g, int32_t J,
+                                                                      TcWs ws, const typename TcLp<PREC>::elem* P,
+                                                                      int64_t ldp, int64_t first, int64_t count,
+                                                                      unsigned long long* ctr) {
+  __shared__ TcUpdSmem sm;
+  __shared__ int64_t s_u;
+  if (tc_err_set(ws.hdr) || ws.noop) return;
+  for (;;) {
+    if (threadIdx.x == 0) s_u = (int64_t)atomicAdd(ctr, 1ull);
+    __syncthreads();  // also: every thread is done with the previous unit's LDS
+    const int64_t u = s_u;
+    if (u >= count) break;
+    tc_run_update_lp<PREC>(A, lda, g, J, tc_decode_trailing(g, J, J, first + u), P, ldp, sm);
+    __syncthreads();  // s_u is rewritten next
   }
 }
 
@@ -1269,6 +1310,87 @@ static int tc_launch_factor_graph(double* A, int64_t n, int64_t lda, int64_t T, 
 
 static int64_t tc_pool_grid_size();
 
+// Fork-join with a one-step lookahead on two streams, after POTRF(0, 0):
+// stream A (the caller's) runs the panel chain and, for step J, the update
+// of column J+1 only; stream B runs the update of the columns beyond J+1,
+// which overlaps the panel chain of step J+1.  Each block still receives its
+// updates in step order: the column-(J+1) update of step J waits for the
+// bulk of step J-1, and the bulk of step J for A's panel J and column J+1
+// (which ran after the bulk of step J-1).
+// The bulk runs as a pool on a per-step unit counter: on B with `reserve`
+// workgroup slots left free for A's panel chain, then on A behind the next
+// step's chain, into the slots the chain frees.  Unit bodies and per-block
+// update order are the fork-join ones, so the factor is bit-identical to
+// every other schedule.
+// before(J) runs on A once panel J is final, ahead of step J's updates
+// (false: a launch failed); range(J, count) launches the column-(J+1)
+// units [0, count) with the fused POTRF(J+1, 0); pool(J, stream, grid,
+// first, count, ctr) launches a pool over units [first, first + count).
+// The per-step unit counters live in the phase-offset words (zeroed by the
+// caller; used by the persistent schedule only).
+template <class Before, class Range, class Pool>
+static int tc_lookahead_steps(double* A, int64_t lda, const TcGeom& g, TcWs ws, hipStream_t st, Before before,
+                              Range range, Pool pool) {
+  hipStream_t sb = tc_side_stream();
+  hipEvent_t ea = tc_side_event(0), eb = tc_side_event(1);
+  if (sb == nullptr || ea == nullptr || eb == nullptr) return TC_LAUNCH_EDEVICE;
+  const int64_t cap = tc_pool_grid_size();
+  if (cap <= 0) return TC_LAUNCH_EDEVICE;
+  // slots left to the chain: 3/16 of the chip, measured best among 1/16 ..
+  // 6/16 at n=32768, T=1024 (205.6 .. 204.4 .. 206.4 ms)
+  const int64_t reserve = cap * 3 / 16 > 0 ? cap * 3 / 16 : 1;
+  unsigned long long* cnt = (unsigned long long*)ws.offs;
+  bool b_used = false;
+  int32_t tail = -1;  // the step whose bulk still needs its second launch on A
+  int64_t tail_first = 0, tail_count = 0;
+  int tail_rec = -1;  // its timing record, ended by the tail too
+  auto launch_tail = [&]() {
+    if (tail < 0) return;
+    pool(tail, st, reserve, tail_first, tail_count, cnt + tail);
+    tc_timed_extend(tail_rec, st);
+    tail = -1;
+  };
+  for (int32_t J = 0; J < g.M; ++J) {
+    for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
+      const int64_t nt = tc_trsm_count(g, J, sc);
+      if (nt > 0)
+        tc_timed(TC_UNIT_TRSM, st, [&] {
+          hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+        });
+      const int64_t np = tc_panel_count(g, J, sc);
+      if (np > 0)
+        tc_timed(TC_UNIT_PANEL, st, [&] {
+          hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
+        });
+    }
+    launch_tail();  // step J-1's bulk, into the slots panel J leaves
+    const int64_t nu = tc_trailing_units(g, J);
+    if (nu <= 0) continue;
+    if (!before(J)) return TC_LAUNCH_EDEVICE;
+    const int64_t ncol = tc_colsize(g, J + 1);  // units of tile column J+1 at step J
+    if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;  // B's bulk J-1
+    // column J+1 first, on the whole chip: the chain of step J+1 waits
+    // for it, while the bulk waits only for its own inputs
+    tc_timed(TC_UNIT_UPDATE, st, [&] { range(J, ncol); });
+    if (hipEventRecord(ea, st) != hipSuccess) return TC_LAUNCH_EDEVICE;  // panel J, bulk J-1, column J+1
+    if (nu > ncol) {
+      if (hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
+      tc_timed(TC_TIMING_REST, sb, [&] { pool(J, sb, cap - reserve, ncol, nu - ncol, cnt + J); });
+      tail_rec = tc_timed_last(TC_TIMING_REST);
+      if (hipEventRecord(eb, sb) != hipSuccess) return TC_LAUNCH_EDEVICE;
+      b_used = true;
+      tail = J;
+      tail_first = ncol;
+      tail_count = nu - ncol;
+    }
+  }
+  launch_tail();
+  // the caller's stream covers all of it
+  if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
+  return tc_chk(hipGetLastError());
+}
+
+
 int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_flags, void* work, hipStream_t st,
                      int64_t grid, int64_t wait_ticks, int64_t chunk) {
   const int sched = sched_flags & 0xff;
@@ -1313,87 +1435,20 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
     return tc_chk(hipGetLastError());
   }
   if (sched == 4) {
-    // fork-join with a one-step lookahead on two streams: stream A (the
-    // caller's) runs the panel chain and, for step J, the update of column
-    // J+1 only; stream B runs the update of the columns beyond J+1, which
-    // overlaps the panel chain of step J+1.  Each block still receives its
-    // updates in step order: the column-(J+1) update of step J waits for the
-    // bulk of step J-1, and the bulk of step J for A's panel J and column
-    // J+1 (which ran after the bulk of step J-1).
-    // The bulk runs as a pool (tc_fj_update_pool) on a per-step unit counter:
-    // on B with `reserve` workgroup slots left free for A's panel chain, then
-    // on A behind the next step's chain, into the slots the chain frees.
-    // Unit bodies and per-block update order are the fork-join ones, so the
-    // factor is bit-identical to every other schedule.
-    hipStream_t sb = tc_side_stream();
-    hipEvent_t ea = tc_side_event(0), eb = tc_side_event(1);
-    if (sb == nullptr || ea == nullptr || eb == nullptr) return TC_LAUNCH_EDEVICE;
-    const int64_t cap = tc_pool_grid_size();
-    if (cap <= 0) return TC_LAUNCH_EDEVICE;
-    // slots left to the chain: 3/16 of the chip, measured best among 1/16 ..
-    // 6/16 at n=32768, T=1024 (205.6 .. 204.4 .. 206.4 ms)
-    const int64_t reserve = cap * 3 / 16 > 0 ? cap * 3 / 16 : 1;
-    // the per-step unit counters live in the phase-offset words (used by the
-    // persistent schedule only)
-    unsigned long long* cnt = (unsigned long long*)ws.offs;
     hipLaunchKernelGGL(tc_fill_zero, dim3(1), dim3(256), 0, st, (int32_t*)ws.offs, (int64_t)(2 * (g.M + 1)));
     tc_timed(TC_UNIT_POTRF, st, [&] {
       hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
     });
-    bool b_used = false;
-    int32_t tail = -1;  // the step whose bulk still needs its second launch on A
-    int64_t tail_first = 0, tail_count = 0;
-    int tail_rec = -1;  // its timing record, ended by the tail too
-    auto launch_tail = [&]() {
-      if (tail < 0) return;
-      hipLaunchKernelGGL(tc_fj_update_pool, dim3((unsigned)reserve), dim3(TC_THREADS), 0, st, A, lda, g, tail, ws,
-                         tail_first, tail_count, cnt + tail);
-      tc_timed_extend(tail_rec, st);
-      tail = -1;
-    };
-    for (int32_t J = 0; J < g.M; ++J) {
-      for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
-        const int64_t nt = tc_trsm_count(g, J, sc);
-        if (nt > 0)
-          tc_timed(TC_UNIT_TRSM, st, [&] {
-            hipLaunchKernelGGL(tc_fj_trsm, dim3((unsigned)(2 * nt)), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
-          });
-        const int64_t np = tc_panel_count(g, J, sc);
-        if (np > 0)
-          tc_timed(TC_UNIT_PANEL, st, [&] {
-            hipLaunchKernelGGL(tc_fj_panel, dim3((unsigned)np), dim3(TC_THREADS), 0, st, A, lda, g, J, sc, ws);
-          });
-      }
-      launch_tail();  // step J-1's bulk, into the slots panel J leaves
-      const int64_t nu = tc_trailing_units(g, J);
-      if (nu <= 0) continue;
-      const int64_t ncol = tc_colsize(g, J + 1);  // units of tile column J+1 at step J
-      if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;  // B's bulk J-1
-      // column J+1 first, on the whole chip: the chain of step J+1 waits
-      // for it, while the bulk waits only for its own inputs
-      tc_timed(TC_UNIT_UPDATE, st, [&] {
-        hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)ncol), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
-                           (int64_t)0);
-      });
-      if (hipEventRecord(ea, st) != hipSuccess) return TC_LAUNCH_EDEVICE;  // panel J, bulk J-1, column J+1
-      if (nu > ncol) {
-        if (hipStreamWaitEvent(sb, ea, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
-        tc_timed(TC_TIMING_REST, sb, [&] {
-          hipLaunchKernelGGL(tc_fj_update_pool, dim3((unsigned)(cap - reserve)), dim3(TC_THREADS), 0, sb, A, lda, g, J,
-                             ws, ncol, nu - ncol, cnt + J);
+    return tc_lookahead_steps(
+        A, lda, g, ws, st, [](int32_t) { return true; },
+        [&](int32_t J, int64_t count) {
+          hipLaunchKernelGGL(tc_fj_update_range, dim3((unsigned)count), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
+                             (int64_t)0);
+        },
+        [&](int32_t J, hipStream_t s, int64_t grid, int64_t first, int64_t count, unsigned long long* ctr) {
+          hipLaunchKernelGGL(tc_fj_update_pool, dim3((unsigned)grid), dim3(TC_THREADS), 0, s, A, lda, g, J, ws, first,
+                             count, ctr);
         });
-        tail_rec = tc_timed_last(TC_TIMING_REST);
-        if (hipEventRecord(eb, sb) != hipSuccess) return TC_LAUNCH_EDEVICE;
-        b_used = true;
-        tail = J;
-        tail_first = ncol;
-        tail_count = nu - ncol;
-      }
-    }
-    launch_tail();
-    // the caller's stream covers all of it
-    if (b_used && hipStreamWaitEvent(st, eb, 0) != hipSuccess) return TC_LAUNCH_EDEVICE;
-    return tc_chk(hipGetLastError());
   }
   if (sched == 5) return tc_launch_factor_graph(A, n, lda, T, g, ws, work, st);
   if (sched == 0) {
@@ -1441,22 +1496,37 @@ int tc_launch_factor(double* A, int64_t n, int64_t lda, int64_t T, int sched_fla
 int64_t tc_lp_ld(int64_t T) { return (T + 63) & ~(int64_t)63; }
 static int64_t tc_lp_elem(int prec) { return prec == TC_PREC_FP32 ? 4 : prec == TC_PREC_BF16 ? 2 : 0; }
 
+// the fork-join workspace, the diagonal scale factors, then two rounded
+// panel copies (the lookahead schedule rounds panel J+1 while the bulk of
+// step J still reads panel J)
 int64_t tc_ws_mixed_bytes(int64_t n, int64_t T, int prec) {
-  return tc_ws_bytes(n, T) + tc_round256(8 * n) + tc_round256(n * tc_lp_ld(T) * tc_lp_elem(prec));
+  return tc_ws_bytes(n, T) + tc_round256(8 * n) + 2 * tc_round256(n * tc_lp_ld(T) * tc_lp_elem(prec));
 }
 
+// The low-precision factorization with the lookahead schedule: panel J is
+// rounded into copy J mod 2, which the column-(J+1) launch and the bulk of
+// step J read.
 template <int PREC>
-static void tc_lp_step(double* A, int64_t lda, const TcGeom& g, int32_t J, TcWs ws, void* P, int64_t ldp,
-                       hipStream_t st) {
+static int tc_lp_lookahead(double* A, int64_t lda, const TcGeom& g, TcWs ws, void* P0, void* P1, int64_t ldp,
+                           hipStream_t st) {
   typedef typename TcLp<PREC>::elem E;
-  const int64_t rows = g.n - (int64_t)(J + 1) * g.T;
-  hipLaunchKernelGGL(tc_round_panel<PREC>, dim3((unsigned)((rows + 15) / 16)), dim3(TC_THREADS), 0, st, A, lda, g,
-                     J, (E*)P, ldp, ws);
-  const int64_t nu = tc_trailing_units(g, J);
-  tc_timed(TC_UNIT_UPDATE, st, [&] {
-    hipLaunchKernelGGL(tc_fj_update_lp<PREC>, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws,
-                       (const E*)P, ldp);
-  });
+  auto pj = [&](int32_t J) { return (E*)((J & 1) ? P1 : P0); };
+  return tc_lookahead_steps(
+      A, lda, g, ws, st,
+      [&](int32_t J) {
+        const int64_t rows = g.n - (int64_t)(J + 1) * g.T;
+        hipLaunchKernelGGL(tc_round_panel<PREC>, dim3((unsigned)((rows + 15) / 16)), dim3(TC_THREADS), 0, st, A, lda,
+                           g, J, pj(J), ldp, ws);
+        return true;
+      },
+      [&](int32_t J, int64_t count) {
+        hipLaunchKernelGGL(tc_fj_update_lp_range<PREC>, dim3((unsigned)count), dim3(TC_THREADS), 0, st, A, lda, g, J,
+                           ws, (const E*)pj(J), ldp, (int64_t)0);
+      },
+      [&](int32_t J, hipStream_t s, int64_t grid, int64_t first, int64_t count, unsigned long long* ctr) {
+        hipLaunchKernelGGL(tc_fj_update_lp_pool<PREC>, dim3((unsigned)grid), dim3(TC_THREADS), 0, s, A, lda, g, J, ws,
+                           (const E*)pj(J), ldp, first, count, ctr);
+      });
 }
 
 int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int prec, int scale, double shift,
@@ -1475,6 +1545,17 @@ int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int pre
   tc_timed(TC_UNIT_POTRF, st, [&] {
     hipLaunchKernelGGL(tc_fj_potrf, dim3(1), dim3(TC_THREADS), 0, st, A, lda, g, 0, 0, ws);
   });
+  if (prec == TC_PREC_FP32 || prec == TC_PREC_BF16) {
+    // the unit counters of the lookahead pool are zero: the whole
+    // fork-join workspace was cleared above
+    void* P1 = (char*)P + tc_round256(n * ldp * tc_lp_elem(prec));
+    const int r = prec == TC_PREC_FP32 ? tc_lp_lookahead<TC_PREC_FP32>(A, lda, g, ws, P, P1, ldp, st)
+                                       : tc_lp_lookahead<TC_PREC_BF16>(A, lda, g, ws, P, P1, ldp, st);
+    if (r != 0) return r;
+    if (scale)
+      hipLaunchKernelGGL(tc_unscale_lower, dim3((unsigned)n), dim3(TC_THREADS), 0, st, A, lda, n, d, ws.hdr);
+    return tc_chk(hipGetLastError());
+  }
   for (int32_t J = 0; J < g.M; ++J) {
     for (int32_t sc = 0; sc < tc_sb(g, J); ++sc) {
       const int64_t nt = tc_trsm_count(g, J, sc);
@@ -1489,11 +1570,7 @@ int tc_launch_factor_mixed(double* A, int64_t n, int64_t lda, int64_t T, int pre
         });
     }
     if (tc_trailing_units(g, J) <= 0) continue;
-    if (prec == TC_PREC_FP32) {
-      tc_lp_step<TC_PREC_FP32>(A, lda, g, J, ws, P, ldp, st);
-    } else if (prec == TC_PREC_BF16) {
-      tc_lp_step<TC_PREC_BF16>(A, lda, g, J, ws, P, ldp, st);
-    } else {
+    {
       const int64_t nu = tc_trailing_units(g, J);
       tc_timed(TC_UNIT_UPDATE, st, [&] {
         hipLaunchKernelGGL(tc_fj_update, dim3((unsigned)nu), dim3(TC_THREADS), 0, st, A, lda, g, J, ws);
