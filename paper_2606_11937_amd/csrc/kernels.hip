@@ -284,7 +284,7 @@ __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_pool(double* A, in
 }
 
 // ----------------------------------------------- low-precision trailing update
-// Mixed-precision fork-join: after the FP64 panel of step J is final, its
+// Mixed precision: after the FP64 panel of step J is final, its
 // rows below the diagonal tile are rounded once into the panel copy P (row r
 // of A at row r of P, column J*T + k at column k); the trailing update then
 // forms its products from P on the FP32 or BF16 matrix cores and subtracts
@@ -315,22 +315,11 @@ __device__ __forceinline__ void tc_run_update_lp(double* A, int64_t lda, const T
                            tc_rows(g, u.K, u.b), (int)tc_tdim(g, J), ri == rk, sm);
 }
 
-template <int PREC>
-__global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp(double* A, int64_t lda, TcGeom g, int32_t J, TcWs ws,
-                                                                 const typename TcLp<PREC>::elem* P, int64_t ldp) {
-  __shared__ TcUpdPotrfSmem sm;
-  if (tc_err_set(ws.hdr) || ws.noop) return;
-  tc_run_update_lp<PREC>(A, lda, g, J, tc_decode_trailing(g, J, J, blockIdx.x), P, ldp, sm.upd);
-  if (blockIdx.x == 0) {  // the last update of diagonal block gid(J+1, 0)
-    __syncthreads();
-    tc_run_potrf(A, lda, g, J + 1, 0, ws.hdr, sm.potrf);
-  }
-}
-
-// The lookahead schedule's kernels for the low-precision update, as for FP64
-// (tc_fj_update_range, tc_fj_update_pool): units [first, first + gridDim.x)
-// with the fused POTRF(J+1, 0) when first == 0, and the pool on a unit
-// counter.  Same unit bodies, so the factor equals the fork-join one.
+// The low-precision factorization runs the lookahead schedule, with
+// kernels as for FP64 (tc_fj_update_range, tc_fj_update_pool): units
+// [first, first + gridDim.x) with the fused POTRF(J+1, 0) when first == 0,
+// and the pool on a unit counter.  The unit bodies and the per-block update
+// order are those of one launch per step, so the factor is too.
 template <int PREC>
 __global__ __launch_bounds__(TC_THREADS, 2) void tc_fj_update_lp_range(double* A, int64_t lda, TcGeom g, int32_t J,
                                                                        TcWs ws, const typename TcLp<PREC>::elem* P,
