@@ -23,6 +23,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "gptr.h"
 #include "launch.h"
 
 #define SV_NB 64        // rows per block
@@ -606,10 +607,14 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_forward_many(const TcSolveJo
   sv_take_job(jobs, count, ctr, j, g);
   const TcSolveJob J = jobs[j];
   const int64_t np = sv_job_passes(J.nrhs), stride = sv_job_stride(J.n);
-  SvWs* ws = (SvWs*)J.work;
-  double* ypay = (double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
+  // the job's addresses in the global address space (read from memory,
+  // they would otherwise be generic and every access a flat one)
+  char* work = tc_global((char*)J.work);
+  SvWs* ws = (SvWs*)work;
+  double* ypay = (double*)(work + sv_jr256(sizeof(SvWs)));
   double* xpay = (double*)((char*)ypay + sv_jr256(8 * stride * np));
-  sv_forward_run<SV_RC_MID>(J.L, J.lda, J.n, J.B, J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks, (int32_t)np, stride, g);
+  sv_forward_run<SV_RC_MID>(tc_global(J.L), J.lda, J.n, tc_global(J.B), J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks,
+                            (int32_t)np, stride, g);
 }
 
 __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward_many(const TcSolveJob* jobs, int64_t count, int32_t* ctr,
@@ -618,10 +623,12 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward_many(const TcSolveJ
   sv_take_job(jobs, count, ctr + 1, j, g);
   const TcSolveJob J = jobs[j];
   const int64_t np = sv_job_passes(J.nrhs), stride = sv_job_stride(J.n);
-  SvWs* ws = (SvWs*)J.work;
-  const double* ypay = (const double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
+  char* work = tc_global((char*)J.work);  // as in the forward sweep
+  SvWs* ws = (SvWs*)work;
+  const double* ypay = (const double*)(work + sv_jr256(sizeof(SvWs)));
   double* xpay = (double*)((char*)ypay + sv_jr256(8 * stride * np));
-  sv_backward_run<SV_RC_MID>(J.L, J.lda, J.n, J.B, J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks, (int32_t)np, stride, g);
+  sv_backward_run<SV_RC_MID>(tc_global(J.L), J.lda, J.n, tc_global(J.B), J.nrhs, J.ldb, ypay, xpay, ws, wait_ticks,
+                             (int32_t)np, stride, g);
 }
 
 // Job blockIdx.y: its status struct cleared (tickets and status word) and
@@ -630,8 +637,9 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward_many(const TcSolveJ
 __global__ void sv_fill_many(const TcSolveJob* jobs, int32_t* ctr) {
   const TcSolveJob J = jobs[blockIdx.y];
   const int64_t count = sv_job_stride(J.n) * sv_job_passes(J.nrhs);
-  double* ypay = (double*)((char*)J.work + sv_jr256(sizeof(SvWs)));
-  if (blockIdx.x == 0 && threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)J.work)[threadIdx.x] = 0;
+  char* work = tc_global((char*)J.work);
+  double* ypay = (double*)(work + sv_jr256(sizeof(SvWs)));
+  if (blockIdx.x == 0 && threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)work)[threadIdx.x] = 0;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0;
   const double s = __builtin_bit_cast(double, SV_SENTINEL);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
