@@ -77,6 +77,26 @@ def test_server_results_against_oracle(tc, mode):
             assert srv.ticks() == len(reqs)
 
 
+def test_server_right_hand_side_counts(tc):
+    """Requests with every right-hand-side count the server takes (1 to 8)
+    in one tick: the tick's solves run as one launch pair in which each item
+    owns its own ticket range and takes its passes of four (one or two);
+    results against the oracle."""
+    rng = np.random.default_rng(64)
+    reqs = []
+    for n, k in ((100, 1), (333, 5), (640, 8), (257, 3), (700, 7), (65, 2), (129, 4), (512, 6)):
+        pts = rng.random((n, 2))
+        reqs.append((pts, rng.standard_normal((n, k)), float(rng.uniform(0.05, 0.5)), 1e-2, 1e-12))
+    with tc.Server(arena(4 << 30), 256 << 20, "continuous") as srv:
+        ids = [srv.submit(p, B, ell, nug, tol) for (p, B, ell, nug, tol) in reqs]
+        for rid, (p, B, ell, nug, tol) in zip(ids, reqs):
+            st, X, eta, lat, info = srv.wait(rid)
+            assert st == tc.CHOL_OK, (st, len(p), B.shape[1])
+            eh = oracle.backward_error(host_matrix(p, ell, nug), X, B)
+            say(f"server n={len(p)} nrhs={B.shape[1]}: eta {eh:.2e}")
+            assert eh <= tol and eta <= tol, (len(p), B.shape[1], eh, eta)
+
+
 def test_server_result_independent_of_the_mix(tc):
     rng = np.random.default_rng(61)
     probe = [make_request(rng, n) for n in (100, 450, 999)]
