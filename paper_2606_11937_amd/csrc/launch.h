@@ -68,10 +68,6 @@ int64_t tc_solve_status_offset();
 // Enqueue forward + backward substitution (64-row blocks).
 int tc_launch_solve(const double* L, int64_t n, int64_t lda, int64_t T, double* B, int64_t nrhs, int64_t ldb,
                     void* work, hipStream_t st, int64_t wait_ticks);
-// Repeated solves with one factor: invert the 64 x 64 diagonal blocks and
-// form the coupling blocks of neighbouring block rows once
-// (tc_solve_inv_bytes of storage), then sweep with one matrix-core product
-// per block step on the chain.
 // Several independent solves in one launch pair (a serving tick's items):
 // job j's sweeps take the tickets [first, first + tc_solve_many_tickets(n,
 // nrhs)) of the launch, in passes of four; `work` is the job's own workspace
@@ -92,6 +88,10 @@ int64_t tc_solve_many_tickets(int64_t n, int64_t nrhs);
 // width); ctr: two int32 of device memory for the launch's counters.
 int tc_launch_solve_many(const TcSolveJob* jobs, int64_t count, int64_t tickets, int64_t max_entries, int32_t* ctr,
                          hipStream_t st, int64_t wait_ticks);
+// Repeated solves with one factor: invert the 64 x 64 diagonal blocks and
+// form the coupling blocks of neighbouring block rows once
+// (tc_solve_inv_bytes of storage), then sweep with one matrix-core product
+// per block step on the chain.
 int64_t tc_solve_inv_bytes(int64_t n);
 int tc_launch_invert_diag(const double* L, int64_t n, int64_t lda, double* Dinv, hipStream_t st);
 int tc_launch_solve_inv(const double* L, int64_t n, int64_t lda, const double* Dinv, double* B, int64_t nrhs,
