@@ -631,19 +631,21 @@ __global__ __launch_bounds__(SV_THREADS, 2) void sv_backward_many(const TcSolveJ
                              (int32_t)np, stride, g);
 }
 
-// Job blockIdx.y: its status struct cleared (tickets and status word) and
-// its forward payloads set to the sentinel; the launch's two counters
-// cleared by the first workgroup.
-__global__ void sv_fill_many(const TcSolveJob* jobs, int32_t* ctr) {
-  const TcSolveJob J = jobs[blockIdx.y];
-  const int64_t count = sv_job_stride(J.n) * sv_job_passes(J.nrhs);
-  char* work = tc_global((char*)J.work);
-  double* ypay = (double*)(work + sv_jr256(sizeof(SvWs)));
-  if (blockIdx.x == 0 && threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)work)[threadIdx.x] = 0;
+// Jobs blockIdx.y, blockIdx.y + gridDim.y, ...: each one's status struct
+// cleared (tickets and status word) and its forward payloads set to the
+// sentinel; the launch's two counters cleared by the first workgroup.
+__global__ void sv_fill_many(const TcSolveJob* jobs, int64_t njobs, int32_t* ctr) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0;
   const double s = __builtin_bit_cast(double, SV_SENTINEL);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    ypay[i] = s;
+  for (int64_t j = blockIdx.y; j < njobs; j += gridDim.y) {
+    const TcSolveJob J = jobs[j];
+    const int64_t count = sv_job_stride(J.n) * sv_job_passes(J.nrhs);
+    char* work = tc_global((char*)J.work);
+    double* ypay = (double*)(work + sv_jr256(sizeof(SvWs)));
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(SvWs) / 4) ((int32_t*)work)[threadIdx.x] = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+      ypay[i] = s;
+  }
 }
 
 // ------------------------------------------------ matrix-core operands
@@ -1226,7 +1228,8 @@ int tc_launch_solve_many(const TcSolveJob* jobs, int64_t count, int64_t tickets,
   if (count <= 0 || tickets <= 0) return 0;
   int64_t bx = (max_entries + 255) / 256;
   bx = bx < 1 ? 1 : (bx > 64 ? 64 : bx);
-  hipLaunchKernelGGL(sv_fill_many, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, st, jobs, ctr);
+  const int64_t by = count < 65535 ? count : 65535;
+  hipLaunchKernelGGL(sv_fill_many, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, st, jobs, count, ctr);
   hipLaunchKernelGGL(sv_forward_many, dim3((unsigned)tickets), dim3(SV_THREADS), 0, st, jobs, count, ctr, wait_ticks);
   hipLaunchKernelGGL(sv_backward_many, dim3((unsigned)tickets), dim3(SV_THREADS), 0, st, jobs, count, ctr, wait_ticks);
   return hipGetLastError() == hipSuccess ? 0 : TC_LAUNCH_EDEVICE;
